@@ -1,0 +1,477 @@
+/*
+ * Plain FP64 CPU oracle for the Centering Triangle Algorithm (CTA) and the
+ * Triangle Algorithm (TA) of Lau & Kalantari, "On the Performance of a Novel
+ * Class of Linear System Solvers and Comparison with State-of-The-Art
+ * Algorithms" (arXiv 2304.12168).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this file.  It shares no code,
+ * header or constant generator with the GPU library, and the GPU library
+ * never calls it.
+ *
+ * Everything is sequential, single-threaded and written for reading, not for
+ * speed.  Build with -O2 -ffp-contract=off so that every a*b+c below is the
+ * two-rounding expression it looks like, and every fma() is one rounding.
+ *
+ * Reductions.  Every inner product (matrix rows, matrix columns, norms) is
+ * evaluated with the compensated algorithm Dot2 of Ogita, Rump and Oishi,
+ * "Accurate sum and dot product", SIAM J. Sci. Comput. 26 (2005), Alg. 5.3:
+ * the result is as accurate as if computed in twice the working precision
+ * and then rounded once.  Terms are taken in index order.
+ *
+ * Stop codes: 1 residual, 2 normal equation, 3 witness, 4 iteration budget,
+ * 5 breakdown (non-finite or degenerate step quantities).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OR_RESIDUAL = 1, OR_NORMAL = 2, OR_WITNESS = 3, OR_MAXITER = 4, OR_BREAKDOWN = 5 };
+enum { OR_DENSE = 0, OR_CSR = 1 };
+
+typedef struct {
+    int32_t kind;           /* OR_DENSE (row-major, leading dimension ld) or OR_CSR */
+    int64_t m, n, ld;
+    const int32_t *row_ptr; /* CSR: m+1 */
+    const int32_t *col_idx; /* CSR: nnz */
+    const double *val;      /* CSR: nnz; dense: m*ld */
+} or_mat;
+
+typedef struct {
+    double tol;        /* stop when ||b - A x|| <= tol ||b|| (true residual) */
+    double tol_normal; /* stop when ||A^T r|| <= tol_normal ||A^T b||; 0: only A^T r = 0 */
+    int32_t t;         /* CTA order */
+    int64_t max_iter;
+    int32_t replace_every; /* recompute r = b - A x every so many iterations; 0: never */
+    int32_t warm_start;    /* CTA x-form: start from the given x */
+    double rho0;           /* TA: initial radius */
+    int32_t fixed_rho;     /* TA: 1 = fixed radius, stop at a witness */
+} or_opts;
+
+typedef struct {
+    int64_t iters, matvecs;
+    int32_t stop;
+    double rel_res, rel_normal, rho, rho_lo;
+} or_info;
+
+/* ---------------------------------------------------------------------- */
+/* Error-free transformations and the Dot2 accumulator                     */
+/* ---------------------------------------------------------------------- */
+typedef struct { double p, s; } acc2;
+
+/* Knuth's TwoSum: a + b = x + y exactly. */
+static void two_sum(double a, double b, double *x, double *y) {
+    double z;
+    *x = a + b;
+    z = *x - a;
+    *y = (a - (*x - z)) + (b - z);
+}
+
+/* TwoProduct with a fused multiply-add: a * b = x + y exactly. */
+static void two_prod(double a, double b, double *x, double *y) {
+    *x = a * b;
+    *y = fma(a, b, -*x);
+}
+
+/* One Dot2 step: acc += a * b. */
+static void acc_add(acc2 *c, double a, double b) {
+    double h, r, q;
+    two_prod(a, b, &h, &r);
+    two_sum(c->p, h, &c->p, &q);
+    c->s = c->s + (q + r);
+}
+
+static double acc_value(acc2 c) { return c.p + c.s; }
+
+double or_dot2(int64_t n, const double *x, const double *y) {
+    acc2 c = {0.0, 0.0};
+    for (int64_t i = 0; i < n; ++i) acc_add(&c, x[i], y[i]);
+    return acc_value(c);
+}
+
+/* ---------------------------------------------------------------------- */
+/* Matrix products: y = A x, w = A^T u, r = b - A x                         */
+/* ---------------------------------------------------------------------- */
+void or_apply(const or_mat *A, const double *x, double *y) {
+    for (int64_t i = 0; i < A->m; ++i) {
+        acc2 c = {0.0, 0.0};
+        if (A->kind == OR_CSR) {
+            for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+                acc_add(&c, A->val[k], x[A->col_idx[k]]);
+        } else {
+            const double *row = A->val + i * A->ld;
+            for (int64_t j = 0; j < A->n; ++j) acc_add(&c, row[j], x[j]);
+        }
+        y[i] = acc_value(c);
+    }
+}
+
+/* (A^T u)_j = sum over i of a_ij u_i, terms in increasing i. */
+void or_apply_t(const or_mat *A, const double *u, double *w) {
+    acc2 *c = (acc2 *)calloc((size_t)A->n, sizeof(acc2));
+    for (int64_t i = 0; i < A->m; ++i) {
+        if (A->kind == OR_CSR) {
+            for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+                acc_add(&c[A->col_idx[k]], A->val[k], u[i]);
+        } else {
+            const double *row = A->val + i * A->ld;
+            for (int64_t j = 0; j < A->n; ++j) acc_add(&c[j], row[j], u[i]);
+        }
+    }
+    for (int64_t j = 0; j < A->n; ++j) w[j] = acc_value(c[j]);
+    free(c);
+}
+
+/* r_i = b_i - (A x)_i as one compensated sum of the terms b_i, -a_i1 x_1, ... */
+void or_residual(const or_mat *A, const double *b, const double *x, double *r) {
+    for (int64_t i = 0; i < A->m; ++i) {
+        acc2 c = {0.0, 0.0};
+        acc_add(&c, b[i], 1.0);
+        if (A->kind == OR_CSR) {
+            for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+                acc_add(&c, -A->val[k], x[A->col_idx[k]]);
+        } else {
+            const double *row = A->val + i * A->ld;
+            for (int64_t j = 0; j < A->n; ++j) acc_add(&c, -row[j], x[j]);
+        }
+        r[i] = acc_value(c);
+    }
+}
+
+/* ---------------------------------------------------------------------- */
+/* The auxiliary equation of CTA (section 3.1, eq. "eqcoeff")               */
+/* ---------------------------------------------------------------------- */
+/*
+ * phi[1..2t] holds phi_i = r^T H^i r.  The auxiliary equation is the t x t
+ * Hankel system M alpha = g with M_ij = phi_{i+j}, g_i = phi_i (i, j = 1..t).
+ * The paper asks for its minimum-norm solution when it is not unique; the
+ * reading used here is a ridge solution of a scaled system, which is
+ * continuous in phi (no threshold):
+ *
+ *   1. te = t, lowered to i-1 at the first i with phi_{2i} <= 0 (then H^i r = 0
+ *      and the higher Krylov directions carry nothing).
+ *   2. te = 1: alpha_1 = phi_1 / phi_2 (Example 1's closed form).
+ *   3. Otherwise scale by powers of two, s_i = 2^-k_i with k_i = floor((e_i-1)/2)
+ *      where phi_{2i} = f 2^e_i, f in [0.5, 1), so that the scaled diagonal lies
+ *      in [1, 4) and the scaling is exact:  Ms_ij = (phi_{i+j} s_i) s_j,
+ *      gs_i = phi_i s_i.  Add a ridge to the diagonal,
+ *      Ms_ii = fma(Ms_ii, 16 te^2 2^-53, Ms_ii).
+ *   4. Unpivoted Cholesky Ms = L L^T, column by column; if a pivot is not
+ *      positive at column j, te is lowered to j (the leading block is kept).
+ *      If te drops to 1 the closed form of step 2 is used.
+ *   5. Forward and back substitution, alpha_i = s_i * alpha~_i, zero past te.
+ * Returns te (0: no usable direction).
+ */
+int or_gram_alpha(const double *phi, int t, double *alpha) {
+    double s[16], Ms[16][16], gs[16], L[16][16], z[16], at[16];
+    int te = t, i, j, k;
+    for (i = 0; i < t; ++i) alpha[i] = 0.0;
+    for (i = 1; i <= t; ++i) {
+        if (!(phi[2 * i] > 0.0)) { te = i - 1; break; }
+    }
+    if (te <= 0) return 0;
+    if (te >= 2) {
+        double ridge;
+        for (i = 0; i < te; ++i) {
+            int e;
+            (void)frexp(phi[2 * (i + 1)], &e);
+            int kk = (int)floor((e - 1) / 2.0);
+            s[i] = ldexp(1.0, -kk);
+        }
+        for (i = 0; i < te; ++i) {
+            for (j = 0; j < te; ++j) Ms[i][j] = (phi[i + j + 2] * s[i]) * s[j];
+            gs[i] = phi[i + 1] * s[i];
+        }
+        ridge = 16.0 * (double)te * (double)te * ldexp(1.0, -53);
+        for (i = 0; i < te; ++i) Ms[i][i] = fma(Ms[i][i], ridge, Ms[i][i]);
+        for (j = 0; j < te; ++j) {
+            double d = Ms[j][j];
+            for (k = 0; k < j; ++k) d = fma(-L[j][k], L[j][k], d);
+            if (!(d > 0.0)) { te = j; break; }
+            L[j][j] = sqrt(d);
+            for (i = j + 1; i < te; ++i) {
+                double v = Ms[i][j];
+                for (k = 0; k < j; ++k) v = fma(-L[i][k], L[j][k], v);
+                L[i][j] = v / L[j][j];
+            }
+        }
+    }
+    if (te == 1) {
+        alpha[0] = phi[1] / phi[2];
+        return 1;
+    }
+    for (i = 0; i < te; ++i) {
+        double v = gs[i];
+        for (k = 0; k < i; ++k) v = fma(-L[i][k], z[k], v);
+        z[i] = v / L[i][i];
+    }
+    for (i = te - 1; i >= 0; --i) {
+        double v = z[i];
+        for (k = i + 1; k < te; ++k) v = fma(-L[k][i], at[k], v);
+        at[i] = v / L[i][i];
+    }
+    for (i = 0; i < te; ++i) alpha[i] = s[i] * at[i];
+    return te;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Algorithm 1 (CTA) with H = A A^T                                         */
+/* ---------------------------------------------------------------------- */
+static int finite_all(const double *v, int n) {
+    for (int i = 0; i < n; ++i)
+        if (!isfinite(v[i])) return 0;
+    return 1;
+}
+
+static void exit_diagnostics(const or_mat *A, const double *b, const double *x, double nb,
+                             double *rel_res, double *rel_normal) {
+    double *rt = (double *)malloc(sizeof(double) * (size_t)A->m);
+    double *w = (double *)malloc(sizeof(double) * (size_t)A->n);
+    double nab, nw;
+    or_residual(A, b, x, rt);
+    *rel_res = sqrt(or_dot2(A->m, rt, rt)) / nb;
+    or_apply_t(A, rt, w);
+    nw = sqrt(or_dot2(A->n, w, w));
+    or_apply_t(A, b, w);
+    nab = sqrt(or_dot2(A->n, w, w));
+    *rel_normal = nab > 0.0 ? nw / nab : 0.0;
+    free(rt);
+    free(w);
+}
+
+/*
+ * CTA iterates F_t (section 3.1, eqs. CTAGEN7 / CTAGEN7A; Algorithm 1):
+ *   w_j = A^T u_j, u_{j+1} = A w_j with u_0 = r (so u_j = H^j r, w_j = A^T H^j r),
+ *   phi_{2j+1} = ||w_j||^2 = r^T H^{2j+1} r,  phi_{2j+2} = ||u_{j+1}||^2 = r^T H^{2j+2} r,
+ *   r'' = r' - sum_i alpha_i u_i,
+ *   x'' = x' + sum_i alpha_i w_{i-1}              (x-form, minnorm = 0)
+ *   y'' = y' + sum_i alpha_i u_{i-1}, x = A^T y   (minnorm = 1; Theorem 1 (4):
+ *                                                   the iterate stays in range(A^T)).
+ * Start x = 0 (Algorithm 1's first choice), r = b.  The relative residual
+ * ||r||/||b|| is tested with the recurrence residual; when it passes, the
+ * true residual b - A x decides, and if it fails the recurrence residual is
+ * replaced by it and the loop goes on without counting an iteration.
+ * The second clause of Algorithm 1 (r^T H r small) is read as
+ * ||A^T r|| <= tol_normal ||A^T b||, or phi_2 = 0 (Example 1: H r = 0 means x
+ * solves the normal equation).
+ */
+int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int minnorm,
+           double *hist, int64_t hist_cap, or_info *info) {
+    const int64_t m = A->m, n = A->n;
+    const int t = o->t;
+    int stop = 0;
+    int64_t k = 0, matvecs = 0, i, e;
+    double nb, nab = 0.0, rr, phi[17], alpha[8];
+    double *r, *y = NULL, *u[9], *w[8], *rt;
+
+    memset(info, 0, sizeof(*info));
+    if (t < 1 || t > 8) return -1;
+    nb = sqrt(or_dot2(m, b, b));
+    if (nb == 0.0) {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        if (hist_cap > 0) hist[0] = 0.0;
+        info->stop = OR_RESIDUAL;
+        return 0;
+    }
+    r = (double *)malloc(sizeof(double) * (size_t)m);
+    rt = (double *)malloc(sizeof(double) * (size_t)m);
+    for (i = 0; i <= t; ++i) u[i] = (double *)malloc(sizeof(double) * (size_t)m);
+    for (i = 0; i < t; ++i) w[i] = (double *)malloc(sizeof(double) * (size_t)n);
+    if (minnorm) y = (double *)calloc((size_t)m, sizeof(double));
+
+    if (o->tol_normal > 0.0) {
+        or_apply_t(A, b, w[0]);
+        nab = sqrt(or_dot2(n, w[0], w[0]));
+        ++matvecs;
+    }
+    if (o->warm_start && !minnorm) {
+        or_residual(A, b, x, r);
+        ++matvecs;
+    } else {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        memcpy(r, b, sizeof(double) * (size_t)m);
+    }
+    rr = or_dot2(m, r, r);
+    if (hist_cap > 0) hist[0] = sqrt(rr) / nb;
+
+    for (;;) {
+        if (sqrt(rr) <= o->tol * nb) {
+            if (minnorm) { or_apply_t(A, y, x); ++matvecs; }
+            or_residual(A, b, x, rt);
+            ++matvecs;
+            double rrt = or_dot2(m, rt, rt);
+            if (sqrt(rrt) <= o->tol * nb) { stop = OR_RESIDUAL; break; }
+            memcpy(r, rt, sizeof(double) * (size_t)m);
+            rr = rrt;
+        }
+        if (k >= o->max_iter) { stop = OR_MAXITER; break; }
+
+        memcpy(u[0], r, sizeof(double) * (size_t)m);
+        for (int j = 0; j < t; ++j) {
+            or_apply_t(A, u[j], w[j]);
+            phi[2 * j + 1] = or_dot2(n, w[j], w[j]);
+            or_apply(A, w[j], u[j + 1]);
+            phi[2 * j + 2] = or_dot2(m, u[j + 1], u[j + 1]);
+            matvecs += 2;
+        }
+        if (!finite_all(phi + 1, 2 * t)) { stop = OR_BREAKDOWN; break; }
+        if (sqrt(phi[1]) <= o->tol_normal * nab || phi[2] == 0.0) { stop = OR_NORMAL; break; }
+        or_gram_alpha(phi, t, alpha);
+        if (!finite_all(alpha, t)) { stop = OR_BREAKDOWN; break; }
+
+        for (int j = 0; j < t; ++j)
+            for (e = 0; e < m; ++e) r[e] = fma(-alpha[j], u[j + 1][e], r[e]);
+        if (minnorm) {
+            for (int j = 0; j < t; ++j)
+                for (e = 0; e < m; ++e) y[e] = fma(alpha[j], u[j][e], y[e]);
+        } else {
+            for (int j = 0; j < t; ++j)
+                for (e = 0; e < n; ++e) x[e] = fma(alpha[j], w[j][e], x[e]);
+        }
+        ++k;
+        rr = or_dot2(m, r, r);
+        if (k < hist_cap) hist[k] = sqrt(rr) / nb;
+        if (o->replace_every > 0 && k % o->replace_every == 0) {
+            if (minnorm) { or_apply_t(A, y, x); ++matvecs; }
+            or_residual(A, b, x, r);
+            ++matvecs;
+            rr = or_dot2(m, r, r);
+        }
+    }
+    if (minnorm) or_apply_t(A, y, x);
+
+    info->iters = k;
+    info->matvecs = matvecs;
+    info->stop = stop;
+    exit_diagnostics(A, b, x, nb, &info->rel_res, &info->rel_normal);
+
+    free(r);
+    free(rt);
+    for (i = 0; i <= t; ++i) free(u[i]);
+    for (i = 0; i < t; ++i) free(w[i]);
+    free(y);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
+/* Algorithms 2 and 3 (TA)                                                  */
+/* ---------------------------------------------------------------------- */
+/*
+ * Iterate b' = A x' inside the ellipsoid E_{A,rho} = {A x : ||x|| <= rho}
+ * (section 4).  With r = b - b' and c = A^T r:
+ *   - stop when ||r|| <= tol ||b|| (confirmed on the true residual b - A x);
+ *   - stop when ||c|| <= tol_normal ||A^T b|| (Theorem prop0TA (1): c = 0 means
+ *     x solves the normal equation);
+ *   - v_rho = rho A c / ||c|| maximises c^T z over E_{A,rho} (eq. vr) and is a
+ *     strict pivot iff rho ||c|| >= r^T b (eq. eqlem2).  Then b'' is the point
+ *     of segment [b', v_rho] nearest to b (Proposition prop1TA, eq. alph):
+ *     alpha = r^T (v - b') / ||v - b'||^2, clamped to [0, 1];
+ *     b'' = b' + alpha (v - b'), x'' = (1 - alpha) x' + alpha rho c / ||c||.
+ *   - otherwise b' is a witness: Algorithm 2 (fixed_rho) stops and reports the
+ *     lower bound r^T b / ||c|| < ||x*|| of Corollary 1; Algorithm 3 sets
+ *     rho = max(2 rho, r^T b / ||c||) and goes on.  When the new rho equals
+ *     r^T b / ||c|| the next step is a strict pivot by eq. eqlem2 with equality,
+ *     so it is taken as one whatever rounding says.
+ * Each while-body is one iteration, radius updates included.  Rounding order:
+ *   gamma = rho / ||c||, s = A c, d_i = fma(gamma, s_i, -b'_i) (= v_i - b'_i),
+ *   b'_i = fma(alpha, d_i, b'_i), x_j = fma(alpha gamma, c_j, (1 - alpha) x_j).
+ */
+int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double *hist,
+          int64_t hist_cap, or_info *info) {
+    const int64_t m = A->m, n = A->n;
+    int stop = 0, pass = 0, have_c = 0;
+    int64_t k = 0, matvecs = 0, i;
+    double nb, nab = 0.0, rr, rb, rho = o->rho0, rho_lo = 0.0, nc = 0.0;
+    double *bp, *r, *c, *s, *d, *rt;
+
+    memset(info, 0, sizeof(*info));
+    nb = sqrt(or_dot2(m, b, b));
+    memset(x, 0, sizeof(double) * (size_t)n);
+    if (nb == 0.0) {
+        if (hist_cap > 0) hist[0] = 0.0;
+        info->stop = OR_RESIDUAL;
+        info->rho = rho;
+        return 0;
+    }
+    bp = (double *)calloc((size_t)m, sizeof(double));
+    r = (double *)malloc(sizeof(double) * (size_t)m);
+    rt = (double *)malloc(sizeof(double) * (size_t)m);
+    s = (double *)malloc(sizeof(double) * (size_t)m);
+    d = (double *)malloc(sizeof(double) * (size_t)m);
+    c = (double *)malloc(sizeof(double) * (size_t)n);
+    if (o->tol_normal > 0.0) {
+        or_apply_t(A, b, c);
+        nab = sqrt(or_dot2(n, c, c));
+        ++matvecs;
+    }
+    for (i = 0; i < m; ++i) r[i] = b[i] - bp[i];
+    rr = or_dot2(m, r, r);
+    rb = or_dot2(m, r, b);
+    if (hist_cap > 0) hist[0] = sqrt(rr) / nb;
+
+    for (;;) {
+        if (sqrt(rr) <= o->tol * nb) {
+            or_residual(A, b, x, rt);
+            ++matvecs;
+            if (sqrt(or_dot2(m, rt, rt)) <= o->tol * nb) { stop = OR_RESIDUAL; break; }
+            or_apply(A, x, bp);
+            ++matvecs;
+            for (i = 0; i < m; ++i) r[i] = b[i] - bp[i];
+            rr = or_dot2(m, r, r);
+            rb = or_dot2(m, r, b);
+            have_c = 0;
+        }
+        if (k >= o->max_iter) { stop = OR_MAXITER; break; }
+        if (!have_c) {
+            or_apply_t(A, r, c);
+            nc = sqrt(or_dot2(n, c, c));
+            ++matvecs;
+            have_c = 1;
+        }
+        if (!isfinite(nc) || !isfinite(rb)) { stop = OR_BREAKDOWN; break; }
+        if (nc <= o->tol_normal * nab) { stop = OR_NORMAL; break; }
+        if (pass || rho * nc >= rb) {
+            double gamma = rho / nc, rd, dd, alpha, beta, a1;
+            or_apply(A, c, s);
+            ++matvecs;
+            for (i = 0; i < m; ++i) d[i] = fma(gamma, s[i], -bp[i]);
+            rd = or_dot2(m, r, d);
+            dd = or_dot2(m, d, d);
+            if (!(dd > 0.0) || !isfinite(rd) || !isfinite(dd)) { stop = OR_BREAKDOWN; break; }
+            alpha = rd / dd;
+            if (alpha < 0.0) alpha = 0.0;
+            if (alpha > 1.0) alpha = 1.0;
+            for (i = 0; i < m; ++i) bp[i] = fma(alpha, d[i], bp[i]);
+            beta = alpha * gamma;
+            a1 = 1.0 - alpha;
+            for (i = 0; i < n; ++i) x[i] = fma(beta, c[i], a1 * x[i]);
+            pass = 0;
+            have_c = 0;
+            for (i = 0; i < m; ++i) r[i] = b[i] - bp[i];
+            rr = or_dot2(m, r, r);
+            rb = or_dot2(m, r, b);
+        } else {
+            double q = rb / nc;
+            if (o->fixed_rho) { rho_lo = q; stop = OR_WITNESS; break; }
+            if (q > rho_lo) rho_lo = q;
+            pass = (q >= 2.0 * rho);
+            rho = (2.0 * rho >= q) ? 2.0 * rho : q;
+        }
+        ++k;
+        if (k < hist_cap) hist[k] = sqrt(rr) / nb;
+    }
+    info->iters = k;
+    info->matvecs = matvecs;
+    info->stop = stop;
+    info->rho = rho;
+    info->rho_lo = rho_lo;
+    exit_diagnostics(A, b, x, nb, &info->rel_res, &info->rel_normal);
+    free(bp);
+    free(r);
+    free(rt);
+    free(s);
+    free(d);
+    free(c);
+    return 0;
+}
