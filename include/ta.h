@@ -1,0 +1,203 @@
+/*
+ * ta.h - C ABI of the MI355X (gfx950) Triangle Algorithm (TA) / Centering
+ * Triangle Algorithm (CTA) library, libta.so.
+ *
+ * The methods are those of Lau & Kalantari, "On the Performance of a Novel
+ * Class of Linear System Solvers and Comparison with State-of-The-Art
+ * Algorithms" (arXiv 2304.12168): CTA is Algorithm 1 of section 3.2 with
+ * H = A A^T (the choice the paper's implementation makes in section 5), TA is
+ * Algorithm 3 (and Algorithm 2 with a fixed radius) of section 4.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are HIP DEVICE pointers owned by the caller.  The
+ *     library never retains or frees them.  Scalars, option and info structs
+ *     and the matrix descriptor itself live in HOST memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Work is ordered on it; solver calls return when the solve has finished
+ *     (the host reads a device flag once per chunk of iterations).  Kernel-
+ *     level calls (ta_spmv, ta_transpose, ...) return after enqueueing.
+ *   - Workspace is taken with stream-ordered hipMallocAsync inside the call
+ *     and released before return.
+ *   - Return value: 0 on success, a negative TA_E* code otherwise (see
+ *     ta_strerror).  Not converging is not an error: it is reported in
+ *     ta_info.stop.
+ *   - One call per stream at a time; calls on different streams share no
+ *     state.
+ *   - Every reduction (inner products, norms, matrix rows) is evaluated with
+ *     compensated (double-double) accumulation, so results do not depend on
+ *     the summation order beyond the last bit.
+ */
+#ifndef TA_H
+#define TA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define TA_OK 0
+#define TA_EINVAL (-1)  /* bad shape, pointer, option value or malformed CSR */
+#define TA_ENOMEM (-2)  /* device allocation failed */
+#define TA_EHIP (-3)    /* a HIP runtime call failed; ta_strerror(TA_EHIP) has the text */
+#define TA_ENOTSUP (-4) /* input outside what the kernels support (see ta_mat) */
+
+/* ---- matrix kinds ---- */
+#define TA_DENSE_ROWMAJOR 0
+#define TA_CSR 1
+
+/* ---- stop codes (ta_info.stop) ----
+ * RESIDUAL : ||b - A x|| <= tol ||b|| on the true FP64 residual (Definition 1 (1),
+ *            in relative form).
+ * NORMAL   : ||A^T r|| <= tol_normal ||A^T b||, or A A^T r = 0 (Definition 1 (2);
+ *            Example 1 and Theorem prop0TA (1): x solves the normal equation).
+ * WITNESS  : ta_solve with fixed_rho only: b' = A x is a witness, so b is not in
+ *            E_{A,rho} (Algorithm 2); info.rho_lo holds the lower bound of
+ *            Corollary 1 on the norm of the minimum-norm solution.
+ * MAXITER  : iteration budget spent.
+ * BREAKDOWN: non-finite step quantities (e.g. NaN or Inf in A or b).          */
+#define TA_STOP_RESIDUAL 1
+#define TA_STOP_NORMAL 2
+#define TA_STOP_WITNESS 3
+#define TA_STOP_MAXITER 4
+#define TA_STOP_BREAKDOWN 5
+
+/* ---- precision of the matrix products ---- */
+#define TA_FP64 0
+#define TA_FP32 1
+#define TA_BF16 2
+
+/*
+ * Matrix descriptor (host struct, device arrays).
+ *   TA_CSR: row_ptr[m+1] (int32, row_ptr[0] = 0, nondecreasing, row_ptr[m] = nnz),
+ *           col_idx[nnz] (int32 in [0, n)), val[nnz] (float64).  Column order
+ *           inside a row is free; duplicates are allowed and act as a sum.
+ *           A^T is built on the device inside each solver call.  Supported:
+ *           nnz < 2^31 and at most 8192 entries in any column.
+ *   TA_DENSE_ROWMAJOR: val[m*ld] row-major, ld >= n; row_ptr/col_idx unused.
+ */
+typedef struct ta_mat {
+    int32_t kind;
+    int64_t m, n, nnz, ld;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+} ta_mat;
+
+/*
+ * Options (host struct).  Inputs of the paper's algorithm headers:
+ * epsilon -> tol (relative), epsilon' -> tol_normal (relative), t, rho.
+ */
+typedef struct ta_opts {
+    double tol;            /* stop when ||b - A x|| <= tol ||b||; in [0, 1) */
+    double tol_normal;     /* stop when ||A^T r|| <= tol_normal ||A^T b||; 0 = only A^T r = 0 */
+    int32_t t;             /* CTA order, 1..8 and <= m (ignored by ta_solve) */
+    int64_t max_iter;      /* iteration budget (>= 0) */
+    int32_t precision;     /* TA_FP64 | TA_FP32 | TA_BF16: precision of the matrix products */
+    int32_t replace_every; /* recompute r = b - A x every so many iterations; 0 = only at stop */
+    int32_t warm_start;    /* cta_solve: 1 = start from the x passed in */
+    double rho0;           /* ta_solve: initial radius (Algorithm 3 starts from 0) */
+    int32_t fixed_rho;     /* ta_solve: 1 = Algorithm 2 (no radius growth, WITNESS exit) */
+    int32_t chunk;         /* iterations per host poll of the stop flag; 0 = automatic */
+} ta_opts;
+
+/* Result summary (host struct). */
+typedef struct ta_info {
+    int64_t iters;      /* while-loop bodies executed (TA radius updates included) */
+    int64_t matvecs;    /* products with A or A^T, true-residual checks included */
+    int32_t stop;       /* TA_STOP_* */
+    double rel_res;     /* ||b - A x|| / ||b|| at exit, true FP64 residual */
+    double rel_normal;  /* ||A^T (b - A x)|| / ||A^T b|| at exit */
+    double rho, rho_lo; /* ta_solve: final radius and best witness lower bound */
+} ta_info;
+
+/*
+ * cta_solve - Algorithm 1 (CTA of order t, H = A A^T), iterate form of
+ * eq. CTAGEN7A: x'' = x' + sum_i alpha_i A^T H^{i-1} r'.
+ *   A       : m x n matrix, any shape and rank.
+ *   b       : device, m doubles (not modified).
+ *   x       : device, n doubles; output (input too when opts->warm_start).
+ *   hist    : device, hist_cap doubles or NULL; hist[k] = ||r_k|| / ||b|| for
+ *             k = 0 .. min(iters, hist_cap - 1) (recurrence residual).
+ *   info    : host, filled on return.
+ * b = 0 returns x = 0, iters = 0, stop = RESIDUAL.
+ */
+int cta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
+              int64_t hist_cap, ta_info *info, void *stream);
+
+/*
+ * cta_minnorm - the same iteration in the y-form x = A^T y (Theorem 1 (4):
+ * from x0 = 0 every iterate is A^T w_k, so on a consistent system the limit is
+ * the minimum-norm solution).  The m-vector y is updated with
+ * y'' = y' + sum_i alpha_i H^{i-1} r' and x = A^T y is formed at the end.
+ * opts->warm_start is not supported (TA_EINVAL).  Arguments as cta_solve.
+ */
+int cta_minnorm(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
+                int64_t hist_cap, ta_info *info, void *stream);
+
+/*
+ * ta_solve - Algorithm 3 (TA with rho <- max(2 rho, (b-b')^T b / ||c||)), or
+ * Algorithm 2 when opts->fixed_rho (then opts->rho0 > 0 is required).
+ * Pivot v_rho = rho A c / ||c|| with c = A^T (b - b') (eq. vr), strict-pivot
+ * test rho ||c|| >= (b - b')^T b (eq. eqlem2), step to the point of segment
+ * [b', v_rho] nearest to b (Proposition prop1TA).  Arguments as cta_solve;
+ * opts->t and opts->warm_start are ignored.
+ */
+int ta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
+             int64_t hist_cap, ta_info *info, void *stream);
+
+/*
+ * ta_validate - host-side argument checks only (shapes, pointers, options);
+ * it reads no device memory and launches nothing, so it runs without a GPU.
+ * `solver` is 0 for cta_solve, 1 for cta_minnorm, 2 for ta_solve.
+ * Returns TA_OK or TA_EINVAL.
+ */
+int ta_validate(const ta_mat *A, const ta_opts *opts, int32_t solver);
+
+/* Text for a return code (TA_EHIP: the last HIP error seen on this thread). */
+const char *ta_strerror(int code);
+
+/* ---- kernel-level entry points (the building blocks of every iteration) ---- */
+
+/*
+ * ta_spmv - y = A x (trans = 0) or y = A^T x (trans = 1), FP64, one
+ * compensated sum per output entry.  For a CSR matrix with trans = 1 the
+ * library builds A^T for the call.  If norm2 != NULL, *norm2 (device, one
+ * double) receives ||y||^2.  Enqueues on `stream` and returns.
+ */
+int ta_spmv(const ta_mat *A, int32_t trans, const double *x, double *y, double *norm2,
+            void *stream);
+
+/*
+ * ta_residual - r = b - A x as one compensated sum per row (Definition 4);
+ * *norm2 (device, may be NULL) receives ||r||^2.
+ */
+int ta_residual(const ta_mat *A, const double *b, const double *x, double *r, double *norm2,
+                void *stream);
+
+/*
+ * ta_transpose - CSR of A^T from the CSR of A, built on the device:
+ * at_row_ptr[n+1], at_col_idx[nnz], at_val[nnz] (device, caller-allocated).
+ * Columns come out sorted inside each row, so the result is canonical and
+ * deterministic.  Returns TA_ENOTSUP if a column of A holds more than 8192
+ * entries.  Synchronises `stream` before returning.
+ */
+int ta_transpose(const ta_mat *A, int32_t *at_row_ptr, int32_t *at_col_idx, double *at_val,
+                 void *stream);
+
+/*
+ * ta_time_matvec - measurement hook: average duration (milliseconds, host
+ * double *avg_ms) of one launch of the FP64 matrix-product kernel that the
+ * solvers use for y = A x (trans = 0) or A^T x (trans = 1), with its fused
+ * ||y||^2 reduction, over `reps` >= 1 back-to-back launches timed with HIP
+ * events on `stream`.  Preparation (checks, transpose) is outside the timed
+ * launches.  Synchronises `stream`.
+ */
+int ta_time_matvec(const ta_mat *A, int32_t trans, const double *x, double *y, int32_t reps,
+                   double *avg_ms, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TA_H */

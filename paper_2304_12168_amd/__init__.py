@@ -1,0 +1,297 @@
+"""MI355X (gfx950) Triangle Algorithm / Centering Triangle Algorithm solvers.
+
+Thin ctypes binding over ``libta.so`` (C ABI declared in ``include/ta.h``).
+This module only marshals arguments: every step of a solve runs in the HIP
+kernels of the library.  PyTorch provides device memory and the stream.
+There is no CPU fallback: if the library is missing, importing the solver
+entry points raises.
+
+Methods: Lau & Kalantari, arXiv 2304.12168 -- CTA (Algorithm 1, H = A A^T)
+and TA (Algorithms 2 and 3).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Union
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libta.so")
+
+TA_DENSE_ROWMAJOR = 0
+TA_CSR = 1
+TA_FP64, TA_FP32, TA_BF16 = 0, 1, 2
+STOP_NAMES = {0: "none", 1: "residual", 2: "normal", 3: "witness", 4: "maxiter", 5: "breakdown"}
+ERRORS = {-1: "TA_EINVAL", -2: "TA_ENOMEM", -3: "TA_EHIP", -4: "TA_ENOTSUP"}
+
+# every symbol the header declares
+EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror", "ta_spmv",
+           "ta_residual", "ta_transpose", "ta_time_matvec")
+
+
+class TaMat(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("ld", C.c_int64), ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p),
+                ("val", C.c_void_p)]
+
+
+class TaOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("tol_normal", C.c_double), ("t", C.c_int32),
+                ("max_iter", C.c_int64), ("precision", C.c_int32), ("replace_every", C.c_int32),
+                ("warm_start", C.c_int32), ("rho0", C.c_double), ("fixed_rho", C.c_int32),
+                ("chunk", C.c_int32)]
+
+
+class TaInfo(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("matvecs", C.c_int64), ("stop", C.c_int32),
+                ("rel_res", C.c_double), ("rel_normal", C.c_double), ("rho", C.c_double),
+                ("rho_lo", C.c_double)]
+
+
+class TaError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libta.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise TaError(f"{path} not found: build it with `python -m paper_2304_12168_amd.build`")
+        lib = C.CDLL(path)
+        P, I64, I32 = C.c_void_p, C.c_int64, C.c_int32
+        MP, OP, IP = C.POINTER(TaMat), C.POINTER(TaOpts), C.POINTER(TaInfo)
+        for name in ("cta_solve", "cta_minnorm", "ta_solve"):
+            f = getattr(lib, name)
+            f.restype = C.c_int
+            f.argtypes = [MP, P, P, OP, P, I64, IP, P]
+        lib.ta_validate.restype = C.c_int
+        lib.ta_validate.argtypes = [MP, OP, I32]
+        lib.ta_strerror.restype = C.c_char_p
+        lib.ta_strerror.argtypes = [C.c_int]
+        lib.ta_spmv.restype = C.c_int
+        lib.ta_spmv.argtypes = [MP, I32, P, P, P, P]
+        lib.ta_residual.restype = C.c_int
+        lib.ta_residual.argtypes = [MP, P, P, P, P, P]
+        lib.ta_transpose.restype = C.c_int
+        lib.ta_transpose.argtypes = [MP, P, P, P, P]
+        lib.ta_time_matvec.restype = C.c_int
+        lib.ta_time_matvec.argtypes = [MP, I32, P, P, I32, C.POINTER(C.c_double), P]
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = load_library().ta_strerror(rc).decode()
+        raise TaError(f"{what}: {ERRORS.get(rc, rc)}: {msg}")
+
+
+# ---------------------------------------------------------------------------
+# device matrices
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class DeviceMatrix:
+    """A matrix resident in device memory (torch tensors) plus its descriptor."""
+
+    kind: int
+    m: int
+    n: int
+    nnz: int
+    ld: int
+    row_ptr: Optional[object] = None  # torch.int32, m+1
+    col_idx: Optional[object] = None  # torch.int32, nnz
+    val: Optional[object] = None      # torch.float64, nnz or (m, ld)
+
+    def desc(self) -> TaMat:
+        def ptr(t):
+            return None if t is None else t.data_ptr()
+
+        return TaMat(self.kind, self.m, self.n, self.nnz, self.ld, ptr(self.row_ptr),
+                     ptr(self.col_idx), ptr(self.val))
+
+    @property
+    def shape(self):
+        return (self.m, self.n)
+
+
+def to_device(A, device="cuda") -> DeviceMatrix:
+    """Copy a host matrix (dense numpy array, or any object with m, n, row_ptr,
+    col_idx, val as numpy arrays) to the GPU."""
+    import torch
+
+    if isinstance(A, DeviceMatrix):
+        return A
+    if isinstance(A, np.ndarray):
+        a = torch.from_numpy(np.ascontiguousarray(A, dtype=np.float64)).to(device)
+        m, n = a.shape
+        return DeviceMatrix(TA_DENSE_ROWMAJOR, m, n, m * n, n, val=a)
+    rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int32)).to(device)
+    ci = torch.from_numpy(np.ascontiguousarray(A.col_idx, dtype=np.int32)).to(device)
+    v = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device)
+    return DeviceMatrix(TA_CSR, int(A.m), int(A.n), int(v.numel()), 0, rp, ci, v)
+
+
+def _vec(v, device="cuda"):
+    import torch
+
+    if isinstance(v, np.ndarray):
+        return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).to(device)
+    if v.dtype != torch.float64 or not v.is_contiguous():
+        raise TaError("vectors must be contiguous float64 tensors")
+    return v
+
+
+def _stream():
+    import torch
+
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclasses.dataclass
+class Info:
+    iters: int
+    matvecs: int
+    stop: str
+    rel_res: float
+    rel_normal: float
+    rho: float
+    rho_lo: float
+
+
+def _info(i: TaInfo) -> Info:
+    return Info(int(i.iters), int(i.matvecs), STOP_NAMES.get(int(i.stop), str(i.stop)),
+                float(i.rel_res), float(i.rel_normal), float(i.rho), float(i.rho_lo))
+
+
+def make_opts(tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0, warm_start=False,
+              rho0=0.0, fixed_rho=False, chunk=0, precision=TA_FP64) -> TaOpts:
+    return TaOpts(float(tol), float(tol_normal), int(t), int(max_iter), int(precision),
+                  int(replace_every), int(bool(warm_start)), float(rho0), int(bool(fixed_rho)),
+                  int(chunk))
+
+
+def _solve(name, A, b, x0=None, hist_cap=None, **kw):
+    import torch
+
+    lib = load_library()
+    dA = to_device(A)
+    bd = _vec(b)
+    opts = make_opts(**kw)
+    x = torch.zeros(dA.n, dtype=torch.float64, device=bd.device)
+    if x0 is not None:
+        x.copy_(_vec(x0))
+    cap = int(opts.max_iter) + 1 if hist_cap is None else int(hist_cap)
+    hist = torch.full((max(cap, 1),), float("nan"), dtype=torch.float64, device=bd.device)
+    info = TaInfo()
+    d = dA.desc()
+    rc = getattr(lib, name)(C.byref(d), C.c_void_p(bd.data_ptr()), C.c_void_p(x.data_ptr()),
+                            C.byref(opts), C.c_void_p(hist.data_ptr()), cap, C.byref(info),
+                            _stream())
+    _check(rc, name)
+    inf = _info(info)
+    return x, hist[: min(inf.iters + 1, cap)], inf
+
+
+def cta_solve(A, b, tol=1e-6, t=3, max_iter=100000, x0=None, **kw):
+    """Algorithm 1 (CTA of order t, H = A A^T), from x0 if given (warm start),
+    else from 0.  Returns (x, hist, info)."""
+    return _solve("cta_solve", A, b, x0=x0, tol=tol, t=t, max_iter=max_iter,
+                  warm_start=x0 is not None, **kw)
+
+
+def cta_minnorm(A, b, tol=1e-6, t=3, max_iter=100000, **kw):
+    """Algorithm 1 in the form x = A^T y (minimum-norm limit).  Returns (x, hist, info)."""
+    return _solve("cta_minnorm", A, b, tol=tol, t=t, max_iter=max_iter, **kw)
+
+
+def ta_solve(A, b, tol=1e-6, max_iter=100000, rho0=0.0, fixed_rho=False, **kw):
+    """Algorithm 3 (or Algorithm 2 with ``fixed_rho``).  Returns (x, hist, info)."""
+    return _solve("ta_solve", A, b, tol=tol, t=1, max_iter=max_iter, rho0=rho0,
+                  fixed_rho=fixed_rho, **kw)
+
+
+def validate(A, solver: int = 0, **kw) -> int:
+    """Host-side argument checks only (no device access).  Returns the code."""
+    lib = load_library()
+    if isinstance(A, TaMat):
+        d = A
+    elif isinstance(A, DeviceMatrix):
+        d = A.desc()
+    else:
+        raise TaError("validate takes a TaMat or a DeviceMatrix")
+    o = make_opts(**kw)
+    return int(lib.ta_validate(C.byref(d), C.byref(o), int(solver)))
+
+
+def spmv(A, x, trans: bool = False, want_norm: bool = False):
+    """y = A x or A^T x (FP64, compensated rows).  Returns y (and ||y||^2)."""
+    import torch
+
+    lib = load_library()
+    dA = to_device(A)
+    xd = _vec(x)
+    y = torch.empty(dA.n if trans else dA.m, dtype=torch.float64, device=xd.device)
+    nrm = torch.zeros(1, dtype=torch.float64, device=xd.device) if want_norm else None
+    d = dA.desc()
+    rc = lib.ta_spmv(C.byref(d), int(bool(trans)), C.c_void_p(xd.data_ptr()),
+                     C.c_void_p(y.data_ptr()), C.c_void_p(nrm.data_ptr() if nrm is not None else 0),
+                     _stream())
+    _check(rc, "ta_spmv")
+    return (y, nrm) if want_norm else y
+
+
+def residual(A, b, x, want_norm: bool = False):
+    """r = b - A x (FP64, one compensated sum per row)."""
+    import torch
+
+    lib = load_library()
+    dA = to_device(A)
+    bd, xd = _vec(b), _vec(x)
+    r = torch.empty(dA.m, dtype=torch.float64, device=bd.device)
+    nrm = torch.zeros(1, dtype=torch.float64, device=bd.device) if want_norm else None
+    d = dA.desc()
+    rc = lib.ta_residual(C.byref(d), C.c_void_p(bd.data_ptr()), C.c_void_p(xd.data_ptr()),
+                         C.c_void_p(r.data_ptr()),
+                         C.c_void_p(nrm.data_ptr() if nrm is not None else 0), _stream())
+    _check(rc, "ta_residual")
+    return (r, nrm) if want_norm else r
+
+
+def transpose(A):
+    """CSR of A^T built on the device: (row_ptr, col_idx, val) tensors."""
+    import torch
+
+    lib = load_library()
+    dA = to_device(A)
+    dev = dA.val.device
+    rp = torch.empty(dA.n + 1, dtype=torch.int32, device=dev)
+    ci = torch.empty(max(dA.nnz, 1), dtype=torch.int32, device=dev)
+    v = torch.empty(max(dA.nnz, 1), dtype=torch.float64, device=dev)
+    d = dA.desc()
+    rc = lib.ta_transpose(C.byref(d), C.c_void_p(rp.data_ptr()), C.c_void_p(ci.data_ptr()),
+                          C.c_void_p(v.data_ptr()), _stream())
+    _check(rc, "ta_transpose")
+    return rp, ci[: dA.nnz], v[: dA.nnz]
+
+
+def time_matvec(A, x, trans: bool = False, reps: int = 50) -> float:
+    """Average milliseconds of one launch of the solvers' FP64 product kernel."""
+    import torch
+
+    lib = load_library()
+    dA = to_device(A)
+    xd = _vec(x)
+    y = torch.empty(dA.n if trans else dA.m, dtype=torch.float64, device=xd.device)
+    ms = C.c_double(0.0)
+    d = dA.desc()
+    rc = lib.ta_time_matvec(C.byref(d), int(bool(trans)), C.c_void_p(xd.data_ptr()),
+                            C.c_void_p(y.data_ptr()), int(reps), C.byref(ms), _stream())
+    _check(rc, "ta_time_matvec")
+    return float(ms.value)

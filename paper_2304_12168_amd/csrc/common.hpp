@@ -1,0 +1,143 @@
+// Internal declarations of libta: device state, compensated arithmetic and
+// the kernel launchers used by the solver drivers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ta.h"
+
+namespace ta {
+
+constexpr int kTMax = 8;       // largest CTA order
+constexpr int kBlock = 256;    // threads per block of every kernel
+constexpr int kChunk = 1024;   // nnz staged through LDS per round (stream kernel)
+constexpr int kMaxColNnz = 8192;  // longest A^T row the transpose can sort
+
+// Internal stop code: the recurrence residual passed the tolerance and the
+// host must confirm it on the true residual.
+constexpr int kStopCandidate = 100;
+
+// ---------------------------------------------------------------------------
+// Solver state, one per call, in device memory.  Only the last block of a
+// kernel (thread 0) writes it; every kernel reads it at entry.
+// ---------------------------------------------------------------------------
+struct State {
+    int32_t done;      // nonzero: the iteration chain does nothing more
+    int32_t stop;      // TA_STOP_* or kStopCandidate
+    int32_t t;         // CTA order
+    int32_t pivot;     // TA: this iteration takes a step
+    int32_t pass;      // TA: next pivot test is passed (radius tie)
+    int32_t have_c;    // TA: c = A^T r is current
+    int32_t fixed_rho; // TA: Algorithm 2
+    int32_t replace;   // a true-residual replacement is due
+    int64_t k;         // iterations done
+    int64_t max_iter;
+    int64_t hist_cap;
+    int64_t matvecs;
+    int64_t replace_every;
+    double nb;         // ||b||
+    double tol, tol_nb;
+    double tol_normal, nab, tol_ne_nab;
+    double rr;         // ||r||^2 of the current residual
+    double rb;         // TA: r^T b
+    double nc;         // TA: ||c||
+    double gamma;      // TA: rho / ||c||
+    double alpha_ta;   // TA: step length
+    double rho, rho_lo;
+    double phi[2 * kTMax + 2];  // phi[1..2t]
+    double alpha[kTMax];
+    double scratch[4];          // results of kernel-level reductions
+    uint32_t counter;           // last-block detection
+    uint32_t pad;
+};
+
+// What the last block of a kernel does with the reduced values.
+enum Post : int32_t {
+    kPostNone = 0,
+    kPostStore,       // state.scratch[arg] = v0
+    kPostCtaInit,     // v0 = ||b||^2: nb, hist[0], loop-top tests
+    kPostCtaWarm,     // v0 = ||b - A x0||^2 (warm start): rr, hist[0], loop-top tests
+    kPostNab,         // v0 = ||A^T b||^2
+    kPostPhi,         // phi[arg] = v0
+    kPostPhiGram,     // phi[arg] = v0, then normal-equation test and the step alpha
+    kPostCtaEnd,      // v0 = ||r||^2 after the update: k, hist, loop-top tests
+    kPostCtaReplace,  // v0 = ||b - A x||^2 after a scheduled replacement
+    kPostCtaCand,     // v0 = ||b - A x||^2 at a candidate stop: accept or replace
+    kPostTaInit,      // v0 = ||b||^2
+    kPostTaC,         // v0 = ||c||^2 (or c current): tests, pivot or radius update
+    kPostTaS,         // v0 = r^T d, v1 = ||d||^2: alpha
+    kPostTaEnd,       // v0 = ||r||^2, v1 = r^T b after the step
+    kPostTaCand,      // v0 = ||b - A x||^2 at a candidate stop
+    kPostTaBp,        // v0 = ||r||^2, v1 = r^T b after b' = A x
+    kPostCount,       // a counted product with no scalar work (x = A^T y)
+};
+
+// Which kernels of a chain run.
+enum Gate : int32_t {
+    kGateAlways = 0,  // unless done
+    kGatePivot,       // unless done, and only when state.pivot
+    kGateNeedC,       // unless done; if c is current only the post action runs
+    kGateReplace,     // unless done, and only when state.replace
+    kGateIgnoreDone,  // always (kernel-level calls, candidate checks)
+};
+
+// Epilogues of the matrix-product kernels.
+enum Epi : int32_t {
+    kEpiNorm = 0,  // y = v;                         v0 += y^2
+    kEpiResid,     // y = b - A x (compensated);     v0 += y^2
+    kEpiTaD,       // d = fma(gamma, v, -b');        v0 += r d, v1 += d^2
+    kEpiTaBp,      // b' = v, r = b - b';            v0 += r^2, v1 += r b
+};
+
+struct EpiArgs {
+    const double *b;   // kEpiResid, kEpiTaBp
+    const double *bp;  // kEpiTaD
+    const double *r;   // kEpiTaD
+    double *r_out;     // kEpiTaBp
+};
+
+struct Tail {  // where the reduction goes and what happens after it
+    State *st;
+    double *hist;
+    double2 *partials;  // 2 * max blocks
+    int32_t post;
+    int32_t arg;
+    int32_t gate;
+};
+
+// Device view of a matrix operand for y = M x (M is A or an explicit A^T).
+struct MatView {
+    int32_t dense;       // 0: CSR, 1: dense row-major (rows of M), 2: dense, M = A^T (columns of A)
+    int64_t rows, cols;  // of M
+    int64_t ld;
+    const int32_t *rp;
+    const int32_t *ci;
+    const double *val;
+    int32_t lanes;       // CSR: 1 = one thread per row (LDS-staged), else lanes per row
+};
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t epi,
+                         const EpiArgs &ea, const Tail &tl, hipStream_t s);
+hipError_t launch_cta_init(int64_t m, int64_t n, const double *b, double *r, double *xy,
+                           int64_t nxy, int32_t zero_xy, const Tail &tl, hipStream_t s);
+hipError_t launch_cta_update(int64_t m, int64_t n, int32_t t, int32_t minnorm, double *r,
+                             double *const *u, double *x, double *const *w, double *y,
+                             const Tail &tl, hipStream_t s);
+hipError_t launch_ta_init(int64_t m, int64_t n, const double *b, double *r, double *bp,
+                          double *x, const Tail &tl, hipStream_t s);
+hipError_t launch_ta_update(int64_t m, int64_t n, const double *b, double *bp, const double *d,
+                            double *r, double *x, const double *c, const Tail &tl,
+                            hipStream_t s);
+hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
+                            const int32_t *ci, const double *val, int32_t *at_rp,
+                            int32_t *at_ci, double *at_val, int32_t *work, int32_t *flag,
+                            hipStream_t s);
+hipError_t launch_copy_norm(int64_t n, const double *src, double *dst, const Tail &tl,
+                            hipStream_t s);
+
+int64_t matvec_blocks(const MatView &M);
+int64_t elementwise_blocks(int64_t n);
+
+}  // namespace ta

@@ -1,0 +1,344 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars:
+  * index work (the device transpose) is bit-exact;
+  * matrix products and residuals agree to 1 ulp per entry (both sides use
+    compensated row sums; one-thread-per-row kernels are bit-exact);
+  * FP64 solves: equal iteration counts and stop codes, residual histories
+    within 1e-10 relative, x within 1e-10 relative (the tolerance the FP64
+    path is held to).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2304_12168_amd as P
+from workloads import (Csr, convection_diffusion, csr_from_coo, csr_from_dense, dense_gaussian,
+                       kac_clement, lp_shaped, poisson5, random_diag_dominant)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+HIST_RTOL = 1e-10
+X_RTOL = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.load_library()
+    oracle.build(force=False)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def ulps(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    scale = np.spacing(np.maximum(np.abs(a), np.abs(b)))
+    scale[scale == 0] = np.finfo(np.float64).tiny
+    return np.abs(a - b) / scale
+
+
+def _ragged_csr(m, n, seed, long_rows=()):
+    """Random CSR with empty rows, a few very long rows and unsorted columns."""
+    g = np.random.default_rng(seed)
+    rows, cols = [], []
+    for i in range(m):
+        k = 0 if g.random() < 0.1 else int(g.integers(1, 9))
+        if i in long_rows:
+            k = min(n, 3000)
+        c = g.choice(n, size=k, replace=False)
+        rows.append(np.full(k, i))
+        cols.append(c)
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    A = csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
+    # shuffle columns inside each row (the ABI allows any order)
+    for i in range(m):
+        s, e = A.row_ptr[i], A.row_ptr[i + 1]
+        p = g.permutation(e - s)
+        A.col_idx[s:e] = A.col_idx[s:e][p]
+        A.val[s:e] = A.val[s:e][p]
+    return A
+
+
+MATS = {
+    "kac_1001": lambda: kac_clement(1001).A,
+    "convdiff_33": lambda: convection_diffusion(33).A,
+    "ragged_700x517": lambda: _ragged_csr(700, 517, 1, long_rows=(5, 300)),
+    "lp_500x20000": lambda: lp_shaped(500, 20000, seed=3).A,
+    "randsparse_3000": lambda: random_diag_dominant(3000, 7, seed=2),
+    "dense_257x131": lambda: dense_gaussian(131, seed=2, m=257).A,
+    "dense_64x300": lambda: dense_gaussian(300, seed=3, m=64).A,
+}
+
+
+@pytest.mark.parametrize("name", sorted(MATS))
+def test_products_match_oracle(name):
+    A = MATS[name]()
+    m, n = (A.shape if isinstance(A, np.ndarray) else (A.m, A.n))
+    g = np.random.default_rng(7)
+    x = g.standard_normal(n)
+    u = g.standard_normal(m)
+    b = g.standard_normal(m)
+    dA = P.to_device(A)
+    y, ny = P.spmv(dA, x, want_norm=True)
+    w, nw = P.spmv(dA, u, trans=True, want_norm=True)
+    r, nr = P.residual(dA, b, x, want_norm=True)
+    torch.cuda.synchronize()
+    y_o, w_o, r_o = oracle.apply(A, x), oracle.apply_t(A, u), oracle.residual(A, b, x)
+    assert ulps(host(y), y_o).max() <= 1
+    assert ulps(host(w), w_o).max() <= 1
+    assert ulps(host(r), r_o).max() <= 1
+    # squared norms: compensated on both sides
+    assert host(ny)[0] == pytest.approx(oracle.dot2(y_o, y_o), rel=4e-16)
+    assert host(nw)[0] == pytest.approx(oracle.dot2(w_o, w_o), rel=4e-16)
+    assert host(nr)[0] == pytest.approx(oracle.dot2(r_o, r_o), rel=4e-16)
+
+
+@pytest.mark.parametrize("name", ["kac_1001", "convdiff_33", "randsparse_3000"])
+def test_one_thread_per_row_products_are_bit_exact(name):
+    A = MATS[name]()
+    x = np.random.default_rng(3).standard_normal(A.n)
+    y = host(P.spmv(P.to_device(A), x))
+    w = host(P.spmv(P.to_device(A), x[: A.m], trans=True))
+    assert np.array_equal(y, oracle.apply(A, x))
+    assert np.array_equal(w, oracle.apply_t(A, x[: A.m]))
+
+
+@pytest.mark.parametrize("name", ["kac_1001", "ragged_700x517", "lp_500x20000", "convdiff_33"])
+def test_transpose_is_exact(name):
+    A = MATS[name]()
+    rp, ci, v = P.transpose(P.to_device(A))
+    ref = A.to_scipy().T.tocsr()
+    ref.sort_indices()
+    assert np.array_equal(host(rp), ref.indptr.astype(np.int32))
+    assert np.array_equal(host(ci), ref.indices.astype(np.int32))
+    assert np.array_equal(host(v), ref.data)
+
+
+def test_transpose_with_duplicates_keeps_storage_order():
+    # duplicates (i, j) act as a sum; A^T keeps them in A's storage order
+    A = Csr(3, 3, np.array([0, 3, 4, 6], np.int32), np.array([1, 1, 0, 2, 1, 1], np.int32),
+            np.array([1.0, 2.0, 3.0, 4.0, 5.0, 6.0]))
+    rp, ci, v = P.transpose(P.to_device(A))
+    assert host(rp).tolist() == [0, 1, 5, 6]
+    assert host(ci).tolist() == [0, 0, 0, 2, 2, 1]
+    assert host(v).tolist() == [3.0, 1.0, 2.0, 5.0, 6.0, 4.0]
+
+
+def test_products_deterministic():
+    A = lp_shaped(300, 40000, seed=1).A
+    x = np.random.default_rng(0).standard_normal(A.n)
+    dA = P.to_device(A)
+    a = host(P.spmv(dA, x))
+    b = host(P.spmv(dA, x))
+    assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------
+# solves
+# ---------------------------------------------------------------------------
+def _compare(res_gpu, res_or, x_rtol=X_RTOL):
+    x, hist, info = res_gpu
+    xo, ho, io = res_or
+    assert info.stop == io.stop, (info, io)
+    assert info.iters == io.iters, (info, io)
+    assert info.matvecs == io.matvecs, (info, io)
+    h = host(hist)
+    assert h.shape == ho.shape
+    np.testing.assert_allclose(h, ho, rtol=HIST_RTOL, atol=0)
+    xg = host(x)
+    nx = np.linalg.norm(xo)
+    assert np.linalg.norm(xg - xo) <= x_rtol * max(nx, 1e-300)
+    assert info.rel_res == pytest.approx(io.rel_res, rel=1e-8, abs=1e-300)
+    assert info.rel_normal == pytest.approx(io.rel_normal, rel=1e-6, abs=1e-18)
+
+
+CTA_CASES = [
+    ("kac_101_t3", lambda: kac_clement(101), 3, 1e-10, 10000),
+    ("kac_1001_t3", lambda: kac_clement(1001), 3, 1e-6, 10000),
+    ("kac_1001_t1", lambda: kac_clement(1001), 1, 1e-6, 100000),
+    ("convdiff_8_t3", lambda: convection_diffusion(8), 3, 1e-6, 10000),
+    ("convdiff_16_t2", lambda: convection_diffusion(16), 2, 1e-6, 20000),
+    ("convdiff_16_t5", lambda: convection_diffusion(16), 5, 1e-6, 20000),
+    ("dense_gauss_12_t2", lambda: dense_gaussian(12, seed=4), 2, 1e-8, 200000),
+    ("dense_gauss_40x25_t3", lambda: dense_gaussian(25, seed=1, m=40), 3, 1e-6, 5000),
+    ("lp_200x5000_t3", lambda: lp_shaped(200, 5000), 3, 1e-10, 1000),
+    ("rand_5000_t3", lambda: type("Pb", (), {"A": random_diag_dominant(5000, 7, seed=3),
+                                               "b": np.random.default_rng(1).uniform(-1, 1, 5000)})(),
+     3, 1e-12, 1000),
+]
+
+
+@pytest.mark.parametrize("case", CTA_CASES, ids=[c[0] for c in CTA_CASES])
+def test_cta_solve_matches_oracle(case):
+    _, make, t, tol, budget = case
+    p = make()
+    g = P.cta_solve(p.A, p.b, tol=tol, t=t, max_iter=budget)
+    o = oracle.cta(p.A, p.b, tol=tol, t=t, max_iter=budget)
+    _compare(g, o)
+
+
+@pytest.mark.parametrize("case", [c for c in CTA_CASES if c[0].startswith(("kac", "lp", "conv"))],
+                         ids=lambda c: c[0])
+def test_cta_minnorm_matches_oracle(case):
+    _, make, t, tol, budget = case
+    p = make()
+    g = P.cta_minnorm(p.A, p.b, tol=tol, t=t, max_iter=budget)
+    o = oracle.cta_minnorm(p.A, p.b, tol=tol, t=t, max_iter=budget)
+    _compare(g, o)
+
+
+def test_cta_budget_and_history_cap():
+    p = convection_diffusion(16)
+    g = P.cta_solve(p.A, p.b, tol=1e-12, t=3, max_iter=37, hist_cap=10)
+    o = oracle.cta(p.A, p.b, tol=1e-12, t=3, max_iter=37, hist_cap=10)
+    assert g[2].stop == o[2].stop == "maxiter" and g[2].iters == 37
+    assert g[1].shape[0] == 10
+    np.testing.assert_allclose(host(g[1]), o[1], rtol=HIST_RTOL)
+
+
+def test_cta_warm_start_and_replacement():
+    p = convection_diffusion(12)
+    x0 = np.random.default_rng(2).uniform(0, 1, p.A.n)
+    g = P.cta_solve(p.A, p.b, tol=1e-8, t=2, max_iter=50000, x0=x0, replace_every=25)
+    o = oracle.cta(p.A, p.b, tol=1e-8, t=2, max_iter=50000, x0=x0, replace_every=25)
+    _compare(g, o)
+    g = P.cta_minnorm(p.A, p.b, tol=1e-8, t=3, max_iter=50000, replace_every=10)
+    o = oracle.cta_minnorm(p.A, p.b, tol=1e-8, t=3, max_iter=50000, replace_every=10)
+    _compare(g, o)
+
+
+def test_cta_normal_equation_stop_on_inconsistent():
+    g0 = np.random.default_rng(4)
+    A = g0.standard_normal((40, 15))
+    b = g0.standard_normal(40)
+    for dense in (True, False):
+        M = A if dense else csr_from_dense(A)
+        g = P.cta_solve(M, b, tol=1e-6, tol_normal=1e-9, t=2, max_iter=100000)
+        o = oracle.cta(M, b, tol=1e-6, tol_normal=1e-9, t=2, max_iter=100000)
+        _compare(g, o)
+        assert g[2].stop == "normal"
+
+
+def test_cta_edge_cases():
+    p = kac_clement(11)
+    # b = 0
+    x, h, info = P.cta_solve(p.A, np.zeros(11), t=3)
+    assert info.stop == "residual" and info.iters == 0 and not host(x).any()
+    # zero budget
+    x, h, info = P.cta_solve(p.A, p.b, tol=1e-6, t=3, max_iter=0)
+    assert info.stop == "maxiter" and info.iters == 0 and host(h)[0] == 1.0
+    # NaN in b
+    bn = p.b.copy()
+    bn[3] = np.nan
+    x, h, info = P.cta_solve(p.A, bn, tol=1e-6, t=2, max_iter=10)
+    assert info.stop == "breakdown"
+    # A = 0 (every direction vanishes): normal equation stop at once
+    Z = csr_from_coo(5, 4, [], [], [])
+    x, h, info = P.cta_solve(Z, np.ones(5), t=2, max_iter=10)
+    o = oracle.cta(Z, np.ones(5), t=2, max_iter=10)
+    assert info.stop == o[2].stop == "normal" and info.iters == 0
+    # t = m (order equal to the row count)
+    q = kac_clement(5)
+    _compare(P.cta_solve(q.A, q.b, tol=1e-12, t=5, max_iter=10),
+             oracle.cta(q.A, q.b, tol=1e-12, t=5, max_iter=10))
+
+
+def test_malformed_csr_is_rejected():
+    bad = Csr(3, 3, np.array([0, 2, 1, 3], np.int32), np.array([0, 1, 2], np.int32),
+              np.ones(3))
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.cta_solve(bad, np.ones(3), t=1)
+    bad2 = Csr(3, 3, np.array([0, 1, 2, 3], np.int32), np.array([0, 5, 2], np.int32),
+               np.ones(3))
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.spmv(bad2, np.ones(3))
+
+
+def test_solve_deterministic():
+    p = convection_diffusion(16)
+    a = P.cta_solve(p.A, p.b, tol=1e-6, t=3, max_iter=500)
+    b = P.cta_solve(p.A, p.b, tol=1e-6, t=3, max_iter=500)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------------------
+# TA
+# ---------------------------------------------------------------------------
+TA_CASES = [
+    ("ta_scalar", lambda: (np.array([[11.0]]), np.array([15.0])), {}, 1e-15, 10),
+    ("ta_6x9", lambda: _consistent(6, 9, 11), {}, 1e-6, 2000000),
+    ("ta_20x20_fixed", lambda: _consistent(20, 20, 3), {"fixed_rho": True, "rho0": 50.0}, 1e-8,
+     20000),
+    ("ta_kac_101", lambda: (kac_clement(101).A, kac_clement(101).b), {}, 1e-3, 200000),
+    ("ta_csr_incons", lambda: (csr_from_dense(np.array([[1.0, 0.0], [0.0, 1.0], [0.0, 0.0]])),
+                               np.array([1.0, 2.0, 3.0])), {"tol_normal": 1e-9}, 1e-9, 100000),
+]
+
+
+def _consistent(m, n, seed):
+    g = np.random.default_rng(seed)
+    A = g.standard_normal((m, n))
+    return A, A @ g.standard_normal(n)
+
+
+@pytest.mark.parametrize("case", TA_CASES, ids=[c[0] for c in TA_CASES])
+def test_ta_solve_matches_oracle(case):
+    _, make, kw, tol, budget = case
+    A, b = make()
+    for M in ((A, csr_from_dense(A)) if isinstance(A, np.ndarray) else (A,)):
+        g = P.ta_solve(M, b, tol=tol, max_iter=budget, **kw)
+        o = oracle.ta(M, b, tol=tol, max_iter=budget, **kw)
+        _compare(g, o, x_rtol=1e-9)
+        assert g[2].rho == o[2].rho and g[2].rho_lo == o[2].rho_lo
+
+
+def test_ta_witness():
+    A, b = _consistent(8, 8, 9)
+    nx = np.linalg.norm(np.linalg.solve(A, b))
+    g = P.ta_solve(A, b, tol=1e-12, max_iter=100000, rho0=0.5 * nx, fixed_rho=True)
+    o = oracle.ta(A, b, tol=1e-12, max_iter=100000, rho0=0.5 * nx, fixed_rho=True)
+    _compare(g, o, x_rtol=1e-9)
+    assert g[2].stop == "witness" and g[2].rho_lo == o[2].rho_lo < nx
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads: sampled parity
+# ---------------------------------------------------------------------------
+@pytest.mark.slow
+def test_kac_10001_full_solve():
+    p = kac_clement(10001)
+    _compare(P.cta_solve(p.A, p.b, tol=1e-6, t=3, max_iter=100000),
+             oracle.cta(p.A, p.b, tol=1e-6, t=3, max_iter=100000))
+
+
+@pytest.mark.slow
+def test_convdiff_512_first_iterations():
+    p = convection_diffusion(512)
+    _compare(P.cta_solve(p.A, p.b, tol=1e-6, t=3, max_iter=4),
+             oracle.cta(p.A, p.b, tol=1e-6, t=3, max_iter=4))
+
+
+@pytest.mark.slow
+def test_lp_shaped_full_minnorm():
+    p = lp_shaped()
+    _compare(P.cta_minnorm(p.A, p.b, tol=1e-6, t=3, max_iter=100),
+             oracle.cta_minnorm(p.A, p.b, tol=1e-6, t=3, max_iter=100))
+
+
+@pytest.mark.slow
+def test_dense_500_first_iterations():
+    p = dense_gaussian(500, seed=0)
+    _compare(P.cta_solve(p.A, p.b, tol=1e-8, t=2, max_iter=30),
+             oracle.cta(p.A, p.b, tol=1e-8, t=2, max_iter=30))
+    _compare(P.ta_solve(p.A, p.b, tol=1e-8, max_iter=30),
+             oracle.ta(p.A, p.b, tol=1e-8, max_iter=30), x_rtol=1e-9)
