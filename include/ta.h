@@ -113,6 +113,8 @@ typedef struct ta_info {
 } ta_info;
 
 /*
+ * The one-shot solvers below prepare A (see ta_plan_create) inside the call.
+ *
  * cta_solve - Algorithm 1 (CTA of order t, H = A A^T), iterate form of
  * eq. CTAGEN7A: x'' = x' + sum_i alpha_i A^T H^{i-1} r'.
  *   A       : m x n matrix, any shape and rank.
@@ -147,6 +149,34 @@ int cta_minnorm(const ta_mat *A, const double *b, double *x, const ta_opts *opts
 int ta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
              int64_t hist_cap, ta_info *info, void *stream);
 
+/* ---- prepared operators (plans) ----
+ *
+ * A plan holds what the solvers derive from A alone: A^T as a canonical CSR
+ * built on the device, and for matrices with long rows (more than 16
+ * nonzeros per row on average) and at least 131072 columns, a copy of A with
+ * sorted columns split into 8 column slices so that each XCD of the MI355X
+ * gathers from its own eighth of x.  Solving many right-hand sides with one
+ * matrix builds them once.  The plan refers to A's device arrays (row_ptr,
+ * col_idx, val, or the dense val): they must stay allocated and unchanged
+ * while the plan lives.  A plan is read-only once created and may serve
+ * calls on several streams at the same time.  Its device memory is taken
+ * stream-ordered on `stream` and returned by ta_plan_destroy on that same
+ * stream.  Errors as the one-shot calls (TA_EINVAL for a malformed CSR,
+ * TA_ENOTSUP for a column with more than 8192 entries).
+ */
+typedef struct ta_plan ta_plan;
+
+int ta_plan_create(const ta_mat *A, ta_plan **plan, void *stream);
+int ta_plan_destroy(ta_plan *plan);
+
+/* The solvers above on a prepared operator; other arguments as there. */
+int cta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                   double *hist, int64_t hist_cap, ta_info *info, void *stream);
+int cta_minnorm_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                     double *hist, int64_t hist_cap, ta_info *info, void *stream);
+int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                  double *hist, int64_t hist_cap, ta_info *info, void *stream);
+
 /*
  * ta_validate - host-side argument checks only (shapes, pointers, options);
  * it reads no device memory and launches nothing, so it runs without a GPU.
@@ -168,6 +198,11 @@ const char *ta_strerror(int code);
  */
 int ta_spmv(const ta_mat *A, int32_t trans, const double *x, double *y, double *norm2,
             void *stream);
+
+/* ta_spmv on a prepared operator: the product kernels the plan's solves use
+ * (for long-row matrices, the XCD column-sliced kernels). */
+int ta_spmv_plan(const ta_plan *plan, int32_t trans, const double *x, double *y, double *norm2,
+                 void *stream);
 
 /*
  * ta_residual - r = b - A x as one compensated sum per row (Definition 4);
@@ -196,6 +231,9 @@ int ta_transpose(const ta_mat *A, int32_t *at_row_ptr, int32_t *at_col_idx, doub
  */
 int ta_time_matvec(const ta_mat *A, int32_t trans, const double *x, double *y, int32_t reps,
                    double *avg_ms, void *stream);
+/* The same on a prepared operator (the kernels a plan's solves launch). */
+int ta_time_matvec_plan(const ta_plan *plan, int32_t trans, const double *x, double *y,
+                        int32_t reps, double *avg_ms, void *stream);
 
 #ifdef __cplusplus
 }

@@ -29,7 +29,9 @@ ERRORS = {-1: "TA_EINVAL", -2: "TA_ENOMEM", -3: "TA_EHIP", -4: "TA_ENOTSUP"}
 
 # every symbol the header declares
 EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror", "ta_spmv",
-           "ta_residual", "ta_transpose", "ta_time_matvec")
+           "ta_residual", "ta_transpose", "ta_time_matvec", "ta_plan_create", "ta_plan_destroy",
+           "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
+           "ta_spmv_plan")
 
 
 class TaMat(C.Structure):
@@ -71,6 +73,18 @@ def load_library(path: str = LIB_PATH):
             f = getattr(lib, name)
             f.restype = C.c_int
             f.argtypes = [MP, P, P, OP, P, I64, IP, P]
+        for name in ("cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan"):
+            f = getattr(lib, name)
+            f.restype = C.c_int
+            f.argtypes = [P, P, P, OP, P, I64, IP, P]
+        lib.ta_plan_create.restype = C.c_int
+        lib.ta_plan_create.argtypes = [MP, C.POINTER(C.c_void_p), P]
+        lib.ta_plan_destroy.restype = C.c_int
+        lib.ta_plan_destroy.argtypes = [P]
+        lib.ta_spmv_plan.restype = C.c_int
+        lib.ta_spmv_plan.argtypes = [P, I32, P, P, P, P]
+        lib.ta_time_matvec_plan.restype = C.c_int
+        lib.ta_time_matvec_plan.argtypes = [P, I32, P, P, I32, C.POINTER(C.c_double), P]
         lib.ta_validate.restype = C.c_int
         lib.ta_validate.argtypes = [MP, OP, I32]
         lib.ta_strerror.restype = C.c_char_p
@@ -177,10 +191,48 @@ def make_opts(tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0, w
                   int(chunk))
 
 
+class Plan:
+    """A prepared operator (ta_plan): A^T and, for long rows, the XCD column
+    slices of A, built once on the device.  Keeps the matrix alive."""
+
+    def __init__(self, A):
+        lib = load_library()
+        self.A = to_device(A)
+        self._desc = self.A.desc()
+        h = C.c_void_p()
+        _check(lib.ta_plan_create(C.byref(self._desc), C.byref(h), _stream()), "ta_plan_create")
+        self.handle = h
+
+    @property
+    def m(self):
+        return self.A.m
+
+    @property
+    def n(self):
+        return self.A.n
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load_library().ta_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan(A) -> Plan:
+    return Plan(A)
+
+
 def _solve(name, A, b, x0=None, hist_cap=None, **kw):
     import torch
 
     lib = load_library()
+    if isinstance(A, Plan):
+        return _solve_plan(name, A, b, x0=x0, hist_cap=hist_cap, **kw)
     dA = to_device(A)
     bd = _vec(b)
     opts = make_opts(**kw)
@@ -195,6 +247,26 @@ def _solve(name, A, b, x0=None, hist_cap=None, **kw):
                             C.byref(opts), C.c_void_p(hist.data_ptr()), cap, C.byref(info),
                             _stream())
     _check(rc, name)
+    inf = _info(info)
+    return x, hist[: min(inf.iters + 1, cap)], inf
+
+
+def _solve_plan(name, pl, b, x0=None, hist_cap=None, **kw):
+    import torch
+
+    lib = load_library()
+    bd = _vec(b)
+    opts = make_opts(**kw)
+    x = torch.zeros(pl.n, dtype=torch.float64, device=bd.device)
+    if x0 is not None:
+        x.copy_(_vec(x0))
+    cap = int(opts.max_iter) + 1 if hist_cap is None else int(hist_cap)
+    hist = torch.full((max(cap, 1),), float("nan"), dtype=torch.float64, device=bd.device)
+    info = TaInfo()
+    rc = getattr(lib, name + "_plan")(pl.handle, C.c_void_p(bd.data_ptr()),
+                                      C.c_void_p(x.data_ptr()), C.byref(opts),
+                                      C.c_void_p(hist.data_ptr()), cap, C.byref(info), _stream())
+    _check(rc, name + "_plan")
     inf = _info(info)
     return x, hist[: min(inf.iters + 1, cap)], inf
 
@@ -235,8 +307,16 @@ def spmv(A, x, trans: bool = False, want_norm: bool = False):
     import torch
 
     lib = load_library()
-    dA = to_device(A)
     xd = _vec(x)
+    if isinstance(A, Plan):
+        y = torch.empty(A.n if trans else A.m, dtype=torch.float64, device=xd.device)
+        nrm = torch.zeros(1, dtype=torch.float64, device=xd.device) if want_norm else None
+        rc = lib.ta_spmv_plan(A.handle, int(bool(trans)), C.c_void_p(xd.data_ptr()),
+                              C.c_void_p(y.data_ptr()),
+                              C.c_void_p(nrm.data_ptr() if nrm is not None else 0), _stream())
+        _check(rc, "ta_spmv_plan")
+        return (y, nrm) if want_norm else y
+    dA = to_device(A)
     y = torch.empty(dA.n if trans else dA.m, dtype=torch.float64, device=xd.device)
     nrm = torch.zeros(1, dtype=torch.float64, device=xd.device) if want_norm else None
     d = dA.desc()
@@ -282,16 +362,21 @@ def transpose(A):
 
 
 def time_matvec(A, x, trans: bool = False, reps: int = 50) -> float:
-    """Average milliseconds of one launch of the solvers' FP64 product kernel."""
+    """Average milliseconds of one launch of the solvers' FP64 product kernel(s)."""
     import torch
 
     lib = load_library()
-    dA = to_device(A)
     xd = _vec(x)
-    y = torch.empty(dA.n if trans else dA.m, dtype=torch.float64, device=xd.device)
     ms = C.c_double(0.0)
-    d = dA.desc()
-    rc = lib.ta_time_matvec(C.byref(d), int(bool(trans)), C.c_void_p(xd.data_ptr()),
-                            C.c_void_p(y.data_ptr()), int(reps), C.byref(ms), _stream())
+    if isinstance(A, Plan):
+        y = torch.empty(A.n if trans else A.m, dtype=torch.float64, device=xd.device)
+        rc = lib.ta_time_matvec_plan(A.handle, int(bool(trans)), C.c_void_p(xd.data_ptr()),
+                                     C.c_void_p(y.data_ptr()), int(reps), C.byref(ms), _stream())
+    else:
+        dA = to_device(A)
+        y = torch.empty(dA.n if trans else dA.m, dtype=torch.float64, device=xd.device)
+        d = dA.desc()
+        rc = lib.ta_time_matvec(C.byref(d), int(bool(trans)), C.c_void_p(xd.data_ptr()),
+                                C.c_void_p(y.data_ptr()), int(reps), C.byref(ms), _stream())
     _check(rc, "ta_time_matvec")
     return float(ms.value)

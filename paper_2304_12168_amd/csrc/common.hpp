@@ -11,7 +11,10 @@ namespace ta {
 
 constexpr int kTMax = 8;       // largest CTA order
 constexpr int kBlock = 256;    // threads per block of every kernel
-constexpr int kChunk = 1024;   // nnz staged through LDS per round (stream kernel)
+#ifndef TA_CHUNK
+#define TA_CHUNK 1024
+#endif
+constexpr int kChunk = TA_CHUNK;  // nnz staged through LDS per round (stream kernel)
 constexpr int kMaxColNnz = 8192;  // longest A^T row the transpose can sort
 
 // Internal stop code: the recurrence residual passed the tolerance and the
@@ -19,8 +22,8 @@ constexpr int kMaxColNnz = 8192;  // longest A^T row the transpose can sort
 constexpr int kStopCandidate = 100;
 
 // ---------------------------------------------------------------------------
-// Solver state, one per call, in device memory.  Only the last block of a
-// kernel (thread 0) writes it; every kernel reads it at entry.
+// Solver state, one per call, in device memory.  Only step kernels (one
+// block, thread 0) write it; every kernel of a chain reads it at entry.
 // ---------------------------------------------------------------------------
 struct State {
     int32_t done;      // nonzero: the iteration chain does nothing more
@@ -48,36 +51,32 @@ struct State {
     double phi[2 * kTMax + 2];  // phi[1..2t]
     double alpha[kTMax];
     double scratch[4];          // results of kernel-level reductions
-    uint32_t counter;           // last-block detection
-    uint32_t pad;
 };
 
-// What the last block of a kernel does with the reduced values.
+// What a step kernel does with the values it reduced (v[0], v[1], ...).
 enum Post : int32_t {
     kPostNone = 0,
-    kPostStore,       // state.scratch[arg] = v0
-    kPostCtaInit,     // v0 = ||b||^2: nb, hist[0], loop-top tests
+    kPostStore,       // state.scratch[arg + i] = v[i]
+    kPostCtaInit,     // v0 = ||b||^2: nb, hist[0], loop-top tests (arg = 1: warm start follows)
     kPostCtaWarm,     // v0 = ||b - A x0||^2 (warm start): rr, hist[0], loop-top tests
     kPostNab,         // v0 = ||A^T b||^2
-    kPostPhi,         // phi[arg] = v0
-    kPostPhiGram,     // phi[arg] = v0, then normal-equation test and the step alpha
+    kPostGram,        // v[0..2t) = phi_1..phi_2t: normal-equation test and the step alpha
     kPostCtaEnd,      // v0 = ||r||^2 after the update: k, hist, loop-top tests
-    kPostCtaReplace,  // v0 = ||b - A x||^2 after a scheduled replacement
-    kPostCtaCand,     // v0 = ||b - A x||^2 at a candidate stop: accept or replace
+    kPostCtaReplace,  // v0 = ||b - A x||^2 after a scheduled replacement (arg: products)
+    kPostCtaCand,     // v0 = ||b - A x||^2 at a candidate stop: accept or replace (arg: products)
     kPostTaInit,      // v0 = ||b||^2
-    kPostTaC,         // v0 = ||c||^2 (or c current): tests, pivot or radius update
+    kPostTaC,         // v0 = ||c||^2 (unless c is current): tests, pivot or radius update
     kPostTaS,         // v0 = r^T d, v1 = ||d||^2: alpha
     kPostTaEnd,       // v0 = ||r||^2, v1 = r^T b after the step
     kPostTaCand,      // v0 = ||b - A x||^2 at a candidate stop
     kPostTaBp,        // v0 = ||r||^2, v1 = r^T b after b' = A x
-    kPostCount,       // a counted product with no scalar work (x = A^T y)
 };
 
 // Which kernels of a chain run.
 enum Gate : int32_t {
     kGateAlways = 0,  // unless done
     kGatePivot,       // unless done, and only when state.pivot
-    kGateNeedC,       // unless done; if c is current only the post action runs
+    kGateNeedC,       // producer: unless done or c is current; step: unless done
     kGateReplace,     // unless done, and only when state.replace
     kGateIgnoreDone,  // always (kernel-level calls, candidate checks)
 };
@@ -97,44 +96,72 @@ struct EpiArgs {
     double *r_out;     // kEpiTaBp
 };
 
-struct Tail {  // where the reduction goes and what happens after it
-    State *st;
-    double *hist;
-    double2 *partials;  // 2 * max blocks
-    int32_t post;
-    int32_t arg;
+constexpr int kMaxSlots = 2 * kTMax + 2;
+
+// Where a producing kernel writes its per-block partial sums: value q of
+// block i goes to partials[(slot + q) * cap + i].  No atomics, no fences:
+// the step kernel that reads them runs after the producer has finished.
+struct Out {
+    const State *st;
+    double2 *partials;
+    int64_t cap;
+    int32_t slot;
     int32_t gate;
 };
 
+// One-block step kernel: reduce slots slot0 .. slot0 + nslots - 1 (count[i]
+// partials each) in a fixed order, then run `post` on the values.
+struct Step {
+    State *st;
+    double *hist;
+    const double2 *partials;
+    int64_t cap;
+    int32_t slot0, nslots;
+    int32_t count[kMaxSlots];
+    int32_t post, arg, gate;
+};
+
 // Device view of a matrix operand for y = M x (M is A or an explicit A^T).
+enum MatKind : int32_t {
+    kCsrRows = 0,    // CSR: one thread per row (LDS-staged) or `lanes` lanes per row
+    kDenseRows = 1,  // dense row-major, rows of M, 64 lanes per row
+    kDenseCols = 2,  // dense row-major A viewed as M = A^T: one thread per column of A
+    kCsrSliced = 3,  // CSR with columns sorted, split into kSlices column slices (one per XCD)
+};
+
+constexpr int kSlices = 8;  // XCDs of the part; blocks b with b % 8 == s take column slice s
+
 struct MatView {
-    int32_t dense;       // 0: CSR, 1: dense row-major (rows of M), 2: dense, M = A^T (columns of A)
+    int32_t kind;
     int64_t rows, cols;  // of M
     int64_t ld;
     const int32_t *rp;
     const int32_t *ci;
     const double *val;
-    int32_t lanes;       // CSR: 1 = one thread per row (LDS-staged), else lanes per row
+    int32_t lanes;       // kCsrRows: 1 = one thread per row, else lanes per row
+    const int32_t *seg;  // kCsrSliced: rows x (kSlices + 1) slice starts inside each row
+    double2 *ypart;      // kCsrSliced: kSlices x rows compensated partial sums (workspace)
 };
 
-// ---- launchers (kernels.hip) ----
+// ---- launchers (kernels.hip); each returns the grid size it used in *blocks ----
 hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t epi,
-                         const EpiArgs &ea, const Tail &tl, hipStream_t s);
-hipError_t launch_cta_init(int64_t m, int64_t n, const double *b, double *r, double *xy,
-                           int64_t nxy, int32_t zero_xy, const Tail &tl, hipStream_t s);
+                         const EpiArgs &ea, const Out &o, hipStream_t s, int32_t *blocks);
+hipError_t launch_cta_init(int64_t m, const double *b, double *r, double *xy, int64_t nxy,
+                           int32_t zero_xy, const Out &o, hipStream_t s, int32_t *blocks);
 hipError_t launch_cta_update(int64_t m, int64_t n, int32_t t, int32_t minnorm, double *r,
                              double *const *u, double *x, double *const *w, double *y,
-                             const Tail &tl, hipStream_t s);
+                             const Out &o, hipStream_t s, int32_t *blocks);
 hipError_t launch_ta_init(int64_t m, int64_t n, const double *b, double *r, double *bp,
-                          double *x, const Tail &tl, hipStream_t s);
+                          double *x, const Out &o, hipStream_t s, int32_t *blocks);
 hipError_t launch_ta_update(int64_t m, int64_t n, const double *b, double *bp, const double *d,
-                            double *r, double *x, const double *c, const Tail &tl,
-                            hipStream_t s);
+                            double *r, double *x, const double *c, const Out &o, hipStream_t s,
+                            int32_t *blocks);
+hipError_t launch_step(const Step &sp, hipStream_t s);
+hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,
+                                 int64_t cols, int32_t *seg, hipStream_t s);
 hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                             const int32_t *ci, const double *val, int32_t *at_rp,
                             int32_t *at_ci, double *at_val, int32_t *work, int32_t *flag,
-                            hipStream_t s);
-hipError_t launch_copy_norm(int64_t n, const double *src, double *dst, const Tail &tl,
                             hipStream_t s);
 
 int64_t matvec_blocks(const MatView &M);

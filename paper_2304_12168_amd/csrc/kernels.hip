@@ -4,10 +4,13 @@
 // returns at once when the chain is finished, so the host can enqueue many
 // iterations ahead and read one flag per chunk.  Reductions are fused into
 // the kernel that produces the vector: each block reduces its part with
-// compensated (double-double) arithmetic, writes one partial, and the last
-// block to finish (atomic counter) reduces the partials in block order and
-// runs the scalar step logic of the method (the "post" action).  There are
-// no floating-point atomics, so every result is run-to-run reproducible.
+// compensated (double-double) arithmetic and writes one partial per value
+// with a plain store.  A one-block step kernel, launched next on the same
+// stream, reduces the partials in block order and runs the scalar logic of
+// the method (Gram solve, stop tests, TA pivot test).  There are no atomics
+// and no cross-block fences on this path (on a multi-XCD part an agent-scope
+// fence writes back the whole L2), and no floating-point atomics anywhere,
+// so every result is run-to-run reproducible.
 //
 // Compensated arithmetic: TwoSum (Knuth) and TwoProduct via fma, combined as
 // in Dot2 of Ogita, Rump and Oishi (SIAM J. Sci. Comput. 26, 2005).  Built
@@ -74,23 +77,6 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
     return x * q + (x < rem ? x : rem) + i;
 }
 
-__device__ __forceinline__ void store_partial(double2 *p, Acc a) {
-    uint64_t *q = reinterpret_cast<uint64_t *>(p);
-    __hip_atomic_store(q, __double_as_longlong(a.p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(q + 1, __double_as_longlong(a.s), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ Acc load_partial(const double2 *p) {
-    const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
-    Acc a;
-    a.p = __longlong_as_double(
-        __hip_atomic_load(const_cast<uint64_t *>(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    a.s = __longlong_as_double(__hip_atomic_load(const_cast<uint64_t *>(q + 1), __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT));
-    return a;
-}
-
 // ---------------------------------------------------------------------------
 // The auxiliary equation of CTA (section 3.1, eq. "eqcoeff"), one thread.
 // M_ij = phi_{i+j}, g_i = phi_i (i, j = 1..t).  Reading of "minimum-norm
@@ -105,50 +91,58 @@ __device__ __forceinline__ Acc load_partial(const double2 *p) {
 //        (te = 1 then uses the closed form);
 //        forward / back substitution; alpha_i = s_i alpha~_i.
 // ---------------------------------------------------------------------------
-constexpr int kGramLds = 2 * kTMax * kTMax + 4 * kTMax;
-
-// lds: kGramLds doubles of workspace (LDS of the calling block)
-__device__ int gram_alpha(const double *phi, int t, double *alpha, double *lds) {
-    double(*M)[kTMax] = reinterpret_cast<double(*)[kTMax]>(lds);
-    double(*L)[kTMax] = reinterpret_cast<double(*)[kTMax]>(lds + kTMax * kTMax);
-    double *s = lds + 2 * kTMax * kTMax;
-    double *g = s + kTMax;
-    double *z = g + kTMax;
-    double *at = z + kTMax;
-    int te = t;
-    for (int i = 0; i < t; ++i) alpha[i] = 0.0;
-    for (int i = 1; i <= t; ++i) {
-        if (!(phi[2 * i] > 0.0)) {
-            te = i - 1;
-            break;
-        }
+// Instantiated per order T with every loop unrolled, so the matrices live in
+// registers of the one thread that runs it (te only shrinks, guarded).
+template <int T>
+__device__ int gram_alpha_t(const double *phi, double *alpha) {
+    double s[T], g[T], z[T], at[T];
+    double L[T][T];  // scaled matrix, overwritten by its Cholesky factor (lower part)
+    int te = T;
+#pragma unroll
+    for (int i = 0; i < T; ++i) alpha[i] = 0.0;
+#pragma unroll
+    for (int i = 1; i <= T; ++i) {
+        if (te == T && !(phi[2 * i] > 0.0)) te = i - 1;
     }
     if (te <= 0) return 0;
     if (te >= 2) {
-        for (int i = 0; i < te; ++i) {
-            int e;
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            int e = 0;
             (void)frexp(phi[2 * (i + 1)], &e);
             const int kk = (int)floor((e - 1) / 2.0);
             s[i] = ldexp(1.0, -kk);
         }
-        for (int i = 0; i < te; ++i) {
-            for (int j = 0; j < te; ++j) M[i][j] = (phi[i + j + 2] * s[i]) * s[j];
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j) L[i][j] = (phi[i + j + 2] * s[i]) * s[j];
             g[i] = phi[i + 1] * s[i];
         }
         const double ridge = 16.0 * (double)te * (double)te * ldexp(1.0, -53);
-        for (int i = 0; i < te; ++i) M[i][i] = __fma_rn(M[i][i], ridge, M[i][i]);
-        for (int j = 0; j < te; ++j) {
-            double d = M[j][j];
-            for (int k = 0; k < j; ++k) d = __fma_rn(-L[j][k], L[j][k], d);
-            if (!(d > 0.0)) {
-                te = j;
-                break;
-            }
-            L[j][j] = sqrt(d);
-            for (int i = j + 1; i < te; ++i) {
-                double v = M[i][j];
-                for (int k = 0; k < j; ++k) v = __fma_rn(-L[i][k], L[j][k], v);
-                L[i][j] = v / L[j][j];
+#pragma unroll
+        for (int i = 0; i < T; ++i) L[i][i] = __fma_rn(L[i][i], ridge, L[i][i]);
+        // Cholesky, column by column; unused columns (j >= te) are skipped
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            if (j < te) {
+                double d = L[j][j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) d = __fma_rn(-L[j][k], L[j][k], d);
+                if (!(d > 0.0)) {
+                    te = j;
+                } else {
+                    L[j][j] = sqrt(d);
+#pragma unroll
+                    for (int i = j + 1; i < T; ++i) {
+                        if (i < te) {
+                            double v = L[i][j];
+#pragma unroll
+                            for (int k = 0; k < j; ++k) v = __fma_rn(-L[i][k], L[j][k], v);
+                            L[i][j] = v / L[j][j];
+                        }
+                    }
+                }
             }
         }
     }
@@ -156,18 +150,42 @@ __device__ int gram_alpha(const double *phi, int t, double *alpha, double *lds) 
         alpha[0] = phi[1] / phi[2];
         return 1;
     }
-    for (int i = 0; i < te; ++i) {
-        double v = g[i];
-        for (int k = 0; k < i; ++k) v = __fma_rn(-L[i][k], z[k], v);
-        z[i] = v / L[i][i];
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i < te) {
+            double v = g[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) v = __fma_rn(-L[i][k], z[k], v);
+            z[i] = v / L[i][i];
+        }
     }
-    for (int i = te - 1; i >= 0; --i) {
-        double v = z[i];
-        for (int k = i + 1; k < te; ++k) v = __fma_rn(-L[k][i], at[k], v);
-        at[i] = v / L[i][i];
+#pragma unroll
+    for (int i = T - 1; i >= 0; --i) {
+        if (i < te) {
+            double v = z[i];
+#pragma unroll
+            for (int k = i + 1; k < T; ++k)
+                if (k < te) v = __fma_rn(-L[k][i], at[k], v);
+            at[i] = v / L[i][i];
+        }
     }
-    for (int i = 0; i < te; ++i) alpha[i] = s[i] * at[i];
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+        if (i < te) alpha[i] = s[i] * at[i];
     return te;
+}
+
+__device__ int gram_alpha(const double *phi, int t, double *alpha) {
+    switch (t) {
+        case 1: return gram_alpha_t<1>(phi, alpha);
+        case 2: return gram_alpha_t<2>(phi, alpha);
+        case 3: return gram_alpha_t<3>(phi, alpha);
+        case 4: return gram_alpha_t<4>(phi, alpha);
+        case 5: return gram_alpha_t<5>(phi, alpha);
+        case 6: return gram_alpha_t<6>(phi, alpha);
+        case 7: return gram_alpha_t<7>(phi, alpha);
+        default: return gram_alpha_t<8>(phi, alpha);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -190,55 +208,48 @@ __device__ __forceinline__ void put_hist(State *st, double *hist) {
     if (hist != nullptr && st->k < st->hist_cap) hist[st->k] = sqrt(st->rr) / st->nb;
 }
 
-__device__ void post_action(const Tail &tl, double v0, double v1, bool computed, double *lds) {
-    State *st = tl.st;
-    switch (tl.post) {
+__device__ void post_action(const Step &sp, const double *v, bool computed) {
+    State *st = sp.st;
+    switch (sp.post) {
         case kPostNone:
             break;
         case kPostStore:
-            st->scratch[tl.arg] = v0;
-            break;
-        case kPostCount:
-            st->matvecs++;
+            for (int i = 0; i < sp.nslots && sp.arg + i < 4; ++i) st->scratch[sp.arg + i] = v[i];
             break;
         case kPostCtaInit:
         case kPostTaInit: {
-            const double nb = sqrt(v0);
+            const double nb = sqrt(v[0]);
             st->nb = nb;
             st->tol_nb = st->tol * nb;
-            st->rr = v0;
-            st->rb = v0;
+            st->rr = v[0];
+            st->rb = v[0];
             st->k = 0;
             if (nb == 0.0) {
-                if (tl.hist != nullptr && st->hist_cap > 0) tl.hist[0] = 0.0;
+                if (sp.hist != nullptr && st->hist_cap > 0) sp.hist[0] = 0.0;
                 finish(st, TA_STOP_RESIDUAL);
                 break;
             }
-            if (tl.arg == 0) {  // arg = 1: a warm start recomputes r next
-                put_hist(st, tl.hist);
+            if (sp.arg == 0) {  // arg = 1: a warm start recomputes r next
+                put_hist(st, sp.hist);
                 loop_top(st);
             }
             break;
         }
         case kPostCtaWarm:
-            st->rr = v0;
+            st->rr = v[0];
             st->matvecs++;
-            put_hist(st, tl.hist);
+            put_hist(st, sp.hist);
             loop_top(st);
             break;
         case kPostNab:
-            st->nab = sqrt(v0);
+            st->nab = sqrt(v[0]);
             st->tol_ne_nab = st->tol_normal * st->nab;
             st->matvecs++;
             break;
-        case kPostPhi:
-            st->phi[tl.arg] = v0;
-            st->matvecs++;
-            break;
-        case kPostPhiGram: {
-            st->phi[tl.arg] = v0;
-            st->matvecs++;
+        case kPostGram: {
             const int t = st->t;
+            for (int i = 0; i < 2 * t; ++i) st->phi[i + 1] = v[i];
+            st->matvecs += 2 * t;
             for (int i = 1; i <= 2 * t; ++i)
                 if (!isfinite(st->phi[i])) {
                     finish(st, TA_STOP_BREAKDOWN);
@@ -248,8 +259,10 @@ __device__ void post_action(const Tail &tl, double v0, double v1, bool computed,
                 finish(st, TA_STOP_NORMAL);
                 return;
             }
-            double *a = lds + kGramLds;
-            gram_alpha(st->phi, t, a, lds);
+            double phi[2 * kTMax + 2];
+            for (int i = 0; i <= 2 * t; ++i) phi[i] = st->phi[i];
+            double a[kTMax];
+            gram_alpha(phi, t, a);
             for (int i = 0; i < t; ++i)
                 if (!isfinite(a[i])) {
                     finish(st, TA_STOP_BREAKDOWN);
@@ -259,24 +272,24 @@ __device__ void post_action(const Tail &tl, double v0, double v1, bool computed,
             break;
         }
         case kPostCtaEnd:
-            st->rr = v0;
+            st->rr = v[0];
             st->k++;
-            put_hist(st, tl.hist);
+            put_hist(st, sp.hist);
             if (st->replace_every > 0 && st->k % st->replace_every == 0)
                 st->replace = 1;
             else
                 loop_top(st);
             break;
         case kPostCtaReplace:
-            st->rr = v0;
+            st->rr = v[0];
             st->replace = 0;
-            st->matvecs++;
+            st->matvecs += sp.arg;
             loop_top(st);
             break;
         case kPostCtaCand:
-            st->matvecs++;
-            st->rr = v0;
-            if (sqrt(v0) <= st->tol_nb) {
+            st->matvecs += sp.arg;
+            st->rr = v[0];
+            if (sqrt(v[0]) <= st->tol_nb) {
                 finish(st, TA_STOP_RESIDUAL);
             } else {
                 st->done = 0;
@@ -286,7 +299,7 @@ __device__ void post_action(const Tail &tl, double v0, double v1, bool computed,
             break;
         case kPostTaC: {
             if (computed) {
-                st->nc = sqrt(v0);
+                st->nc = sqrt(v[0]);
                 st->have_c = 1;
                 st->matvecs++;
             }
@@ -314,14 +327,14 @@ __device__ void post_action(const Tail &tl, double v0, double v1, bool computed,
                 st->pass = (q >= 2.0 * st->rho);
                 st->rho = (2.0 * st->rho >= q) ? 2.0 * st->rho : q;
                 st->k++;
-                put_hist(st, tl.hist);
+                put_hist(st, sp.hist);
                 loop_top(st);
             }
             break;
         }
         case kPostTaS: {
             st->matvecs++;
-            const double rd = v0, dd = v1;
+            const double rd = v[0], dd = v[1];
             if (!(dd > 0.0) || !isfinite(rd) || !isfinite(dd)) {
                 finish(st, TA_STOP_BREAKDOWN);
                 break;
@@ -333,18 +346,18 @@ __device__ void post_action(const Tail &tl, double v0, double v1, bool computed,
             break;
         }
         case kPostTaEnd:
-            st->rr = v0;
-            st->rb = v1;
+            st->rr = v[0];
+            st->rb = v[1];
             st->pass = 0;
             st->have_c = 0;
             st->pivot = 0;
             st->k++;
-            put_hist(st, tl.hist);
+            put_hist(st, sp.hist);
             loop_top(st);
             break;
         case kPostTaCand:
             st->matvecs++;
-            if (sqrt(v0) <= st->tol_nb) {
+            if (sqrt(v[0]) <= st->tol_nb) {
                 finish(st, TA_STOP_RESIDUAL);
             } else {
                 st->done = 0;
@@ -353,8 +366,8 @@ __device__ void post_action(const Tail &tl, double v0, double v1, bool computed,
             break;
         case kPostTaBp:
             st->matvecs++;
-            st->rr = v0;
-            st->rb = v1;
+            st->rr = v[0];
+            st->rb = v[1];
             st->have_c = 0;
             if (st->k >= st->max_iter) finish(st, TA_STOP_MAXITER);
             break;
@@ -363,23 +376,21 @@ __device__ void post_action(const Tail &tl, double v0, double v1, bool computed,
     }
 }
 
-// 0: skip, 1: run, 2: only block 0 runs the post action (c is current)
-__device__ __forceinline__ int gate_of(const Tail &tl) {
-    if (tl.gate == kGateIgnoreDone) return 1;
-    const State *st = tl.st;
-    if (st->done) return 0;
-    if (tl.gate == kGatePivot && !st->pivot) return 0;
-    if (tl.gate == kGateReplace && !st->replace) return 0;
-    if (tl.gate == kGateNeedC && st->have_c) return 2;
-    return 1;
+// Producers: run unless the chain says otherwise.
+__device__ __forceinline__ bool producer_runs(const Out &o) {
+    if (o.gate == kGateIgnoreDone) return true;
+    const State *st = o.st;
+    if (st->done) return false;
+    if (o.gate == kGatePivot && !st->pivot) return false;
+    if (o.gate == kGateReplace && !st->replace) return false;
+    if (o.gate == kGateNeedC && st->have_c) return false;
+    return true;
 }
 
-// Reduce NV values over the grid; the last block runs the post action.
+// Block-reduce NV values and write one partial each (thread 0, plain stores).
 template <int NV>
-__device__ void block_finish(Acc (&v)[NV], const Tail &tl) {
-    __shared__ double gram_lds[kGramLds + kTMax];
+__device__ void block_partials(Acc (&v)[NV], const Out &o) {
     __shared__ Acc red[2][kBlock / 64];
-    __shared__ int is_last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
@@ -392,35 +403,54 @@ __device__ void block_finish(Acc (&v)[NV], const Tail &tl) {
         for (int q = 0; q < NV; ++q) {
             Acc a = red[q][0];
             for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[q][w]);
-            store_partial(&tl.partials[(int64_t)q * gridDim.x + blockIdx.x], a);
+            o.partials[(int64_t)(o.slot + q) * o.cap + blockIdx.x] = make_double2(a.p, a.s);
         }
-        __threadfence();
-        const uint32_t prev = atomicAdd(&tl.st->counter, 1u);
-        is_last = (prev == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!is_last) return;
-    __threadfence();
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-        Acc a = {0.0, 0.0};
-        for (int64_t i = threadIdx.x; i < (int64_t)gridDim.x; i += kBlock)
-            a = acc_merge(a, load_partial(&tl.partials[(int64_t)q * gridDim.x + i]));
-        a = group_reduce<64>(a);
-        if (lane == 0) red[q][wave] = a;
+}
+
+// One block: reduce the listed slots in a fixed order, then the step logic.
+__global__ __launch_bounds__(kBlock) void k_step(Step sp) {
+    const State *st = sp.st;
+    bool computed = true;
+    if (sp.gate != kGateIgnoreDone) {
+        if (st->done) return;
+        if (sp.gate == kGatePivot && !st->pivot) return;
+        if (sp.gate == kGateReplace && !st->replace) return;
+        if (sp.gate == kGateNeedC && st->have_c) computed = false;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double vals[2] = {0.0, 0.0};
+    __shared__ double vals[kMaxSlots];
+    __shared__ Acc red[kBlock / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (computed) {
+        for (int q = 0; q < sp.nslots; ++q) {
+            const double2 *p = sp.partials + (int64_t)(sp.slot0 + q) * sp.cap;
+            const int cnt = sp.count[q];
+            Acc a = {0.0, 0.0};
+            // thread i takes partials i, i + 256, i + 512, ... in that order;
+            // eight loads are issued before the merges that consume them
+            for (int base = threadIdx.x; base < cnt; base += 8 * kBlock) {
+                double2 d[8];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) {
-            Acc a = red[q][0];
-            for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[q][w]);
-            vals[q] = acc_val(a);
+                for (int u = 0; u < 8; ++u) {
+                    const int i = base + u * kBlock;
+                    d[u] = i < cnt ? p[i] : make_double2(0.0, 0.0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (base + u * kBlock < cnt) a = acc_merge(a, Acc{d[u].x, d[u].y});
+            }
+            a = group_reduce<64>(a);
+            if (lane == 0) red[wave] = a;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                Acc b = red[0];
+                for (int w = 1; w < kBlock / 64; ++w) b = acc_merge(b, red[w]);
+                vals[q] = acc_val(b);
+            }
+            __syncthreads();
         }
-        tl.st->counter = 0;
-        post_action(tl, vals[0], vals[1], true, gram_lds);
     }
+    if (threadIdx.x == 0) post_action(sp, vals, computed);
 }
 
 template <int EPI>
@@ -458,13 +488,8 @@ __device__ __forceinline__ void epilogue(int64_t row, double yv, double *y, cons
 // ---------------------------------------------------------------------------
 template <int EPI>
 __global__ __launch_bounds__(kBlock) void k_csr_stream(MatView M, const double *__restrict__ x,
-                                                        double *y, EpiArgs ea, Tail tl) {
-    const int g = gate_of(tl);
-    if (g == 0) return;
-    if (g == 2) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) post_action(tl, 0.0, 0.0, false, nullptr);
-        return;
-    }
+                                                        double *y, EpiArgs ea, Out o) {
+    if (!producer_runs(o)) return;
     __shared__ double sh[kChunk];
     __shared__ double se[kChunk];
     __shared__ int32_t srp[kBlock + 1];
@@ -485,18 +510,31 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(MatView M, const double *
     }
     for (int32_t base = k0; base < k1; base += kChunk) {
         const int32_t cnt = min((int32_t)kChunk, k1 - base);
-        for (int i = tid; i < cnt; i += kBlock) {
-            const int32_t k = base + i;
-            const double a = M.val[k];
-            const double xv = x[M.ci[k]];
-            double h = a * xv;
-            double e = __fma_rn(a, xv, -h);
-            if constexpr (EPI == kEpiResid) {
-                h = -h;
-                e = -e;
+        for (int i0 = tid; i0 < cnt; i0 += 4 * kBlock) {
+            int32_t c[4];
+            double a[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * kBlock;
+                c[u] = i < cnt ? M.ci[base + i] : 0;
+                a[u] = i < cnt ? M.val[base + i] : 0.0;
             }
-            sh[i] = h;
-            se[i] = e;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * kBlock;
+                if (i < cnt) {
+                    double h = a[u] * xv[u];
+                    double e = __fma_rn(a[u], xv[u], -h);
+                    if constexpr (EPI == kEpiResid) {
+                        h = -h;
+                        e = -e;
+                    }
+                    sh[i] = h;
+                    se[i] = e;
+                }
+            }
         }
         __syncthreads();
         const int32_t lo = max(rs, base), hi = min(re, base + cnt);
@@ -504,8 +542,8 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(MatView M, const double *
         __syncthreads();
     }
     Acc v[EpiNV<EPI>::value] = {};
-    if (has_row) epilogue<EPI>(r0 + tid, acc_val(acc), y, ea, tl.st, v);
-    block_finish<EpiNV<EPI>::value>(v, tl);
+    if (has_row) epilogue<EPI>(r0 + tid, acc_val(acc), y, ea, o.st, v);
+    block_partials<EpiNV<EPI>::value>(v, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -513,14 +551,10 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(MatView M, const double *
 // ---------------------------------------------------------------------------
 template <int W, int EPI>
 __global__ __launch_bounds__(kBlock) void k_rows_vector(MatView M, const double *__restrict__ x,
-                                                         double *y, EpiArgs ea, Tail tl) {
-    const int g = gate_of(tl);
-    if (g == 0) return;
-    if (g == 2) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) post_action(tl, 0.0, 0.0, false, nullptr);
-        return;
-    }
+                                                         double *y, EpiArgs ea, Out o) {
+    if (!producer_runs(o)) return;
     constexpr int G = kBlock / W;
+    constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
     const int tid = threadIdx.x;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t row = blk * G + tid / W;
@@ -530,20 +564,129 @@ __global__ __launch_bounds__(kBlock) void k_rows_vector(MatView M, const double 
         if constexpr (EPI == kEpiResid) {
             if (lane == 0) acc.p = ea.b[row];
         }
-        constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
-        if (M.dense) {
+        if (M.kind == kDenseRows) {
             const double *a = M.val + row * M.ld;
-            for (int64_t j = lane; j < M.cols; j += W) acc_fma(acc, sgn * a[j], x[j]);
+            int64_t j = lane;
+            for (; j + 3 * W < M.cols; j += 4 * W) {
+                const double a0 = a[j], a1 = a[j + W], a2 = a[j + 2 * W], a3 = a[j + 3 * W];
+                const double x0 = x[j], x1 = x[j + W], x2 = x[j + 2 * W], x3 = x[j + 3 * W];
+                acc_fma(acc, sgn * a0, x0);
+                acc_fma(acc, sgn * a1, x1);
+                acc_fma(acc, sgn * a2, x2);
+                acc_fma(acc, sgn * a3, x3);
+            }
+            for (; j < M.cols; j += W) acc_fma(acc, sgn * a[j], x[j]);
         } else {
             const int32_t e = M.rp[row + 1];
-            for (int32_t k = M.rp[row] + lane; k < e; k += W)
-                acc_fma(acc, sgn * M.val[k], x[M.ci[k]]);
+            int32_t k = M.rp[row] + lane;
+            for (; k + 3 * W < e; k += 4 * W) {
+                const int32_t c0 = M.ci[k], c1 = M.ci[k + W], c2 = M.ci[k + 2 * W],
+                              c3 = M.ci[k + 3 * W];
+                const double a0 = M.val[k], a1 = M.val[k + W], a2 = M.val[k + 2 * W],
+                             a3 = M.val[k + 3 * W];
+                const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+                acc_fma(acc, sgn * a0, x0);
+                acc_fma(acc, sgn * a1, x1);
+                acc_fma(acc, sgn * a2, x2);
+                acc_fma(acc, sgn * a3, x3);
+            }
+            for (; k < e; k += W) acc_fma(acc, sgn * M.val[k], x[M.ci[k]]);
         }
     }
     acc = group_reduce<W>(acc);
     Acc v[EpiNV<EPI>::value] = {};
-    if (row < M.rows && lane == 0) epilogue<EPI>(row, acc_val(acc), y, ea, tl.st, v);
-    block_finish<EpiNV<EPI>::value>(v, tl);
+    if (row < M.rows && lane == 0) epilogue<EPI>(row, acc_val(acc), y, ea, o.st, v);
+    block_partials<EpiNV<EPI>::value>(v, o);
+}
+
+// ---------------------------------------------------------------------------
+// CSR split into kSlices column slices.  Block b works on slice b % 8 (its
+// XCD under round-robin dispatch) for a group of rows, so each XCD gathers
+// only from its own 1/8 of x, which stays in that XCD's L2.  The matrix
+// stream is read non-temporally so it does not evict the slice of x.  Each
+// (row, slice) partial is kept as an unrounded compensated pair; the combine
+// kernel merges the slices of a row in slice order and runs the epilogue.
+// ---------------------------------------------------------------------------
+template <int W, int EPI>
+__global__ __launch_bounds__(kBlock) void k_rows_sliced(MatView M, const double *__restrict__ x,
+                                                         EpiArgs ea, Out o) {
+    if (!producer_runs(o)) return;
+    constexpr int G = kBlock / W;
+    constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
+    const int tid = threadIdx.x;
+    const int slice = (int)(blockIdx.x % kSlices);
+    const int64_t row = (int64_t)(blockIdx.x / kSlices) * G + tid / W;
+    const int lane = tid % W;
+    if (row >= M.rows) return;  // no block-wide synchronisation below
+    Acc acc = {0.0, 0.0};
+    if constexpr (EPI == kEpiResid) {
+        if (slice == 0 && lane == 0) acc.p = ea.b[row];
+    }
+    const int32_t *sg = M.seg + row * (kSlices + 1) + slice;
+    const int32_t e = sg[1];
+    int32_t k = sg[0] + lane;
+    for (; k + 3 * W < e; k += 4 * W) {
+        const int32_t c0 = __builtin_nontemporal_load(M.ci + k);
+        const int32_t c1 = __builtin_nontemporal_load(M.ci + k + W);
+        const int32_t c2 = __builtin_nontemporal_load(M.ci + k + 2 * W);
+        const int32_t c3 = __builtin_nontemporal_load(M.ci + k + 3 * W);
+        const double a0 = __builtin_nontemporal_load(M.val + k);
+        const double a1 = __builtin_nontemporal_load(M.val + k + W);
+        const double a2 = __builtin_nontemporal_load(M.val + k + 2 * W);
+        const double a3 = __builtin_nontemporal_load(M.val + k + 3 * W);
+        const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+        acc_fma(acc, sgn * a0, x0);
+        acc_fma(acc, sgn * a1, x1);
+        acc_fma(acc, sgn * a2, x2);
+        acc_fma(acc, sgn * a3, x3);
+    }
+    for (; k < e; k += W)
+        acc_fma(acc, sgn * __builtin_nontemporal_load(M.val + k), x[__builtin_nontemporal_load(M.ci + k)]);
+    acc = group_reduce<W>(acc);
+    if (lane == 0) M.ypart[(int64_t)slice * M.rows + row] = make_double2(acc.p, acc.s);
+}
+
+template <int EPI>
+__global__ __launch_bounds__(kBlock) void k_slices_combine(MatView M, double *y, EpiArgs ea,
+                                                            Out o) {
+    if (!producer_runs(o)) return;
+    Acc v[EpiNV<EPI>::value] = {};
+    for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row < M.rows;
+         row += (int64_t)gridDim.x * kBlock) {
+        double2 p = M.ypart[row];
+        Acc a = {p.x, p.y};
+#pragma unroll
+        for (int sl = 1; sl < kSlices; ++sl) {
+            p = M.ypart[(int64_t)sl * M.rows + row];
+            a = acc_merge(a, Acc{p.x, p.y});
+        }
+        epilogue<EPI>(row, acc_val(a), y, ea, o.st, v);
+    }
+    block_partials<EpiNV<EPI>::value>(v, o);
+}
+
+// First entry of each column slice inside each row of a column-sorted CSR.
+__global__ void k_slice_segments(int64_t m, const int32_t *__restrict__ rp,
+                                 const int32_t *__restrict__ ci, int64_t slice_w, int32_t *seg) {
+    for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row < m;
+         row += (int64_t)gridDim.x * kBlock) {
+        const int32_t s = rp[row], e = rp[row + 1];
+        int32_t *out = seg + row * (kSlices + 1);
+        out[0] = s;
+        for (int sl = 1; sl < kSlices; ++sl) {
+            const int64_t bound = sl * slice_w;
+            int32_t lo = s, hi = e;  // first k with ci[k] >= bound
+            while (lo < hi) {
+                const int32_t mid = lo + (hi - lo) / 2;
+                if (ci[mid] < bound)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            out[sl] = lo;
+        }
+        out[kSlices] = e;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -552,13 +695,8 @@ __global__ __launch_bounds__(kBlock) void k_rows_vector(MatView M, const double 
 // ---------------------------------------------------------------------------
 template <int EPI>
 __global__ __launch_bounds__(kBlock) void k_dense_cols(MatView M, const double *__restrict__ x,
-                                                        double *y, EpiArgs ea, Tail tl) {
-    const int g = gate_of(tl);
-    if (g == 0) return;
-    if (g == 2) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) post_action(tl, 0.0, 0.0, false, nullptr);
-        return;
-    }
+                                                        double *y, EpiArgs ea, Out o) {
+    if (!producer_runs(o)) return;
     // M = A^T: M.rows = columns of A, M.cols = rows of A
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     Acc acc = {0.0, 0.0};
@@ -567,8 +705,8 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols(MatView M, const double *
         for (int64_t i = 0; i < M.cols; ++i) acc_fma(acc, a[i * M.ld], x[i]);
     }
     Acc v[EpiNV<EPI>::value] = {};
-    if (j < M.rows) epilogue<EPI>(j, acc_val(acc), y, ea, tl.st, v);
-    block_finish<EpiNV<EPI>::value>(v, tl);
+    if (j < M.rows) epilogue<EPI>(j, acc_val(acc), y, ea, o.st, v);
+    block_partials<EpiNV<EPI>::value>(v, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,7 +714,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols(MatView M, const double *
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_cta_init(int64_t m, const double *__restrict__ b,
                                                       double *r, double *xy, int64_t nxy,
-                                                      int32_t zero_xy, Tail tl) {
+                                                      int32_t zero_xy, Out o) {
     Acc v[1] = {};
     const int64_t N = m > nxy ? m : nxy;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
@@ -588,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_cta_init(int64_t m, const double *__
         }
         if (zero_xy && i < nxy) xy[i] = 0.0;
     }
-    block_finish<1>(v, tl);
+    block_partials<1>(v, o);
 }
 
 struct VecPtrs {
@@ -597,11 +735,11 @@ struct VecPtrs {
 
 __global__ __launch_bounds__(kBlock) void k_cta_update(int64_t m, int64_t n, int32_t t,
                                                         int32_t minnorm, double *r, VecPtrs u,
-                                                        double *x, VecPtrs w, double *y, Tail tl) {
-    if (tl.st->done) return;
+                                                        double *x, VecPtrs w, double *y, Out o) {
+    if (o.st->done) return;
     double al[kTMax];
 #pragma unroll
-    for (int j = 0; j < kTMax; ++j) al[j] = j < t ? tl.st->alpha[j] : 0.0;
+    for (int j = 0; j < kTMax; ++j) al[j] = j < t ? o.st->alpha[j] : 0.0;
     Acc v[1] = {};
     const int64_t N = (minnorm || m > n) ? m : n;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
@@ -624,12 +762,12 @@ __global__ __launch_bounds__(kBlock) void k_cta_update(int64_t m, int64_t n, int
             x[i] = xi;
         }
     }
-    block_finish<1>(v, tl);
+    block_partials<1>(v, o);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ta_init(int64_t m, int64_t n,
                                                      const double *__restrict__ b, double *r,
-                                                     double *bp, double *x, Tail tl) {
+                                                     double *bp, double *x, Out o) {
     Acc v[1] = {};
     const int64_t N = m > n ? m : n;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
@@ -642,15 +780,15 @@ __global__ __launch_bounds__(kBlock) void k_ta_init(int64_t m, int64_t n,
         }
         if (i < n) x[i] = 0.0;
     }
-    block_finish<1>(v, tl);
+    block_partials<1>(v, o);
 }
 
 __global__ __launch_bounds__(kBlock) void k_ta_update(int64_t m, int64_t n,
                                                        const double *__restrict__ b, double *bp,
                                                        const double *__restrict__ d, double *r,
                                                        double *x, const double *__restrict__ c,
-                                                       Tail tl) {
-    const State *st = tl.st;
+                                                       Out o) {
+    const State *st = o.st;
     if (st->done || !st->pivot) return;
     const double alpha = st->alpha_ta;
     const double beta = alpha * st->gamma;
@@ -670,19 +808,7 @@ __global__ __launch_bounds__(kBlock) void k_ta_update(int64_t m, int64_t n,
         }
         if (i < n) x[i] = __fma_rn(beta, c[i], a1 * x[i]);
     }
-    block_finish<2>(v, tl);
-}
-
-__global__ __launch_bounds__(kBlock) void k_copy_norm(int64_t n, const double *__restrict__ src,
-                                                       double *dst, Tail tl) {
-    Acc v[1] = {};
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBlock) {
-        const double s = src[i];
-        if (dst != nullptr) dst[i] = s;
-        acc_fma(v[0], s, s);
-    }
-    block_finish<1>(v, tl);
+    block_partials<2>(v, o);
 }
 
 // ---------------------------------------------------------------------------
@@ -859,92 +985,136 @@ int64_t elementwise_blocks(int64_t n) {
 
 int64_t matvec_blocks(const MatView &M) {
     const int64_t rows = M.rows > 0 ? M.rows : 1;
-    if (M.dense == 2) return cdiv(rows, kBlock);
-    if (M.dense == 1 || M.lanes > 1) return cdiv(rows, kBlock / (M.lanes > 1 ? M.lanes : 64));
-    return cdiv(rows, kBlock);
+    switch (M.kind) {
+        case kDenseCols: return cdiv(rows, kBlock);
+        case kDenseRows: return cdiv(rows, kBlock / 64);
+        case kCsrSliced: return elementwise_blocks(rows);  // the combine kernel
+        default: return M.lanes > 1 ? cdiv(rows, kBlock / M.lanes) : cdiv(rows, kBlock);
+    }
 }
 
 template <int EPI>
 static void launch_vec_lanes(const MatView &M, dim3 grid, const double *x, double *y,
-                             const EpiArgs &ea, const Tail &tl, hipStream_t s) {
+                             const EpiArgs &ea, const Out &o, hipStream_t s) {
     switch (M.lanes) {
-        case 2: k_rows_vector<2, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl); break;
-        case 4: k_rows_vector<4, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl); break;
-        case 8: k_rows_vector<8, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl); break;
-        case 16: k_rows_vector<16, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl); break;
-        case 32: k_rows_vector<32, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl); break;
-        default: k_rows_vector<64, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl); break;
+        case 2: k_rows_vector<2, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        case 4: k_rows_vector<4, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        case 8: k_rows_vector<8, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        case 16: k_rows_vector<16, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        case 32: k_rows_vector<32, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        default: k_rows_vector<64, EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+    }
+}
+
+template <int EPI>
+static void launch_sliced(const MatView &M, const double *x, const EpiArgs &ea, const Out &o,
+                          hipStream_t s) {
+    const int W = M.lanes;
+    const dim3 grid((unsigned)(kSlices * cdiv(M.rows > 0 ? M.rows : 1, kBlock / W)));
+    switch (W) {
+        case 2: k_rows_sliced<2, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
+        case 4: k_rows_sliced<4, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
+        case 8: k_rows_sliced<8, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
+        case 16: k_rows_sliced<16, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
+        case 32: k_rows_sliced<32, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
+        default: k_rows_sliced<64, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
     }
 }
 
 template <int EPI>
 static void launch_matvec_t(const MatView &M, const double *x, double *y, const EpiArgs &ea,
-                            const Tail &tl, hipStream_t s) {
-    const dim3 grid((unsigned)matvec_blocks(M));
-    if (M.dense == 2) {
-        k_dense_cols<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl);
-    } else if (M.dense == 1) {
-        MatView V = M;
-        V.lanes = 64;
-        launch_vec_lanes<EPI>(V, grid, x, y, ea, tl, s);
-    } else if (M.lanes > 1) {
-        launch_vec_lanes<EPI>(M, grid, x, y, ea, tl, s);
-    } else {
-        k_csr_stream<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, tl);
+                            const Out &o, hipStream_t s, dim3 grid) {
+    switch (M.kind) {
+        case kDenseCols: k_dense_cols<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        case kDenseRows: {
+            MatView V = M;
+            V.lanes = 64;
+            launch_vec_lanes<EPI>(V, grid, x, y, ea, o, s);
+            break;
+        }
+        case kCsrSliced:
+            launch_sliced<EPI>(M, x, ea, o, s);
+            k_slices_combine<EPI><<<grid, kBlock, 0, s>>>(M, y, ea, o);
+            break;
+        default:
+            if (M.lanes > 1)
+                launch_vec_lanes<EPI>(M, grid, x, y, ea, o, s);
+            else
+                k_csr_stream<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o);
+            break;
     }
 }
 
 hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t epi,
-                         const EpiArgs &ea, const Tail &tl, hipStream_t s) {
+                         const EpiArgs &ea, const Out &o, hipStream_t s, int32_t *blocks) {
+    const int64_t g = matvec_blocks(M);
+    if (g > o.cap) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)g);
     switch (epi) {
-        case kEpiNorm: launch_matvec_t<kEpiNorm>(M, x, y, ea, tl, s); break;
-        case kEpiResid: launch_matvec_t<kEpiResid>(M, x, y, ea, tl, s); break;
-        case kEpiTaD: launch_matvec_t<kEpiTaD>(M, x, y, ea, tl, s); break;
-        case kEpiTaBp: launch_matvec_t<kEpiTaBp>(M, x, y, ea, tl, s); break;
+        case kEpiNorm: launch_matvec_t<kEpiNorm>(M, x, y, ea, o, s, grid); break;
+        case kEpiResid: launch_matvec_t<kEpiResid>(M, x, y, ea, o, s, grid); break;
+        case kEpiTaD: launch_matvec_t<kEpiTaD>(M, x, y, ea, o, s, grid); break;
+        case kEpiTaBp: launch_matvec_t<kEpiTaBp>(M, x, y, ea, o, s, grid); break;
         default: return hipErrorInvalidValue;
     }
+    if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }
 
-hipError_t launch_cta_init(int64_t m, int64_t n, const double *b, double *r, double *xy,
-                           int64_t nxy, int32_t zero_xy, const Tail &tl, hipStream_t s) {
-    (void)n;
-    const dim3 grid((unsigned)elementwise_blocks(m > nxy ? m : nxy));
-    k_cta_init<<<grid, kBlock, 0, s>>>(m, b, r, xy, nxy, zero_xy, tl);
+hipError_t launch_cta_init(int64_t m, const double *b, double *r, double *xy, int64_t nxy,
+                           int32_t zero_xy, const Out &o, hipStream_t s, int32_t *blocks) {
+    const int64_t g = elementwise_blocks(m > nxy ? m : nxy);
+    if (g > o.cap) return hipErrorInvalidValue;
+    k_cta_init<<<dim3((unsigned)g), kBlock, 0, s>>>(m, b, r, xy, nxy, zero_xy, o);
+    if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }
 
 hipError_t launch_cta_update(int64_t m, int64_t n, int32_t t, int32_t minnorm, double *r,
                              double *const *u, double *x, double *const *w, double *y,
-                             const Tail &tl, hipStream_t s) {
+                             const Out &o, hipStream_t s, int32_t *blocks) {
     VecPtrs U{}, Wp{};
     for (int j = 0; j <= t && j <= kTMax; ++j) U.p[j] = u[j];
     for (int j = 0; j < t && j < kTMax; ++j) Wp.p[j] = w ? w[j] : nullptr;
     const int64_t N = (minnorm || m > n) ? m : n;
-    const dim3 grid((unsigned)elementwise_blocks(N));
-    k_cta_update<<<grid, kBlock, 0, s>>>(m, n, t, minnorm, r, U, x, Wp, y, tl);
+    const int64_t g = elementwise_blocks(N);
+    if (g > o.cap) return hipErrorInvalidValue;
+    k_cta_update<<<dim3((unsigned)g), kBlock, 0, s>>>(m, n, t, minnorm, r, U, x, Wp, y, o);
+    if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }
 
 hipError_t launch_ta_init(int64_t m, int64_t n, const double *b, double *r, double *bp,
-                          double *x, const Tail &tl, hipStream_t s) {
-    const dim3 grid((unsigned)elementwise_blocks(m > n ? m : n));
-    k_ta_init<<<grid, kBlock, 0, s>>>(m, n, b, r, bp, x, tl);
+                          double *x, const Out &o, hipStream_t s, int32_t *blocks) {
+    const int64_t g = elementwise_blocks(m > n ? m : n);
+    if (g > o.cap) return hipErrorInvalidValue;
+    k_ta_init<<<dim3((unsigned)g), kBlock, 0, s>>>(m, n, b, r, bp, x, o);
+    if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }
 
 hipError_t launch_ta_update(int64_t m, int64_t n, const double *b, double *bp, const double *d,
-                            double *r, double *x, const double *c, const Tail &tl,
-                            hipStream_t s) {
-    const dim3 grid((unsigned)elementwise_blocks(m > n ? m : n));
-    k_ta_update<<<grid, kBlock, 0, s>>>(m, n, b, bp, d, r, x, c, tl);
+                            double *r, double *x, const double *c, const Out &o, hipStream_t s,
+                            int32_t *blocks) {
+    const int64_t g = elementwise_blocks(m > n ? m : n);
+    if (g > o.cap) return hipErrorInvalidValue;
+    k_ta_update<<<dim3((unsigned)g), kBlock, 0, s>>>(m, n, b, bp, d, r, x, c, o);
+    if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }
 
-hipError_t launch_copy_norm(int64_t n, const double *src, double *dst, const Tail &tl,
-                            hipStream_t s) {
-    const dim3 grid((unsigned)elementwise_blocks(n));
-    k_copy_norm<<<grid, kBlock, 0, s>>>(n, src, dst, tl);
+hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,
+                                 int64_t cols, int32_t *seg, hipStream_t s) {
+    const int64_t w = cdiv(cols > 0 ? cols : 1, kSlices);
+    k_slice_segments<<<(unsigned)elementwise_blocks(m), kBlock, 0, s>>>(m, rp, ci_sorted, w, seg);
+    return hipGetLastError();
+}
+
+hipError_t launch_step(const Step &sp, hipStream_t s) {
+    if (sp.nslots < 0 || sp.nslots > kMaxSlots) return hipErrorInvalidValue;
+    for (int i = 0; i < sp.nslots; ++i)
+        if (sp.count[i] < 0 || sp.count[i] > sp.cap) return hipErrorInvalidValue;
+    k_step<<<1, kBlock, 0, s>>>(sp);
     return hipGetLastError();
 }
 

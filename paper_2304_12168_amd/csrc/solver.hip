@@ -11,6 +11,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <initializer_list>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -66,6 +68,12 @@ class Workspace {
             p += (r.bytes + 255) & ~size_t(255);
         }
         return TA_OK;
+    }
+    // hand the allocation to the caller (it is not freed by the destructor)
+    void *release() {
+        void *b = base_;
+        base_ = nullptr;
+        return b;
     }
 
    private:
@@ -174,64 +182,166 @@ static int pick_lanes(int64_t nnz, int64_t rows) {
     return 64;
 }
 
-struct Operator {
+// Matrices whose rows hold more nonzeros than this per row, on average, get
+// lanes-per-row kernels; with at least kSliceMinCols columns they are also
+// split into XCD column slices so the gathered x stays in L2.
+constexpr int64_t kSliceMinCols = 1 << 17;
+
+// ---------------------------------------------------------------------------
+// Plan: a prepared operator.  Holds A^T (canonical CSR built on the device)
+// and, for long-row matrices, a column-sorted copy of A with its slice
+// table.  Immutable after creation, so one plan can serve calls on several
+// streams at once; per-call scratch lives in each call's workspace.
+// ---------------------------------------------------------------------------
+// Lanes per row for the sliced kernel, from the nonzeros per (row, slice).
+static int pick_slice_lanes(int64_t nnz, int64_t rows) {
+#ifdef TA_SLICE_LANES
+    return TA_SLICE_LANES;
+#endif
+    const double avg = rows > 0 ? (double)nnz / (double)rows / kSlices : 0.0;
+    if (avg <= 32.0) return 4;
+    if (avg <= 64.0) return 8;
+    if (avg <= 128.0) return 16;
+    if (avg <= 256.0) return 32;
+    return 64;
+}
+
+struct Plan {
+    ta_mat desc{};
     MatView A{}, AT{};
-    int32_t *at_rp = nullptr, *at_ci = nullptr;
-    double *at_val = nullptr;
-    int32_t *tr_work = nullptr;
-    int32_t *flag = nullptr;
-    int64_t m = 0, n = 0, nnz = 0;
-    bool csr = false;
-
-    void reserve(Workspace &ws, const ta_mat *M, bool need_t) {
-        m = M->m;
-        n = M->n;
-        csr = M->kind == TA_CSR;
-        nnz = csr ? M->nnz : m * n;
-        ws.reserve(&flag, 8);
-        if (csr && need_t) {
-            const int64_t ntiles = (std::max<int64_t>(n, 1) + 1023) / 1024;
-            ws.reserve(&at_rp, n + 1);
-            ws.reserve(&at_ci, nnz);
-            ws.reserve(&at_val, nnz);
-            ws.reserve(&tr_work, 2 * n + ntiles + 8 + nnz);
-        }
-    }
-
-    // After Workspace::commit.  Validates the CSR and builds A^T if needed.
-    int build(const ta_mat *M, bool need_t, hipStream_t s) {
-        if (csr) {
-            int rc = check_csr_device(M, flag, s);
-            if (rc != TA_OK) return rc;
-            A = MatView{0, m, n, 0, M->row_ptr, M->col_idx, M->val, pick_lanes(nnz, m)};
-            if (need_t) {
-                HIP_TRY(launch_transpose(m, n, nnz, M->row_ptr, M->col_idx, M->val, at_rp, at_ci,
-                                         at_val, tr_work, flag, s));
-                int32_t h = 0;
-                HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                if (h) return TA_ENOTSUP;
-                AT = MatView{0, n, m, 0, at_rp, at_ci, at_val, pick_lanes(nnz, n)};
-            }
-        } else {
-            A = MatView{1, m, n, M->ld, nullptr, nullptr, M->val, 64};
-            AT = MatView{2, n, m, M->ld, nullptr, nullptr, M->val, 1};
-        }
-        return TA_OK;
-    }
+    bool has_t = false;
+    void *mem = nullptr;
+    hipStream_t s_mem = nullptr;
 };
 
-static Tail make_tail(State *st, double *hist, double2 *partials, int32_t post, int32_t arg,
-                      int32_t gate) {
-    Tail t;
-    t.st = st;
-    t.hist = hist;
-    t.partials = partials;
-    t.post = post;
-    t.arg = arg;
-    t.gate = gate;
-    return t;
+static void plan_free(Plan *P) {
+    if (P->mem != nullptr) (void)hipFreeAsync(P->mem, P->s_mem);
+    P->mem = nullptr;
 }
+
+static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P) {
+    int rc = validate_mat(M);
+    if (rc != TA_OK) return rc;
+    P->desc = *M;
+    const int64_t m = M->m, n = M->n;
+    P->has_t = need_t;
+    if (M->kind == TA_DENSE_ROWMAJOR) {
+        P->A = MatView{kDenseRows, m, n, M->ld, nullptr, nullptr, M->val, 64, nullptr, nullptr};
+        P->AT = MatView{kDenseCols, n, m, M->ld, nullptr, nullptr, M->val, 1, nullptr, nullptr};
+        P->has_t = true;
+        return TA_OK;
+    }
+    const int64_t nnz = M->nnz;
+    const int la = pick_lanes(nnz, m), lt = pick_lanes(nnz, n);
+    const bool slice_a = need_t && la > 1 && n >= kSliceMinCols;
+    const bool slice_t = need_t && lt > 1 && m >= kSliceMinCols;
+
+    // owned memory
+    Workspace own(s);
+    int32_t *at_rp = nullptr, *at_ci = nullptr, *ac_ci = nullptr, *a_seg = nullptr,
+            *t_seg = nullptr;
+    double *at_val = nullptr, *ac_val = nullptr;
+    if (need_t) {
+        own.reserve(&at_rp, n + 1);
+        own.reserve(&at_ci, nnz);
+        own.reserve(&at_val, nnz);
+    }
+    if (slice_a) {
+        own.reserve(&ac_ci, nnz);
+        own.reserve(&ac_val, nnz);
+        own.reserve(&a_seg, m * (kSlices + 1));
+    }
+    if (slice_t) own.reserve(&t_seg, n * (kSlices + 1));
+    // temporary memory
+    Workspace tmp(s);
+    int32_t *flag = nullptr, *work = nullptr, *ac_rp = nullptr;
+    const int64_t mx = std::max(m, n);
+    const int64_t ntiles = (std::max<int64_t>(mx, 1) + 1023) / 1024;
+    tmp.reserve(&flag, 8);
+    if (need_t) tmp.reserve(&work, 2 * mx + ntiles + 8 + nnz);
+    if (slice_a) tmp.reserve(&ac_rp, m + 1);
+    if ((rc = own.commit()) != TA_OK) return rc;
+    if ((rc = tmp.commit()) != TA_OK) return rc;
+    if ((rc = check_csr_device(M, flag, s)) != TA_OK) return rc;
+
+    P->A = MatView{kCsrRows, m, n, 0, M->row_ptr, M->col_idx, M->val, la, nullptr, nullptr};
+    if (need_t) {
+        HIP_TRY(launch_transpose(m, n, nnz, M->row_ptr, M->col_idx, M->val, at_rp, at_ci, at_val,
+                                 work, flag, s));
+        P->AT = MatView{kCsrRows, n, m, 0, at_rp, at_ci, at_val, lt, nullptr, nullptr};
+        if (slice_a) {
+            // (A^T)^T: A with columns sorted inside each row
+            HIP_TRY(launch_transpose(n, m, nnz, at_rp, at_ci, at_val, ac_rp, ac_ci, ac_val, work,
+                                     flag, s));
+            HIP_TRY(launch_slice_segments(m, M->row_ptr, ac_ci, n, a_seg, s));
+            P->A = MatView{kCsrSliced, m, n, 0, M->row_ptr, ac_ci, ac_val,
+                           pick_slice_lanes(nnz, m), a_seg, nullptr};
+        }
+        if (slice_t) {
+            HIP_TRY(launch_slice_segments(n, at_rp, at_ci, m, t_seg, s));
+            P->AT = MatView{kCsrSliced, n, m, 0, at_rp, at_ci, at_val, pick_slice_lanes(nnz, n),
+                            t_seg, nullptr};
+        }
+        int32_t h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (h) return TA_ENOTSUP;
+    }
+    P->mem = own.release();
+    P->s_mem = s;
+    return TA_OK;
+}
+
+// Per-call launch helper: producers write into slots of `partials`, step
+// kernels reduce them.  Views carry this call's slice scratch.
+struct Chain {
+    State *st = nullptr;
+    double *hist = nullptr;
+    double2 *partials = nullptr;
+    int64_t cap = 0;  // partials per slot
+    hipStream_t s = nullptr;
+    MatView A{}, AT{};
+
+    // reserve the per-call pieces every chain needs
+    void reserve(Workspace &ws, const Plan &P, int32_t nslots) {
+        A = P.A;
+        AT = P.AT;
+        cap = std::max(matvec_blocks(P.A), elementwise_blocks(std::max(P.desc.m, P.desc.n)));
+        if (P.has_t) cap = std::max(cap, matvec_blocks(P.AT));
+        cap = std::max<int64_t>(cap, 1);
+        ws.reserve(&st, 1);
+        ws.reserve(&partials, (int64_t)nslots * cap);
+        if (A.kind == kCsrSliced) ws.reserve(&A.ypart, kSlices * std::max<int64_t>(A.rows, 1));
+        if (P.has_t && AT.kind == kCsrSliced)
+            ws.reserve(&AT.ypart, kSlices * std::max<int64_t>(AT.rows, 1));
+    }
+    Out out(int32_t slot, int32_t gate) const {
+        Out o;
+        o.st = st;
+        o.partials = partials;
+        o.cap = cap;
+        o.slot = slot;
+        o.gate = gate;
+        return o;
+    }
+    hipError_t step(int32_t slot0, std::initializer_list<int32_t> counts, int32_t post, int32_t arg,
+                    int32_t gate, bool with_hist = true) const {
+        Step sp;
+        memset(&sp, 0, sizeof sp);
+        sp.st = st;
+        sp.hist = with_hist ? hist : nullptr;
+        sp.partials = partials;
+        sp.cap = cap;
+        sp.slot0 = slot0;
+        sp.nslots = (int32_t)counts.size();
+        int i = 0;
+        for (int32_t c : counts) sp.count[i++] = c;
+        sp.post = post;
+        sp.arg = arg;
+        sp.gate = gate;
+        return launch_step(sp, s);
+    }
+};
 
 static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
     State h;
@@ -259,21 +369,20 @@ static int upload_state(State *d, const State &h, hipStream_t s) {
 }
 
 // Relative residual and normal-equation residual of the final x (FP64).
-static int exit_diagnostics(const Operator &op, const ta_mat *M, const double *b, const double *x,
-                            double *tmp_m, double *tmp_n, State *st, double2 *partials,
-                            hipStream_t s, double nb, ta_info *info) {
+static int exit_diagnostics(const Chain &c, const double *b, const double *x, double *tmp_m,
+                            double *tmp_n, double nb, ta_info *info) {
     EpiArgs ea{};
     ea.b = b;
-    HIP_TRY(launch_matvec(op.A, x, tmp_m, kEpiResid, ea,
-                          make_tail(st, nullptr, partials, kPostStore, 0, kGateIgnoreDone), s));
-    HIP_TRY(launch_matvec(op.AT, tmp_m, tmp_n, kEpiNorm, EpiArgs{},
-                          make_tail(st, nullptr, partials, kPostStore, 1, kGateIgnoreDone), s));
-    HIP_TRY(launch_matvec(op.AT, b, tmp_n, kEpiNorm, EpiArgs{},
-                          make_tail(st, nullptr, partials, kPostStore, 2, kGateIgnoreDone), s));
+    int32_t g0 = 0, g1 = 0, g2 = 0;
+    HIP_TRY(launch_matvec(c.A, x, tmp_m, kEpiResid, ea, c.out(0, kGateIgnoreDone), c.s, &g0));
+    HIP_TRY(launch_matvec(c.AT, tmp_m, tmp_n, kEpiNorm, EpiArgs{}, c.out(1, kGateIgnoreDone), c.s,
+                          &g1));
+    HIP_TRY(launch_matvec(c.AT, b, tmp_n, kEpiNorm, EpiArgs{}, c.out(2, kGateIgnoreDone), c.s,
+                          &g2));
+    HIP_TRY(c.step(0, {g0, g1, g2}, kPostStore, 0, kGateIgnoreDone, false));
     State h;
-    int rc = read_state(st, h, s);
+    int rc = read_state(c.st, h, c.s);
     if (rc != TA_OK) return rc;
-    (void)M;
     info->rel_res = nb > 0.0 ? sqrt(h.scratch[0]) / nb : 0.0;
     const double nab = sqrt(h.scratch[2]);
     info->rel_normal = nab > 0.0 ? sqrt(h.scratch[1]) / nab : 0.0;
@@ -300,139 +409,145 @@ struct Chunker {
     }
 };
 
-// ---------------------------------------------------------------------------
-// CTA (x-form and y-form)
-// ---------------------------------------------------------------------------
-static int cta_impl(const ta_mat *M, const double *b, double *x, const ta_opts *o, double *hist,
-                    int64_t hist_cap, ta_info *info, hipStream_t s, bool minnorm) {
+static int check_solve_args(const ta_mat *M, const double *b, double *x, const ta_opts *o,
+                            double *hist, int64_t hist_cap, ta_info *info, int solver) {
     if (info == nullptr) return TA_EINVAL;
     memset(info, 0, sizeof *info);
     int rc = validate_mat(M);
-    if (rc == TA_OK) rc = validate_opts(M, o, minnorm ? 1 : 0);
+    if (rc == TA_OK) rc = validate_opts(M, o, solver);
     if (rc != TA_OK) return rc;
     if ((M->m > 0 && b == nullptr) || (M->n > 0 && x == nullptr)) return TA_EINVAL;
     if (hist != nullptr && hist_cap < 0) return TA_EINVAL;
+    return TA_OK;
+}
+
+// Empty system (m = 0, so b = 0): x = 0 at once.
+static int solve_empty(const ta_mat *M, double *x, double *hist, int64_t hist_cap, ta_info *info,
+                       double rho0, hipStream_t s) {
+    if (M->n > 0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)M->n, s));
+    if (hist != nullptr && hist_cap > 0) HIP_TRY(hipMemsetAsync(hist, 0, sizeof(double), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    info->stop = TA_STOP_RESIDUAL;
+    info->rho = rho0;
+    return TA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// CTA (x-form and y-form)
+// ---------------------------------------------------------------------------
+static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, double *hist,
+                   int64_t hist_cap, ta_info *info, hipStream_t s, bool minnorm) {
+    const ta_mat *M = &P.desc;
+    int rc = check_solve_args(M, b, x, o, hist, hist_cap, info, minnorm ? 1 : 0);
+    if (rc != TA_OK) return rc;
+    if (!P.has_t) return TA_EINVAL;
     const int64_t m = M->m, n = M->n;
     const int t = o->t;
-    if (m == 0) {  // empty system: b = 0
-        if (n > 0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
-        if (hist != nullptr && hist_cap > 0) HIP_TRY(hipMemsetAsync(hist, 0, sizeof(double), s));
-        HIP_TRY(hipStreamSynchronize(s));
-        info->stop = TA_STOP_RESIDUAL;
-        return TA_OK;
-    }
+    if (m == 0) return solve_empty(M, x, hist, hist_cap, info, 0.0, s);
 
     Workspace ws(s);
-    Operator op;
-    op.reserve(ws, M, true);
-    State *st = nullptr;
+    Chain c;
+    c.s = s;
+    c.hist = hist;
+    c.reserve(ws, P, 2 * t + 1);
     double *r = nullptr, *y = nullptr, *tmp_n = nullptr;
     double *u[kTMax + 1] = {}, *w[kTMax] = {};
-    double2 *partials = nullptr;
-    ws.reserve(&st, 1);
     ws.reserve(&r, m);
     for (int j = 1; j <= t; ++j) ws.reserve(&u[j], m);
     const int nw = minnorm ? 1 : t;
     for (int j = 0; j < nw; ++j) ws.reserve(&w[j], n);
     if (minnorm) ws.reserve(&y, m);
     ws.reserve(&tmp_n, n);
-    // partial capacity: 2 values per block of the widest grid of the chain
-    {
-        MatView a{}, at{};
-        const int64_t nnz = M->kind == TA_CSR ? M->nnz : m * n;
-        if (M->kind == TA_CSR) {
-            a = MatView{0, m, n, 0, nullptr, nullptr, nullptr, pick_lanes(nnz, m)};
-            at = MatView{0, n, m, 0, nullptr, nullptr, nullptr, pick_lanes(nnz, n)};
-        } else {
-            a = MatView{1, m, n, M->ld, nullptr, nullptr, nullptr, 64};
-            at = MatView{2, n, m, M->ld, nullptr, nullptr, nullptr, 1};
-        }
-        int64_t cap = std::max({matvec_blocks(a), matvec_blocks(at),
-                                elementwise_blocks(std::max(m, n)), (int64_t)1});
-        ws.reserve(&partials, 2 * cap);
-    }
     if ((rc = ws.commit()) != TA_OK) return rc;
-    if ((rc = op.build(M, true, s)) != TA_OK) return rc;
 
     State h0 = initial_state(o, hist_cap, hist);
-    if ((rc = upload_state(st, h0, s)) != TA_OK) return rc;
+    if ((rc = upload_state(c.st, h0, s)) != TA_OK) return rc;
     u[0] = r;
     double *const xy = minnorm ? y : x;
     const int64_t nxy = minnorm ? m : n;
     const bool warm = o->warm_start && !minnorm;
+    const int32_t R = 2 * t;  // slot of ||r||^2
+    const int32_t products = minnorm ? 2 : 1;
+    int32_t g = 0, gr = 0;
 
     // initial state: r = b, x = 0 (or y = 0), ||b||
-    HIP_TRY(launch_cta_init(m, n, b, r, xy, nxy, warm ? 0 : 1,
-                            make_tail(st, hist, partials, kPostCtaInit, warm ? 1 : 0, kGateAlways), s));
-    if (o->tol_normal > 0.0)
-        HIP_TRY(launch_matvec(op.AT, b, tmp_n, kEpiNorm, EpiArgs{},
-                              make_tail(st, nullptr, partials, kPostNab, 0, kGateAlways), s));
+    HIP_TRY(launch_cta_init(m, b, r, xy, nxy, warm ? 0 : 1, c.out(R, kGateAlways), s, &g));
+    HIP_TRY(c.step(R, {g}, kPostCtaInit, warm ? 1 : 0, kGateAlways));
+    if (o->tol_normal > 0.0) {
+        HIP_TRY(launch_matvec(c.AT, b, tmp_n, kEpiNorm, EpiArgs{}, c.out(0, kGateAlways), s, &g));
+        HIP_TRY(c.step(0, {g}, kPostNab, 0, kGateAlways));
+    }
     EpiArgs eres{};
     eres.b = b;
-    if (warm)
-        HIP_TRY(launch_matvec(op.A, x, r, kEpiResid, eres,
-                              make_tail(st, hist, partials, kPostCtaWarm, 0, kGateAlways), s));
+    if (warm) {
+        HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateAlways), s, &g));
+        HIP_TRY(c.step(R, {g}, kPostCtaWarm, 0, kGateAlways));
+    }
 
+    int32_t gphi[2 * kTMax] = {};
     auto enqueue_iteration = [&]() -> int {
         for (int j = 0; j < t; ++j) {
             double *wj = w[minnorm ? 0 : j];
-            HIP_TRY(launch_matvec(op.AT, u[j], wj, kEpiNorm, EpiArgs{},
-                                  make_tail(st, nullptr, partials, kPostPhi, 2 * j + 1, kGateAlways),
-                                  s));
-            HIP_TRY(launch_matvec(op.A, wj, u[j + 1], kEpiNorm, EpiArgs{},
-                                  make_tail(st, nullptr, partials,
-                                            j == t - 1 ? kPostPhiGram : kPostPhi, 2 * j + 2,
-                                            kGateAlways),
-                                  s));
+            HIP_TRY(launch_matvec(c.AT, u[j], wj, kEpiNorm, EpiArgs{}, c.out(2 * j, kGateAlways), s,
+                                  &gphi[2 * j]));
+            HIP_TRY(launch_matvec(c.A, wj, u[j + 1], kEpiNorm, EpiArgs{},
+                                  c.out(2 * j + 1, kGateAlways), s, &gphi[2 * j + 1]));
         }
-        HIP_TRY(launch_cta_update(m, n, t, minnorm ? 1 : 0, r, u, x, w, y,
-                                  make_tail(st, hist, partials, kPostCtaEnd, 0, kGateAlways), s));
+        Step sp;
+        memset(&sp, 0, sizeof sp);
+        sp.st = c.st;
+        sp.partials = c.partials;
+        sp.cap = c.cap;
+        sp.slot0 = 0;
+        sp.nslots = 2 * t;
+        for (int i = 0; i < 2 * t; ++i) sp.count[i] = gphi[i];
+        sp.post = kPostGram;
+        sp.gate = kGateAlways;
+        HIP_TRY(launch_step(sp, s));
+        HIP_TRY(launch_cta_update(m, n, t, minnorm ? 1 : 0, r, u, x, w, y, c.out(R, kGateAlways), s,
+                                  &g));
+        HIP_TRY(c.step(R, {g}, kPostCtaEnd, 0, kGateAlways));
         if (o->replace_every > 0) {
             if (minnorm)
-                HIP_TRY(launch_matvec(op.AT, y, x, kEpiNorm, EpiArgs{},
-                                      make_tail(st, nullptr, partials, kPostCount, 0, kGateReplace),
-                                      s));
-            HIP_TRY(launch_matvec(op.A, x, r, kEpiResid, eres,
-                                  make_tail(st, nullptr, partials, kPostCtaReplace, 0, kGateReplace),
-                                  s));
+                HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateReplace), s,
+                                      nullptr));
+            HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateReplace), s, &gr));
+            HIP_TRY(c.step(R, {gr}, kPostCtaReplace, products, kGateReplace));
         }
         return TA_OK;
     };
 
     Chunker ch(o->chunk);
     State h;
-    if ((rc = read_state(st, h, s)) != TA_OK) return rc;
+    if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
     while (!h.done || h.stop == kStopCandidate) {
         if (h.stop == kStopCandidate) {
             if (minnorm)
-                HIP_TRY(launch_matvec(op.AT, y, x, kEpiNorm, EpiArgs{},
-                                      make_tail(st, nullptr, partials, kPostCount, 0, kGateIgnoreDone),
-                                      s));
-            HIP_TRY(launch_matvec(op.A, x, r, kEpiResid, eres,
-                                  make_tail(st, nullptr, partials, kPostCtaCand, 0, kGateIgnoreDone),
-                                  s));
-        } else {
-            const int64_t k = ch.take();
-            for (int64_t i = 0; i < k; ++i)
-                if ((rc = enqueue_iteration()) != TA_OK) return rc;
-            const int64_t k_before = h.k;
-            if ((rc = read_state(st, h, s)) != TA_OK) return rc;
-            // every enqueued iteration advances k until the solve stops
-            if (!h.done && h.k == k_before) {
-                g_hip_msg = "iteration chain made no progress";
-                return TA_EHIP;
-            }
+                HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateIgnoreDone), s,
+                                      nullptr));
+            HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateIgnoreDone), s, &g));
+            HIP_TRY(c.step(R, {g}, kPostCtaCand, products, kGateIgnoreDone));
+            if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
             continue;
         }
-        if ((rc = read_state(st, h, s)) != TA_OK) return rc;
+        const int64_t k = ch.take();
+        for (int64_t i = 0; i < k; ++i)
+            if ((rc = enqueue_iteration()) != TA_OK) return rc;
+        const int64_t k_before = h.k;
+        if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
+        // every enqueued iteration advances k until the solve stops
+        if (!h.done && h.k == k_before) {
+            g_hip_msg = "iteration chain made no progress";
+            return TA_EHIP;
+        }
     }
     if (h.nb == 0.0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
     if (minnorm)
-        HIP_TRY(launch_matvec(op.AT, y, x, kEpiNorm, EpiArgs{},
-                              make_tail(st, nullptr, partials, kPostNone, 0, kGateIgnoreDone), s));
+        HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateIgnoreDone), s,
+                              nullptr));
     fill_info(h, info);
     if (h.nb > 0.0) {
-        rc = exit_diagnostics(op, M, b, x, r, tmp_n, st, partials, s, h.nb, info);
+        rc = exit_diagnostics(c, b, x, r, tmp_n, h.nb, info);
         if (rc != TA_OK) return rc;
     } else {
         HIP_TRY(hipStreamSynchronize(s));
@@ -443,73 +558,49 @@ static int cta_impl(const ta_mat *M, const double *b, double *x, const ta_opts *
 // ---------------------------------------------------------------------------
 // TA (Algorithm 3, or Algorithm 2 with a fixed radius)
 // ---------------------------------------------------------------------------
-static int ta_impl(const ta_mat *M, const double *b, double *x, const ta_opts *o, double *hist,
-                   int64_t hist_cap, ta_info *info, hipStream_t s) {
-    if (info == nullptr) return TA_EINVAL;
-    memset(info, 0, sizeof *info);
-    int rc = validate_mat(M);
-    if (rc == TA_OK) rc = validate_opts(M, o, 2);
+static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, double *hist,
+                  int64_t hist_cap, ta_info *info, hipStream_t s) {
+    const ta_mat *M = &P.desc;
+    int rc = check_solve_args(M, b, x, o, hist, hist_cap, info, 2);
     if (rc != TA_OK) return rc;
-    if ((M->m > 0 && b == nullptr) || (M->n > 0 && x == nullptr)) return TA_EINVAL;
-    if (hist != nullptr && hist_cap < 0) return TA_EINVAL;
+    if (!P.has_t) return TA_EINVAL;
     const int64_t m = M->m, n = M->n;
-    if (m == 0) {
-        if (n > 0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
-        if (hist != nullptr && hist_cap > 0) HIP_TRY(hipMemsetAsync(hist, 0, sizeof(double), s));
-        HIP_TRY(hipStreamSynchronize(s));
-        info->stop = TA_STOP_RESIDUAL;
-        info->rho = o->rho0;
-        return TA_OK;
-    }
+    if (m == 0) return solve_empty(M, x, hist, hist_cap, info, o->rho0, s);
 
     Workspace ws(s);
-    Operator op;
-    op.reserve(ws, M, true);
-    State *st = nullptr;
-    double *r = nullptr, *bp = nullptr, *c = nullptr, *d = nullptr, *tmp_m = nullptr;
-    double2 *partials = nullptr;
-    ws.reserve(&st, 1);
+    Chain c;
+    c.s = s;
+    c.hist = hist;
+    c.reserve(ws, P, 5);
+    double *r = nullptr, *bp = nullptr, *cv = nullptr, *d = nullptr, *tmp_m = nullptr;
     ws.reserve(&r, m);
     ws.reserve(&bp, m);
     ws.reserve(&d, m);
     ws.reserve(&tmp_m, m);
-    ws.reserve(&c, n);
-    {
-        MatView a{}, at{};
-        const int64_t nnz = M->kind == TA_CSR ? M->nnz : m * n;
-        if (M->kind == TA_CSR) {
-            a = MatView{0, m, n, 0, nullptr, nullptr, nullptr, pick_lanes(nnz, m)};
-            at = MatView{0, n, m, 0, nullptr, nullptr, nullptr, pick_lanes(nnz, n)};
-        } else {
-            a = MatView{1, m, n, M->ld, nullptr, nullptr, nullptr, 64};
-            at = MatView{2, n, m, M->ld, nullptr, nullptr, nullptr, 1};
-        }
-        int64_t cap = std::max({matvec_blocks(a), matvec_blocks(at),
-                                elementwise_blocks(std::max(m, n)), (int64_t)1});
-        ws.reserve(&partials, 2 * cap);
-    }
+    ws.reserve(&cv, n);
     if ((rc = ws.commit()) != TA_OK) return rc;
-    if ((rc = op.build(M, true, s)) != TA_OK) return rc;
 
     State h0 = initial_state(o, hist_cap, hist);
-    if ((rc = upload_state(st, h0, s)) != TA_OK) return rc;
-
-    HIP_TRY(launch_ta_init(m, n, b, r, bp, x,
-                           make_tail(st, hist, partials, kPostTaInit, 0, kGateAlways), s));
-    if (o->tol_normal > 0.0)
-        HIP_TRY(launch_matvec(op.AT, b, c, kEpiNorm, EpiArgs{},
-                              make_tail(st, nullptr, partials, kPostNab, 0, kGateAlways), s));
+    if ((rc = upload_state(c.st, h0, s)) != TA_OK) return rc;
+    int32_t g = 0, g2 = 0;
+    // slots: 0 ||c||^2; 1, 2: r^T d, ||d||^2; 3, 4: ||r||^2, r^T b
+    HIP_TRY(launch_ta_init(m, n, b, r, bp, x, c.out(3, kGateAlways), s, &g));
+    HIP_TRY(c.step(3, {g}, kPostTaInit, 0, kGateAlways));
+    if (o->tol_normal > 0.0) {
+        HIP_TRY(launch_matvec(c.AT, b, cv, kEpiNorm, EpiArgs{}, c.out(0, kGateAlways), s, &g));
+        HIP_TRY(c.step(0, {g}, kPostNab, 0, kGateAlways));
+    }
 
     EpiArgs ed{};
     ed.bp = bp;
     ed.r = r;
     auto enqueue_iteration = [&]() -> int {
-        HIP_TRY(launch_matvec(op.AT, r, c, kEpiNorm, EpiArgs{},
-                              make_tail(st, hist, partials, kPostTaC, 0, kGateNeedC), s));
-        HIP_TRY(launch_matvec(op.A, c, d, kEpiTaD, ed,
-                              make_tail(st, nullptr, partials, kPostTaS, 0, kGatePivot), s));
-        HIP_TRY(launch_ta_update(m, n, b, bp, d, r, x, c,
-                                 make_tail(st, hist, partials, kPostTaEnd, 0, kGatePivot), s));
+        HIP_TRY(launch_matvec(c.AT, r, cv, kEpiNorm, EpiArgs{}, c.out(0, kGateNeedC), s, &g));
+        HIP_TRY(c.step(0, {g}, kPostTaC, 0, kGateNeedC));
+        HIP_TRY(launch_matvec(c.A, cv, d, kEpiTaD, ed, c.out(1, kGatePivot), s, &g));
+        HIP_TRY(c.step(1, {g, g}, kPostTaS, 0, kGatePivot));
+        HIP_TRY(launch_ta_update(m, n, b, bp, d, r, x, cv, c.out(3, kGatePivot), s, &g));
+        HIP_TRY(c.step(3, {g, g}, kPostTaEnd, 0, kGatePivot));
         return TA_OK;
     };
 
@@ -520,32 +611,29 @@ static int ta_impl(const ta_mat *M, const double *b, double *x, const ta_opts *o
     ebp.r_out = r;
     Chunker ch(o->chunk);
     State h;
-    if ((rc = read_state(st, h, s)) != TA_OK) return rc;
+    if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
     while (!h.done || h.stop == kStopCandidate) {
         if (h.stop == kStopCandidate) {
-            HIP_TRY(launch_matvec(op.A, x, tmp_m, kEpiResid, eres,
-                                  make_tail(st, nullptr, partials, kPostTaCand, 0, kGateIgnoreDone),
-                                  s));
-            HIP_TRY(launch_matvec(op.A, x, bp, kEpiTaBp, ebp,
-                                  make_tail(st, nullptr, partials, kPostTaBp, 0, kGateAlways), s));
-        } else {
-            const int64_t k = ch.take();
-            for (int64_t i = 0; i < k; ++i)
-                if ((rc = enqueue_iteration()) != TA_OK) return rc;
-            const int64_t k_before = h.k;
-            if ((rc = read_state(st, h, s)) != TA_OK) return rc;
-            // every enqueued iteration advances k until the solve stops
-            if (!h.done && h.k == k_before) {
-                g_hip_msg = "iteration chain made no progress";
-                return TA_EHIP;
-            }
+            HIP_TRY(launch_matvec(c.A, x, tmp_m, kEpiResid, eres, c.out(3, kGateIgnoreDone), s, &g));
+            HIP_TRY(c.step(3, {g}, kPostTaCand, 0, kGateIgnoreDone));
+            HIP_TRY(launch_matvec(c.A, x, bp, kEpiTaBp, ebp, c.out(3, kGateAlways), s, &g2));
+            HIP_TRY(c.step(3, {g2, g2}, kPostTaBp, 0, kGateAlways));
+            if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
             continue;
         }
-        if ((rc = read_state(st, h, s)) != TA_OK) return rc;
+        const int64_t k = ch.take();
+        for (int64_t i = 0; i < k; ++i)
+            if ((rc = enqueue_iteration()) != TA_OK) return rc;
+        const int64_t k_before = h.k;
+        if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
+        if (!h.done && h.k == k_before) {
+            g_hip_msg = "iteration chain made no progress";
+            return TA_EHIP;
+        }
     }
     fill_info(h, info);
     if (h.nb > 0.0) {
-        rc = exit_diagnostics(op, M, b, x, tmp_m, c, st, partials, s, h.nb, info);
+        rc = exit_diagnostics(c, b, x, tmp_m, cv, h.nb, info);
         if (rc != TA_OK) return rc;
     } else {
         HIP_TRY(hipStreamSynchronize(s));
@@ -556,65 +644,58 @@ static int ta_impl(const ta_mat *M, const double *b, double *x, const ta_opts *o
 // ---------------------------------------------------------------------------
 // kernel-level entry points
 // ---------------------------------------------------------------------------
-static int product_impl(const ta_mat *M, int32_t trans, const double *x, double *y,
-                        const double *b, double *norm2, hipStream_t s) {
-    int rc = validate_mat(M);
-    if (rc != TA_OK) return rc;
+static int product_run(const Plan &P, int32_t trans, const double *x, double *y, const double *b,
+                       double *norm2, hipStream_t s) {
+    const ta_mat *M = &P.desc;
     const int64_t rows = trans ? M->n : M->m, cols = trans ? M->m : M->n;
     if ((cols > 0 && x == nullptr) || (rows > 0 && y == nullptr)) return TA_EINVAL;
+    if (trans && !P.has_t) return TA_EINVAL;
     if (rows == 0) {
         if (norm2 != nullptr) HIP_TRY(hipMemsetAsync(norm2, 0, sizeof(double), s));
         return TA_OK;
     }
     Workspace ws(s);
-    Operator op;
-    const bool need_t = trans != 0;
-    op.reserve(ws, M, need_t);
-    State *st = nullptr;
-    double2 *partials = nullptr;
-    ws.reserve(&st, 1);
-    ws.reserve(&partials, 2 * std::max<int64_t>(rows, 1));
-    if ((rc = ws.commit()) != TA_OK) return rc;
-    if ((rc = op.build(M, need_t, s)) != TA_OK) return rc;
-    HIP_TRY(hipMemsetAsync(st, 0, sizeof(State), s));
+    Chain c;
+    c.s = s;
+    c.reserve(ws, P, 1);
+    int rc = ws.commit();
+    if (rc != TA_OK) return rc;
+    HIP_TRY(hipMemsetAsync(c.st, 0, sizeof(State), s));
     EpiArgs ea{};
     ea.b = b;
-    const MatView &V = trans ? op.AT : op.A;
+    const MatView &V = trans ? c.AT : c.A;
+    int32_t g = 0;
     HIP_TRY(launch_matvec(V, x, y, b != nullptr ? kEpiResid : kEpiNorm, ea,
-                          make_tail(st, nullptr, partials, kPostStore, 0, kGateIgnoreDone), s));
+                          c.out(0, kGateIgnoreDone), s, &g));
+    HIP_TRY(c.step(0, {g}, kPostStore, 0, kGateIgnoreDone, false));
     if (norm2 != nullptr)
-        HIP_TRY(hipMemcpyAsync(norm2, &st->scratch[0], sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(norm2, &c.st->scratch[0], sizeof(double), hipMemcpyDeviceToDevice, s));
     return TA_OK;
 }
 
-// Average duration of one launch of the matvec kernel the solvers use for
-// y = A x (trans = 0) or y = A^T x (trans = 1), over `reps` back-to-back
+// Average duration of one launch of the product kernel(s) the solvers use
+// for y = A x (trans = 0) or y = A^T x (trans = 1), over `reps` back-to-back
 // launches bracketed by HIP events on `s`.
-static int time_matvec_impl(const ta_mat *M, int32_t trans, const double *x, double *y,
-                            int32_t reps, double *avg_ms, hipStream_t s) {
-    int rc = validate_mat(M);
-    if (rc != TA_OK) return rc;
+static int time_run(const Plan &P, int32_t trans, const double *x, double *y, int32_t reps,
+                    double *avg_ms, hipStream_t s) {
     if (reps < 1 || avg_ms == nullptr || x == nullptr || y == nullptr) return TA_EINVAL;
-    const int64_t rows = trans ? M->n : M->m;
+    if (trans && !P.has_t) return TA_EINVAL;
     Workspace ws(s);
-    Operator op;
-    const bool need_t = trans != 0;
-    op.reserve(ws, M, need_t);
-    State *st = nullptr;
-    double2 *partials = nullptr;
-    ws.reserve(&st, 1);
-    ws.reserve(&partials, 2 * std::max<int64_t>(rows, 1));
-    if ((rc = ws.commit()) != TA_OK) return rc;
-    if ((rc = op.build(M, need_t, s)) != TA_OK) return rc;
-    HIP_TRY(hipMemsetAsync(st, 0, sizeof(State), s));
-    const MatView &V = trans ? op.AT : op.A;
-    const Tail tl = make_tail(st, nullptr, partials, kPostStore, 0, kGateIgnoreDone);
-    HIP_TRY(launch_matvec(V, x, y, kEpiNorm, EpiArgs{}, tl, s));  // warm-up
+    Chain c;
+    c.s = s;
+    c.reserve(ws, P, 1);
+    int rc = ws.commit();
+    if (rc != TA_OK) return rc;
+    HIP_TRY(hipMemsetAsync(c.st, 0, sizeof(State), s));
+    const MatView &V = trans ? c.AT : c.A;
+    const Out out = c.out(0, kGateIgnoreDone);
+    HIP_TRY(launch_matvec(V, x, y, kEpiNorm, EpiArgs{}, out, s, nullptr));  // warm-up
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, s));
-    for (int32_t i = 0; i < reps; ++i) HIP_TRY(launch_matvec(V, x, y, kEpiNorm, EpiArgs{}, tl, s));
+    for (int32_t i = 0; i < reps; ++i)
+        HIP_TRY(launch_matvec(V, x, y, kEpiNorm, EpiArgs{}, out, s, nullptr));
     HIP_TRY(hipEventRecord(e1, s));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -625,7 +706,21 @@ static int time_matvec_impl(const ta_mat *M, int32_t trans, const double *x, dou
     return TA_OK;
 }
 
+// One-shot calls: a transient plan on the call's stream.
+template <class F>
+static int with_plan(const ta_mat *M, bool need_t, hipStream_t s, F &&f) {
+    Plan P;
+    int rc = plan_build(M, need_t, s, &P);
+    if (rc == TA_OK) rc = f(P);
+    plan_free(&P);
+    return rc;
+}
+
 }  // namespace ta
+
+struct ta_plan {
+    ta::Plan p;
+};
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -634,17 +729,75 @@ extern "C" {
 
 int cta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
               int64_t hist_cap, ta_info *info, void *stream) {
-    return ta::cta_impl(A, b, x, opts, hist, hist_cap, info, (hipStream_t)stream, false);
+    hipStream_t s = (hipStream_t)stream;
+    if (info == nullptr) return TA_EINVAL;
+    int rc = ta::check_solve_args(A, b, x, opts, hist, hist_cap, info, 0);
+    if (rc != TA_OK) return rc;
+    return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
+        return ta::cta_run(P, b, x, opts, hist, hist_cap, info, s, false);
+    });
 }
 
 int cta_minnorm(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
                 int64_t hist_cap, ta_info *info, void *stream) {
-    return ta::cta_impl(A, b, x, opts, hist, hist_cap, info, (hipStream_t)stream, true);
+    hipStream_t s = (hipStream_t)stream;
+    if (info == nullptr) return TA_EINVAL;
+    int rc = ta::check_solve_args(A, b, x, opts, hist, hist_cap, info, 1);
+    if (rc != TA_OK) return rc;
+    return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
+        return ta::cta_run(P, b, x, opts, hist, hist_cap, info, s, true);
+    });
 }
 
 int ta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
              int64_t hist_cap, ta_info *info, void *stream) {
-    return ta::ta_impl(A, b, x, opts, hist, hist_cap, info, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    if (info == nullptr) return TA_EINVAL;
+    int rc = ta::check_solve_args(A, b, x, opts, hist, hist_cap, info, 2);
+    if (rc != TA_OK) return rc;
+    return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
+        return ta::ta_run(P, b, x, opts, hist, hist_cap, info, s);
+    });
+}
+
+int ta_plan_create(const ta_mat *A, ta_plan **plan, void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    *plan = nullptr;
+    ta_plan *p = new (std::nothrow) ta_plan;
+    if (p == nullptr) return TA_ENOMEM;
+    int rc = ta::plan_build(A, true, (hipStream_t)stream, &p->p);
+    if (rc != TA_OK) {
+        ta::plan_free(&p->p);
+        delete p;
+        return rc;
+    }
+    *plan = p;
+    return TA_OK;
+}
+
+int ta_plan_destroy(ta_plan *plan) {
+    if (plan == nullptr) return TA_OK;
+    ta::plan_free(&plan->p);
+    delete plan;
+    return TA_OK;
+}
+
+int cta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                   double *hist, int64_t hist_cap, ta_info *info, void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    return ta::cta_run(plan->p, b, x, opts, hist, hist_cap, info, (hipStream_t)stream, false);
+}
+
+int cta_minnorm_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                     double *hist, int64_t hist_cap, ta_info *info, void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    return ta::cta_run(plan->p, b, x, opts, hist, hist_cap, info, (hipStream_t)stream, true);
+}
+
+int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                  double *hist, int64_t hist_cap, ta_info *info, void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    return ta::ta_run(plan->p, b, x, opts, hist, hist_cap, info, (hipStream_t)stream);
 }
 
 int ta_validate(const ta_mat *A, const ta_opts *opts, int32_t solver) {
@@ -666,18 +819,39 @@ const char *ta_strerror(int code) {
 
 int ta_spmv(const ta_mat *A, int32_t trans, const double *x, double *y, double *norm2,
             void *stream) {
-    return ta::product_impl(A, trans, x, y, nullptr, norm2, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    return ta::with_plan(A, trans != 0, s, [&](const ta::Plan &P) {
+        return ta::product_run(P, trans, x, y, nullptr, norm2, s);
+    });
+}
+
+int ta_spmv_plan(const ta_plan *plan, int32_t trans, const double *x, double *y, double *norm2,
+                 void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    return ta::product_run(plan->p, trans, x, y, nullptr, norm2, (hipStream_t)stream);
 }
 
 int ta_residual(const ta_mat *A, const double *b, const double *x, double *r, double *norm2,
                 void *stream) {
     if (b == nullptr && A != nullptr && A->m > 0) return TA_EINVAL;
-    return ta::product_impl(A, 0, x, r, b, norm2, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    return ta::with_plan(A, false, s, [&](const ta::Plan &P) {
+        return ta::product_run(P, 0, x, r, b, norm2, s);
+    });
 }
 
 int ta_time_matvec(const ta_mat *A, int32_t trans, const double *x, double *y, int32_t reps,
                    double *avg_ms, void *stream) {
-    return ta::time_matvec_impl(A, trans, x, y, reps, avg_ms, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
+        return ta::time_run(P, trans, x, y, reps, avg_ms, s);
+    });
+}
+
+int ta_time_matvec_plan(const ta_plan *plan, int32_t trans, const double *x, double *y,
+                        int32_t reps, double *avg_ms, void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    return ta::time_run(plan->p, trans, x, y, reps, avg_ms, (hipStream_t)stream);
 }
 
 int ta_transpose(const ta_mat *A, int32_t *at_row_ptr, int32_t *at_col_idx, double *at_val,

@@ -342,3 +342,67 @@ def test_dense_500_first_iterations():
              oracle.cta(p.A, p.b, tol=1e-8, t=2, max_iter=30))
     _compare(P.ta_solve(p.A, p.b, tol=1e-8, max_iter=30),
              oracle.ta(p.A, p.b, tol=1e-8, max_iter=30), x_rtol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# prepared operators and the XCD column-sliced kernels
+# ---------------------------------------------------------------------------
+def _wide():  # 600 nonzeros per row, 200k columns: A is split into column slices
+    return lp_shaped(2000, 200_000, seed=5)
+
+
+def _tall():  # its transpose: A^T has the long rows and is the sliced operand
+    p = _wide()
+    At = p.A.to_scipy().T.tocsr()
+    At.sort_indices()
+    A = Csr(At.shape[0], At.shape[1], At.indptr.astype(np.int32), At.indices.astype(np.int32),
+            At.data.copy())
+    xs = np.random.default_rng(11).standard_normal(A.n)
+    return type("Pb", (), {"A": A, "b": A.to_scipy() @ xs})()
+
+
+@pytest.mark.parametrize("make", [_wide, _tall], ids=["wide_sliced_A", "tall_sliced_AT"])
+def test_sliced_products_match_oracle(make):
+    p = make()
+    A = p.A
+    pl = P.plan(A)
+    g = np.random.default_rng(4)
+    x = g.standard_normal(A.n)
+    u = g.standard_normal(A.m)
+    # the plan's product kernels are the ones the solvers launch
+    for trans, vec, ref in ((False, x, oracle.apply(A, x)), (True, u, oracle.apply_t(A, u))):
+        y = host(P.spmv(pl, vec, trans=trans))
+        assert ulps(y, ref).max() <= 1
+    pl.close()
+
+
+@pytest.mark.parametrize("make", [_wide, _tall], ids=["wide_sliced_A", "tall_sliced_AT"])
+def test_sliced_solves_match_oracle(make):
+    p = make()
+    pl = P.plan(p.A)
+    g = P.cta_minnorm(pl, p.b, tol=1e-10, t=3, max_iter=200)
+    o = oracle.cta_minnorm(p.A, p.b, tol=1e-10, t=3, max_iter=200)
+    _compare(g, o)
+    g = P.cta_solve(pl, p.b, tol=1e-10, t=2, max_iter=200)
+    o = oracle.cta(p.A, p.b, tol=1e-10, t=2, max_iter=200)
+    _compare(g, o)
+    pl.close()
+
+
+def test_plan_and_one_shot_are_identical():
+    p = kac_clement(3001)
+    pl = P.plan(p.A)
+    a = P.cta_solve(pl, p.b, tol=1e-6, t=3, max_iter=5000)
+    b = P.cta_solve(p.A, p.b, tol=1e-6, t=3, max_iter=5000)
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[2] == b[2]
+    c = P.ta_solve(pl, p.b, tol=1e-2, max_iter=5000)
+    d = oracle.ta(p.A, p.b, tol=1e-2, max_iter=5000)
+    _compare(c, d, x_rtol=1e-9)
+    pl.close()
+
+
+def test_plan_rejects_malformed_csr():
+    bad = Csr(3, 3, np.array([0, 2, 1, 3], np.int32), np.array([0, 1, 2], np.int32), np.ones(3))
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.plan(bad)
