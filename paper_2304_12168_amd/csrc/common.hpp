@@ -34,6 +34,8 @@ struct State {
     int32_t have_c;    // TA: c = A^T r is current
     int32_t fixed_rho; // TA: Algorithm 2
     int32_t replace;   // a true-residual replacement is due
+    int32_t rejected;  // TA: a candidate stop failed, b' = A x must be recomputed
+    int32_t pad0;
     int64_t k;         // iterations done
     int64_t max_iter;
     int64_t hist_cap;
@@ -78,7 +80,10 @@ enum Gate : int32_t {
     kGatePivot,       // unless done, and only when state.pivot
     kGateNeedC,       // producer: unless done or c is current; step: unless done
     kGateReplace,     // unless done, and only when state.replace
-    kGateIgnoreDone,  // always (kernel-level calls, candidate checks)
+    kGateIgnoreDone,  // always (kernel-level calls)
+    kGateCandidate,   // only when the chain stopped at a candidate (true-residual check)
+    kGateFinal,       // only when the solve has finished (final x, exit diagnostics)
+    kGateRejected,    // unless done, and only after a rejected TA candidate
 };
 
 // Epilogues of the matrix-product kernels.

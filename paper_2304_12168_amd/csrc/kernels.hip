@@ -362,6 +362,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             } else {
                 st->done = 0;
                 st->stop = 0;
+                st->rejected = 1;
             }
             break;
         case kPostTaBp:
@@ -369,6 +370,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             st->rr = v[0];
             st->rb = v[1];
             st->have_c = 0;
+            st->rejected = 0;
             if (st->k >= st->max_iter) finish(st, TA_STOP_MAXITER);
             break;
         default:
@@ -377,13 +379,23 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
 }
 
 // Producers: run unless the chain says otherwise.
-__device__ __forceinline__ bool producer_runs(const Out &o) {
-    if (o.gate == kGateIgnoreDone) return true;
-    const State *st = o.st;
+__device__ __forceinline__ bool gate_open(int32_t gate, const State *st) {
+    switch (gate) {
+        case kGateIgnoreDone: return true;
+        case kGateCandidate: return st->done && st->stop == kStopCandidate;
+        case kGateFinal: return st->done && st->stop != kStopCandidate;
+        default: break;
+    }
     if (st->done) return false;
-    if (o.gate == kGatePivot && !st->pivot) return false;
-    if (o.gate == kGateReplace && !st->replace) return false;
-    if (o.gate == kGateNeedC && st->have_c) return false;
+    if (gate == kGatePivot && !st->pivot) return false;
+    if (gate == kGateReplace && !st->replace) return false;
+    if (gate == kGateRejected && !st->rejected) return false;
+    return true;
+}
+
+__device__ __forceinline__ bool producer_runs(const Out &o) {
+    if (!gate_open(o.gate, o.st)) return false;
+    if (o.gate == kGateNeedC && o.st->have_c) return false;
     return true;
 }
 
@@ -411,13 +423,8 @@ __device__ void block_partials(Acc (&v)[NV], const Out &o) {
 // One block: reduce the listed slots in a fixed order, then the step logic.
 __global__ __launch_bounds__(kBlock) void k_step(Step sp) {
     const State *st = sp.st;
-    bool computed = true;
-    if (sp.gate != kGateIgnoreDone) {
-        if (st->done) return;
-        if (sp.gate == kGatePivot && !st->pivot) return;
-        if (sp.gate == kGateReplace && !st->replace) return;
-        if (sp.gate == kGateNeedC && st->have_c) computed = false;
-    }
+    if (!gate_open(sp.gate, st)) return;
+    const bool computed = !(sp.gate == kGateNeedC && st->have_c);
     __shared__ double vals[kMaxSlots];
     __shared__ Acc red[kBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

@@ -357,36 +357,46 @@ static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
     return h;
 }
 
-// One State upload; the pinned staging buffer keeps the copy asynchronous.
+// One State upload from a pinned buffer of its own.  Every solve ends with a
+// synchronising State read, so when the next solve of this host thread
+// starts, the previous upload from the buffer has completed.
 static int upload_state(State *d, const State &h, hipStream_t s) {
-    State *p = host_state();
-    if (p == nullptr) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
-    HIP_TRY(hipStreamSynchronize(s));  // the staging buffer may still be in use
-    *p = h;
-    HIP_TRY(hipMemcpyAsync(d, p, sizeof(State), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    static thread_local State *up = nullptr;
+    if (up == nullptr &&
+        hipHostMalloc(reinterpret_cast<void **>(&up), sizeof(State)) != hipSuccess) {
+        up = nullptr;
+        return hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
+    }
+    *up = h;
+    HIP_TRY(hipMemcpyAsync(d, up, sizeof(State), hipMemcpyHostToDevice, s));
     return TA_OK;
 }
 
-// Relative residual and normal-equation residual of the final x (FP64).
-static int exit_diagnostics(const Chain &c, const double *b, const double *x, double *tmp_m,
-                            double *tmp_n, double nb, ta_info *info) {
+// Exit diagnostics, enqueued behind every chunk and run only once the solve
+// has finished: ||b - A x||^2, ||A^T (b - A x)||^2 and ||A^T b||^2 of the
+// final x into State.scratch[0..2].
+static hipError_t enqueue_exit_diagnostics(const Chain &c, const double *b, const double *x,
+                                           double *tmp_m, double *tmp_n) {
     EpiArgs ea{};
     ea.b = b;
     int32_t g0 = 0, g1 = 0, g2 = 0;
-    HIP_TRY(launch_matvec(c.A, x, tmp_m, kEpiResid, ea, c.out(0, kGateIgnoreDone), c.s, &g0));
-    HIP_TRY(launch_matvec(c.AT, tmp_m, tmp_n, kEpiNorm, EpiArgs{}, c.out(1, kGateIgnoreDone), c.s,
-                          &g1));
-    HIP_TRY(launch_matvec(c.AT, b, tmp_n, kEpiNorm, EpiArgs{}, c.out(2, kGateIgnoreDone), c.s,
-                          &g2));
-    HIP_TRY(c.step(0, {g0, g1, g2}, kPostStore, 0, kGateIgnoreDone, false));
-    State h;
-    int rc = read_state(c.st, h, c.s);
-    if (rc != TA_OK) return rc;
-    info->rel_res = nb > 0.0 ? sqrt(h.scratch[0]) / nb : 0.0;
+    hipError_t e;
+    if ((e = launch_matvec(c.A, x, tmp_m, kEpiResid, ea, c.out(0, kGateFinal), c.s, &g0)) !=
+        hipSuccess)
+        return e;
+    if ((e = launch_matvec(c.AT, tmp_m, tmp_n, kEpiNorm, EpiArgs{}, c.out(1, kGateFinal), c.s,
+                           &g1)) != hipSuccess)
+        return e;
+    if ((e = launch_matvec(c.AT, b, tmp_n, kEpiNorm, EpiArgs{}, c.out(2, kGateFinal), c.s, &g2)) !=
+        hipSuccess)
+        return e;
+    return c.step(0, {g0, g1, g2}, kPostStore, 0, kGateFinal, false);
+}
+
+static void fill_diagnostics(const State &h, ta_info *info) {
+    info->rel_res = h.nb > 0.0 ? sqrt(h.scratch[0]) / h.nb : 0.0;
     const double nab = sqrt(h.scratch[2]);
-    info->rel_normal = nab > 0.0 ? sqrt(h.scratch[1]) / nab : 0.0;
-    return TA_OK;
+    info->rel_normal = (h.nb > 0.0 && nab > 0.0) ? sqrt(h.scratch[1]) / nab : 0.0;
 }
 
 static void fill_info(const State &h, ta_info *info) {
@@ -517,40 +527,40 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         return TA_OK;
     };
 
+    // Each chunk: k iterations, then a candidate check (runs only if the chain
+    // stopped at a candidate), then the final x and the exit diagnostics (run
+    // only once the solve has finished).  One State read per chunk.
     Chunker ch(o->chunk);
     State h;
-    if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
-    while (!h.done || h.stop == kStopCandidate) {
-        if (h.stop == kStopCandidate) {
-            if (minnorm)
-                HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateIgnoreDone), s,
-                                      nullptr));
-            HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateIgnoreDone), s, &g));
-            HIP_TRY(c.step(R, {g}, kPostCtaCand, products, kGateIgnoreDone));
-            if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
-            continue;
-        }
+    int64_t progress = -1;
+    for (;;) {
         const int64_t k = ch.take();
         for (int64_t i = 0; i < k; ++i)
             if ((rc = enqueue_iteration()) != TA_OK) return rc;
-        const int64_t k_before = h.k;
+        if (minnorm)
+            HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateCandidate), s,
+                                  nullptr));
+        HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateCandidate), s, &g));
+        HIP_TRY(c.step(R, {g}, kPostCtaCand, products, kGateCandidate));
+        if (minnorm)
+            HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateFinal), s,
+                                  nullptr));
+        HIP_TRY(enqueue_exit_diagnostics(c, b, x, r, tmp_n));
         if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
-        // every enqueued iteration advances k until the solve stops
-        if (!h.done && h.k == k_before) {
+        if (h.done && h.stop != kStopCandidate) break;
+        // every chunk advances k or checks a candidate until the solve stops
+        if (h.k + h.matvecs == progress) {
             g_hip_msg = "iteration chain made no progress";
             return TA_EHIP;
         }
+        progress = h.k + h.matvecs;
     }
-    if (h.nb == 0.0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
-    if (minnorm)
-        HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateIgnoreDone), s,
-                              nullptr));
     fill_info(h, info);
-    if (h.nb > 0.0) {
-        rc = exit_diagnostics(c, b, x, r, tmp_n, h.nb, info);
-        if (rc != TA_OK) return rc;
-    } else {
+    if (h.nb == 0.0) {
+        HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
         HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        fill_diagnostics(h, info);
     }
     return TA_OK;
 }
@@ -611,33 +621,27 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     ebp.r_out = r;
     Chunker ch(o->chunk);
     State h;
-    if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
-    while (!h.done || h.stop == kStopCandidate) {
-        if (h.stop == kStopCandidate) {
-            HIP_TRY(launch_matvec(c.A, x, tmp_m, kEpiResid, eres, c.out(3, kGateIgnoreDone), s, &g));
-            HIP_TRY(c.step(3, {g}, kPostTaCand, 0, kGateIgnoreDone));
-            HIP_TRY(launch_matvec(c.A, x, bp, kEpiTaBp, ebp, c.out(3, kGateAlways), s, &g2));
-            HIP_TRY(c.step(3, {g2, g2}, kPostTaBp, 0, kGateAlways));
-            if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
-            continue;
-        }
+    int64_t progress = -1;
+    for (;;) {
         const int64_t k = ch.take();
         for (int64_t i = 0; i < k; ++i)
             if ((rc = enqueue_iteration()) != TA_OK) return rc;
-        const int64_t k_before = h.k;
+        // candidate check; on rejection b' = A x and r = b - b' are recomputed
+        HIP_TRY(launch_matvec(c.A, x, tmp_m, kEpiResid, eres, c.out(3, kGateCandidate), s, &g));
+        HIP_TRY(c.step(3, {g}, kPostTaCand, 0, kGateCandidate));
+        HIP_TRY(launch_matvec(c.A, x, bp, kEpiTaBp, ebp, c.out(3, kGateRejected), s, &g2));
+        HIP_TRY(c.step(3, {g2, g2}, kPostTaBp, 0, kGateRejected));
+        HIP_TRY(enqueue_exit_diagnostics(c, b, x, tmp_m, cv));
         if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
-        if (!h.done && h.k == k_before) {
+        if (h.done && h.stop != kStopCandidate) break;
+        if (h.k + h.matvecs == progress) {
             g_hip_msg = "iteration chain made no progress";
             return TA_EHIP;
         }
+        progress = h.k + h.matvecs;
     }
     fill_info(h, info);
-    if (h.nb > 0.0) {
-        rc = exit_diagnostics(c, b, x, tmp_m, cv, h.nb, info);
-        if (rc != TA_OK) return rc;
-    } else {
-        HIP_TRY(hipStreamSynchronize(s));
-    }
+    if (h.nb > 0.0) fill_diagnostics(h, info);
     return TA_OK;
 }
 
