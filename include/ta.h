@@ -177,6 +177,43 @@ int cta_minnorm_plan(const ta_plan *plan, const double *b, double *x, const ta_o
 int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
                   double *hist, int64_t hist_cap, ta_info *info, void *stream);
 
+/* ---- batched solves: many systems, many right-hand sides, one set of kernels ----
+ *
+ * ta_batch_plan_create concatenates nsys CSR systems (A[0..nsys-1], host array
+ * of descriptors, each TA_CSR, sizes m_s x n_s) into one block-diagonal
+ * operator on the device, builds its transpose, and, for precision TA_FP32 or
+ * TA_BF16, low-precision copies of the values.  The plan copies A's values,
+ * so A may change or be freed afterwards.  Totals (sum of m_s, sum of n_s,
+ * sum of nnz_s) must stay below 2^31.
+ *
+ * cta_solve_batched runs Algorithm 1 (CTA, H = A_s A_s^T) independently for
+ * every (system s, right-hand side c), all advanced together:
+ *   nrhs : host, nsys counts k_s in [0, 64];
+ *   B    : host array of nsys device pointers, B[s] column-major m_s x k_s;
+ *   X    : host array of nsys device pointers, X[s] column-major n_s x k_s (out);
+ *   opts : as cta_solve; opts->precision is TA_FP64 or the plan's precision;
+ *          opts->warm_start and opts->replace_every are not used; opts->chunk
+ *          is the number of iterations between true-residual checks
+ *          (0 = automatic);
+ *   minnorm : 1 = the y-form of cta_minnorm (x = A^T y), 0 = the x-form;
+ *   info : host, sum k_s entries, system-major (s, then c): iterations, products,
+ *          stop code, FP64 true relative residual, normal-equation residual.
+ * TA_FP64: each (s, c) follows exactly the single-right-hand-side iteration
+ * (same iteration count and stop code as cta_solve / cta_minnorm on that
+ * column).  TA_FP32 / TA_BF16: products of the Krylov chain use the low
+ * precision copies and FP32 vectors; Gram entries, steps, x (or y) and every
+ * true-residual check are FP64, and the true residual replaces the recurrence
+ * residual after every chunk; stop codes and residuals refer to FP64.
+ */
+typedef struct ta_batch_plan ta_batch_plan;
+
+int ta_batch_plan_create(int32_t nsys, const ta_mat *A, int32_t precision, ta_batch_plan **plan,
+                         void *stream);
+int ta_batch_plan_destroy(ta_batch_plan *plan);
+int cta_solve_batched(const ta_batch_plan *plan, const int32_t *nrhs, const double *const *B,
+                      double *const *X, const ta_opts *opts, int32_t minnorm, ta_info *info,
+                      void *stream);
+
 /*
  * ta_validate - host-side argument checks only (shapes, pointers, options);
  * it reads no device memory and launches nothing, so it runs without a GPU.

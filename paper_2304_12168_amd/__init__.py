@@ -31,7 +31,7 @@ ERRORS = {-1: "TA_EINVAL", -2: "TA_ENOMEM", -3: "TA_EHIP", -4: "TA_ENOTSUP"}
 EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror", "ta_spmv",
            "ta_residual", "ta_transpose", "ta_time_matvec", "ta_plan_create", "ta_plan_destroy",
            "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
-           "ta_spmv_plan")
+           "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched")
 
 
 class TaMat(C.Structure):
@@ -81,6 +81,12 @@ def load_library(path: str = LIB_PATH):
         lib.ta_plan_create.argtypes = [MP, C.POINTER(C.c_void_p), P]
         lib.ta_plan_destroy.restype = C.c_int
         lib.ta_plan_destroy.argtypes = [P]
+        lib.ta_batch_plan_create.restype = C.c_int
+        lib.ta_batch_plan_create.argtypes = [I32, P, I32, C.POINTER(C.c_void_p), P]
+        lib.ta_batch_plan_destroy.restype = C.c_int
+        lib.ta_batch_plan_destroy.argtypes = [P]
+        lib.cta_solve_batched.restype = C.c_int
+        lib.cta_solve_batched.argtypes = [P, P, P, P, OP, I32, P, P]
         lib.ta_spmv_plan.restype = C.c_int
         lib.ta_spmv_plan.argtypes = [P, I32, P, P, P, P]
         lib.ta_time_matvec_plan.restype = C.c_int
@@ -380,3 +386,72 @@ def time_matvec(A, x, trans: bool = False, reps: int = 50) -> float:
                                 C.c_void_p(y.data_ptr()), int(reps), C.byref(ms), _stream())
     _check(rc, "ta_time_matvec")
     return float(ms.value)
+
+
+PRECISIONS = {"fp64": TA_FP64, "fp32": TA_FP32, "bf16": TA_BF16}
+
+
+class BatchPlan:
+    """Block-diagonal operator over several CSR systems (ta_batch_plan), with
+    low-precision copies of the values for ``precision`` 'fp32' or 'bf16'."""
+
+    def __init__(self, systems, precision: str = "fp64"):
+        lib = load_library()
+        self.systems = [to_device(A) for A in systems]
+        if any(d.kind != TA_CSR for d in self.systems):
+            raise TaError("batched solves take CSR systems")
+        self.precision = PRECISIONS[precision]
+        descs = (TaMat * len(self.systems))(*[d.desc() for d in self.systems])
+        h = C.c_void_p()
+        _check(lib.ta_batch_plan_create(len(self.systems), descs, self.precision, C.byref(h),
+                                        _stream()), "ta_batch_plan_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load_library().ta_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cta_solve_batched(plan: BatchPlan, B, tol=1e-6, t=3, max_iter=100000, minnorm=False,
+                      precision: str = "fp64", **kw):
+    """Solve every column of every B[s] (an (m_s, k_s) float64 tensor or
+    array) with CTA.  Returns (X, infos): X[s] is (n_s, k_s), infos[s] a list
+    of Info per column."""
+    import torch
+
+    lib = load_library()
+    S = len(plan.systems)
+    if len(B) != S:
+        raise TaError("one right-hand-side block per system")
+    cols, xs, ks = [], [], []
+    for d, b in zip(plan.systems, B):
+        bt = b if isinstance(b, torch.Tensor) else torch.from_numpy(np.asarray(b, dtype=np.float64))
+        if bt.dim() == 1:
+            bt = bt[:, None]
+        bt = bt.to(device="cuda", dtype=torch.float64)
+        k = int(bt.shape[1])
+        cm = bt.t().contiguous()  # (k, m) storage = column-major m x k
+        cols.append(cm)
+        xs.append(torch.zeros((k, d.n), dtype=torch.float64, device=cm.device))
+        ks.append(k)
+    nrhs = (C.c_int32 * S)(*ks)
+    bp = (C.c_void_p * S)(*[c.data_ptr() for c in cols])
+    xp = (C.c_void_p * S)(*[x.data_ptr() for x in xs])
+    opts = make_opts(tol=tol, t=t, max_iter=max_iter, precision=PRECISIONS[precision], **kw)
+    total = max(sum(ks), 1)
+    infos = (TaInfo * total)()
+    rc = lib.cta_solve_batched(plan.handle, nrhs, bp, xp, C.byref(opts), int(bool(minnorm)),
+                               infos, _stream())
+    _check(rc, "cta_solve_batched")
+    out_info, i = [], 0
+    for k in ks:
+        out_info.append([_info(infos[i + c]) for c in range(k)])
+        i += k
+    return [x.t() for x in xs], out_info

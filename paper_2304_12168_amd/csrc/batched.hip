@@ -1,0 +1,998 @@
+// Batched CTA: many independent solves -- systems s = 0..S-1, each with k_s
+// right-hand sides -- advanced in lockstep by one set of kernels.
+//
+// Layout.  The systems are concatenated into one block-diagonal CSR (and its
+// transpose, built on the device); vectors are row-major blocks of K columns
+// (K = the smallest power of two >= max k_s), so the nonzero a_ij of a row
+// multiplies the K contiguous entries of row j of the input block: one
+// gather per nonzero serves every right-hand side.  A group g = s * K + c is
+// one (system, right-hand side) solve with its own CTA state (phi, alpha,
+// iteration count, stop code); columns c >= k_s are inactive padding.
+//
+// Precision.  TA_FP64: products, vectors and reductions in FP64, every row
+// sum compensated and taken in storage order, so each group follows the
+// single-right-hand-side iteration exactly.  TA_FP32 / TA_BF16: the Krylov
+// chain uses FP32 or BF16 matrix values and FP32 vectors with FP32
+// accumulation; the Gram entries, the step alpha, the iterate (x or y) and
+// every true-residual check stay in FP64.  At the end of each chunk of
+// iterations the FP64 true residual b - A x replaces the recurrence
+// residual of every running group, so the low-precision products only slow
+// convergence; the stop test is always the FP64 true residual.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <type_traits>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "device_math.hpp"
+#include "host.hpp"
+
+namespace ta {
+namespace bt {
+
+constexpr int kMaxK = 64;  // right-hand sides per system
+constexpr int kPhiStride = 2 * kTMax + 2;
+
+enum Status : int32_t { kActive = 0, kCandidate = 1, kFinished = 2, kInactive = 3 };
+
+// rows [r0, r1) of the concatenated matrix, all in system `sys`
+struct BRange {
+    int32_t r0, r1, sys, pad;
+};
+
+// per-group state, structure of arrays over G = nsys * K groups
+struct Groups {
+    int32_t *status, *stop, *repl;
+    int64_t *k, *matvecs;
+    double *nb, *tol_nb, *tol_ne_nab, *rr, *phi, *alpha, *diag;
+    int32_t *flags;  // [0] every group finished, [1] some group waits for a check
+    const int32_t *ksys;   // right-hand sides in use per system
+    const int32_t *a_blk;  // per system: first block of the A-row table (nsys + 1)
+    const int32_t *t_blk;  // per system: first block of the A^T-row table (nsys + 1)
+    int32_t nsys, K, t;
+    int32_t minnorm, mixed;
+    int64_t max_iter;
+    double tol, tol_normal;
+};
+
+enum BGate : int32_t {
+    kBRun = 0,    // unless every group has finished
+    kBCheck = 1,  // only when some group waits for a true-residual check
+    kBFinal = 2,  // only when every group has finished
+    kBAlways = 3,
+};
+
+__device__ __forceinline__ bool bgate(int32_t gate, const Groups &gs) {
+    switch (gate) {
+        case kBRun: return !gs.flags[0];
+        case kBCheck: return gs.flags[1] != 0;
+        case kBFinal: return gs.flags[0] != 0;
+        default: return true;
+    }
+}
+
+__host__ __device__ inline uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ double ldv(const double *v, int64_t k) { return v[k]; }
+__device__ __forceinline__ float ldv(const float *v, int64_t k) { return v[k]; }
+__device__ __forceinline__ float ldv(const uint16_t *v, int64_t k) {
+    return __uint_as_float((uint32_t)v[k] << 16);
+}
+
+enum BEpi : int32_t { kBNorm = 0, kBResid = 1 };
+
+// ---------------------------------------------------------------------------
+// SpMM: Y = M X (or B - M X) over a block table of M's rows; lane c of a row
+// group works on column c.  Per block and column: partial sum of Y^2.
+// ---------------------------------------------------------------------------
+template <typename V, typename X, int K, int EPI>
+__global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const V *__restrict__ val,
+                                                   const X *__restrict__ x, X *y,
+                                                   const double *__restrict__ b,
+                                                   const BRange *__restrict__ blocks, Groups gs,
+                                                   double2 *partials, int64_t cap, int32_t slot,
+                                                   int32_t gate) {
+    if (!bgate(gate, gs)) return;
+    constexpr int R = 64 / K;  // rows per wave step
+    constexpr bool kF64 = sizeof(X) == 8;
+    const BRange br = blocks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane % K, rsub = lane / K;
+    const int g = br.sys * K + c;
+    // the iteration chain skips paused and finished groups; checks and
+    // diagnostics cover every column
+    const bool work = (gate != kBRun) || gs.status[g] == kActive;
+    Acc part = {0.0, 0.0};
+    if (work) {
+        for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
+            const int32_t e = rp[row + 1];
+            int32_t k = rp[row];
+            double yv;
+            if constexpr (kF64) {
+                Acc acc = {0.0, 0.0};
+                if constexpr (EPI == kBResid) acc.p = b[row * K + c];
+                constexpr double sgn = (EPI == kBResid) ? -1.0 : 1.0;
+                for (; k + 3 < e; k += 4) {
+                    const int32_t j0 = ci[k], j1 = ci[k + 1], j2 = ci[k + 2], j3 = ci[k + 3];
+                    const double a0 = ldv(val, k), a1 = ldv(val, k + 1), a2 = ldv(val, k + 2),
+                                 a3 = ldv(val, k + 3);
+                    const double x0 = x[(int64_t)j0 * K + c], x1 = x[(int64_t)j1 * K + c],
+                                 x2 = x[(int64_t)j2 * K + c], x3 = x[(int64_t)j3 * K + c];
+                    acc_fma(acc, sgn * a0, x0);
+                    acc_fma(acc, sgn * a1, x1);
+                    acc_fma(acc, sgn * a2, x2);
+                    acc_fma(acc, sgn * a3, x3);
+                }
+                for (; k < e; ++k) acc_fma(acc, sgn * ldv(val, k), x[(int64_t)ci[k] * K + c]);
+                yv = acc_val(acc);
+            } else {
+                float acc = 0.0f;
+                for (; k + 3 < e; k += 4) {
+                    const int32_t j0 = ci[k], j1 = ci[k + 1], j2 = ci[k + 2], j3 = ci[k + 3];
+                    const float a0 = ldv(val, k), a1 = ldv(val, k + 1), a2 = ldv(val, k + 2),
+                                a3 = ldv(val, k + 3);
+                    const float x0 = x[(int64_t)j0 * K + c], x1 = x[(int64_t)j1 * K + c],
+                                x2 = x[(int64_t)j2 * K + c], x3 = x[(int64_t)j3 * K + c];
+                    acc = fmaf(a0, x0, acc);
+                    acc = fmaf(a1, x1, acc);
+                    acc = fmaf(a2, x2, acc);
+                    acc = fmaf(a3, x3, acc);
+                }
+                for (; k < e; ++k) acc = fmaf(ldv(val, k), x[(int64_t)ci[k] * K + c], acc);
+                yv = (double)acc;
+            }
+            y[row * K + c] = (X)yv;
+            acc_fma(part, yv, yv);
+        }
+    }
+    // reduce over the rows of the block for each column
+#pragma unroll
+    for (int off = K; off < 64; off <<= 1) {
+        Acc o;
+        o.p = __shfl_xor(part.p, off);
+        o.s = __shfl_xor(part.s, off);
+        part = acc_merge(part, o);
+    }
+    __shared__ Acc red[kBlock / 64][K];
+    if (rsub == 0) red[wave][c] = part;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc a = red[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
+        partials[((int64_t)slot * K + threadIdx.x) * cap + blockIdx.x] = make_double2(a.p, a.s);
+    }
+}
+
+// Wave-level reduction of one slot over a block range, 8 loads in flight.
+__device__ double wave_slot_sum(const double2 *p, int32_t b0, int32_t b1) {
+    const int lane = threadIdx.x & 63;
+    Acc a = {0.0, 0.0};
+    for (int32_t base = b0 + lane; base < b1; base += 8 * 64) {
+        double2 d[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int32_t i = base + u * 64;
+            d[u] = i < b1 ? p[i] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (base + u * 64 < b1) a = acc_merge(a, Acc{d[u].x, d[u].y});
+    }
+    a = group_reduce<64>(a);
+    return acc_val(a);
+}
+
+__device__ __forceinline__ void group_loop_top(const Groups &gs, int g) {
+    if (sqrt(gs.rr[g]) <= gs.tol_nb[g]) {
+        gs.status[g] = kCandidate;
+    } else if (gs.k[g] >= gs.max_iter) {
+        gs.status[g] = kFinished;
+        gs.stop[g] = TA_STOP_MAXITER;
+    }
+}
+
+// Init: ||b||^2 per group (slot 0 of the A-row table) and, with has_nab,
+// ||A^T b||^2 (slot 1 of the A^T-row table).
+__global__ __launch_bounds__(kBlock) void k_bstep_init(Groups gs, const double2 *partials,
+                                                        int64_t cap, int32_t has_nab) {
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= gs.nsys * gs.K) return;
+    const int s = g / gs.K, c = g % gs.K;
+    const double bb = wave_slot_sum(partials + (int64_t)c * cap, gs.a_blk[s], gs.a_blk[s + 1]);
+    const double ab = has_nab ? wave_slot_sum(partials + ((int64_t)gs.K + c) * cap, gs.t_blk[s],
+                                              gs.t_blk[s + 1])
+                              : 0.0;
+    if ((threadIdx.x & 63) != 0) return;
+    gs.k[g] = 0;
+    gs.matvecs[g] = has_nab ? 1 : 0;
+    gs.repl[g] = 0;
+    gs.tol_ne_nab[g] = gs.tol_normal * sqrt(ab);
+    if (c >= gs.ksys[s]) {
+        gs.status[g] = kInactive;
+        gs.stop[g] = 0;
+        gs.nb[g] = 0.0;
+        return;
+    }
+    const double nb = sqrt(bb);
+    gs.nb[g] = nb;
+    gs.tol_nb[g] = gs.tol * nb;
+    gs.rr[g] = bb;
+    gs.status[g] = kActive;
+    gs.stop[g] = 0;
+    if (nb == 0.0) {
+        gs.status[g] = kFinished;
+        gs.stop[g] = TA_STOP_RESIDUAL;
+        return;
+    }
+    group_loop_top(gs, g);
+}
+
+// Gram step: one block per group; wave w reduces slots w, w + 4, ...
+// (even slots: A^T passes over the A^T-row table, odd: A passes).
+__global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 *partials,
+                                                        int64_t cap) {
+    if (gs.flags[0]) return;
+    const int g = blockIdx.x;
+    if (gs.status[g] != kActive) return;
+    const int s = g / gs.K, c = g % gs.K, t = gs.t;
+    const int wave = threadIdx.x >> 6;
+    __shared__ double phi[kPhiStride];
+    for (int q = wave; q < 2 * t; q += kBlock / 64) {
+        const int32_t *tab = (q % 2 == 0) ? gs.t_blk : gs.a_blk;
+        const double v = wave_slot_sum(partials + ((int64_t)q * gs.K + c) * cap, tab[s], tab[s + 1]);
+        if ((threadIdx.x & 63) == 0) phi[q + 1] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double *gp = gs.phi + (int64_t)g * kPhiStride;
+    for (int i = 1; i <= 2 * t; ++i) gp[i] = phi[i];
+    gs.matvecs[g] += 2 * t;
+    for (int i = 1; i <= 2 * t; ++i)
+        if (!isfinite(phi[i])) {
+            gs.status[g] = kFinished;
+            gs.stop[g] = TA_STOP_BREAKDOWN;
+            return;
+        }
+    if (sqrt(phi[1]) <= gs.tol_ne_nab[g] || phi[2] == 0.0) {
+        gs.status[g] = kFinished;
+        gs.stop[g] = TA_STOP_NORMAL;
+        return;
+    }
+    double a[kTMax];
+    gram_alpha(phi, t, a);
+    for (int i = 0; i < t; ++i)
+        if (!isfinite(a[i])) {
+            gs.status[g] = kFinished;
+            gs.stop[g] = TA_STOP_BREAKDOWN;
+            return;
+        }
+    for (int i = 0; i < kTMax; ++i) gs.alpha[(int64_t)g * kTMax + i] = i < t ? a[i] : 0.0;
+}
+
+struct BVecs {
+    void *p[kTMax + 1];
+};
+
+// R -= sum alpha_j U_{j+1}; y-form: Y += alpha_1 R_old + sum alpha_j U_j.
+// Over the A-row table; partial ||R||^2 per (block, column) in slot 0.
+template <typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
+                                                       const BRange *__restrict__ blocks,
+                                                       Groups gs, double2 *partials,
+                                                       int64_t cap) {
+    if (gs.flags[0]) return;
+    constexpr int R = 64 / K;
+    const BRange br = blocks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane % K, rsub = lane / K;
+    const int g = br.sys * K + c;
+    const int t = gs.t;
+    Acc part = {0.0, 0.0};
+    if (gs.status[g] == kActive) {
+        double al[kTMax];
+#pragma unroll
+        for (int j = 0; j < kTMax; ++j) al[j] = gs.alpha[(int64_t)g * kTMax + j];
+        for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
+            const int64_t e = row * K + c;
+            double ri = (double)r[e];
+            if (gs.minnorm) {
+                double yi = yv[e];
+                yi = __fma_rn(al[0], ri, yi);
+                for (int j = 1; j < t; ++j) yi = __fma_rn(al[j], (double)((const X *)U.p[j])[e], yi);
+                yv[e] = yi;
+            }
+            for (int j = 0; j < t; ++j) ri = __fma_rn(-al[j], (double)((const X *)U.p[j + 1])[e], ri);
+            const X rs = (X)ri;
+            r[e] = rs;
+            acc_fma(part, (double)rs, (double)rs);
+        }
+    }
+#pragma unroll
+    for (int off = K; off < 64; off <<= 1) {
+        Acc o;
+        o.p = __shfl_xor(part.p, off);
+        o.s = __shfl_xor(part.s, off);
+        part = acc_merge(part, o);
+    }
+    __shared__ Acc red[kBlock / 64][K];
+    if (rsub == 0) red[wave][c] = part;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc a = red[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
+        partials[(int64_t)threadIdx.x * cap + blockIdx.x] = make_double2(a.p, a.s);
+    }
+}
+
+// x-form: X += sum alpha_j W_{j-1}, over the A^T-row table.
+template <typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, double *xv,
+                                                       const BRange *__restrict__ blocks,
+                                                       Groups gs) {
+    if (gs.flags[0]) return;
+    constexpr int R = 64 / K;
+    const BRange br = blocks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane % K, rsub = lane / K;
+    const int g = br.sys * K + c;
+    if (gs.status[g] != kActive) return;
+    double al[kTMax];
+#pragma unroll
+    for (int j = 0; j < kTMax; ++j) al[j] = gs.alpha[(int64_t)g * kTMax + j];
+    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
+        const int64_t e = row * K + c;
+        double xi = xv[e];
+        for (int j = 0; j < gs.t; ++j) xi = __fma_rn(al[j], (double)((const X *)W.p[j])[e], xi);
+        xv[e] = xi;
+    }
+}
+
+// End of an iteration: ||r||^2 per group, k, loop-top tests.
+__global__ __launch_bounds__(kBlock) void k_bstep_end(Groups gs, const double2 *partials,
+                                                       int64_t cap) {
+    if (gs.flags[0]) return;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= gs.nsys * gs.K) return;
+    if (gs.status[g] != kActive) return;
+    const int s = g / gs.K, c = g % gs.K;
+    const double rr = wave_slot_sum(partials + (int64_t)c * cap, gs.a_blk[s], gs.a_blk[s + 1]);
+    if ((threadIdx.x & 63) != 0) return;
+    gs.rr[g] = rr;
+    gs.k[g] += 1;
+    group_loop_top(gs, g);
+}
+
+// True-residual check (slot 0 holds ||b - A x||^2 per group): a waiting
+// group stops or resumes from the true residual; in mixed precision every
+// running group resumes from it.
+__global__ __launch_bounds__(kBlock) void k_bstep_check(Groups gs, const double2 *partials,
+                                                         int64_t cap, int32_t products) {
+    if (!gs.flags[1]) return;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= gs.nsys * gs.K) return;
+    const int st = gs.status[g];
+    if (st != kCandidate && !(gs.mixed && st == kActive)) return;
+    const int s = g / gs.K, c = g % gs.K;
+    const double rr = wave_slot_sum(partials + (int64_t)c * cap, gs.a_blk[s], gs.a_blk[s + 1]);
+    if ((threadIdx.x & 63) != 0) return;
+    gs.matvecs[g] += products;
+    if (st == kCandidate && sqrt(rr) <= gs.tol_nb[g]) {
+        gs.status[g] = kFinished;
+        gs.stop[g] = TA_STOP_RESIDUAL;
+        gs.rr[g] = rr;
+        return;
+    }
+    gs.rr[g] = rr;
+    gs.repl[g] = 1;
+    gs.status[g] = kActive;
+    if (sqrt(rr) <= gs.tol_nb[g]) {  // a running (mixed) group already converged
+        gs.status[g] = kFinished;
+        gs.stop[g] = TA_STOP_RESIDUAL;
+        gs.repl[g] = 0;
+        return;
+    }
+    if (gs.k[g] >= gs.max_iter) {
+        gs.status[g] = kFinished;
+        gs.stop[g] = TA_STOP_MAXITER;
+    }
+}
+
+// R = true residual for the groups that resume from it.
+template <typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_breplace(const double *__restrict__ rt, X *r,
+                                                      const BRange *__restrict__ blocks,
+                                                      Groups gs) {
+    if (!gs.flags[1]) return;
+    constexpr int R = 64 / K;
+    const BRange br = blocks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane % K, rsub = lane / K;
+    const int g = br.sys * K + c;
+    if (!gs.repl[g]) return;
+    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R)
+        r[row * K + c] = (X)rt[row * K + c];
+}
+
+// Flags: [0] every group finished, [1] some group waits for a check.
+// Clears the replacement marks.
+__global__ __launch_bounds__(kBlock) void k_bsummary(Groups gs) {
+    __shared__ int any_open, any_wait;
+    if (threadIdx.x == 0) {
+        any_open = 0;
+        any_wait = 0;
+    }
+    __syncthreads();
+    const int G = gs.nsys * gs.K;
+    int open = 0, wait = 0;
+    for (int g = threadIdx.x; g < G; g += kBlock) {
+        const int st = gs.status[g];
+        open |= (st == kActive || st == kCandidate);
+        wait |= (st == kCandidate);
+        gs.repl[g] = 0;
+    }
+    if (open) any_open = 1;  // benign same-value stores
+    if (wait) any_wait = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // mixed precision: every chunk ends with a true-residual pass
+        gs.flags[1] = any_wait || (gs.mixed && any_open);
+        gs.flags[0] = !any_open;
+    }
+}
+
+// Exit diagnostics per group: slots 0, 1, 2 hold ||b - A x||^2 (A-row
+// table), ||A^T (b - A x)||^2 and ||A^T b||^2 (A^T-row table).
+__global__ __launch_bounds__(kBlock) void k_bstep_diag(Groups gs, const double2 *partials,
+                                                        int64_t cap) {
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= gs.nsys * gs.K) return;
+    const int s = g / gs.K, c = g % gs.K;
+    const double r2 = wave_slot_sum(partials + (int64_t)c * cap, gs.a_blk[s], gs.a_blk[s + 1]);
+    const double w2 = wave_slot_sum(partials + ((int64_t)gs.K + c) * cap, gs.t_blk[s], gs.t_blk[s + 1]);
+    const double v2 =
+        wave_slot_sum(partials + ((int64_t)2 * gs.K + c) * cap, gs.t_blk[s], gs.t_blk[s + 1]);
+    if ((threadIdx.x & 63) != 0) return;
+    const double nb = gs.nb[g];
+    gs.diag[(int64_t)g * 3 + 0] = nb > 0.0 ? sqrt(r2) / nb : 0.0;
+    const double nab = sqrt(v2);
+    gs.diag[(int64_t)g * 3 + 1] = (nb > 0.0 && nab > 0.0) ? sqrt(w2) / nab : 0.0;
+}
+
+// pack: Bc[i*K + c] = B_s[(i - ro_s) + c m_s] (column-major user blocks)
+__global__ void k_pack(int64_t M, int32_t K, const int64_t *__restrict__ ro, int32_t nsys,
+                       const int32_t *__restrict__ ksys, const double *const *__restrict__ src,
+                       double *dst) {
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M * K;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / K;
+        const int c = (int)(e % K);
+        int lo = 0, hi = nsys;  // system s with ro[s] <= i < ro[s+1]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (ro[mid] <= i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t ms = ro[lo + 1] - ro[lo];
+        dst[e] = c < ksys[lo] ? src[lo][(i - ro[lo]) + (int64_t)c * ms] : 0.0;
+    }
+}
+
+__global__ void k_unpack(int64_t N, int32_t K, const int64_t *__restrict__ co, int32_t nsys,
+                         const int32_t *__restrict__ ksys, const double *__restrict__ src,
+                         double *const *__restrict__ dst) {
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < N * K;
+         e += (int64_t)gridDim.x * kBlock) {
+        const int64_t i = e / K;
+        const int c = (int)(e % K);
+        int lo = 0, hi = nsys;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (co[mid] <= i)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const int64_t ns = co[lo + 1] - co[lo];
+        if (c < ksys[lo]) dst[lo][(i - co[lo]) + (int64_t)c * ns] = src[e];
+    }
+}
+
+// r = (X) b, ||b||^2 partials (slot 0 over the A-row table)
+template <typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_binit(const double *__restrict__ b, X *r,
+                                                   const BRange *__restrict__ blocks,
+                                                   double2 *partials, int64_t cap) {
+    constexpr int R = 64 / K;
+    const BRange br = blocks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane % K, rsub = lane / K;
+    Acc part = {0.0, 0.0};
+    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
+        const double v = b[row * K + c];
+        r[row * K + c] = (X)v;
+        acc_fma(part, v, v);
+    }
+#pragma unroll
+    for (int off = K; off < 64; off <<= 1) {
+        Acc o;
+        o.p = __shfl_xor(part.p, off);
+        o.s = __shfl_xor(part.s, off);
+        part = acc_merge(part, o);
+    }
+    __shared__ Acc red[kBlock / 64][K];
+    if (rsub == 0) red[wave][c] = part;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc a = red[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
+        partials[(int64_t)threadIdx.x * cap + blockIdx.x] = make_double2(a.p, a.s);
+    }
+}
+
+// low-precision copies of the values
+__global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *o) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        o[i] = (float)a[i];
+}
+__global__ void k_to_bf16(int64_t n, const double *__restrict__ a, uint16_t *o) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        o[i] = f32_to_bf16((float)a[i]);
+}
+
+// concatenation: copy system s's CSR into the block-diagonal matrix
+__global__ void k_concat(int64_t m, int64_t nnz, const int32_t *__restrict__ rp,
+                         const int32_t *__restrict__ ci, const double *__restrict__ val,
+                         int64_t row0, int64_t col0, int64_t k0, int32_t *crp, int32_t *cci,
+                         double *cval) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock)
+        crp[row0 + i] = (int32_t)(k0 + rp[i]);
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < nnz;
+         k += (int64_t)gridDim.x * kBlock) {
+        cci[k0 + k] = (int32_t)(col0 + ci[k]);
+        cval[k0 + k] = val[k];
+    }
+}
+
+// ===========================================================================
+// host side
+// ===========================================================================
+static inline int64_t cdivh(int64_t a, int64_t b) { return (a + b - 1) / b; }
+static inline unsigned grid_for(int64_t n) {
+    return (unsigned)std::min<int64_t>(std::max<int64_t>(cdivh(n, kBlock), 1), 4096);
+}
+
+struct BatchPlan {
+    int32_t nsys = 0, precision = TA_FP64;
+    int64_t M = 0, N = 0, nnz = 0;
+    std::vector<int64_t> ro, co;  // row / column offsets of the systems (nsys + 1)
+    int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr;
+    double *a_val = nullptr, *t_val = nullptr;
+    void *a_low = nullptr, *t_low = nullptr;
+    void *mem = nullptr;
+    hipStream_t s_mem = nullptr;
+};
+
+static void bplan_free(BatchPlan *P) {
+    if (P->mem != nullptr) (void)hipFreeAsync(P->mem, P->s_mem);
+    P->mem = nullptr;
+}
+
+static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStream_t s,
+                       BatchPlan *P) {
+    if (nsys < 1 || A == nullptr) return TA_EINVAL;
+    if (precision != TA_FP64 && precision != TA_FP32 && precision != TA_BF16) return TA_EINVAL;
+    P->nsys = nsys;
+    P->precision = precision;
+    P->ro.assign(nsys + 1, 0);
+    P->co.assign(nsys + 1, 0);
+    int64_t nnz = 0;
+    for (int32_t i = 0; i < nsys; ++i) {
+        int rc = validate_mat(&A[i]);
+        if (rc != TA_OK) return rc;
+        if (A[i].kind != TA_CSR) return TA_EINVAL;
+        P->ro[i + 1] = P->ro[i] + A[i].m;
+        P->co[i + 1] = P->co[i] + A[i].n;
+        nnz += A[i].nnz;
+    }
+    P->M = P->ro[nsys];
+    P->N = P->co[nsys];
+    P->nnz = nnz;
+    if (P->M >= INT32_MAX || P->N >= INT32_MAX || nnz >= INT32_MAX) return TA_ENOTSUP;
+    const int64_t M = P->M, N = P->N, mx = std::max(M, N);
+    Workspace own(s), tmp(s);
+    own.reserve(&P->a_rp, M + 1);
+    own.reserve(&P->a_ci, nnz);
+    own.reserve(&P->a_val, nnz);
+    own.reserve(&P->t_rp, N + 1);
+    own.reserve(&P->t_ci, nnz);
+    own.reserve(&P->t_val, nnz);
+    float *al32 = nullptr, *tl32 = nullptr;
+    uint16_t *al16 = nullptr, *tl16 = nullptr;
+    if (precision == TA_FP32) {
+        own.reserve(&al32, nnz);
+        own.reserve(&tl32, nnz);
+    } else if (precision == TA_BF16) {
+        own.reserve(&al16, nnz);
+        own.reserve(&tl16, nnz);
+    }
+    int32_t *flag = nullptr, *work = nullptr;
+    tmp.reserve(&flag, 8);
+    tmp.reserve(&work, 2 * mx + cdivh(std::max<int64_t>(mx, 1), 1024) + 8 + nnz);
+    int rc;
+    if ((rc = own.commit()) != TA_OK) return rc;
+    if ((rc = tmp.commit()) != TA_OK) return rc;
+    int64_t k0 = 0;
+    for (int32_t i = 0; i < nsys; ++i) {
+        if ((rc = check_csr_device(&A[i], flag, s)) != TA_OK) return rc;
+        const int64_t w = std::max<int64_t>(A[i].m, A[i].nnz);
+        if (w > 0)
+            k_concat<<<grid_for(w), kBlock, 0, s>>>(A[i].m, A[i].nnz, A[i].row_ptr, A[i].col_idx,
+                                                    A[i].val, P->ro[i], P->co[i], k0, P->a_rp,
+                                                    P->a_ci, P->a_val);
+        HIP_TRY(hipGetLastError());
+        k0 += A[i].nnz;
+    }
+    const int32_t total = (int32_t)nnz;
+    HIP_TRY(hipMemcpyAsync(P->a_rp + M, &total, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_transpose(M, N, nnz, P->a_rp, P->a_ci, P->a_val, P->t_rp, P->t_ci, P->t_val,
+                             work, flag, s));
+    if (precision == TA_FP32 && nnz > 0) {
+        k_to_f32<<<grid_for(nnz), kBlock, 0, s>>>(nnz, P->a_val, al32);
+        k_to_f32<<<grid_for(nnz), kBlock, 0, s>>>(nnz, P->t_val, tl32);
+        P->a_low = al32;
+        P->t_low = tl32;
+    } else if (precision == TA_BF16 && nnz > 0) {
+        k_to_bf16<<<grid_for(nnz), kBlock, 0, s>>>(nnz, P->a_val, al16);
+        k_to_bf16<<<grid_for(nnz), kBlock, 0, s>>>(nnz, P->t_val, tl16);
+        P->a_low = al16;
+        P->t_low = tl16;
+    }
+    HIP_TRY(hipGetLastError());
+    int32_t h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h) return TA_ENOTSUP;
+    P->mem = own.release();
+    P->s_mem = s;
+    return TA_OK;
+}
+
+// Block table over the rows of every system: at least four row steps per
+// block, at most 1024 blocks per system.
+static void make_blocks(const std::vector<int64_t> &off, int K, std::vector<BRange> &tab,
+                        std::vector<int32_t> &first) {
+    const int64_t step = 4 * (64 / K);
+    tab.clear();
+    first.assign(off.size(), 0);
+    for (size_t sidx = 0; sidx + 1 < off.size(); ++sidx) {
+        first[sidx] = (int32_t)tab.size();
+        const int64_t rows = off[sidx + 1] - off[sidx];
+        int64_t rb = std::max<int64_t>(4 * step, cdivh(rows, 1024));
+        rb = cdivh(rb, step) * step;
+        for (int64_t r0 = off[sidx]; r0 < off[sidx + 1]; r0 += rb)
+            tab.push_back(BRange{(int32_t)r0, (int32_t)std::min(r0 + rb, off[sidx + 1]),
+                                 (int32_t)sidx, 0});
+    }
+    first[off.size() - 1] = (int32_t)tab.size();
+}
+
+template <typename V, typename X, int K, int EPI>
+static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const void *x, void *y,
+                 const double *b, const BRange *tab, int32_t nblk, const Groups &gs,
+                 double2 *partials, int64_t cap, int32_t slot, int32_t gate, hipStream_t s) {
+    if (nblk <= 0) return;
+    k_bspmm<V, X, K, EPI><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y, b,
+                                                  tab, gs, partials, cap, slot, gate);
+}
+
+// The per-K, per-precision pieces of one solve.
+template <typename V, typename X, int K>
+struct Engine {
+    static int run(const BatchPlan &P, const int32_t *nrhs, const double *const *B,
+                   double *const *Xout, const ta_opts *o, int32_t minnorm, ta_info *info,
+                   hipStream_t s) {
+        const int32_t nsys = P.nsys, t = o->t;
+        const int64_t M = P.M, N = P.N, G = (int64_t)nsys * K;
+        const bool mixed = !std::is_same<V, double>::value;
+        const void *aval = mixed ? P.a_low : (const void *)P.a_val;
+        const void *tval = mixed ? P.t_low : (const void *)P.t_val;
+
+        std::vector<BRange> ta_tab, tt_tab;
+        std::vector<int32_t> a_first, t_first;
+        make_blocks(P.ro, K, ta_tab, a_first);
+        make_blocks(P.co, K, tt_tab, t_first);
+        const int32_t na = (int32_t)ta_tab.size(), nt = (int32_t)tt_tab.size();
+        const int64_t cap = std::max<int64_t>(std::max(na, nt), 1);
+        const int32_t nslots = std::max(2 * t, 3);
+
+        Workspace ws(s);
+        double *Bc = nullptr, *Y = nullptr, *Xc = nullptr, *RT = nullptr, *TN = nullptr;
+        X *R = nullptr;
+        X *U[kTMax + 1] = {}, *W[kTMax] = {};
+        double2 *partials = nullptr;
+        BRange *d_ta = nullptr, *d_tt = nullptr;
+        int32_t *d_afirst = nullptr, *d_tfirst = nullptr, *d_ksys = nullptr;
+        int64_t *d_ro = nullptr, *d_co = nullptr;
+        const double **d_B = nullptr;
+        double **d_X = nullptr;
+        Groups gs{};
+        ws.reserve(&Bc, M * K);
+        ws.reserve(&R, M * K);
+        for (int j = 1; j <= t; ++j) ws.reserve(&U[j], M * K);
+        for (int j = 0; j < (minnorm ? 1 : t); ++j) ws.reserve(&W[j], N * K);
+        if (minnorm) ws.reserve(&Y, M * K);
+        ws.reserve(&Xc, N * K);
+        ws.reserve(&RT, M * K);
+        ws.reserve(&TN, N * K);
+        ws.reserve(&partials, (int64_t)nslots * K * cap);
+        ws.reserve(&d_ta, std::max(na, 1));
+        ws.reserve(&d_tt, std::max(nt, 1));
+        ws.reserve(&d_afirst, nsys + 1);
+        ws.reserve(&d_tfirst, nsys + 1);
+        ws.reserve(&d_ksys, nsys);
+        ws.reserve(&d_ro, nsys + 1);
+        ws.reserve(&d_co, nsys + 1);
+        ws.reserve(&d_B, nsys);
+        ws.reserve(&d_X, nsys);
+        ws.reserve(&gs.status, G);
+        ws.reserve(&gs.stop, G);
+        ws.reserve(&gs.repl, G);
+        ws.reserve(&gs.k, G);
+        ws.reserve(&gs.matvecs, G);
+        ws.reserve(&gs.nb, G);
+        ws.reserve(&gs.tol_nb, G);
+        ws.reserve(&gs.tol_ne_nab, G);
+        ws.reserve(&gs.rr, G);
+        ws.reserve(&gs.phi, G * kPhiStride);
+        ws.reserve(&gs.alpha, G * kTMax);
+        ws.reserve(&gs.diag, G * 3);
+        ws.reserve(&gs.flags, 4);
+        int rc = ws.commit();
+        if (rc != TA_OK) return rc;
+
+        // host tables -> device (pageable copies complete before return)
+        std::vector<int32_t> ks(nsys);
+        for (int32_t i = 0; i < nsys; ++i) ks[i] = nrhs[i];
+        HIP_TRY(hipMemcpyAsync(d_ta, ta_tab.data(), sizeof(BRange) * na, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_tt, tt_tab.data(), sizeof(BRange) * nt, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_afirst, a_first.data(), sizeof(int32_t) * (nsys + 1),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_tfirst, t_first.data(), sizeof(int32_t) * (nsys + 1),
+                               hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_ksys, ks.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_ro, P.ro.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice,
+                               s));
+        HIP_TRY(hipMemcpyAsync(d_co, P.co.data(), sizeof(int64_t) * (nsys + 1), hipMemcpyHostToDevice,
+                               s));
+        HIP_TRY(hipMemcpyAsync(d_B, B, sizeof(double *) * nsys, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(d_X, Xout, sizeof(double *) * nsys, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemsetAsync(gs.flags, 0, sizeof(int32_t) * 4, s));
+        HIP_TRY(hipMemsetAsync(Xc, 0, sizeof(double) * (size_t)(N * K), s));
+        if (minnorm) HIP_TRY(hipMemsetAsync(Y, 0, sizeof(double) * (size_t)(M * K), s));
+        gs.ksys = d_ksys;
+        gs.a_blk = d_afirst;
+        gs.t_blk = d_tfirst;
+        gs.nsys = nsys;
+        gs.K = K;
+        gs.t = t;
+        gs.minnorm = minnorm;
+        gs.mixed = mixed;
+        gs.max_iter = o->max_iter;
+        gs.tol = o->tol;
+        gs.tol_normal = o->tol_normal;
+        const unsigned gw = (unsigned)cdivh(G, 4);  // one wave per group
+
+        // initial state
+        if (M * K > 0)
+            k_pack<<<grid_for(M * K), kBlock, 0, s>>>(M, K, d_ro, nsys, d_ksys, d_B, Bc);
+        if (na > 0) k_binit<X, K><<<na, kBlock, 0, s>>>(Bc, R, d_ta, partials, cap);
+        const bool has_nab = o->tol_normal > 0.0;
+        if (has_nab)
+            spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt, gs,
+                                            partials, cap, 1, kBAlways, s);
+        k_bstep_init<<<gw, kBlock, 0, s>>>(gs, partials, cap, has_nab ? 1 : 0);
+        k_bsummary<<<1, kBlock, 0, s>>>(gs);
+        HIP_TRY(hipGetLastError());
+
+        auto iteration = [&]() {
+            for (int j = 0; j < t; ++j) {
+                const void *uj = j == 0 ? (const void *)R : (const void *)U[j];
+                X *wj = W[minnorm ? 0 : j];
+                spmm<V, X, K, kBNorm>(P.t_rp, P.t_ci, tval, uj, wj, nullptr, d_tt, nt, gs, partials,
+                                      cap, 2 * j, kBRun, s);
+                spmm<V, X, K, kBNorm>(P.a_rp, P.a_ci, aval, wj, U[j + 1], nullptr, d_ta, na, gs,
+                                      partials, cap, 2 * j + 1, kBRun, s);
+            }
+            k_bstep_gram<<<(unsigned)G, kBlock, 0, s>>>(gs, partials, cap);
+            BVecs uv{};
+            uv.p[0] = R;
+            for (int j = 1; j <= t; ++j) uv.p[j] = U[j];
+            if (na > 0) k_bupdate_r<X, K><<<na, kBlock, 0, s>>>(uv, R, Y, d_ta, gs, partials, cap);
+            if (!minnorm && nt > 0) {
+                BVecs wv{};
+                for (int j = 0; j < t; ++j) wv.p[j] = W[j];
+                k_bupdate_x<X, K><<<nt, kBlock, 0, s>>>(wv, Xc, d_tt, gs);
+            }
+            k_bstep_end<<<gw, kBlock, 0, s>>>(gs, partials, cap);
+            k_bsummary<<<1, kBlock, 0, s>>>(gs);
+        };
+        const int32_t products = minnorm ? 2 : 1;
+        auto tail = [&]() {
+            // true-residual check for waiting groups (every running group when mixed)
+            if (minnorm)
+                spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Y, Xc, nullptr, d_tt, nt, gs,
+                                                partials, cap, 1, kBCheck, s);
+            spmm<double, double, K, kBResid>(P.a_rp, P.a_ci, P.a_val, Xc, RT, Bc, d_ta, na, gs,
+                                             partials, cap, 0, kBCheck, s);
+            k_bstep_check<<<gw, kBlock, 0, s>>>(gs, partials, cap, products);
+            if (na > 0) k_breplace<X, K><<<na, kBlock, 0, s>>>(RT, R, d_ta, gs);
+            k_bsummary<<<1, kBlock, 0, s>>>(gs);
+            // exit diagnostics once every group has finished
+            if (minnorm)
+                spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Y, Xc, nullptr, d_tt, nt, gs,
+                                                partials, cap, 1, kBFinal, s);
+            spmm<double, double, K, kBResid>(P.a_rp, P.a_ci, P.a_val, Xc, RT, Bc, d_ta, na, gs,
+                                             partials, cap, 0, kBFinal, s);
+            spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, RT, TN, nullptr, d_tt, nt, gs,
+                                            partials, cap, 1, kBFinal, s);
+            spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt, gs,
+                                            partials, cap, 2, kBFinal, s);
+        };
+
+        int32_t hflags[4] = {0, 0, 0, 0};
+        int64_t chunk = o->chunk > 0 ? o->chunk : 4;
+        const int64_t chunk_cap = o->chunk > 0 ? o->chunk : (mixed ? 8 : 64);
+        std::vector<int64_t> kh(G), kh_prev(G, -1);
+        for (;;) {
+            for (int64_t i = 0; i < chunk; ++i) iteration();
+            tail();
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipMemcpyAsync(hflags, gs.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (hflags[0]) break;
+            // progress: some group's k or product count moved
+            HIP_TRY(hipMemcpyAsync(kh.data(), gs.matvecs, sizeof(int64_t) * G, hipMemcpyDeviceToHost,
+                                   s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (kh == kh_prev) {
+                hip_msg() = "batched iteration made no progress";
+                return TA_EHIP;
+            }
+            kh_prev = kh;
+            chunk = std::min(chunk_cap, chunk * 2);
+        }
+        k_bstep_diag<<<gw, kBlock, 0, s>>>(gs, partials, cap);
+        if (N * K > 0)
+            k_unpack<<<grid_for(N * K), kBlock, 0, s>>>(N, K, d_co, nsys, d_ksys, Xc, d_X);
+        HIP_TRY(hipGetLastError());
+
+        // per-group results to the host
+        std::vector<int32_t> hst(G), hstop(G);
+        std::vector<int64_t> hk(G), hmv(G);
+        std::vector<double> hdiag(G * 3);
+        HIP_TRY(hipMemcpyAsync(hst.data(), gs.status, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hstop.data(), gs.stop, sizeof(int32_t) * G, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hk.data(), gs.k, sizeof(int64_t) * G, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hmv.data(), gs.matvecs, sizeof(int64_t) * G, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(hdiag.data(), gs.diag, sizeof(double) * G * 3, hipMemcpyDeviceToHost,
+                               s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int64_t out = 0;
+        for (int32_t sy = 0; sy < nsys; ++sy)
+            for (int32_t c = 0; c < nrhs[sy]; ++c) {
+                const int64_t g = (int64_t)sy * K + c;
+                ta_info &inf = info[out++];
+                memset(&inf, 0, sizeof inf);
+                inf.iters = hk[g];
+                inf.matvecs = hmv[g];
+                inf.stop = hstop[g];
+                inf.rel_res = hdiag[g * 3 + 0];
+                inf.rel_normal = hdiag[g * 3 + 1];
+            }
+        return TA_OK;
+    }
+};
+
+template <typename V, typename X>
+static int run_k(int K, const BatchPlan &P, const int32_t *nrhs, const double *const *B,
+                 double *const *Xo, const ta_opts *o, int32_t minnorm, ta_info *info,
+                 hipStream_t s) {
+    switch (K) {
+        case 1: return Engine<V, X, 1>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+        case 2: return Engine<V, X, 2>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+        case 4: return Engine<V, X, 4>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+        case 8: return Engine<V, X, 8>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+        case 16: return Engine<V, X, 16>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+        case 32: return Engine<V, X, 32>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+        default: return Engine<V, X, 64>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+    }
+}
+
+static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *const *B,
+                         double *const *Xo, const ta_opts *o, int32_t minnorm, ta_info *info,
+                         hipStream_t s) {
+    if (nrhs == nullptr || B == nullptr || Xo == nullptr || o == nullptr || info == nullptr)
+        return TA_EINVAL;
+    if (!(o->tol >= 0.0 && o->tol < 1.0) || !(o->tol_normal >= 0.0 && o->tol_normal < 1.0))
+        return TA_EINVAL;
+    if (o->t < 1 || o->t > kTMax || o->max_iter < 0 || o->chunk < 0) return TA_EINVAL;
+    if (minnorm && o->warm_start) return TA_EINVAL;
+    if (o->precision != TA_FP64 && o->precision != P.precision) return TA_EINVAL;
+    int32_t kmax = 0;
+    for (int32_t i = 0; i < P.nsys; ++i) {
+        if (nrhs[i] < 0 || nrhs[i] > kMaxK) return TA_EINVAL;
+        const int64_t m = P.ro[i + 1] - P.ro[i];
+        if (m > 0 && o->t > m) return TA_EINVAL;
+        if (nrhs[i] > 0 && ((m > 0 && B[i] == nullptr) ||
+                            (P.co[i + 1] - P.co[i] > 0 && Xo[i] == nullptr)))
+            return TA_EINVAL;
+        kmax = std::max(kmax, nrhs[i]);
+    }
+    if (kmax == 0) return TA_OK;
+    int K = 1;
+    while (K < kmax) K <<= 1;
+    switch (o->precision) {
+        case TA_FP32: return run_k<float, float>(K, P, nrhs, B, Xo, o, minnorm, info, s);
+        case TA_BF16: return run_k<uint16_t, float>(K, P, nrhs, B, Xo, o, minnorm, info, s);
+        default: return run_k<double, double>(K, P, nrhs, B, Xo, o, minnorm, info, s);
+    }
+}
+
+}  // namespace bt
+}  // namespace ta
+
+struct ta_batch_plan {
+    ta::bt::BatchPlan p;
+};
+
+extern "C" {
+
+int ta_batch_plan_create(int32_t nsys, const ta_mat *A, int32_t precision, ta_batch_plan **plan,
+                         void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    *plan = nullptr;
+    ta_batch_plan *p = new (std::nothrow) ta_batch_plan;
+    if (p == nullptr) return TA_ENOMEM;
+    const int rc = ta::bt::bplan_build(nsys, A, precision, (hipStream_t)stream, &p->p);
+    if (rc != TA_OK) {
+        ta::bt::bplan_free(&p->p);
+        delete p;
+        return rc;
+    }
+    *plan = p;
+    return TA_OK;
+}
+
+int ta_batch_plan_destroy(ta_batch_plan *plan) {
+    if (plan == nullptr) return TA_OK;
+    ta::bt::bplan_free(&plan->p);
+    delete plan;
+    return TA_OK;
+}
+
+int cta_solve_batched(const ta_batch_plan *plan, const int32_t *nrhs, const double *const *B,
+                      double *const *X, const ta_opts *opts, int32_t minnorm, ta_info *info,
+                      void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    return ta::bt::solve_batched(plan->p, nrhs, B, X, opts, minnorm ? 1 : 0, info,
+                                 (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+// Device helpers shared by the kernels of libta: compensated (double-double)
+// accumulation, wave-level reductions, XCD-aware block mapping and the
+// solution of CTA's auxiliary equation.
+#pragma once
+
+#include <math.h>
+
+#include "common.hpp"
+
+namespace ta {
+
+// ---------------------------------------------------------------------------
+// compensated accumulation
+// ---------------------------------------------------------------------------
+struct Acc {
+    double p, s;  // value p + s
+};
+
+__device__ __forceinline__ void two_sum(double a, double b, double &x, double &y) {
+    x = a + b;
+    const double z = x - a;
+    y = (a - (x - z)) + (b - z);
+}
+
+// acc += h + r where h + r is an exact product split (h = fl(a b), r = error)
+__device__ __forceinline__ void acc_add_split(Acc &c, double h, double r) {
+    double q;
+    two_sum(c.p, h, c.p, q);
+    c.s = c.s + (q + r);
+}
+
+__device__ __forceinline__ void acc_fma(Acc &c, double a, double b) {
+    const double h = a * b;
+    const double r = __fma_rn(a, b, -h);
+    acc_add_split(c, h, r);
+}
+
+__device__ __forceinline__ Acc acc_merge(Acc a, Acc b) {
+    Acc o;
+    double q;
+    two_sum(a.p, b.p, o.p, q);
+    o.s = (a.s + b.s) + q;
+    return o;
+}
+
+__device__ __forceinline__ double acc_val(Acc a) { return a.p + a.s; }
+
+template <int W>
+__device__ __forceinline__ Acc group_reduce(Acc v) {
+#pragma unroll
+    for (int off = W / 2; off > 0; off >>= 1) {
+        Acc o;
+        o.p = __shfl_xor(v.p, off);
+        o.s = __shfl_xor(v.s, off);
+        v = acc_merge(v, o);
+    }
+    return v;
+}
+
+// Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous
+// range of logical blocks so neighbouring rows share one L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t q = G / 8, rem = G % 8;
+    const int64_t x = b % 8, i = b / 8;
+    return x * q + (x < rem ? x : rem) + i;
+}
+
+// ---------------------------------------------------------------------------
+// The auxiliary equation of CTA (section 3.1, eq. "eqcoeff"), one thread.
+// M_ij = phi_{i+j}, g_i = phi_i (i, j = 1..t).  Reading of "minimum-norm
+// solution when not unique": ridge solution of an exactly (power-of-two)
+// scaled system, continuous in phi.  Steps:
+//   order te: t, lowered to i-1 at the first phi_{2i} <= 0;
+//   te = 1: alpha_1 = phi_1 / phi_2 (Example 1);
+//   else s_i = 2^-floor((e_i - 1)/2) with phi_{2i} = f 2^e_i, f in [0.5, 1);
+//        Ms_ij = (phi_{i+j} s_i) s_j, gs_i = phi_i s_i,
+//        Ms_ii = fma(Ms_ii, 16 te^2 2^-53, Ms_ii);
+//        Cholesky column by column, te lowered to j at a pivot <= 0
+//        (te = 1 then uses the closed form);
+//        forward / back substitution; alpha_i = s_i alpha~_i.
+// ---------------------------------------------------------------------------
+// Instantiated per order T with every loop unrolled, so the matrices live in
+// registers of the one thread that runs it (te only shrinks, guarded).
+template <int T>
+__device__ int gram_alpha_t(const double *phi, double *alpha) {
+    double s[T], g[T], z[T], at[T];
+    double L[T][T];  // scaled matrix, overwritten by its Cholesky factor (lower part)
+    int te = T;
+#pragma unroll
+    for (int i = 0; i < T; ++i) alpha[i] = 0.0;
+#pragma unroll
+    for (int i = 1; i <= T; ++i) {
+        if (te == T && !(phi[2 * i] > 0.0)) te = i - 1;
+    }
+    if (te <= 0) return 0;
+    if (te >= 2) {
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            int e = 0;
+            (void)frexp(phi[2 * (i + 1)], &e);
+            const int kk = (int)floor((e - 1) / 2.0);
+            s[i] = ldexp(1.0, -kk);
+        }
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+#pragma unroll
+            for (int j = 0; j <= i; ++j) L[i][j] = (phi[i + j + 2] * s[i]) * s[j];
+            g[i] = phi[i + 1] * s[i];
+        }
+        const double ridge = 16.0 * (double)te * (double)te * ldexp(1.0, -53);
+#pragma unroll
+        for (int i = 0; i < T; ++i) L[i][i] = __fma_rn(L[i][i], ridge, L[i][i]);
+        // Cholesky, column by column; unused columns (j >= te) are skipped
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            if (j < te) {
+                double d = L[j][j];
+#pragma unroll
+                for (int k = 0; k < j; ++k) d = __fma_rn(-L[j][k], L[j][k], d);
+                if (!(d > 0.0)) {
+                    te = j;
+                } else {
+                    L[j][j] = sqrt(d);
+#pragma unroll
+                    for (int i = j + 1; i < T; ++i) {
+                        if (i < te) {
+                            double v = L[i][j];
+#pragma unroll
+                            for (int k = 0; k < j; ++k) v = __fma_rn(-L[i][k], L[j][k], v);
+                            L[i][j] = v / L[j][j];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (te == 1) {
+        alpha[0] = phi[1] / phi[2];
+        return 1;
+    }
+#pragma unroll
+    for (int i = 0; i < T; ++i) {
+        if (i < te) {
+            double v = g[i];
+#pragma unroll
+            for (int k = 0; k < i; ++k) v = __fma_rn(-L[i][k], z[k], v);
+            z[i] = v / L[i][i];
+        }
+    }
+#pragma unroll
+    for (int i = T - 1; i >= 0; --i) {
+        if (i < te) {
+            double v = z[i];
+#pragma unroll
+            for (int k = i + 1; k < T; ++k)
+                if (k < te) v = __fma_rn(-L[k][i], at[k], v);
+            at[i] = v / L[i][i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+        if (i < te) alpha[i] = s[i] * at[i];
+    return te;
+}
+
+__device__ inline int gram_alpha(const double *phi, int t, double *alpha) {
+    switch (t) {
+        case 1: return gram_alpha_t<1>(phi, alpha);
+        case 2: return gram_alpha_t<2>(phi, alpha);
+        case 3: return gram_alpha_t<3>(phi, alpha);
+        case 4: return gram_alpha_t<4>(phi, alpha);
+        case 5: return gram_alpha_t<5>(phi, alpha);
+        case 6: return gram_alpha_t<6>(phi, alpha);
+        case 7: return gram_alpha_t<7>(phi, alpha);
+        default: return gram_alpha_t<8>(phi, alpha);
+    }
+}
+
+}  // namespace ta

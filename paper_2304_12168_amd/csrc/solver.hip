@@ -17,74 +17,9 @@
 #include <vector>
 
 #include "common.hpp"
+#include "host.hpp"
 
 namespace ta {
-
-static thread_local std::string g_hip_msg;
-
-static int hip_fail(hipError_t e, const char *what) {
-    char buf[256];
-    snprintf(buf, sizeof buf, "%s: %s", what, hipGetErrorString(e));
-    g_hip_msg = buf;
-    return e == hipErrorOutOfMemory ? TA_ENOMEM : TA_EHIP;
-}
-
-#define HIP_TRY(call)                                   \
-    do {                                                \
-        hipError_t e_ = (call);                         \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
-
-// ---------------------------------------------------------------------------
-// workspace: one stream-ordered allocation carved into aligned pieces
-// ---------------------------------------------------------------------------
-class Workspace {
-   public:
-    explicit Workspace(hipStream_t s) : s_(s) {}
-    ~Workspace() {
-        if (base_ != nullptr) (void)hipFreeAsync(base_, s_);
-    }
-    template <class T>
-    void reserve(T **slot, int64_t count) {
-        reqs_.push_back({reinterpret_cast<void **>(slot), (size_t)std::max<int64_t>(count, 1) * sizeof(T)});
-    }
-    int commit() {
-        size_t total = 0;
-        for (auto &r : reqs_) total += (r.bytes + 255) & ~size_t(255);
-        static thread_local bool pool_set = false;
-        if (!pool_set) {
-            int dev = 0;
-            hipMemPool_t pool;
-            if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-                uint64_t thr = UINT64_MAX;
-                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-            }
-            pool_set = true;
-        }
-        HIP_TRY(hipMallocAsync(&base_, total, s_));
-        char *p = static_cast<char *>(base_);
-        for (auto &r : reqs_) {
-            *r.slot = p;
-            p += (r.bytes + 255) & ~size_t(255);
-        }
-        return TA_OK;
-    }
-    // hand the allocation to the caller (it is not freed by the destructor)
-    void *release() {
-        void *b = base_;
-        base_ = nullptr;
-        return b;
-    }
-
-   private:
-    struct Req {
-        void **slot;
-        size_t bytes;
-    };
-    hipStream_t s_;
-    void *base_ = nullptr;
-    std::vector<Req> reqs_;
-};
 
 // pinned host copy of the State, one per host thread
 static State *host_state() {
@@ -107,21 +42,6 @@ static int read_state(State *d, State &out, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // validation
 // ---------------------------------------------------------------------------
-static int validate_mat(const ta_mat *A) {
-    if (A == nullptr) return TA_EINVAL;
-    if (A->m < 0 || A->n < 0 || A->m >= INT32_MAX || A->n >= INT32_MAX) return TA_EINVAL;
-    if (A->kind == TA_CSR) {
-        if (A->row_ptr == nullptr || A->nnz < 0 || A->nnz >= INT32_MAX) return TA_EINVAL;
-        if (A->nnz > 0 && (A->col_idx == nullptr || A->val == nullptr)) return TA_EINVAL;
-        return TA_OK;
-    }
-    if (A->kind == TA_DENSE_ROWMAJOR) {
-        if (A->ld < A->n || (A->m > 0 && A->n > 0 && A->val == nullptr)) return TA_EINVAL;
-        return TA_OK;
-    }
-    return TA_EINVAL;
-}
-
 static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (o == nullptr) return TA_EINVAL;
     if (!(o->tol >= 0.0 && o->tol < 1.0)) return TA_EINVAL;
@@ -139,35 +59,6 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
         return TA_EINVAL;
     }
     return TA_OK;
-}
-
-__global__ void k_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
-                            const int32_t *ci, int32_t *flag) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= m;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t a = rp[i];
-        if (i == 0 && a != 0) atomicOr(flag, 1);
-        if (i == m && a != nnz) atomicOr(flag, 1);
-        if (i < m && rp[i + 1] < a) atomicOr(flag, 1);
-    }
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t c = ci[k];
-        if (c < 0 || c >= n) atomicOr(flag, 2);
-    }
-}
-
-// Checks the CSR arrays on the device before any kernel indexes through them.
-static int check_csr_device(const ta_mat *A, int32_t *dflag, hipStream_t s) {
-    HIP_TRY(hipMemsetAsync(dflag, 0, sizeof(int32_t), s));
-    const int64_t work = std::max<int64_t>(A->m + 1, A->nnz);
-    const unsigned grid = (unsigned)std::min<int64_t>((work + kBlock - 1) / kBlock, 4096);
-    k_check_csr<<<grid, kBlock, 0, s>>>(A->m, A->n, A->nnz, A->row_ptr, A->col_idx, dflag);
-    HIP_TRY(hipGetLastError());
-    int32_t h = 0;
-    HIP_TRY(hipMemcpyAsync(&h, dflag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    return h ? TA_EINVAL : TA_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -550,7 +441,7 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         if (h.done && h.stop != kStopCandidate) break;
         // every chunk advances k or checks a candidate until the solve stops
         if (h.k + h.matvecs == progress) {
-            g_hip_msg = "iteration chain made no progress";
+            hip_msg() = "iteration chain made no progress";
             return TA_EHIP;
         }
         progress = h.k + h.matvecs;
@@ -635,7 +526,7 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
         if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
         if (h.done && h.stop != kStopCandidate) break;
         if (h.k + h.matvecs == progress) {
-            g_hip_msg = "iteration chain made no progress";
+            hip_msg() = "iteration chain made no progress";
             return TA_EHIP;
         }
         progress = h.k + h.matvecs;
@@ -815,7 +706,7 @@ const char *ta_strerror(int code) {
         case TA_OK: return "ok";
         case TA_EINVAL: return "invalid argument";
         case TA_ENOMEM: return "device allocation failed";
-        case TA_EHIP: return ta::g_hip_msg.empty() ? "HIP error" : ta::g_hip_msg.c_str();
+        case TA_EHIP: return ta::hip_msg().empty() ? "HIP error" : ta::hip_msg().c_str();
         case TA_ENOTSUP: return "input not supported (a column of A holds more than 8192 entries)";
         default: return "unknown error";
     }

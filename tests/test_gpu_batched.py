@@ -1,0 +1,120 @@
+"""Batched CTA (many systems x many right-hand sides, one set of kernels)
+through the C ABI, against the FP64 CPU oracle run column by column.
+
+FP64: every (system, column) must follow its own single-right-hand-side
+oracle run exactly -- same stop code, iteration count and product count,
+x within 1e-10 relative.  FP32 / BF16 products with FP64 refinement: every
+column must stop on the FP64 true residual at the tolerance, and x must agree
+with the FP64 oracle's x to the accuracy that residual allows.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2304_12168_amd as P
+from workloads import (convection_diffusion, dense_gaussian, csr_from_dense, kac_clement,
+                       lp_shaped, poisson5, random_diag_dominant)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.load_library()
+    oracle.build(force=False)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _systems():
+    g = np.random.default_rng(21)
+    A = [kac_clement(101).A, convection_diffusion(8).A, lp_shaped(150, 3000, seed=2).A,
+         random_diag_dominant(700, 7, seed=4), csr_from_dense(g.standard_normal((30, 20)))]
+    ks = [3, 1, 5, 2, 4]
+    B = []
+    for a, k in zip(A, ks):
+        xs = g.standard_normal((a.n, k))
+        B.append(a.to_scipy() @ xs)
+    # an inconsistent right-hand side for the tall dense system
+    B[4][:, 1] = g.standard_normal(30)
+    return A, B, ks
+
+
+@pytest.mark.parametrize("minnorm", [False, True], ids=["x_form", "y_form"])
+def test_fp64_batched_matches_oracle_per_column(minnorm):
+    A, B, ks = _systems()
+    plan = P.BatchPlan(A, "fp64")
+    tol, t, budget = 1e-9, 3, 20000
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=budget, minnorm=minnorm,
+                                   tol_normal=1e-12)
+    run = oracle.cta_minnorm if minnorm else oracle.cta
+    for s, (a, b) in enumerate(zip(A, B)):
+        xg = host(X[s])
+        for c in range(ks[s]):
+            xo, ho, io = run(a, b[:, c], tol=tol, t=t, max_iter=budget, tol_normal=1e-12)
+            ig = infos[s][c]
+            assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), (s, c, ig, io)
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-10 * max(np.linalg.norm(xo), 1e-300)
+            assert ig.rel_res == pytest.approx(io.rel_res, rel=1e-8, abs=1e-300)
+    plan.close()
+
+
+def test_fp64_batched_budget_and_empty_columns():
+    A = [kac_clement(51).A, poisson5(6), kac_clement(21).A]
+    g = np.random.default_rng(3)
+    B = [g.standard_normal((51, 2)), np.zeros((36, 0)), g.standard_normal((21, 3))]
+    B[2][:, 1] = 0.0  # b = 0 column
+    plan = P.BatchPlan(A, "fp64")
+    X, infos = P.cta_solve_batched(plan, B, tol=1e-14, t=2, max_iter=7)
+    assert len(infos[1]) == 0
+    for s, c in [(0, 0), (0, 1), (2, 0), (2, 2)]:
+        xo, ho, io = oracle.cta(A[s], B[s][:, c], tol=1e-14, t=2, max_iter=7)
+        assert infos[s][c].stop == io.stop == "maxiter" and infos[s][c].iters == 7
+        np.testing.assert_allclose(host(X[s])[:, c], xo, rtol=1e-10, atol=1e-12)
+    assert infos[2][1].stop == "residual" and infos[2][1].iters == 0
+    assert not host(X[2])[:, 1].any()
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("minnorm", [False, True], ids=["x_form", "y_form"])
+def test_mixed_precision_reaches_fp64_tolerance(prec, minnorm):
+    p = lp_shaped(1500, 60000, seed=7)
+    g = np.random.default_rng(5)
+    k = 8
+    xs = g.standard_normal((p.A.n, k))
+    Bm = p.A.to_scipy() @ xs
+    plan = P.BatchPlan([p.A], prec)
+    tol = 1e-8
+    X, infos = P.cta_solve_batched(plan, [Bm], tol=tol, t=3, max_iter=2000, minnorm=minnorm,
+                                   precision=prec)
+    xg = host(X[0])
+    run = oracle.cta_minnorm if minnorm else oracle.cta
+    for c in range(k):
+        ig = infos[0][c]
+        assert ig.stop == "residual" and ig.rel_res <= tol, (c, ig)
+        # the FP64 true residual of x itself
+        r = Bm[:, c] - p.A.to_scipy() @ xg[:, c]
+        assert np.linalg.norm(r) <= tol * np.linalg.norm(Bm[:, c]) * (1 + 1e-6)
+        if minnorm:
+            xo, _, io = run(p.A, Bm[:, c], tol=tol, t=3, max_iter=2000)
+            # both are within tol of the minimum-norm solution's residual;
+            # on range(A^T) the map is well conditioned here
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-6 * np.linalg.norm(xo)
+    plan.close()
+
+
+def test_batched_deterministic():
+    A, B, ks = _systems()
+    plan = P.BatchPlan(A, "fp32")
+    X1, i1 = P.cta_solve_batched(plan, B, tol=1e-8, t=3, max_iter=5000, precision="fp32")
+    X2, i2 = P.cta_solve_batched(plan, B, tol=1e-8, t=3, max_iter=5000, precision="fp32")
+    for a, b in zip(X1, X2):
+        assert torch.equal(a, b)
+    assert i1 == i2
+    plan.close()
