@@ -215,6 +215,17 @@ int cta_solve_batched(const ta_batch_plan *plan, const int32_t *nrhs, const doub
                       void *stream);
 
 /*
+ * ta_batch_time_spmm - measurement hook: average milliseconds of one launch
+ * of the SpMM kernel that a batched solve with K (1, 2, 4, ..., 64) columns
+ * and the given precision runs on the plan's A (trans = 0) or A^T (trans = 1),
+ * with its fused per-column ||y||^2 partial sums, over `reps` >= 1
+ * back-to-back launches timed with HIP events on `stream` (input block
+ * zero-filled).  Synchronises `stream`.
+ */
+int ta_batch_time_spmm(const ta_batch_plan *plan, int32_t K, int32_t trans, int32_t precision,
+                       int32_t reps, double *avg_ms, void *stream);
+
+/*
  * ta_validate - host-side argument checks only (shapes, pointers, options);
  * it reads no device memory and launches nothing, so it runs without a GPU.
  * `solver` is 0 for cta_solve, 1 for cta_minnorm, 2 for ta_solve.

@@ -31,7 +31,8 @@ ERRORS = {-1: "TA_EINVAL", -2: "TA_ENOMEM", -3: "TA_EHIP", -4: "TA_ENOTSUP"}
 EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror", "ta_spmv",
            "ta_residual", "ta_transpose", "ta_time_matvec", "ta_plan_create", "ta_plan_destroy",
            "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
-           "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched")
+           "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched",
+           "ta_batch_time_spmm")
 
 
 class TaMat(C.Structure):
@@ -85,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         lib.ta_batch_plan_create.argtypes = [I32, P, I32, C.POINTER(C.c_void_p), P]
         lib.ta_batch_plan_destroy.restype = C.c_int
         lib.ta_batch_plan_destroy.argtypes = [P]
+        lib.ta_batch_time_spmm.restype = C.c_int
+        lib.ta_batch_time_spmm.argtypes = [P, I32, I32, I32, I32, C.POINTER(C.c_double), P]
         lib.cta_solve_batched.restype = C.c_int
         lib.cta_solve_batched.argtypes = [P, P, P, P, OP, I32, P, P]
         lib.ta_spmv_plan.restype = C.c_int
@@ -455,3 +458,14 @@ def cta_solve_batched(plan: BatchPlan, B, tol=1e-6, t=3, max_iter=100000, minnor
         out_info.append([_info(infos[i + c]) for c in range(k)])
         i += k
     return [x.t() for x in xs], out_info
+
+
+def batch_time_spmm(plan: BatchPlan, K: int, trans: bool = False, precision: str = "fp64",
+                    reps: int = 20) -> float:
+    """Average milliseconds of one launch of the batched SpMM kernel."""
+    lib = load_library()
+    ms = C.c_double(0.0)
+    rc = lib.ta_batch_time_spmm(plan.handle, int(K), int(bool(trans)), PRECISIONS[precision],
+                                int(reps), C.byref(ms), _stream())
+    _check(rc, "ta_batch_time_spmm")
+    return float(ms.value)

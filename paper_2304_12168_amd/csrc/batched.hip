@@ -50,6 +50,7 @@ struct Groups {
     int64_t *k, *matvecs;
     double *nb, *tol_nb, *tol_ne_nab, *rr, *phi, *alpha, *diag;
     int32_t *flags;  // [0] every group finished, [1] some group waits for a check
+    int32_t *sys_active;   // per system: some group still running
     const int32_t *ksys;   // right-hand sides in use per system
     const int32_t *a_blk;  // per system: first block of the A-row table (nsys + 1)
     const int32_t *t_blk;  // per system: first block of the A^T-row table (nsys + 1)
@@ -60,17 +61,21 @@ struct Groups {
 };
 
 enum BGate : int32_t {
-    kBRun = 0,    // unless every group has finished
-    kBCheck = 1,  // only when some group waits for a true-residual check
-    kBFinal = 2,  // only when every group has finished
+    kBRun = 0,      // unless every group has finished
+    kBCheck = 1,    // only when some group waits for a true-residual check
+    kBFinal = 2,    // only when every group has finished
     kBAlways = 3,
+    kBFinalNew = 4, // finished, and x and b - A x were not just computed by a check
 };
 
+// flags: [0] every group finished, [1] a check is due, [2] a check ran in
+// this chunk's tail (x and b - A x are current for every group)
 __device__ __forceinline__ bool bgate(int32_t gate, const Groups &gs) {
     switch (gate) {
         case kBRun: return !gs.flags[0];
         case kBCheck: return gs.flags[1] != 0;
         case kBFinal: return gs.flags[0] != 0;
+        case kBFinalNew: return gs.flags[0] != 0 && !gs.flags[2];
         default: return true;
     }
 }
@@ -89,12 +94,60 @@ __device__ __forceinline__ float ldv(const uint16_t *v, int64_t k) {
     return __uint_as_float((uint32_t)v[k] << 16);
 }
 
-enum BEpi : int32_t { kBNorm = 0, kBResid = 1 };
+enum BEpi : int32_t { kBNorm = 0, kBResid = 1, kBNormOnly = 2 };
 
 // ---------------------------------------------------------------------------
-// SpMM: Y = M X (or B - M X) over a block table of M's rows; lane c of a row
-// group works on column c.  Per block and column: partial sum of Y^2.
+// SpMM: Y = M X (or B - M X) over a block table of M's rows.  A lane covers
+// CV consecutive columns with one 16-byte load of the input row (2 doubles or
+// 4 floats); KL = K / CV lanes cover the K columns, and L lanes split the
+// nonzeros of a row (L = 1: terms in storage order, as the single-vector
+// kernels; L > 1: lane-strided terms merged by a fixed butterfly).  Per block
+// and column: partial sum of Y^2.
 // ---------------------------------------------------------------------------
+template <typename X, int CV>
+struct VecLoad;
+template <>
+struct VecLoad<double, 1> {
+    __device__ static void ld(const double *p, double *o) { o[0] = p[0]; }
+};
+template <>
+struct VecLoad<double, 2> {
+    __device__ static void ld(const double *p, double *o) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct VecLoad<float, 1> {
+    __device__ static void ld(const float *p, float *o) { o[0] = p[0]; }
+};
+template <>
+struct VecLoad<float, 2> {
+    __device__ static void ld(const float *p, float *o) {
+        const float2 v = *reinterpret_cast<const float2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct VecLoad<float, 4> {
+    __device__ static void ld(const float *p, float *o) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+
+template <typename X, int K>
+struct Lanes {
+    static constexpr int CV0 = sizeof(X) == 8 ? 2 : 4;
+    static constexpr int CV = K < CV0 ? K : CV0;  // columns per lane
+    static constexpr int KL = K / CV;             // lanes across the columns
+};
+
 template <typename V, typename X, int K, int EPI>
 __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci,
@@ -103,70 +156,118 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
                                                    const double *__restrict__ b,
                                                    const BRange *__restrict__ blocks, Groups gs,
                                                    double2 *partials, int64_t cap, int32_t slot,
-                                                   int32_t gate) {
+                                                   int32_t gate, int32_t L) {
     if (!bgate(gate, gs)) return;
-    constexpr int R = 64 / K;  // rows per wave step
+    constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL;
     constexpr bool kF64 = sizeof(X) == 8;
     const BRange br = blocks[blockIdx.x];
+    // the iteration chain skips systems with no running group (their
+    // partials are never read); checks and diagnostics cover every system
+    if (gate == kBRun && !gs.sys_active[br.sys]) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = lane % K, rsub = lane / K;
-    const int g = br.sys * K + c;
-    // the iteration chain skips paused and finished groups; checks and
-    // diagnostics cover every column
-    const bool work = (gate != kBRun) || gs.status[g] == kActive;
-    Acc part = {0.0, 0.0};
-    if (work) {
-        for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
-            const int32_t e = rp[row + 1];
-            int32_t k = rp[row];
-            double yv;
-            if constexpr (kF64) {
-                Acc acc = {0.0, 0.0};
-                if constexpr (EPI == kBResid) acc.p = b[row * K + c];
-                constexpr double sgn = (EPI == kBResid) ? -1.0 : 1.0;
-                for (; k + 3 < e; k += 4) {
-                    const int32_t j0 = ci[k], j1 = ci[k + 1], j2 = ci[k + 2], j3 = ci[k + 3];
-                    const double a0 = ldv(val, k), a1 = ldv(val, k + 1), a2 = ldv(val, k + 2),
-                                 a3 = ldv(val, k + 3);
-                    const double x0 = x[(int64_t)j0 * K + c], x1 = x[(int64_t)j1 * K + c],
-                                 x2 = x[(int64_t)j2 * K + c], x3 = x[(int64_t)j3 * K + c];
-                    acc_fma(acc, sgn * a0, x0);
-                    acc_fma(acc, sgn * a1, x1);
-                    acc_fma(acc, sgn * a2, x2);
-                    acc_fma(acc, sgn * a3, x3);
+    const int cl = lane % KL, l = (lane / KL) % L, rsub = lane / (KL * L);
+    const int RL = 64 / (KL * L);
+    const int c0 = cl * CV;
+    Acc part[CV];
+#pragma unroll
+    for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
+    for (int64_t row = br.r0 + wave * RL + rsub; row < br.r1; row += 4 * RL) {
+        const int32_t e = rp[row + 1];
+        double yv[CV];
+        if constexpr (kF64) {
+            Acc acc[CV];
+#pragma unroll
+            for (int v = 0; v < CV; ++v) {
+                acc[v] = Acc{0.0, 0.0};
+                if constexpr (EPI == kBResid) {
+                    if (l == 0) acc[v].p = b[row * K + c0 + v];
                 }
-                for (; k < e; ++k) acc_fma(acc, sgn * ldv(val, k), x[(int64_t)ci[k] * K + c]);
-                yv = acc_val(acc);
-            } else {
-                float acc = 0.0f;
-                for (; k + 3 < e; k += 4) {
-                    const int32_t j0 = ci[k], j1 = ci[k + 1], j2 = ci[k + 2], j3 = ci[k + 3];
-                    const float a0 = ldv(val, k), a1 = ldv(val, k + 1), a2 = ldv(val, k + 2),
-                                a3 = ldv(val, k + 3);
-                    const float x0 = x[(int64_t)j0 * K + c], x1 = x[(int64_t)j1 * K + c],
-                                x2 = x[(int64_t)j2 * K + c], x3 = x[(int64_t)j3 * K + c];
-                    acc = fmaf(a0, x0, acc);
-                    acc = fmaf(a1, x1, acc);
-                    acc = fmaf(a2, x2, acc);
-                    acc = fmaf(a3, x3, acc);
-                }
-                for (; k < e; ++k) acc = fmaf(ldv(val, k), x[(int64_t)ci[k] * K + c], acc);
-                yv = (double)acc;
             }
-            y[row * K + c] = (X)yv;
-            acc_fma(part, yv, yv);
+            constexpr double sgn = (EPI == kBResid) ? -1.0 : 1.0;
+            int32_t k = rp[row] + l;
+            for (; k + L < e; k += 2 * L) {
+                const int32_t j0 = ci[k], j1 = ci[k + L];
+                const double a0 = sgn * ldv(val, k), a1 = sgn * ldv(val, k + L);
+                double x0[CV], x1[CV];
+                VecLoad<double, CV>::ld((const double *)x + (int64_t)j0 * K + c0, x0);
+                VecLoad<double, CV>::ld((const double *)x + (int64_t)j1 * K + c0, x1);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc_fma(acc[v], a0, x0[v]);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc_fma(acc[v], a1, x1[v]);
+            }
+            if (k < e) {
+                double x0[CV];
+                VecLoad<double, CV>::ld((const double *)x + (int64_t)ci[k] * K + c0, x0);
+                const double a0 = sgn * ldv(val, k);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc_fma(acc[v], a0, x0[v]);
+            }
+            for (int off = KL; off < KL * L; off <<= 1) {
+#pragma unroll
+                for (int v = 0; v < CV; ++v) {
+                    Acc o;
+                    o.p = __shfl_xor(acc[v].p, off);
+                    o.s = __shfl_xor(acc[v].s, off);
+                    acc[v] = acc_merge(acc[v], o);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < CV; ++v) yv[v] = acc_val(acc[v]);
+        } else {
+            float acc[CV];
+#pragma unroll
+            for (int v = 0; v < CV; ++v) acc[v] = 0.0f;
+            int32_t k = rp[row] + l;
+            for (; k + L < e; k += 2 * L) {
+                const int32_t j0 = ci[k], j1 = ci[k + L];
+                const float a0 = ldv(val, k), a1 = ldv(val, k + L);
+                float x0[CV], x1[CV];
+                VecLoad<float, CV>::ld((const float *)x + (int64_t)j0 * K + c0, x0);
+                VecLoad<float, CV>::ld((const float *)x + (int64_t)j1 * K + c0, x1);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc[v] = fmaf(a0, x0[v], acc[v]);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc[v] = fmaf(a1, x1[v], acc[v]);
+            }
+            if (k < e) {
+                float x0[CV];
+                VecLoad<float, CV>::ld((const float *)x + (int64_t)ci[k] * K + c0, x0);
+                const float a0 = ldv(val, k);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc[v] = fmaf(a0, x0[v], acc[v]);
+            }
+            for (int off = KL; off < KL * L; off <<= 1) {
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc[v] += __shfl_xor(acc[v], off);
+            }
+#pragma unroll
+            for (int v = 0; v < CV; ++v) yv[v] = (double)acc[v];
+        }
+        if (l == 0) {
+#pragma unroll
+            for (int v = 0; v < CV; ++v) {
+                if constexpr (EPI != kBNormOnly) y[row * K + c0 + v] = (X)yv[v];
+                const double q = (double)(X)yv[v];
+                acc_fma(part[v], q, q);
+            }
         }
     }
     // reduce over the rows of the block for each column
+    for (int off = KL; off < 64; off <<= 1) {
 #pragma unroll
-    for (int off = K; off < 64; off <<= 1) {
-        Acc o;
-        o.p = __shfl_xor(part.p, off);
-        o.s = __shfl_xor(part.s, off);
-        part = acc_merge(part, o);
+        for (int v = 0; v < CV; ++v) {
+            Acc o;
+            o.p = __shfl_xor(part[v].p, off);
+            o.s = __shfl_xor(part[v].s, off);
+            part[v] = acc_merge(part[v], o);
+        }
     }
     __shared__ Acc red[kBlock / 64][K];
-    if (rsub == 0) red[wave][c] = part;
+    if (lane < KL) {
+#pragma unroll
+        for (int v = 0; v < CV; ++v) red[wave][c0 + v] = part[v];
+    }
     __syncthreads();
     if (threadIdx.x < K) {
         Acc a = red[0][threadIdx.x];
@@ -380,6 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_bstep_end(Groups gs, const double2 *
 __global__ __launch_bounds__(kBlock) void k_bstep_check(Groups gs, const double2 *partials,
                                                          int64_t cap, int32_t products) {
     if (!gs.flags[1]) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0) gs.flags[2] = 1;
     const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (g >= gs.nsys * gs.K) return;
     const int st = gs.status[g];
@@ -427,7 +529,7 @@ __global__ __launch_bounds__(kBlock) void k_breplace(const double *__restrict__ 
 
 // Flags: [0] every group finished, [1] some group waits for a check.
 // Clears the replacement marks.
-__global__ __launch_bounds__(kBlock) void k_bsummary(Groups gs) {
+__global__ __launch_bounds__(kBlock) void k_bsummary(Groups gs, int32_t reset_check) {
     __shared__ int any_open, any_wait;
     if (threadIdx.x == 0) {
         any_open = 0;
@@ -442,6 +544,11 @@ __global__ __launch_bounds__(kBlock) void k_bsummary(Groups gs) {
         wait |= (st == kCandidate);
         gs.repl[g] = 0;
     }
+    for (int sy = threadIdx.x; sy < gs.nsys; sy += kBlock) {
+        int act = 0;
+        for (int c = 0; c < gs.K; ++c) act |= (gs.status[sy * gs.K + c] == kActive);
+        gs.sys_active[sy] = act;
+    }
     if (open) any_open = 1;  // benign same-value stores
     if (wait) any_wait = 1;
     __syncthreads();
@@ -449,6 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_bsummary(Groups gs) {
         // mixed precision: every chunk ends with a true-residual pass
         gs.flags[1] = any_wait || (gs.mixed && any_open);
         gs.flags[0] = !any_open;
+        if (reset_check) gs.flags[2] = 0;
     }
 }
 
@@ -470,44 +578,62 @@ __global__ __launch_bounds__(kBlock) void k_bstep_diag(Groups gs, const double2 
     gs.diag[(int64_t)g * 3 + 1] = (nb > 0.0 && nab > 0.0) ? sqrt(w2) / nab : 0.0;
 }
 
-// pack: Bc[i*K + c] = B_s[(i - ro_s) + c m_s] (column-major user blocks)
-__global__ void k_pack(int64_t M, int32_t K, const int64_t *__restrict__ ro, int32_t nsys,
-                       const int32_t *__restrict__ ksys, const double *const *__restrict__ src,
-                       double *dst) {
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < M * K;
-         e += (int64_t)gridDim.x * kBlock) {
-        const int64_t i = e / K;
-        const int c = (int)(e % K);
-        int lo = 0, hi = nsys;  // system s with ro[s] <= i < ro[s+1]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (ro[mid] <= i)
-                lo = mid;
-            else
-                hi = mid;
+// System of row i (offsets off[0..nsys]).
+__device__ __forceinline__ int sys_of(const int64_t *off, int nsys, int64_t i) {
+    int lo = 0, hi = nsys;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// pack: Bc[i*K + c] = B_s[(i - ro_s) + c m_s] (column-major user blocks),
+// through a 64-row LDS tile so both sides are read and written coalesced.
+__global__ __launch_bounds__(kBlock) void k_pack(int64_t M, int32_t K,
+                                                  const int64_t *__restrict__ ro, int32_t nsys,
+                                                  const int32_t *__restrict__ ksys,
+                                                  const double *const *__restrict__ src,
+                                                  double *dst) {
+    __shared__ double tile[64][kMaxK + 1];
+    const int t = threadIdx.x;
+    for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < M; r0 += (int64_t)gridDim.x * 64) {
+        const int64_t i = r0 + (t % 64);
+        if (i < M) {
+            const int sy = sys_of(ro, nsys, i);
+            const int64_t ms = ro[sy + 1] - ro[sy];
+            for (int c = t / 64; c < K; c += kBlock / 64)
+                tile[t % 64][c] = c < ksys[sy] ? src[sy][(i - ro[sy]) + (int64_t)c * ms] : 0.0;
         }
-        const int64_t ms = ro[lo + 1] - ro[lo];
-        dst[e] = c < ksys[lo] ? src[lo][(i - ro[lo]) + (int64_t)c * ms] : 0.0;
+        __syncthreads();
+        const int64_t rows = (M - r0) < 64 ? (M - r0) : 64;
+        for (int e = t; e < rows * K; e += kBlock) dst[r0 * K + e] = tile[e / K][e % K];
+        __syncthreads();
     }
 }
 
-__global__ void k_unpack(int64_t N, int32_t K, const int64_t *__restrict__ co, int32_t nsys,
-                         const int32_t *__restrict__ ksys, const double *__restrict__ src,
-                         double *const *__restrict__ dst) {
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < N * K;
-         e += (int64_t)gridDim.x * kBlock) {
-        const int64_t i = e / K;
-        const int c = (int)(e % K);
-        int lo = 0, hi = nsys;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (co[mid] <= i)
-                lo = mid;
-            else
-                hi = mid;
+__global__ __launch_bounds__(kBlock) void k_unpack(int64_t N, int32_t K,
+                                                    const int64_t *__restrict__ co, int32_t nsys,
+                                                    const int32_t *__restrict__ ksys,
+                                                    const double *__restrict__ src,
+                                                    double *const *__restrict__ dst) {
+    __shared__ double tile[64][kMaxK + 1];
+    const int t = threadIdx.x;
+    for (int64_t r0 = (int64_t)blockIdx.x * 64; r0 < N; r0 += (int64_t)gridDim.x * 64) {
+        const int64_t rows = (N - r0) < 64 ? (N - r0) : 64;
+        for (int e = t; e < rows * K; e += kBlock) tile[e / K][e % K] = src[r0 * K + e];
+        __syncthreads();
+        const int64_t i = r0 + (t % 64);
+        if (i < N) {
+            const int sy = sys_of(co, nsys, i);
+            const int64_t ns = co[sy + 1] - co[sy];
+            for (int c = t / 64; c < K; c += kBlock / 64)
+                if (c < ksys[sy]) dst[sy][(i - co[sy]) + (int64_t)c * ns] = tile[t % 64][c];
         }
-        const int64_t ns = co[lo + 1] - co[lo];
-        if (c < ksys[lo]) dst[lo][(i - co[lo]) + (int64_t)c * ns] = src[e];
+        __syncthreads();
     }
 }
 
@@ -582,6 +708,7 @@ struct BatchPlan {
     int32_t nsys = 0, precision = TA_FP64;
     int64_t M = 0, N = 0, nnz = 0;
     std::vector<int64_t> ro, co;  // row / column offsets of the systems (nsys + 1)
+    std::vector<int32_t> h_arp, h_trp;  // host copies of the row pointers of A and A^T
     int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr;
     double *a_val = nullptr, *t_val = nullptr;
     void *a_low = nullptr, *t_low = nullptr;
@@ -667,6 +794,12 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
     HIP_TRY(hipGetLastError());
     int32_t h = 0;
     HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    P->h_arp.resize(M + 1);
+    P->h_trp.resize(N + 1);
+    HIP_TRY(hipMemcpyAsync(P->h_arp.data(), P->a_rp, sizeof(int32_t) * (M + 1),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(P->h_trp.data(), P->t_rp, sizeof(int32_t) * (N + 1),
+                           hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (h) return TA_ENOTSUP;
     P->mem = own.release();
@@ -674,32 +807,57 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
     return TA_OK;
 }
 
-// Block table over the rows of every system: at least four row steps per
-// block, at most 1024 blocks per system.
-static void make_blocks(const std::vector<int64_t> &off, int K, std::vector<BRange> &tab,
-                        std::vector<int32_t> &first) {
-    const int64_t step = 4 * (64 / K);
+// Block table over the rows of every system, balanced by nonzeros: about
+// max(1024, nnz K / 2^18) blocks in all, shared out in proportion to each
+// system's nonzeros (at least one per system with rows).
+static void make_blocks(const std::vector<int64_t> &off, const std::vector<int32_t> &rp, int K,
+                        std::vector<BRange> &tab, std::vector<int32_t> &first) {
+    const int64_t total_nnz = rp.empty() ? 0 : rp.back();
+    const int64_t target = std::max<int64_t>(1024, cdivh(total_nnz * K, 1 << 18));
     tab.clear();
     first.assign(off.size(), 0);
     for (size_t sidx = 0; sidx + 1 < off.size(); ++sidx) {
         first[sidx] = (int32_t)tab.size();
-        const int64_t rows = off[sidx + 1] - off[sidx];
-        int64_t rb = std::max<int64_t>(4 * step, cdivh(rows, 1024));
-        rb = cdivh(rb, step) * step;
-        for (int64_t r0 = off[sidx]; r0 < off[sidx + 1]; r0 += rb)
-            tab.push_back(BRange{(int32_t)r0, (int32_t)std::min(r0 + rb, off[sidx + 1]),
-                                 (int32_t)sidx, 0});
+        const int64_t r0 = off[sidx], r1 = off[sidx + 1];
+        if (r1 <= r0) continue;
+        const int64_t nnz_s = rp[r1] - rp[r0];
+        int64_t nb = total_nnz > 0 ? (target * nnz_s + total_nnz - 1) / total_nnz : 1;
+        nb = std::max<int64_t>(1, std::min<int64_t>(nb, r1 - r0));
+        const double per = (double)std::max<int64_t>(nnz_s, 1) / (double)nb;
+        int64_t start = r0;
+        for (int64_t bi = 1; bi <= nb && start < r1; ++bi) {
+            int64_t end;
+            if (bi == nb) {
+                end = r1;
+            } else {
+                const int64_t goal = rp[r0] + (int64_t)(per * (double)bi);
+                end = start + 1;
+                while (end < r1 && rp[end] < goal) ++end;
+            }
+            tab.push_back(BRange{(int32_t)start, (int32_t)end, (int32_t)sidx, 0});
+            start = end;
+        }
     }
     first[off.size() - 1] = (int32_t)tab.size();
+}
+
+// Lanes per row: about a quarter of the nonzeros per row, within the lanes
+// the columns leave free.
+static int pick_row_lanes(int64_t nnz, int64_t rows, int KL) {
+    const double avg = rows > 0 ? (double)nnz / (double)rows : 0.0;
+    int L = 1;
+    while (L * 2 <= 64 / KL && (double)(L * 2) * 4.0 <= avg) L *= 2;
+    return L;
 }
 
 template <typename V, typename X, int K, int EPI>
 static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const void *x, void *y,
                  const double *b, const BRange *tab, int32_t nblk, const Groups &gs,
-                 double2 *partials, int64_t cap, int32_t slot, int32_t gate, hipStream_t s) {
+                 double2 *partials, int64_t cap, int32_t slot, int32_t gate, int32_t L,
+                 hipStream_t s) {
     if (nblk <= 0) return;
     k_bspmm<V, X, K, EPI><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y, b,
-                                                  tab, gs, partials, cap, slot, gate);
+                                                  tab, gs, partials, cap, slot, gate, L);
 }
 
 // The per-K, per-precision pieces of one solve.
@@ -716,8 +874,11 @@ struct Engine {
 
         std::vector<BRange> ta_tab, tt_tab;
         std::vector<int32_t> a_first, t_first;
-        make_blocks(P.ro, K, ta_tab, a_first);
-        make_blocks(P.co, K, tt_tab, t_first);
+        make_blocks(P.ro, P.h_arp, K, ta_tab, a_first);
+        make_blocks(P.co, P.h_trp, K, tt_tab, t_first);
+        const int KLc = Lanes<X, K>::KL, KL64 = Lanes<double, K>::KL;
+        const int La = pick_row_lanes(P.nnz, M, KLc), Lt = pick_row_lanes(P.nnz, N, KLc);
+        const int La64 = pick_row_lanes(P.nnz, M, KL64), Lt64 = pick_row_lanes(P.nnz, N, KL64);
         const int32_t na = (int32_t)ta_tab.size(), nt = (int32_t)tt_tab.size();
         const int64_t cap = std::max<int64_t>(std::max(na, nt), 1);
         const int32_t nslots = std::max(2 * t, 3);
@@ -764,6 +925,7 @@ struct Engine {
         ws.reserve(&gs.alpha, G * kTMax);
         ws.reserve(&gs.diag, G * 3);
         ws.reserve(&gs.flags, 4);
+        ws.reserve(&gs.sys_active, nsys);
         int rc = ws.commit();
         if (rc != TA_OK) return rc;
 
@@ -784,6 +946,7 @@ struct Engine {
         HIP_TRY(hipMemcpyAsync(d_B, B, sizeof(double *) * nsys, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemcpyAsync(d_X, Xout, sizeof(double *) * nsys, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemsetAsync(gs.flags, 0, sizeof(int32_t) * 4, s));
+        HIP_TRY(hipMemsetAsync(gs.sys_active, 0, sizeof(int32_t) * nsys, s));
         HIP_TRY(hipMemsetAsync(Xc, 0, sizeof(double) * (size_t)(N * K), s));
         if (minnorm) HIP_TRY(hipMemsetAsync(Y, 0, sizeof(double) * (size_t)(M * K), s));
         gs.ksys = d_ksys;
@@ -800,15 +963,14 @@ struct Engine {
         const unsigned gw = (unsigned)cdivh(G, 4);  // one wave per group
 
         // initial state
-        if (M * K > 0)
-            k_pack<<<grid_for(M * K), kBlock, 0, s>>>(M, K, d_ro, nsys, d_ksys, d_B, Bc);
+        if (M > 0) k_pack<<<grid_for(M / 4 + 1), kBlock, 0, s>>>(M, K, d_ro, nsys, d_ksys, d_B, Bc);
         if (na > 0) k_binit<X, K><<<na, kBlock, 0, s>>>(Bc, R, d_ta, partials, cap);
         const bool has_nab = o->tol_normal > 0.0;
         if (has_nab)
-            spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt, gs,
-                                            partials, cap, 1, kBAlways, s);
+            spmm<double, double, K, kBNormOnly>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt,
+                                                gs, partials, cap, 1, kBAlways, Lt64, s);
         k_bstep_init<<<gw, kBlock, 0, s>>>(gs, partials, cap, has_nab ? 1 : 0);
-        k_bsummary<<<1, kBlock, 0, s>>>(gs);
+        k_bsummary<<<1, kBlock, 0, s>>>(gs, 1);
         HIP_TRY(hipGetLastError());
 
         auto iteration = [&]() {
@@ -816,9 +978,9 @@ struct Engine {
                 const void *uj = j == 0 ? (const void *)R : (const void *)U[j];
                 X *wj = W[minnorm ? 0 : j];
                 spmm<V, X, K, kBNorm>(P.t_rp, P.t_ci, tval, uj, wj, nullptr, d_tt, nt, gs, partials,
-                                      cap, 2 * j, kBRun, s);
+                                      cap, 2 * j, kBRun, Lt, s);
                 spmm<V, X, K, kBNorm>(P.a_rp, P.a_ci, aval, wj, U[j + 1], nullptr, d_ta, na, gs,
-                                      partials, cap, 2 * j + 1, kBRun, s);
+                                      partials, cap, 2 * j + 1, kBRun, La, s);
             }
             k_bstep_gram<<<(unsigned)G, kBlock, 0, s>>>(gs, partials, cap);
             BVecs uv{};
@@ -831,29 +993,30 @@ struct Engine {
                 k_bupdate_x<X, K><<<nt, kBlock, 0, s>>>(wv, Xc, d_tt, gs);
             }
             k_bstep_end<<<gw, kBlock, 0, s>>>(gs, partials, cap);
-            k_bsummary<<<1, kBlock, 0, s>>>(gs);
+            k_bsummary<<<1, kBlock, 0, s>>>(gs, 1);
         };
         const int32_t products = minnorm ? 2 : 1;
         auto tail = [&]() {
             // true-residual check for waiting groups (every running group when mixed)
             if (minnorm)
                 spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Y, Xc, nullptr, d_tt, nt, gs,
-                                                partials, cap, 1, kBCheck, s);
+                                                partials, cap, 1, kBCheck, Lt64, s);
             spmm<double, double, K, kBResid>(P.a_rp, P.a_ci, P.a_val, Xc, RT, Bc, d_ta, na, gs,
-                                             partials, cap, 0, kBCheck, s);
+                                             partials, cap, 0, kBCheck, La64, s);
             k_bstep_check<<<gw, kBlock, 0, s>>>(gs, partials, cap, products);
             if (na > 0) k_breplace<X, K><<<na, kBlock, 0, s>>>(RT, R, d_ta, gs);
-            k_bsummary<<<1, kBlock, 0, s>>>(gs);
-            // exit diagnostics once every group has finished
+            k_bsummary<<<1, kBlock, 0, s>>>(gs, 0);
+            // exit diagnostics once every group has finished; x (y-form) and
+            // b - A x are recomputed only if no check just produced them
             if (minnorm)
                 spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Y, Xc, nullptr, d_tt, nt, gs,
-                                                partials, cap, 1, kBFinal, s);
+                                                partials, cap, 1, kBFinalNew, Lt64, s);
             spmm<double, double, K, kBResid>(P.a_rp, P.a_ci, P.a_val, Xc, RT, Bc, d_ta, na, gs,
-                                             partials, cap, 0, kBFinal, s);
-            spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, RT, TN, nullptr, d_tt, nt, gs,
-                                            partials, cap, 1, kBFinal, s);
-            spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt, gs,
-                                            partials, cap, 2, kBFinal, s);
+                                             partials, cap, 0, kBFinalNew, La64, s);
+            spmm<double, double, K, kBNormOnly>(P.t_rp, P.t_ci, P.t_val, RT, TN, nullptr, d_tt, nt,
+                                                gs, partials, cap, 1, kBFinal, Lt64, s);
+            spmm<double, double, K, kBNormOnly>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt,
+                                                gs, partials, cap, 2, kBFinal, Lt64, s);
         };
 
         int32_t hflags[4] = {0, 0, 0, 0};
@@ -879,8 +1042,7 @@ struct Engine {
             chunk = std::min(chunk_cap, chunk * 2);
         }
         k_bstep_diag<<<gw, kBlock, 0, s>>>(gs, partials, cap);
-        if (N * K > 0)
-            k_unpack<<<grid_for(N * K), kBlock, 0, s>>>(N, K, d_co, nsys, d_ksys, Xc, d_X);
+        if (N > 0) k_unpack<<<grid_for(N / 4 + 1), kBlock, 0, s>>>(N, K, d_co, nsys, d_ksys, Xc, d_X);
         HIP_TRY(hipGetLastError());
 
         // per-group results to the host
@@ -955,6 +1117,77 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
     }
 }
 
+// Timing hook: `reps` launches of the SpMM kernel a batched solve with K
+// columns uses on A (trans = 0) or A^T (trans = 1), back to back between two
+// HIP events on `s`; returns the average milliseconds per launch.
+template <typename V, typename X, int K>
+static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *avg_ms,
+                       hipStream_t s) {
+    const bool mixed = !std::is_same<V, double>::value;
+    const int64_t rows = trans ? P.N : P.M, cols = trans ? P.M : P.N;
+    std::vector<BRange> tab;
+    std::vector<int32_t> first;
+    make_blocks(trans ? P.co : P.ro, trans ? P.h_trp : P.h_arp, K, tab, first);
+    const int32_t nb = (int32_t)tab.size();
+    const int L = pick_row_lanes(P.nnz, rows, Lanes<X, K>::KL);
+    Workspace ws(s);
+    X *xin = nullptr, *yout = nullptr;
+    double2 *partials = nullptr;
+    BRange *d_tab = nullptr;
+    Groups gs{};
+    ws.reserve(&xin, std::max<int64_t>(cols, 1) * K);
+    ws.reserve(&yout, std::max<int64_t>(rows, 1) * K);
+    ws.reserve(&partials, (int64_t)K * std::max(nb, 1));
+    ws.reserve(&d_tab, std::max(nb, 1));
+    ws.reserve(&gs.flags, 4);
+    ws.reserve(&gs.sys_active, P.nsys);
+    int rc = ws.commit();
+    if (rc != TA_OK) return rc;
+    HIP_TRY(hipMemcpyAsync(d_tab, tab.data(), sizeof(BRange) * nb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemsetAsync(xin, 0, sizeof(X) * (size_t)(std::max<int64_t>(cols, 1) * K), s));
+    HIP_TRY(hipMemsetAsync(gs.flags, 0, sizeof(int32_t) * 4, s));
+    gs.nsys = P.nsys;
+    gs.K = K;
+    const int32_t *rp = trans ? P.t_rp : P.a_rp;
+    const int32_t *ci = trans ? P.t_ci : P.a_ci;
+    const void *val = mixed ? (trans ? P.t_low : P.a_low) : (trans ? (const void *)P.t_val
+                                                                   : (const void *)P.a_val);
+    if (val == nullptr) return TA_EINVAL;
+    const int64_t cap = std::max(nb, 1);
+    spmm<V, X, K, kBNorm>(rp, ci, val, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0,
+                          kBAlways, L, s);
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+    for (int32_t i = 0; i < reps; ++i)
+        spmm<V, X, K, kBNorm>(rp, ci, val, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0,
+                              kBAlways, L, s);
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = (double)ms / reps;
+    return TA_OK;
+}
+
+template <typename V, typename X>
+static int time_spmm(const BatchPlan &P, int32_t K, int32_t trans, int32_t reps, double *avg_ms,
+                     hipStream_t s) {
+    switch (K) {
+        case 1: return time_spmm_k<V, X, 1>(P, trans, reps, avg_ms, s);
+        case 2: return time_spmm_k<V, X, 2>(P, trans, reps, avg_ms, s);
+        case 4: return time_spmm_k<V, X, 4>(P, trans, reps, avg_ms, s);
+        case 8: return time_spmm_k<V, X, 8>(P, trans, reps, avg_ms, s);
+        case 16: return time_spmm_k<V, X, 16>(P, trans, reps, avg_ms, s);
+        case 32: return time_spmm_k<V, X, 32>(P, trans, reps, avg_ms, s);
+        case 64: return time_spmm_k<V, X, 64>(P, trans, reps, avg_ms, s);
+        default: return TA_EINVAL;
+    }
+}
+
 }  // namespace bt
 }  // namespace ta
 
@@ -985,6 +1218,19 @@ int ta_batch_plan_destroy(ta_batch_plan *plan) {
     ta::bt::bplan_free(&plan->p);
     delete plan;
     return TA_OK;
+}
+
+int ta_batch_time_spmm(const ta_batch_plan *plan, int32_t K, int32_t trans, int32_t precision,
+                       int32_t reps, double *avg_ms, void *stream) {
+    if (plan == nullptr || avg_ms == nullptr || reps < 1) return TA_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const ta::bt::BatchPlan &P = plan->p;
+    if (precision != TA_FP64 && precision != P.precision) return TA_EINVAL;
+    switch (precision) {
+        case TA_FP32: return ta::bt::time_spmm<float, float>(P, K, trans, reps, avg_ms, s);
+        case TA_BF16: return ta::bt::time_spmm<uint16_t, float>(P, K, trans, reps, avg_ms, s);
+        default: return ta::bt::time_spmm<double, double>(P, K, trans, reps, avg_ms, s);
+    }
 }
 
 int cta_solve_batched(const ta_batch_plan *plan, const int32_t *nrhs, const double *const *B,
