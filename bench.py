@@ -34,6 +34,12 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the batched SpMM passes on this workload, from two
+# rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy
+# kernel); see profiles/k_bspmm_fp32_k32_lp_shaped_traffic.md.  Valid for
+# fp32, k = 32 only.
+MEASURED_TRAFFIC = {("fp32", 32, "A"): 748.9e6, ("fp32", 32, "AT"): 192.3e6}
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -171,9 +177,11 @@ def main():
     if ms_a >= ms_at:
         kname, kms, kbytes = (f"k_bspmm<{args.precision},K={K}> on A "
                               "(1e4 rows x ~600 nnz; gathers rows of the n x K block)"), ms_a, by_a
+        traffic = MEASURED_TRAFFIC.get((args.precision, K, "A"))
     else:
         kname, kms, kbytes = (f"k_bspmm<{args.precision},K={K}> on A^T "
                               "(1e6 rows x ~6 nnz)"), ms_at, by_at
+        traffic = MEASURED_TRAFFIC.get((args.precision, K, "AT"))
     achieved = kbytes / (kms * 1e-3) / 1e9
 
     cpu = None
@@ -217,7 +225,7 @@ def main():
                    "speedup_vs_fp64_plain": value / plain_rate},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None, "bytes_per_launch": kbytes, "avg_launch_us": kms * 1e3},
+                     "traffic": traffic, "bytes_per_launch": kbytes, "avg_launch_us": kms * 1e3},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

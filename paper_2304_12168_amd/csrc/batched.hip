@@ -148,7 +148,7 @@ struct Lanes {
     static constexpr int KL = K / CV;             // lanes across the columns
 };
 
-template <typename V, typename X, int K, int EPI>
+template <typename V, typename X, int K, int EPI, int U>
 __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci,
                                                    const V *__restrict__ val,
@@ -185,18 +185,23 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
             }
             constexpr double sgn = (EPI == kBResid) ? -1.0 : 1.0;
             int32_t k = rp[row] + l;
-            for (; k + L < e; k += 2 * L) {
-                const int32_t j0 = ci[k], j1 = ci[k + L];
-                const double a0 = sgn * ldv(val, k), a1 = sgn * ldv(val, k + L);
-                double x0[CV], x1[CV];
-                VecLoad<double, CV>::ld((const double *)x + (int64_t)j0 * K + c0, x0);
-                VecLoad<double, CV>::ld((const double *)x + (int64_t)j1 * K + c0, x1);
+            for (; k + (U - 1) * L < e; k += U * L) {
+                int32_t j[U];
+                double a[U], xv[U][CV];
 #pragma unroll
-                for (int v = 0; v < CV; ++v) acc_fma(acc[v], a0, x0[v]);
+                for (int u = 0; u < U; ++u) {
+                    j[u] = ci[k + u * L];
+                    a[u] = sgn * ldv(val, k + u * L);
+                }
 #pragma unroll
-                for (int v = 0; v < CV; ++v) acc_fma(acc[v], a1, x1[v]);
+                for (int u = 0; u < U; ++u)
+                    VecLoad<double, CV>::ld((const double *)x + (int64_t)j[u] * K + c0, xv[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int v = 0; v < CV; ++v) acc_fma(acc[v], a[u], xv[u][v]);
             }
-            if (k < e) {
+            for (; k < e; k += L) {
                 double x0[CV];
                 VecLoad<double, CV>::ld((const double *)x + (int64_t)ci[k] * K + c0, x0);
                 const double a0 = sgn * ldv(val, k);
@@ -219,18 +224,23 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
 #pragma unroll
             for (int v = 0; v < CV; ++v) acc[v] = 0.0f;
             int32_t k = rp[row] + l;
-            for (; k + L < e; k += 2 * L) {
-                const int32_t j0 = ci[k], j1 = ci[k + L];
-                const float a0 = ldv(val, k), a1 = ldv(val, k + L);
-                float x0[CV], x1[CV];
-                VecLoad<float, CV>::ld((const float *)x + (int64_t)j0 * K + c0, x0);
-                VecLoad<float, CV>::ld((const float *)x + (int64_t)j1 * K + c0, x1);
+            for (; k + (U - 1) * L < e; k += U * L) {
+                int32_t j[U];
+                float a[U], xv[U][CV];
 #pragma unroll
-                for (int v = 0; v < CV; ++v) acc[v] = fmaf(a0, x0[v], acc[v]);
+                for (int u = 0; u < U; ++u) {
+                    j[u] = ci[k + u * L];
+                    a[u] = ldv(val, k + u * L);
+                }
 #pragma unroll
-                for (int v = 0; v < CV; ++v) acc[v] = fmaf(a1, x1[v], acc[v]);
+                for (int u = 0; u < U; ++u)
+                    VecLoad<float, CV>::ld((const float *)x + (int64_t)j[u] * K + c0, xv[u]);
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int v = 0; v < CV; ++v) acc[v] = fmaf(a[u], xv[u][v], acc[v]);
             }
-            if (k < e) {
+            for (; k < e; k += L) {
                 float x0[CV];
                 VecLoad<float, CV>::ld((const float *)x + (int64_t)ci[k] * K + c0, x0);
                 const float a0 = ldv(val, k);
@@ -856,8 +866,13 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
                  double2 *partials, int64_t cap, int32_t slot, int32_t gate, int32_t L,
                  hipStream_t s) {
     if (nblk <= 0) return;
-    k_bspmm<V, X, K, EPI><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y, b,
-                                                  tab, gs, partials, cap, slot, gate, L);
+#ifdef TA_SPMM_UNROLL
+    constexpr int kU = TA_SPMM_UNROLL;
+#else
+    constexpr int kU = 2;
+#endif
+    k_bspmm<V, X, K, EPI, kU><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y,
+                                                      b, tab, gs, partials, cap, slot, gate, L);
 }
 
 // The per-K, per-precision pieces of one solve.
@@ -963,7 +978,9 @@ struct Engine {
         const unsigned gw = (unsigned)cdivh(G, 4);  // one wave per group
 
         // initial state
-        if (M > 0) k_pack<<<grid_for(M / 4 + 1), kBlock, 0, s>>>(M, K, d_ro, nsys, d_ksys, d_B, Bc);
+        if (M > 0)
+            k_pack<<<(unsigned)std::min<int64_t>(cdivh(M, 64), 4096), kBlock, 0, s>>>(
+                M, K, d_ro, nsys, d_ksys, d_B, Bc);
         if (na > 0) k_binit<X, K><<<na, kBlock, 0, s>>>(Bc, R, d_ta, partials, cap);
         const bool has_nab = o->tol_normal > 0.0;
         if (has_nab)
@@ -1042,7 +1059,9 @@ struct Engine {
             chunk = std::min(chunk_cap, chunk * 2);
         }
         k_bstep_diag<<<gw, kBlock, 0, s>>>(gs, partials, cap);
-        if (N > 0) k_unpack<<<grid_for(N / 4 + 1), kBlock, 0, s>>>(N, K, d_co, nsys, d_ksys, Xc, d_X);
+        if (N > 0)
+            k_unpack<<<(unsigned)std::min<int64_t>(cdivh(N, 64), 4096), kBlock, 0, s>>>(
+                N, K, d_co, nsys, d_ksys, Xc, d_X);
         HIP_TRY(hipGetLastError());
 
         // per-group results to the host
