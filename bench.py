@@ -1,22 +1,28 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the MI355X TA / CTA solvers: CTA mixed+batched vs
-FP64 plain.
+"""Throughput benchmark of the MI355X CTA solvers: mixed+batched vs FP64 plain.
 
-Workload: the LP-shaped rectangular minimum-norm system, A = S + [I 0] with
-m = 10,000 rows, n = 1,000,000 columns, six N(0,1) nonzeros per column at
-uniformly drawn rows plus the identity slack block (about 6.0e6 nonzeros);
-right-hand sides b = A x* with x* ~ N(0,1); CTA of order t = 3 in the
-minimum-norm (y) form; every solve stops on the FP64 true relative residual
-||b - A x|| / ||b|| <= 1e-6.
+Headline workload -- batched uneven systems: 256 square systems with sizes
+n ~ U{1024..65536}, even-numbered ones Poisson 5-point stencils on an
+nx x ny grid (nx = floor(sqrt(n))), odd-numbered ones random sparse with 7
+off-diagonal N(0,1) entries per row and a diagonal of 2 x the row's absolute
+sum; each system has k ~ U{1..64} right-hand sides with entries ~ U[-1, 1]
+(about 8.5e3 columns, 5e7 nonzeros in all).  CTA of order t = 3 (x-form) on
+every column with a budget of 400 iterations per column, stop at FP64 true
+relative residual 1e-6.
 
-Headline (value): mixed+batched -- one step solves a block of 32 right-hand
-sides with the batched engine, FP32 matrix values and vectors in the Krylov
-chain, FP64 Gram entries, steps, y and true-residual checks; the value is
-right-hand sides solved per second.  Beside it, measured in the same run:
-FP64 plain (one right-hand side per solve on a prepared operator) and FP64
-batched (32 right-hand sides, all FP64).  Matrix preparation (transposes,
-low-precision copies) happens once per matrix, before timing, and is
-reported as plan_ms.
+A step is one batched solve of the whole set: FP32 matrix values and vectors
+in the Krylov chain, FP64 Gram entries, steps, x and true-residual checks.
+value = columns that reach 1e-6 (FP64 true residual), per second.  The
+stencil columns do not converge within the budget (H = A A^T squares the
+condition number); they run their 400 iterations inside the step and are
+reported as iterations per second.
+
+Beside it, in the same run: FP64 batched (the same call in FP64) and FP64
+plain (one column per cta_solve call on a prepared operator, on a seeded
+sample of columns; rate = converged columns / time of the sample).  Plans
+(transposes, low-precision copies) are built before timing and reported as
+plan_ms.  A secondary block measures the LP-shaped rectangular minimum-norm
+system (m = 1e4, n = 1e6) the same way with 32 right-hand sides per step.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -34,11 +40,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the batched SpMM passes on this workload, from two
+# HBM bytes per launch of the dominant kernel on this workload, from two
 # rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy
-# kernel); see profiles/k_bspmm_fp32_k32_lp_shaped_traffic.md.  Valid for
-# fp32, k = 32 only.
-MEASURED_TRAFFIC = {("fp32", 32, "A"): 748.9e6, ("fp32", 32, "AT"): 192.3e6}
+# kernel); see profiles/.  Keyed by (kernel, precision, K, pass); None when the
+# kernel has changed since the counters were taken.
+MEASURED_TRAFFIC: dict = {}
 
 
 def log(*a):
@@ -54,17 +60,233 @@ def csr_pass_bytes(rows: int, cols: int, nnz: int, val_bytes: int, idx_bytes: in
             + rows * k * vec_bytes)
 
 
+def kwidth(k: int) -> int:
+    K = 1
+    while K < k:
+        K *= 2
+    return K
+
+
+def batched_uneven_bench(args, P, torch, dev):
+    import numpy as np
+
+    from workloads import batched_uneven
+
+    tol, t, budget = 1e-6, 3, args.budget
+    t0 = time.perf_counter()
+    bt = batched_uneven(nsys=256, nmin=1024, nmax=65536, kmin=1, kmax=64, seed=args.seed)
+    log(f"[bench] batched uneven: generated in {time.perf_counter() - t0:.1f} s")
+    systems = [P.to_device(a) for a in bt.systems]
+    # right-hand sides stored column-major (k, m) so the call makes no copy
+    B = [torch.from_numpy(np.ascontiguousarray(b.T)).to(dev).t() for b in bt.B]
+    ks = [b.shape[1] for b in bt.B]
+    ncols = sum(ks)
+    M = sum(a.m for a in bt.systems)
+    nnz = sum(a.nnz for a in bt.systems)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    bp = P.BatchPlan(systems, args.precision)
+    bp64 = P.BatchPlan(systems, "fp64") if args.precision != "fp64" else bp
+    torch.cuda.synchronize()
+    plan_ms = 1e3 * (time.perf_counter() - t0)
+
+    def solve(plan, prec):
+        _, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=budget, precision=prec)
+        return infos
+
+    def summary(infos):
+        conv = iters_st = 0
+        for s, inf in enumerate(infos):
+            for i in inf:
+                if i.stop == "residual":
+                    if not i.rel_res <= tol:
+                        raise SystemExit(f"column of system {s} reported converged at {i.rel_res}")
+                    conv += 1
+                if bt.kinds[s] == "stencil":
+                    iters_st += i.iters
+        return conv, iters_st
+
+    for i in range(args.warmup):
+        c, _ = summary(solve(bp, args.precision))
+        log(f"[bench] warmup {i}: {c} of {ncols} columns converged")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = [solve(bp, args.precision) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sums = [summary(r) for r in runs]
+    conv = sum(c for c, _ in sums)
+    value = conv / elapsed
+    ms_per_step = 1e3 * elapsed / args.steps
+    stencil_its = sum(s for _, s in sums) / elapsed
+    rand_iters = sorted(i.iters for s, inf in enumerate(runs[-1]) for i in inf
+                        if bt.kinds[s] == "random" and i.stop == "residual")
+    log(f"[bench] mixed+batched ({args.precision}): {ms_per_step:.1f} ms per step, "
+        f"{conv // args.steps} of {ncols} columns converged per step, {value:.1f} columns/s")
+
+    # FP64 batched, one solve
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inf64 = solve(bp64, "fp64")
+    torch.cuda.synchronize()
+    b64_s = time.perf_counter() - t0
+    conv64, _ = summary(inf64)
+    log(f"[bench] FP64 batched: {b64_s * 1e3:.1f} ms, {conv64} columns converged")
+
+    # FP64 plain on a seeded sample of columns, one cta_solve call each
+    g = np.random.default_rng([args.seed, 7])
+    flat = [(s, c) for s in range(len(ks)) for c in range(ks[s])]
+    pick = [flat[i] for i in g.choice(len(flat), size=args.plain_sample, replace=False)]
+    plans = {s: P.plan(systems[s]) for s in sorted({s for s, _ in pick})}
+    cols = [B[s][:, c].contiguous() for s, c in pick]
+    P.cta_solve(plans[pick[0][0]], cols[0], tol=tol, t=t, max_iter=budget, hist_cap=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pinf = [P.cta_solve(plans[s], cols[i], tol=tol, t=t, max_iter=budget, hist_cap=1)[2]
+            for i, (s, _) in enumerate(pick)]
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    plain_conv = sum(i.stop == "residual" for i in pinf)
+    plain_rate = plain_conv / plain_s
+    log(f"[bench] FP64 plain: {len(pick)} sampled columns in {plain_s:.2f} s, "
+        f"{plain_conv} converged: {plain_rate:.1f} columns/s")
+
+    # dominant kernel: the SpMM of the widest group (K = 64), A and A^T passes,
+    # timed on a plan over exactly that group's systems (the launch the solve makes)
+    Kd = max(kwidth(k) for k in ks)
+    grp = [s for s, k in enumerate(ks) if kwidth(k) == Kd]
+    gp = P.BatchPlan([systems[s] for s in grp], args.precision)
+    gm = sum(bt.systems[s].m for s in grp)
+    gnnz = sum(bt.systems[s].nnz for s in grp)
+    vb = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
+    xb = 8 if args.precision == "fp64" else 4
+    ms_a = P.batch_time_spmm(gp, Kd, trans=False, precision=args.precision, reps=args.reps)
+    ms_at = P.batch_time_spmm(gp, Kd, trans=True, precision=args.precision, reps=args.reps)
+    by = csr_pass_bytes(gm, gm, gnnz, vb, 4, xb, Kd)
+    log(f"[bench] SpMM K={Kd} {args.precision} over {len(grp)} systems: A {ms_a * 1e3:.1f} us, "
+        f"A^T {ms_at * 1e3:.1f} us, {by / 1e9:.3f} GB per pass")
+    trans = ms_at > ms_a
+    kms = max(ms_a, ms_at)
+    gp.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build(force=False)
+        sample = pick[: args.cpu_sample]
+        log(f"[bench] CPU oracle: {len(sample)} sampled columns, 1 thread")
+        c0 = time.perf_counter()
+        cconv = 0
+        for s, c in sample:
+            _, _, oi = oracle.cta(bt.systems[s], bt.B[s][:, c], tol=tol, t=t, max_iter=budget,
+                                  hist_cap=1)
+            cconv += oi.stop == "residual"
+        csec = time.perf_counter() - c0
+        cpu = {"value": cconv / csec, "unit": "columns solved to 1e-6/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{len(sample)} seeded (system, column) pairs of the same batch, each "
+                         f"a full single-column CTA-3 solve (budget {budget}), sequential C, "
+                         f"{cconv} converged, {csec:.1f} s"}
+
+    res = {
+        "value": value, "ms_per_step": ms_per_step,
+        "config": {
+            "workload": "batched_uneven: 256 systems n~U{1024..65536}, half Poisson 5-point, half "
+                        "random 8 nnz/row diag 2*rowsum, k~U{1..64} rhs ~U[-1,1]; CTA t=3 x-form, "
+                        f"budget {budget} iterations/column, FP64 true rel-res 1e-6; "
+                        f"{args.precision} products + FP64 refinement",
+            "systems": 256, "columns": ncols, "rows": M, "nnz": nnz, "t": t, "tol": tol,
+            "budget": budget, "seed": args.seed, "precision": args.precision,
+            "columns_converged_per_step": conv // args.steps,
+            "random_iterations_median": rand_iters[len(rand_iters) // 2] if rand_iters else None,
+            "stencil_iterations_per_s": stencil_its, "plan_ms": plan_ms,
+            "fp64_batched_columns_per_s": conv64 / b64_s,
+            "fp64_plain_columns_per_s": plain_rate,
+            "fp64_plain_sample": f"{len(pick)} columns, {plain_conv} converged, {plain_s:.2f} s",
+            "speedup_vs_fp64_plain": value / plain_rate if plain_rate > 0 else None,
+            "speedup_vs_fp64_batched": value / (conv64 / b64_s) if conv64 else None},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"k_bspmm<{args.precision}, K={Kd}> {'A^T' if trans else 'A'} pass over the "
+                      f"{len(grp)} systems with {Kd // 2 + 1}-{Kd} right-hand sides "
+                      f"({gm} rows, {gnnz} nonzeros)",
+            "achieved": by / (kms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "traffic": MEASURED_TRAFFIC.get(("k_bspmm", args.precision, Kd,
+                                             "AT" if trans else "A")),
+            "bytes_per_launch": by, "avg_launch_us": kms * 1e3,
+            "other_pass_us": min(ms_a, ms_at) * 1e3},
+        "cpu_baseline": cpu,
+    }
+    return res
+
+
+def lp_shaped_bench(args, P, torch, dev):
+    """Secondary: the LP-shaped minimum-norm system, 32 right-hand sides per
+    step (mixed+batched) vs one per solve (FP64 plain)."""
+    import numpy as np
+
+    from workloads import lp_shaped
+
+    m, n, tol, t, K = 10_000, 1_000_000, 1e-6, 3, 32
+    prob = lp_shaped(m, n, per_col=6, seed=args.seed)
+    A = P.to_device(prob.A)
+    sp = prob.A.to_scipy()
+    g = np.random.default_rng([args.seed, 99])
+    blocks = [torch.from_numpy(sp @ g.standard_normal((n, K))).to(dev) for _ in range(2)]
+    pl = P.plan(A)
+    bp = P.BatchPlan([A], args.precision)
+    torch.cuda.synchronize()
+
+    def step(i):
+        _, infos = P.cta_solve_batched(bp, [blocks[i % 2]], tol=tol, t=t, max_iter=1000,
+                                       minnorm=True, precision=args.precision)
+        return infos[0]
+
+    step(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    inf = sum((step(i) for i in range(args.lp_steps)), [])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if any(i.stop != "residual" or not i.rel_res <= tol for i in inf):
+        raise SystemExit("LP-shaped mixed+batched: a column missed the tolerance")
+    singles = [blocks[0][:, i].contiguous() for i in range(args.lp_steps)]
+    P.cta_minnorm(pl, singles[0], tol=tol, t=t, max_iter=1000, hist_cap=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pinf = [P.cta_minnorm(pl, b, tol=tol, t=t, max_iter=1000, hist_cap=1)[2] for b in singles]
+    torch.cuda.synchronize()
+    pl_s = time.perf_counter() - t0
+    if any(i.stop != "residual" for i in pinf):
+        raise SystemExit("LP-shaped FP64 plain: a solve missed the tolerance")
+    rate, prate = K * args.lp_steps / el, len(singles) / pl_s
+    log(f"[bench] LP-shaped: mixed+batched {rate:.0f} columns/s, FP64 plain {prate:.0f} solves/s")
+    bp.close()
+    return {"workload": "lp_shaped_minnorm m=10000 n=1000000 nnz/col=6 +I slack, CTA t=3 y-form, "
+                        f"k={K} per step", "nnz": A.nnz,
+            "mixed_batched_columns_per_s": rate, "fp64_plain_solves_per_s": prate,
+            "speedup": rate / prate, "iterations": max(i.iters for i in inf)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--k", type=int, default=32, help="right-hand sides per batched step")
+    ap.add_argument("--budget", type=int, default=400, help="iterations per column")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
+    ap.add_argument("--plain-sample", type=int, default=24,
+                    help="columns solved one at a time for the FP64 plain rate")
+    ap.add_argument("--cpu-sample", type=int, default=8,
+                    help="columns solved by the CPU oracle for the CPU baseline")
+    ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
+    ap.add_argument("--lp-steps", type=int, default=5)
+    ap.add_argument("--no-lp", action="store_true", help="skip the LP-shaped secondary block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-solves", type=int, default=8,
-                    help="oracle solves timed for the CPU baseline (about 1.5 s each)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -72,11 +294,9 @@ def main():
               "(the multi-GPU layout is described, not built)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2304_12168_amd as P
-    from workloads import lp_shaped
 
     if not torch.cuda.is_available():
         log("no GPU visible")
@@ -85,148 +305,25 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    m, n, tol, t, K = 10_000, 1_000_000, 1e-6, 3, args.k
-    log(f"[bench] generating LP-shaped {m}x{n} (seed {args.seed})")
-    prob = lp_shaped(m, n, per_col=6, seed=args.seed)
-    A = P.to_device(prob.A)
-    nnz = A.nnz
-    sp = prob.A.to_scipy()
-    g = np.random.default_rng([args.seed, 99])
-    nblk = 4  # distinct right-hand-side blocks, cycled over the steps
-    blocks = [torch.from_numpy(sp @ g.standard_normal((n, K))).to(dev) for _ in range(nblk)]
-    singles = [blocks[i % nblk][:, i // nblk].contiguous() for i in range(args.warmup + args.steps)]
-    torch.cuda.synchronize()
-
-    # ---- prepared operators ----
-    t0 = time.perf_counter()
-    pl = P.plan(A)
-    bp = P.BatchPlan([A], args.precision)
-    bp64 = P.BatchPlan([A], "fp64") if args.precision != "fp64" else bp
-    torch.cuda.synchronize()
-    plan_ms = 1e3 * (time.perf_counter() - t0)
-    log(f"[bench] plans built in {plan_ms:.1f} ms")
-
-    def check(infos, what):
-        bad = [i for i in infos if i.stop != "residual" or not i.rel_res <= tol]
-        if bad:
-            raise SystemExit(f"{what}: {len(bad)} solves missed the tolerance: {bad[0]}")
-
-    # ---- headline: mixed + batched ----
-    def batched_step(plan, prec, i):
-        _, infos = P.cta_solve_batched(plan, [blocks[i % nblk]], tol=tol, t=t, max_iter=1000,
-                                       minnorm=True, precision=prec)
-        return infos[0]
-
-    for i in range(args.warmup):
-        inf = batched_step(bp, args.precision, i)
-        log(f"[bench] warmup {i}: iterations {max(x.iters for x in inf)}, "
-            f"max rel_res {max(x.rel_res for x in inf):.2e}")
-        check(inf, "warmup")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    allinf = []
-    for i in range(args.steps):
-        allinf += batched_step(bp, args.precision, i)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    check(allinf, "mixed+batched")
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = K * args.steps / elapsed
-    iters = [x.iters for x in allinf]
-    log(f"[bench] mixed+batched ({args.precision}, k={K}): {ms_per_step:.3f} ms per step, "
-        f"{value:.1f} right-hand sides/s, iterations {min(iters)}-{max(iters)}")
-
-    # ---- FP64 plain: one right-hand side per solve ----
-    nplain = max(5, args.steps)
-    for i in range(min(2, args.warmup)):
-        P.cta_minnorm(pl, singles[i], tol=tol, t=t, max_iter=1000, hist_cap=64)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    pinf = [P.cta_minnorm(pl, singles[i % len(singles)], tol=tol, t=t, max_iter=1000,
-                          hist_cap=64)[2] for i in range(nplain)]
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t0
-    check(pinf, "fp64 plain")
-    plain_rate = nplain / plain_s
-    log(f"[bench] FP64 plain: {1e3 * plain_s / nplain:.3f} ms per solve, {plain_rate:.1f} solves/s")
-
-    # ---- FP64 batched, same blocks ----
-    nb64 = max(3, args.steps // 4)
-    batched_step(bp64, "fp64", 0)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b64inf = []
-    for i in range(nb64):
-        b64inf += batched_step(bp64, "fp64", i)
-    torch.cuda.synchronize()
-    b64_s = time.perf_counter() - t0
-    check(b64inf, "fp64 batched")
-    b64_rate = K * nb64 / b64_s
-    log(f"[bench] FP64 batched (k={K}): {b64_rate:.1f} right-hand sides/s")
-
-    # ---- dominant kernel of the headline path ----
-    vb = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
-    xb = 8 if args.precision == "fp64" else 4
-    ms_a = P.batch_time_spmm(bp, K, trans=False, precision=args.precision, reps=20)
-    ms_at = P.batch_time_spmm(bp, K, trans=True, precision=args.precision, reps=20)
-    by_a = csr_pass_bytes(m, n, nnz, vb, 4, xb, K)
-    by_at = csr_pass_bytes(n, m, nnz, vb, 4, xb, K)
-    log(f"[bench] SpMM k={K} {args.precision}: A pass {ms_a * 1e3:.1f} us "
-        f"({by_a / ms_a / 1e6:.0f} GB/s), A^T pass {ms_at * 1e3:.1f} us "
-        f"({by_at / ms_at / 1e6:.0f} GB/s)")
-    if ms_a >= ms_at:
-        kname, kms, kbytes = (f"k_bspmm<{args.precision},K={K}> on A "
-                              "(1e4 rows x ~600 nnz; gathers rows of the n x K block)"), ms_a, by_a
-        traffic = MEASURED_TRAFFIC.get((args.precision, K, "A"))
-    else:
-        kname, kms, kbytes = (f"k_bspmm<{args.precision},K={K}> on A^T "
-                              "(1e6 rows x ~6 nnz)"), ms_at, by_at
-        traffic = MEASURED_TRAFFIC.get((args.precision, K, "AT"))
-    achieved = kbytes / (kms * 1e-3) / 1e9
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        oracle.build(force=False)
-        k = max(1, args.cpu_solves)
-        log(f"[bench] CPU oracle: {k} solves, 1 thread")
-        c0 = time.perf_counter()
-        for i in range(k):
-            _, _, oi = oracle.cta_minnorm(prob.A, singles[i % len(singles)].cpu().numpy(), tol=tol,
-                                          t=t, max_iter=1000, hist_cap=64)
-        csec = time.perf_counter() - c0
-        cpu = {"value": k / csec, "unit": "right-hand sides/s", "cores": 1, "kind": "oracle",
-               "sample": f"{k} full single-right-hand-side solves of the same system (FP64, "
-                         f"sequential C, {oi.iters} iterations each), {csec:.1f} s"}
-
+    res = batched_uneven_bench(args, P, torch, dev)
+    if not args.no_lp:
+        res["config"]["lp_shaped"] = lp_shaped_bench(args, P, torch, dev)
     out = {
         "metric": "solves/s and HBM GB/s to rel-residual 1e-6: CTA mixed+batched vs FP64 plain",
-        "value": value,
-        "unit": "right-hand sides solved/s",
+        "value": res["value"],
+        "unit": "columns solved to 1e-6 per second",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32/f64" if args.precision == "fp32" else
-                 ("bf16/f32/f64" if args.precision == "bf16" else "f64"),
+        "dtype": {"fp32": "f32/f64", "bf16": "bf16/f32/f64", "fp64": "f64"}[args.precision],
         "data": "synthetic",
-        "config": {"workload": "lp_shaped_minnorm m=10000 n=1000000 nnz/col=6 +I slack, "
-                               f"CTA t=3 y-form, mixed ({args.precision} products, FP64 "
-                               f"refinement) batched k={K}, rel-res 1e-6",
-                   "m": m, "n": n, "nnz": nnz, "t": t, "tol": tol, "seed": args.seed,
-                   "k_per_step": K, "precision": args.precision,
-                   "iterations": max(iters), "plan_ms": plan_ms,
-                   "fp64_plain_solves_per_s": plain_rate,
-                   "fp64_batched_rhs_per_s": b64_rate,
-                   "speedup_vs_fp64_plain": value / plain_rate},
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "bytes_per_launch": kbytes, "avg_launch_us": kms * 1e3},
-        "cpu_baseline": cpu,
+        "config": res["config"],
+        "roofline": res["roofline"],
+        "cpu_baseline": res["cpu_baseline"],
     }
     print(json.dumps(out), flush=True)
 

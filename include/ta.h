@@ -204,6 +204,9 @@ int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts
  * precision copies and FP32 vectors; Gram entries, steps, x (or y) and every
  * true-residual check are FP64, and the true residual replaces the recurrence
  * residual after every chunk; stop codes and residuals refer to FP64.
+ * Systems are advanced in groups of equal vector width (k_s rounded up to a
+ * power of two), one group after another on `stream`; the results do not
+ * depend on the grouping.
  */
 typedef struct ta_batch_plan ta_batch_plan;
 

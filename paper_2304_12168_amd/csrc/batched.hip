@@ -96,6 +96,51 @@ __device__ __forceinline__ float ldv(const uint16_t *v, int64_t k) {
 
 enum BEpi : int32_t { kBNorm = 0, kBResid = 1, kBNormOnly = 2 };
 
+// Column indices and values of one chunk of U nonzeros of a row (positions
+// k, k + L, ..., k + (U-1) L below the row end e) for the KL lanes that share
+// the row.  Unless TA_SPMM_LANE_LOADS is defined, the lanes load distinct
+// entries and pass them round with lane shuffles (KL times less load data
+// than every lane loading every entry); gbase is the group's first lane.
+// Entries past the row end come back as j = -1, a = 0.
+template <int U, int KL, typename V, typename T>
+__device__ __forceinline__ void load_chunk(const int32_t *__restrict__ ci,
+                                           const V *__restrict__ val, int32_t k, int32_t e,
+                                           int L, int cl, int gbase, T sgn, int32_t (&j)[U],
+                                           T (&a)[U]) {
+#ifdef TA_SPMM_LANE_LOADS
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t kk = k + u * L;
+        j[u] = -1;
+        a[u] = T(0);
+        if (kk < e) {
+            j[u] = ci[kk];
+            a[u] = sgn * (T)ldv(val, kk);
+        }
+    }
+#else
+    constexpr int NL = (U + KL - 1) / KL;  // entries loaded per lane
+    int32_t jl[NL];
+    T al[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int idx = cl + q * KL;
+        const int32_t kk = k + idx * L;
+        jl[q] = -1;
+        al[q] = T(0);
+        if (idx < U && kk < e) {
+            jl[q] = ci[kk];
+            al[q] = sgn * (T)ldv(val, kk);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        j[u] = __shfl(jl[u / KL], gbase + (u % KL));
+        a[u] = __shfl(al[u / KL], gbase + (u % KL));
+    }
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // SpMM: Y = M X (or B - M X) over a block table of M's rows.  A lane covers
 // CV consecutive columns with one 16-byte load of the input row (2 doubles or
@@ -167,12 +212,29 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane % KL, l = (lane / KL) % L, rsub = lane / (KL * L);
     const int RL = 64 / (KL * L);
-    const int c0 = cl * CV;
+    const int c0 = cl * CV, gbase = lane - cl;
     Acc part[CV];
 #pragma unroll
     for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
-    for (int64_t row = br.r0 + wave * RL + rsub; row < br.r1; row += 4 * RL) {
-        const int32_t e = rp[row + 1];
+    // Rows are visited with a stride of 4 * RL; the bounds of a lane's next
+    // row are loaded before the current row's nonzeros so that their latency
+    // overlaps the gathers.  Nonzeros go in chunks of U per lane, each chunk
+    // predicated on the row end: a short row issues all its column-index and
+    // x loads in one round.
+    const int64_t rstep = 4 * RL;
+    int64_t row = br.r0 + wave * RL + rsub;
+    int32_t s_cur = 0, e_cur = 0;
+    if (row < br.r1) {
+        s_cur = rp[row];
+        e_cur = rp[row + 1];
+    }
+    for (; row < br.r1; row += rstep) {
+        int32_t s_nxt = 0, e_nxt = 0;
+        if (row + rstep < br.r1) {
+            s_nxt = rp[row + rstep];
+            e_nxt = rp[row + rstep + 1];
+        }
+        const int32_t e = e_cur;
         double yv[CV];
         if constexpr (kF64) {
             Acc acc[CV];
@@ -184,29 +246,25 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
                 }
             }
             constexpr double sgn = (EPI == kBResid) ? -1.0 : 1.0;
-            int32_t k = rp[row] + l;
-            for (; k + (U - 1) * L < e; k += U * L) {
+            for (int32_t k = s_cur + l; k < e; k += U * L) {
                 int32_t j[U];
                 double a[U], xv[U][CV];
+                load_chunk<U, KL>(ci, val, k, e, L, cl, gbase, sgn, j, a);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    j[u] = ci[k + u * L];
-                    a[u] = sgn * ldv(val, k + u * L);
+                    if (j[u] >= 0) {
+                        VecLoad<double, CV>::ld((const double *)x + (int64_t)j[u] * K + c0, xv[u]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < CV; ++v) xv[u][v] = 0.0;
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    VecLoad<double, CV>::ld((const double *)x + (int64_t)j[u] * K + c0, xv[u]);
+                    if (j[u] >= 0) {
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int v = 0; v < CV; ++v) acc_fma(acc[v], a[u], xv[u][v]);
-            }
-            for (; k < e; k += L) {
-                double x0[CV];
-                VecLoad<double, CV>::ld((const double *)x + (int64_t)ci[k] * K + c0, x0);
-                const double a0 = sgn * ldv(val, k);
-#pragma unroll
-                for (int v = 0; v < CV; ++v) acc_fma(acc[v], a0, x0[v]);
+                        for (int v = 0; v < CV; ++v) acc_fma(acc[v], a[u], xv[u][v]);
+                    }
             }
             for (int off = KL; off < KL * L; off <<= 1) {
 #pragma unroll
@@ -223,29 +281,25 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
             float acc[CV];
 #pragma unroll
             for (int v = 0; v < CV; ++v) acc[v] = 0.0f;
-            int32_t k = rp[row] + l;
-            for (; k + (U - 1) * L < e; k += U * L) {
+            for (int32_t k = s_cur + l; k < e; k += U * L) {
                 int32_t j[U];
                 float a[U], xv[U][CV];
+                load_chunk<U, KL>(ci, val, k, e, L, cl, gbase, 1.0f, j, a);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    j[u] = ci[k + u * L];
-                    a[u] = ldv(val, k + u * L);
+                    if (j[u] >= 0) {
+                        VecLoad<float, CV>::ld((const float *)x + (int64_t)j[u] * K + c0, xv[u]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < CV; ++v) xv[u][v] = 0.0f;
+                    }
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u)
-                    VecLoad<float, CV>::ld((const float *)x + (int64_t)j[u] * K + c0, xv[u]);
+                    if (j[u] >= 0) {
 #pragma unroll
-                for (int u = 0; u < U; ++u)
-#pragma unroll
-                    for (int v = 0; v < CV; ++v) acc[v] = fmaf(a[u], xv[u][v], acc[v]);
-            }
-            for (; k < e; k += L) {
-                float x0[CV];
-                VecLoad<float, CV>::ld((const float *)x + (int64_t)ci[k] * K + c0, x0);
-                const float a0 = ldv(val, k);
-#pragma unroll
-                for (int v = 0; v < CV; ++v) acc[v] = fmaf(a0, x0[v], acc[v]);
+                        for (int v = 0; v < CV; ++v) acc[v] = fmaf(a[u], xv[u][v], acc[v]);
+                    }
             }
             for (int off = KL; off < KL * L; off <<= 1) {
 #pragma unroll
@@ -262,6 +316,8 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
                 acc_fma(part[v], q, q);
             }
         }
+        s_cur = s_nxt;
+        e_cur = e_nxt;
     }
     // reduce over the rows of the block for each column
     for (int off = KL; off < 64; off <<= 1) {
@@ -821,15 +877,20 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
 // max(1024, nnz K / 2^18) blocks in all, shared out in proportion to each
 // system's nonzeros (at least one per system with rows).
 static void make_blocks(const std::vector<int64_t> &off, const std::vector<int32_t> &rp, int K,
-                        std::vector<BRange> &tab, std::vector<int32_t> &first) {
-    const int64_t total_nnz = rp.empty() ? 0 : rp.back();
+                        std::vector<BRange> &tab, std::vector<int32_t> &first,
+                        const int32_t *nrhs = nullptr) {
+    // systems with no right-hand side in this run (nrhs[s] == 0) get no blocks
+    auto active = [&](size_t sidx) { return nrhs == nullptr || nrhs[sidx] > 0; };
+    int64_t total_nnz = 0;
+    for (size_t sidx = 0; sidx + 1 < off.size(); ++sidx)
+        if (active(sidx)) total_nnz += rp[off[sidx + 1]] - rp[off[sidx]];
     const int64_t target = std::max<int64_t>(1024, cdivh(total_nnz * K, 1 << 18));
     tab.clear();
     first.assign(off.size(), 0);
     for (size_t sidx = 0; sidx + 1 < off.size(); ++sidx) {
         first[sidx] = (int32_t)tab.size();
         const int64_t r0 = off[sidx], r1 = off[sidx + 1];
-        if (r1 <= r0) continue;
+        if (r1 <= r0 || !active(sidx)) continue;
         const int64_t nnz_s = rp[r1] - rp[r0];
         int64_t nb = total_nnz > 0 ? (target * nnz_s + total_nnz - 1) / total_nnz : 1;
         nb = std::max<int64_t>(1, std::min<int64_t>(nb, r1 - r0));
@@ -869,7 +930,7 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
 #ifdef TA_SPMM_UNROLL
     constexpr int kU = TA_SPMM_UNROLL;
 #else
-    constexpr int kU = 2;
+    constexpr int kU = 8;
 #endif
     k_bspmm<V, X, K, EPI, kU><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y,
                                                       b, tab, gs, partials, cap, slot, gate, L);
@@ -878,9 +939,10 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
 // The per-K, per-precision pieces of one solve.
 template <typename V, typename X, int K>
 struct Engine {
+    // info[info_off[s] + c] receives the result of column c of system s.
     static int run(const BatchPlan &P, const int32_t *nrhs, const double *const *B,
                    double *const *Xout, const ta_opts *o, int32_t minnorm, ta_info *info,
-                   hipStream_t s) {
+                   const int64_t *info_off, hipStream_t s) {
         const int32_t nsys = P.nsys, t = o->t;
         const int64_t M = P.M, N = P.N, G = (int64_t)nsys * K;
         const bool mixed = !std::is_same<V, double>::value;
@@ -889,11 +951,21 @@ struct Engine {
 
         std::vector<BRange> ta_tab, tt_tab;
         std::vector<int32_t> a_first, t_first;
-        make_blocks(P.ro, P.h_arp, K, ta_tab, a_first);
-        make_blocks(P.co, P.h_trp, K, tt_tab, t_first);
+        make_blocks(P.ro, P.h_arp, K, ta_tab, a_first, nrhs);
+        make_blocks(P.co, P.h_trp, K, tt_tab, t_first, nrhs);
+        int64_t nnz_run = 0;
+        for (int32_t i = 0; i < nsys; ++i)
+            if (nrhs[i] > 0) nnz_run += P.h_arp[P.ro[i + 1]] - P.h_arp[P.ro[i]];
         const int KLc = Lanes<X, K>::KL, KL64 = Lanes<double, K>::KL;
-        const int La = pick_row_lanes(P.nnz, M, KLc), Lt = pick_row_lanes(P.nnz, N, KLc);
-        const int La64 = pick_row_lanes(P.nnz, M, KL64), Lt64 = pick_row_lanes(P.nnz, N, KL64);
+        int64_t m_run = 0, n_run = 0;
+        for (int32_t i = 0; i < nsys; ++i)
+            if (nrhs[i] > 0) {
+                m_run += P.ro[i + 1] - P.ro[i];
+                n_run += P.co[i + 1] - P.co[i];
+            }
+        const int La = pick_row_lanes(nnz_run, m_run, KLc), Lt = pick_row_lanes(nnz_run, n_run, KLc);
+        const int La64 = pick_row_lanes(nnz_run, m_run, KL64),
+                  Lt64 = pick_row_lanes(nnz_run, n_run, KL64);
         const int32_t na = (int32_t)ta_tab.size(), nt = (int32_t)tt_tab.size();
         const int64_t cap = std::max<int64_t>(std::max(na, nt), 1);
         const int32_t nslots = std::max(2 * t, 3);
@@ -1075,11 +1147,10 @@ struct Engine {
         HIP_TRY(hipMemcpyAsync(hdiag.data(), gs.diag, sizeof(double) * G * 3, hipMemcpyDeviceToHost,
                                s));
         HIP_TRY(hipStreamSynchronize(s));
-        int64_t out = 0;
         for (int32_t sy = 0; sy < nsys; ++sy)
             for (int32_t c = 0; c < nrhs[sy]; ++c) {
                 const int64_t g = (int64_t)sy * K + c;
-                ta_info &inf = info[out++];
+                ta_info &inf = info[info_off[sy] + c];
                 memset(&inf, 0, sizeof inf);
                 inf.iters = hk[g];
                 inf.matvecs = hmv[g];
@@ -1094,16 +1165,22 @@ struct Engine {
 template <typename V, typename X>
 static int run_k(int K, const BatchPlan &P, const int32_t *nrhs, const double *const *B,
                  double *const *Xo, const ta_opts *o, int32_t minnorm, ta_info *info,
-                 hipStream_t s) {
+                 const int64_t *off, hipStream_t s) {
     switch (K) {
-        case 1: return Engine<V, X, 1>::run(P, nrhs, B, Xo, o, minnorm, info, s);
-        case 2: return Engine<V, X, 2>::run(P, nrhs, B, Xo, o, minnorm, info, s);
-        case 4: return Engine<V, X, 4>::run(P, nrhs, B, Xo, o, minnorm, info, s);
-        case 8: return Engine<V, X, 8>::run(P, nrhs, B, Xo, o, minnorm, info, s);
-        case 16: return Engine<V, X, 16>::run(P, nrhs, B, Xo, o, minnorm, info, s);
-        case 32: return Engine<V, X, 32>::run(P, nrhs, B, Xo, o, minnorm, info, s);
-        default: return Engine<V, X, 64>::run(P, nrhs, B, Xo, o, minnorm, info, s);
+        case 1: return Engine<V, X, 1>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
+        case 2: return Engine<V, X, 2>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
+        case 4: return Engine<V, X, 4>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
+        case 8: return Engine<V, X, 8>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
+        case 16: return Engine<V, X, 16>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
+        case 32: return Engine<V, X, 32>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
+        default: return Engine<V, X, 64>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
     }
+}
+
+static int kwidth(int32_t k) {
+    int K = 1;
+    while (K < k) K <<= 1;
+    return K;
 }
 
 static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *const *B,
@@ -1127,13 +1204,39 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         kmax = std::max(kmax, nrhs[i]);
     }
     if (kmax == 0) return TA_OK;
-    int K = 1;
-    while (K < kmax) K <<= 1;
-    switch (o->precision) {
-        case TA_FP32: return run_k<float, float>(K, P, nrhs, B, Xo, o, minnorm, info, s);
-        case TA_BF16: return run_k<uint16_t, float>(K, P, nrhs, B, Xo, o, minnorm, info, s);
-        default: return run_k<double, double>(K, P, nrhs, B, Xo, o, minnorm, info, s);
+    // Systems are run in groups of equal vector width K (the power of two
+    // covering their right-hand-side count), narrowest first, so that a
+    // system with few right-hand sides does not stream K - k padding columns.
+    std::vector<int64_t> off(P.nsys);
+    int64_t acc = 0;
+    for (int32_t i = 0; i < P.nsys; ++i) {
+        off[i] = acc;
+        acc += nrhs[i];
     }
+    std::vector<int32_t> part(P.nsys);
+    for (int K = 1; K <= kwidth(kmax); K <<= 1) {
+        bool any = false;
+        for (int32_t i = 0; i < P.nsys; ++i) {
+            part[i] = (nrhs[i] > 0 && kwidth(nrhs[i]) == K) ? nrhs[i] : 0;
+            any = any || part[i] > 0;
+        }
+        if (!any) continue;
+        int rc;
+        switch (o->precision) {
+            case TA_FP32:
+                rc = run_k<float, float>(K, P, part.data(), B, Xo, o, minnorm, info, off.data(), s);
+                break;
+            case TA_BF16:
+                rc = run_k<uint16_t, float>(K, P, part.data(), B, Xo, o, minnorm, info, off.data(),
+                                            s);
+                break;
+            default:
+                rc = run_k<double, double>(K, P, part.data(), B, Xo, o, minnorm, info, off.data(),
+                                           s);
+        }
+        if (rc != TA_OK) return rc;
+    }
+    return TA_OK;
 }
 
 // Timing hook: `reps` launches of the SpMM kernel a batched solve with K

@@ -101,16 +101,18 @@ def csr_from_coo(m: int, n: int, rows, cols, vals) -> Csr:
     if rows.size:
         if rows.min() < 0 or rows.max() >= m or cols.min() < 0 or cols.max() >= n:
             raise ValueError("coordinate out of range")
-    order = np.lexsort((cols, rows))
-    rows, cols, vals = rows[order], cols[order], vals[order]
+    key = rows * n + cols
+    order = np.argsort(key, kind="stable")
+    key, rows, cols, vals = key[order], rows[order], cols[order], vals[order]
     if rows.size:
-        key = rows * n + cols
         first = np.ones(key.size, dtype=bool)
         first[1:] = key[1:] != key[:-1]
-        grp = np.cumsum(first) - 1
-        summed = np.zeros(int(first.sum()), dtype=np.float64)
-        # Duplicates are summed in their coordinate order.
-        np.add.at(summed, grp, vals)
+        summed = vals[first]
+        if not first.all():
+            # Duplicates are summed in their coordinate order.
+            grp = np.cumsum(first) - 1
+            dup = ~first
+            np.add.at(summed, grp[dup], vals[dup])
         rows, cols, vals = rows[first], cols[first], summed
     counts = np.bincount(rows, minlength=m) if rows.size else np.zeros(m, dtype=np.int64)
     row_ptr = np.zeros(m + 1, dtype=np.int64)
