@@ -40,9 +40,45 @@ constexpr int kPhiStride = 2 * kTMax + 2;
 enum Status : int32_t { kActive = 0, kCandidate = 1, kFinished = 2, kInactive = 3 };
 
 // rows [r0, r1) of the concatenated matrix, all in system `sys`
+// One workgroup's share of a unit: the rows [r0, r1) of system sys are cut
+// into chunks of `chunk` rows (chunk = 0: one tile of the kernel, 4 waves'
+// rows), and workgroup q of the unit's nq takes chunks q, q + nq, q + 2 nq,
+// ...  With one-tile chunks the unit's workgroups sweep its rows side by
+// side, so x entries gathered by neighbouring rows (a banded or stencil
+// matrix) are reused from L2 while they are still there.  Tables are stored
+// in dispatch order (see make_blocks); `part` is the entry's index in system
+// order, which addresses its partial sums.  Entries with r0 == r1 are
+// padding.
 struct BRange {
-    int32_t r0, r1, sys, pad;
+    int32_t r0, r1, sys, part, q, nq, chunk, pad;
 };
+
+// Rows of a workgroup, R rows per wave and 4 waves: the lane's first row
+// and the one after `it` (row = -1 when done); c0 is the current chunk.
+struct BIter {
+    int32_t row, c0;
+};
+__device__ __forceinline__ int32_t bchunk(const BRange &br, int R) {
+    return br.chunk > 0 ? br.chunk : 4 * R;
+}
+__device__ __forceinline__ BIter brow_scan(const BRange &br, int R, int wave, int rsub,
+                                           int32_t c0) {
+    const int32_t ch = bchunk(br, R);
+    for (; c0 < br.r1; c0 += br.nq * ch) {
+        const int32_t row = c0 + wave * R + rsub;
+        if (row < c0 + ch && row < br.r1) return BIter{row, c0};
+    }
+    return BIter{-1, c0};
+}
+__device__ __forceinline__ BIter brow_first(const BRange &br, int R, int wave, int rsub) {
+    return brow_scan(br, R, wave, rsub, br.r0 + br.q * bchunk(br, R));
+}
+__device__ __forceinline__ BIter brow_next(const BRange &br, int R, int wave, int rsub,
+                                           BIter it) {
+    const int32_t ch = bchunk(br, R), nxt = it.row + 4 * R;
+    if (nxt < it.c0 + ch && nxt < br.r1) return BIter{nxt, it.c0};
+    return brow_scan(br, R, wave, rsub, it.c0 + br.nq * ch);
+}
 
 // per-group state, structure of arrays over G = nsys * K groups
 struct Groups {
@@ -206,6 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
     constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL;
     constexpr bool kF64 = sizeof(X) == 8;
     const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1) return;
     // the iteration chain skips systems with no running group (their
     // partials are never read); checks and diagnostics cover every system
     if (gate == kBRun && !gs.sys_active[br.sys]) return;
@@ -216,23 +253,24 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
     Acc part[CV];
 #pragma unroll
     for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
-    // Rows are visited with a stride of 4 * RL; the bounds of a lane's next
+    // Rows are visited tile by tile (see BRange); the bounds of a lane's next
     // row are loaded before the current row's nonzeros so that their latency
     // overlaps the gathers.  Nonzeros go in chunks of U per lane, each chunk
     // predicated on the row end: a short row issues all its column-index and
     // x loads in one round.
-    const int64_t rstep = 4 * RL;
-    int64_t row = br.r0 + wave * RL + rsub;
+    BIter it = brow_first(br, RL, wave, rsub);
     int32_t s_cur = 0, e_cur = 0;
-    if (row < br.r1) {
-        s_cur = rp[row];
-        e_cur = rp[row + 1];
+    if (it.row >= 0) {
+        s_cur = rp[it.row];
+        e_cur = rp[it.row + 1];
     }
-    for (; row < br.r1; row += rstep) {
+    while (it.row >= 0) {
+        const int64_t row = it.row;
+        const BIter nit = brow_next(br, RL, wave, rsub, it);
         int32_t s_nxt = 0, e_nxt = 0;
-        if (row + rstep < br.r1) {
-            s_nxt = rp[row + rstep];
-            e_nxt = rp[row + rstep + 1];
+        if (nit.row >= 0) {
+            s_nxt = rp[nit.row];
+            e_nxt = rp[nit.row + 1];
         }
         const int32_t e = e_cur;
         double yv[CV];
@@ -318,6 +356,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
         }
         s_cur = s_nxt;
         e_cur = e_nxt;
+        it = nit;
     }
     // reduce over the rows of the block for each column
     for (int off = KL; off < 64; off <<= 1) {
@@ -338,7 +377,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
     if (threadIdx.x < K) {
         Acc a = red[0][threadIdx.x];
         for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
-        partials[((int64_t)slot * K + threadIdx.x) * cap + blockIdx.x] = make_double2(a.p, a.s);
+        partials[((int64_t)slot * K + threadIdx.x) * cap + br.part] = make_double2(a.p, a.s);
     }
 }
 
@@ -462,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
     if (gs.flags[0]) return;
     constexpr int R = 64 / K;
     const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane % K, rsub = lane / K;
     const int g = br.sys * K + c;
@@ -471,8 +511,9 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
         double al[kTMax];
 #pragma unroll
         for (int j = 0; j < kTMax; ++j) al[j] = gs.alpha[(int64_t)g * kTMax + j];
-        for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
-            const int64_t e = row * K + c;
+        for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+             it = brow_next(br, R, wave, rsub, it)) {
+            const int64_t e = (int64_t)it.row * K + c;
             double ri = (double)r[e];
             if (gs.minnorm) {
                 double yi = yv[e];
@@ -499,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
     if (threadIdx.x < K) {
         Acc a = red[0][threadIdx.x];
         for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
-        partials[(int64_t)threadIdx.x * cap + blockIdx.x] = make_double2(a.p, a.s);
+        partials[(int64_t)threadIdx.x * cap + br.part] = make_double2(a.p, a.s);
     }
 }
 
@@ -511,6 +552,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, double *xv,
     if (gs.flags[0]) return;
     constexpr int R = 64 / K;
     const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane % K, rsub = lane / K;
     const int g = br.sys * K + c;
@@ -518,8 +560,9 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, double *xv,
     double al[kTMax];
 #pragma unroll
     for (int j = 0; j < kTMax; ++j) al[j] = gs.alpha[(int64_t)g * kTMax + j];
-    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
-        const int64_t e = row * K + c;
+    for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+         it = brow_next(br, R, wave, rsub, it)) {
+        const int64_t e = (int64_t)it.row * K + c;
         double xi = xv[e];
         for (int j = 0; j < gs.t; ++j) xi = __fma_rn(al[j], (double)((const X *)W.p[j])[e], xi);
         xv[e] = xi;
@@ -585,12 +628,14 @@ __global__ __launch_bounds__(kBlock) void k_breplace(const double *__restrict__ 
     if (!gs.flags[1]) return;
     constexpr int R = 64 / K;
     const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane % K, rsub = lane / K;
     const int g = br.sys * K + c;
     if (!gs.repl[g]) return;
-    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R)
-        r[row * K + c] = (X)rt[row * K + c];
+    for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+         it = brow_next(br, R, wave, rsub, it))
+        r[(int64_t)it.row * K + c] = (X)rt[(int64_t)it.row * K + c];
 }
 
 // Flags: [0] every group finished, [1] some group waits for a check.
@@ -710,12 +755,14 @@ __global__ __launch_bounds__(kBlock) void k_binit(const double *__restrict__ b, 
                                                    double2 *partials, int64_t cap) {
     constexpr int R = 64 / K;
     const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane % K, rsub = lane / K;
     Acc part = {0.0, 0.0};
-    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
-        const double v = b[row * K + c];
-        r[row * K + c] = (X)v;
+    for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+         it = brow_next(br, R, wave, rsub, it)) {
+        const double v = b[(int64_t)it.row * K + c];
+        r[(int64_t)it.row * K + c] = (X)v;
         acc_fma(part, v, v);
     }
 #pragma unroll
@@ -731,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_binit(const double *__restrict__ b, 
     if (threadIdx.x < K) {
         Acc a = red[0][threadIdx.x];
         for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
-        partials[(int64_t)threadIdx.x * cap + blockIdx.x] = make_double2(a.p, a.s);
+        partials[(int64_t)threadIdx.x * cap + br.part] = make_double2(a.p, a.s);
     }
 }
 
@@ -775,6 +822,7 @@ struct BatchPlan {
     int64_t M = 0, N = 0, nnz = 0;
     std::vector<int64_t> ro, co;  // row / column offsets of the systems (nsys + 1)
     std::vector<int32_t> h_arp, h_trp;  // host copies of the row pointers of A and A^T
+    std::vector<uint8_t> square;        // 1 where system s has m_s == n_s
     int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr;
     double *a_val = nullptr, *t_val = nullptr;
     void *a_low = nullptr, *t_low = nullptr;
@@ -795,6 +843,7 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
     P->precision = precision;
     P->ro.assign(nsys + 1, 0);
     P->co.assign(nsys + 1, 0);
+    P->square.assign(nsys, 0);
     int64_t nnz = 0;
     for (int32_t i = 0; i < nsys; ++i) {
         int rc = validate_mat(&A[i]);
@@ -802,6 +851,7 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
         if (A[i].kind != TA_CSR) return TA_EINVAL;
         P->ro[i + 1] = P->ro[i] + A[i].m;
         P->co[i + 1] = P->co[i] + A[i].n;
+        P->square[i] = A[i].m == A[i].n;
         nnz += A[i].nnz;
     }
     P->M = P->ro[nsys];
@@ -876,40 +926,108 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
 // Block table over the rows of every system, balanced by nonzeros: about
 // max(1024, nnz K / 2^18) blocks in all, shared out in proportion to each
 // system's nonzeros (at least one per system with rows).
+// Block table of one launch over the rows of the systems that take part
+// (nrhs[s] > 0, or all if nrhs is null).  About max(1024, nnz K / 2^18)
+// workgroups in all.  Each system is one unit, or for a system heavier than
+// 1/16 of the total (weight = nonzeros + rows) several units of contiguous
+// rows of about that weight; a unit gets workgroups in proportion to its
+// weight, which interleave over its rows in chunks (BRange).  `first[s]` is the index
+// of system s's first workgroup in system order.
+//
+// Dispatch order: workgroup b of a launch runs on XCD b mod 8, and each XCD
+// has its own L2.  The units are dealt to the 8 XCDs heaviest first, each to
+// the least loaded one; entry 8 i + x of the table is the i-th workgroup of
+// XCD x's list (its units in system order), and shorter lists are padded with
+// empty entries.  A system's rows therefore share one L2 (a large system: one
+// contiguous share per XCD).
 static void make_blocks(const std::vector<int64_t> &off, const std::vector<int32_t> &rp, int K,
                         std::vector<BRange> &tab, std::vector<int32_t> &first,
-                        const int32_t *nrhs = nullptr) {
-    // systems with no right-hand side in this run (nrhs[s] == 0) get no blocks
+                        const int32_t *nrhs = nullptr, const uint8_t *sq = nullptr) {
+    constexpr int kX = 8;
+    const size_t nsys = off.size() - 1;
     auto active = [&](size_t sidx) { return nrhs == nullptr || nrhs[sidx] > 0; };
-    int64_t total_nnz = 0;
-    for (size_t sidx = 0; sidx + 1 < off.size(); ++sidx)
-        if (active(sidx)) total_nnz += rp[off[sidx + 1]] - rp[off[sidx]];
+    auto weight = [&](int64_t r0, int64_t r1) { return (int64_t)(rp[r1] - rp[r0]) + (r1 - r0); };
+    int64_t total_nnz = 0, total_w = 0;
+    for (size_t sidx = 0; sidx < nsys; ++sidx)
+        if (active(sidx)) {
+            total_nnz += rp[off[sidx + 1]] - rp[off[sidx]];
+            total_w += weight(off[sidx], off[sidx + 1]);
+        }
     const int64_t target = std::max<int64_t>(1024, cdivh(total_nnz * K, 1 << 18));
+    struct Unit {
+        int32_t r0, r1, sys;
+        int64_t w, b0, nb;  // first workgroup (system order) and count
+    };
+    std::vector<Unit> units;
     tab.clear();
     first.assign(off.size(), 0);
-    for (size_t sidx = 0; sidx + 1 < off.size(); ++sidx) {
-        first[sidx] = (int32_t)tab.size();
+    int64_t nlog = 0;
+    for (size_t sidx = 0; sidx < nsys; ++sidx) {
+        first[sidx] = (int32_t)nlog;
         const int64_t r0 = off[sidx], r1 = off[sidx + 1];
         if (r1 <= r0 || !active(sidx)) continue;
-        const int64_t nnz_s = rp[r1] - rp[r0];
-        int64_t nb = total_nnz > 0 ? (target * nnz_s + total_nnz - 1) / total_nnz : 1;
-        nb = std::max<int64_t>(1, std::min<int64_t>(nb, r1 - r0));
-        const double per = (double)std::max<int64_t>(nnz_s, 1) / (double)nb;
+        // a system heavier than 1/16 of the total is cut into a multiple of 8
+        // pieces, so that the XCDs can take equal shares of it
+        const int64_t ws = weight(r0, r1);
+        int64_t pieces = cdivh(ws * 2 * kX, std::max<int64_t>(total_w, 1));
+        if (pieces > 1) pieces = kX * cdivh(pieces, kX);
+        pieces = std::max<int64_t>(1, std::min<int64_t>(pieces, r1 - r0));
         int64_t start = r0;
-        for (int64_t bi = 1; bi <= nb && start < r1; ++bi) {
-            int64_t end;
-            if (bi == nb) {
-                end = r1;
-            } else {
-                const int64_t goal = rp[r0] + (int64_t)(per * (double)bi);
+        for (int64_t pi = 1; pi <= pieces && start < r1; ++pi) {
+            int64_t end = r1;
+            if (pi < pieces) {
+                // rows up to the pi-th weight quantile of the system
+                const int64_t goal = ws * pi / pieces;
                 end = start + 1;
-                while (end < r1 && rp[end] < goal) ++end;
+                while (end < r1 && weight(r0, end) < goal) ++end;
             }
-            tab.push_back(BRange{(int32_t)start, (int32_t)end, (int32_t)sidx, 0});
+            Unit u{(int32_t)start, (int32_t)end, (int32_t)sidx, weight(start, end), nlog, 0};
+            u.nb = std::max<int64_t>(1, std::min<int64_t>((target * u.w + total_w - 1) / total_w,
+                                                          end - start));
+            nlog += u.nb;
+            units.push_back(u);
             start = end;
         }
     }
-    first[off.size() - 1] = (int32_t)tab.size();
+    first[nsys] = (int32_t)nlog;
+    // chunk: one tile (0) for square systems, whose rows are taken to gather
+    // near their own index (stencils, banded matrices); else the whole
+    // per-workgroup share, contiguous
+    auto emit = [&](const Unit &u, std::vector<BRange> &dst) {
+        const int64_t rows = u.r1 - u.r0;
+        const bool square = sq != nullptr && sq[u.sys];
+        const int32_t chunk = square ? 0 : (int32_t)cdivh(rows, u.nb);
+        for (int64_t q = 0; q < u.nb; ++q)
+            dst.push_back(BRange{u.r0, u.r1, u.sys, (int32_t)(u.b0 + q), (int32_t)q, (int32_t)u.nb,
+                                 chunk, 0});
+    };
+    if (nlog < 2 * kX) {
+        for (const Unit &u : units) emit(u, tab);
+        return;
+    }
+    std::vector<size_t> order(units.size());
+    for (size_t i = 0; i < units.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return units[a].w > units[b].w; });
+    std::vector<std::vector<size_t>> mine(kX);
+    int64_t load[kX] = {};
+    for (size_t i : order) {
+        int x = 0;
+        for (int y = 1; y < kX; ++y)
+            if (load[y] < load[x]) x = y;
+        load[x] += units[i].w;
+        mine[x].push_back(i);
+    }
+    std::vector<std::vector<BRange>> lists(kX);
+    size_t len = 0;
+    for (int x = 0; x < kX; ++x) {
+        std::sort(mine[x].begin(), mine[x].end());
+        for (size_t i : mine[x]) emit(units[i], lists[x]);
+        len = std::max(len, lists[x].size());
+    }
+    tab.assign(len * kX, BRange{0, 0, 0, -1, 0, 1, 1, 0});
+    for (int x = 0; x < kX; ++x)
+        for (size_t i = 0; i < lists[x].size(); ++i) tab[i * kX + x] = lists[x][i];
 }
 
 // Lanes per row: about a quarter of the nonzeros per row, within the lanes
@@ -930,7 +1048,8 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
 #ifdef TA_SPMM_UNROLL
     constexpr int kU = TA_SPMM_UNROLL;
 #else
-    constexpr int kU = 8;
+    // nonzeros per lane in flight: FP64 vectors hold twice the registers
+    constexpr int kU = sizeof(X) == 8 ? 4 : 8;
 #endif
     k_bspmm<V, X, K, EPI, kU><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y,
                                                       b, tab, gs, partials, cap, slot, gate, L);
@@ -951,8 +1070,8 @@ struct Engine {
 
         std::vector<BRange> ta_tab, tt_tab;
         std::vector<int32_t> a_first, t_first;
-        make_blocks(P.ro, P.h_arp, K, ta_tab, a_first, nrhs);
-        make_blocks(P.co, P.h_trp, K, tt_tab, t_first, nrhs);
+        make_blocks(P.ro, P.h_arp, K, ta_tab, a_first, nrhs, P.square.data());
+        make_blocks(P.co, P.h_trp, K, tt_tab, t_first, nrhs, P.square.data());
         int64_t nnz_run = 0;
         for (int32_t i = 0; i < nsys; ++i)
             if (nrhs[i] > 0) nnz_run += P.h_arp[P.ro[i + 1]] - P.h_arp[P.ro[i]];
@@ -1249,7 +1368,8 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
     const int64_t rows = trans ? P.N : P.M, cols = trans ? P.M : P.N;
     std::vector<BRange> tab;
     std::vector<int32_t> first;
-    make_blocks(trans ? P.co : P.ro, trans ? P.h_trp : P.h_arp, K, tab, first);
+    make_blocks(trans ? P.co : P.ro, trans ? P.h_trp : P.h_arp, K, tab, first, nullptr,
+                P.square.data());
     const int32_t nb = (int32_t)tab.size();
     const int L = pick_row_lanes(P.nnz, rows, Lanes<X, K>::KL);
     Workspace ws(s);
