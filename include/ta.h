@@ -179,12 +179,17 @@ int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts
 
 /* ---- batched solves: many systems, many right-hand sides, one set of kernels ----
  *
- * ta_batch_plan_create concatenates nsys CSR systems (A[0..nsys-1], host array
- * of descriptors, each TA_CSR, sizes m_s x n_s) into one block-diagonal
- * operator on the device, builds its transpose, and, for precision TA_FP32 or
- * TA_BF16, low-precision copies of the values.  The plan copies A's values,
- * so A may change or be freed afterwards.  Totals (sum of m_s, sum of n_s,
- * sum of nnz_s) must stay below 2^31.
+ * ta_batch_plan_create concatenates nsys systems (A[0..nsys-1], host array
+ * of descriptors, sizes m_s x n_s, either all TA_CSR or all
+ * TA_DENSE_ROWMAJOR; a mix is TA_EINVAL) into one block-diagonal operator on
+ * the device, builds its transpose, and, for precision TA_FP32 or TA_BF16,
+ * low-precision copies of the values.  The plan copies A's values, so A may
+ * change or be freed afterwards.  Totals (sum of m_s, sum of n_s, and for
+ * CSR sum of nnz_s) must stay below 2^31.  Dense systems are stored with rows
+ * padded to a multiple of 16 and run their products on the matrix cores
+ * (MFMA: FP64 16x16x4 in FP64, FP32 16x16x4 in TA_FP32, BF16 16x16x16 with
+ * FP32 accumulation in TA_BF16, where the vector entries are rounded to BF16
+ * too); their FP64 products are plain (not compensated) sums.
  *
  * cta_solve_batched runs Algorithm 1 (CTA, H = A_s A_s^T) independently for
  * every (system s, right-hand side c), all advanced together:
@@ -198,9 +203,10 @@ int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts
  *   minnorm : 1 = the y-form of cta_minnorm (x = A^T y), 0 = the x-form;
  *   info : host, sum k_s entries, system-major (s, then c): iterations, products,
  *          stop code, FP64 true relative residual, normal-equation residual.
- * TA_FP64: each (s, c) follows exactly the single-right-hand-side iteration
- * (same iteration count and stop code as cta_solve / cta_minnorm on that
- * column).  TA_FP32 / TA_BF16: products of the Krylov chain use the low
+ * TA_FP64 on CSR systems: each (s, c) follows exactly the single-right-hand-
+ * side iteration (same iteration count and stop code as cta_solve /
+ * cta_minnorm on that column); on dense systems it follows it up to the
+ * rounding of the plain matrix-core sums.  TA_FP32 / TA_BF16: products of the Krylov chain use the low
  * precision copies and FP32 vectors; Gram entries, steps, x (or y) and every
  * true-residual check are FP64, and the true residual replaces the recurrence
  * residual after every chunk; stop codes and residuals refer to FP64.

@@ -395,14 +395,17 @@ PRECISIONS = {"fp64": TA_FP64, "fp32": TA_FP32, "bf16": TA_BF16}
 
 
 class BatchPlan:
-    """Block-diagonal operator over several CSR systems (ta_batch_plan), with
-    low-precision copies of the values for ``precision`` 'fp32' or 'bf16'."""
+    """Block-diagonal operator over several systems (ta_batch_plan), all CSR or
+    all dense, with low-precision copies of the values for ``precision``
+    'fp32' or 'bf16'.  Dense systems run their products on the matrix cores."""
 
     def __init__(self, systems, precision: str = "fp64"):
         lib = load_library()
         self.systems = [to_device(A) for A in systems]
-        if any(d.kind != TA_CSR for d in self.systems):
-            raise TaError("batched solves take CSR systems")
+        kinds = {d.kind for d in self.systems}
+        if len(kinds) != 1:
+            raise TaError("a batch holds CSR systems or dense systems, not both")
+        self.dense = kinds == {TA_DENSE_ROWMAJOR}
         self.precision = PRECISIONS[precision]
         descs = (TaMat * len(self.systems))(*[d.desc() for d in self.systems])
         h = C.c_void_p()

@@ -381,6 +381,276 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
     }
 }
 
+// ---------------------------------------------------------------------------
+// Dense systems: Y = M X (or B - M X) with matrix cores.
+//
+// A dense batch stores every system's matrix (and, separately, its transpose)
+// row-major with a row stride padded with zeros to a multiple of 16.  One
+// workgroup computes a tile of 64 rows of one system against all K columns:
+// wave w takes rows 16 w .. 16 w + 15, as ceil(K / 16) output tiles of 16 x 16
+// on the MFMA unit.  Per step of 16 matrix columns the workgroup stages the
+// 16 x K slice of X in LDS (converted to the instruction's input type and
+// stored column by column), each lane loads 4 consecutive matrix entries of
+// its row, and the products run as
+//   FP64: v_mfma_f64_16x16x4f64, 4 instructions per column tile,
+//   FP32: v_mfma_f32_16x16x4f32, 4 instructions per column tile,
+//   BF16: v_mfma_f32_16x16x16bf16_1k, 1 instruction per column tile (the FP32
+//         vector entries are rounded to BF16 on the way into LDS).
+// Lane l supplies row l % 16 and matrix columns 16 s + 4 (l / 16) + e; the
+// instructions sum over l / 16, so every column of the step is covered once.
+// The epilogues are those of the sparse kernel.
+struct DSys {
+    int64_t off;   // offset of the system's matrix in the packed array
+    int32_t ld;    // row stride (elements): a multiple of 16, zero padded
+    int32_t cols;  // columns of the matrix = rows of the input block it multiplies
+    int32_t x0;    // the system's first row in the input block
+    int32_t y0;    // the system's first row in the output block
+};
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bf4 __attribute__((ext_vector_type(4)));
+
+template <typename V>
+struct MfmaOp;
+template <>
+struct MfmaOp<double> {
+    using In = double;     // LDS / operand element
+    using Acc4 = dbl4;
+    using AccT = double;
+    // D entry v of lane l: row l / 16 + 4 v, column l % 16
+    __device__ static int drow(int l, int v) { return l / 16 + 4 * v; }
+    __device__ static In conv(double x) { return x; }
+    __device__ static void step(const In (&a)[4], const In (&b)[4], Acc4 &acc) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], acc, 0, 0, 0);
+    }
+};
+template <>
+struct MfmaOp<float> {
+    using In = float;
+    using Acc4 = flt4;
+    using AccT = float;
+    // D entry v of lane l: row 4 (l / 16) + v, column l % 16
+    __device__ static int drow(int l, int v) { return 4 * (l / 16) + v; }
+    __device__ static In conv(float x) { return x; }
+    __device__ static void step(const In (&a)[4], const In (&b)[4], Acc4 &acc) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[e], acc, 0, 0, 0);
+    }
+};
+template <>
+struct MfmaOp<uint16_t> {
+    using In = uint16_t;
+    using Acc4 = flt4;
+    using AccT = float;
+    __device__ static int drow(int l, int v) { return 4 * (l / 16) + v; }
+    __device__ static In conv(float x) { return f32_to_bf16(x); }
+    __device__ static void step(const In (&a)[4], const In (&b)[4], Acc4 &acc) {
+        bf4 av, bv;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            av[e] = (short)a[e];
+            bv[e] = (short)b[e];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+};
+
+// Split over the matrix columns: with nseg > 1, workgroup b takes tile
+// b / nseg and the seg = b % nseg-th share of the columns (a multiple of 16),
+// and writes its raw sums to part_y[seg][row][c] (rows of the whole output
+// block); k_bgemm_fin adds the shares in order and applies the epilogue.
+template <typename V, typename X, int K, int EPI>
+__global__ __launch_bounds__(kBlock) void k_bgemm(const V *__restrict__ mat,
+                                                   const DSys *__restrict__ dsys,
+                                                   const X *__restrict__ x, X *y,
+                                                   const double *__restrict__ b,
+                                                   const BRange *__restrict__ blocks, Groups gs,
+                                                   double2 *partials, int64_t cap, int32_t slot,
+                                                   int32_t gate, int32_t nseg,
+                                                   typename MfmaOp<V>::AccT *part_y,
+                                                   int64_t rows_all) {
+    using Op = MfmaOp<V>;
+    using In = typename Op::In;
+    constexpr int NT = (K + 15) / 16;  // column tiles
+    constexpr int KP = 16 * NT;        // columns held in LDS
+    if (!bgate(gate, gs)) return;
+    const int seg = blockIdx.x % nseg;
+    const BRange br = blocks[blockIdx.x / nseg];
+    if (br.r0 >= br.r1) return;
+    if (gate == kBRun && !gs.sys_active[br.sys]) return;
+    const DSys ds = dsys[br.sys];
+    const int32_t klen = ((ds.ld / 16 + nseg - 1) / nseg) * 16;
+    const int32_t k_lo = min(seg * klen, ds.ld), k_hi = min(k_lo + klen, ds.ld);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane % 16, g = lane / 16;
+    const int64_t arow = (int64_t)br.r0 + wave * 16 + li;  // this lane's A-operand row
+    const bool arow_ok = arow < br.r1;
+    const V *mrow = mat + ds.off + (arow_ok ? (arow - ds.y0) : 0) * (int64_t)ds.ld;
+    // A stage covers KB = 64 matrix columns: lane group g holds columns
+    // kb + 16 g + [0, 16) of its row and feeds them as 4 sub-steps of 4.
+    constexpr int KB = 64;
+    constexpr int LSB = KB + (sizeof(In) == 8 ? 2 : 4);  // LDS column stride (padded)
+    __shared__ In bt[KP * LSB];  // X slice, bt[c * LSB + k]
+    typename Op::Acc4 acc[NT];
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[ct][v] = 0;
+    for (int kb = k_lo; kb < k_hi; kb += KB) {
+        // stage X[kb .. kb+KB)[0 .. KP) (zero outside the share, the system or K),
+        // 4 consecutive columns per thread when K allows
+        constexpr int CW = K >= 4 ? 4 : 1;
+        for (int e = threadIdx.x; e < KB * KP / CW; e += kBlock) {
+            const int k = e / (KP / CW), c = (e % (KP / CW)) * CW;
+            X v[CW];
+#pragma unroll
+            for (int w = 0; w < CW; ++w) v[w] = X(0);
+            if (kb + k < k_hi && kb + k < ds.cols && c < K) {
+                const X *src = x + ((int64_t)ds.x0 + kb + k) * K + c;
+                if constexpr (CW == 4 && sizeof(X) == 4) {
+                    const float4 q = *reinterpret_cast<const float4 *>(src);
+                    v[0] = q.x;
+                    v[1] = q.y;
+                    v[2] = q.z;
+                    v[3] = q.w;
+                } else if constexpr (CW == 4) {
+                    const double2 q0 = *reinterpret_cast<const double2 *>(src);
+                    const double2 q1 = *reinterpret_cast<const double2 *>(src + 2);
+                    v[0] = q0.x;
+                    v[1] = q0.y;
+                    v[2] = q1.x;
+                    v[3] = q1.y;
+                } else {
+                    v[0] = src[0];
+                }
+            }
+#pragma unroll
+            for (int w = 0; w < CW; ++w) bt[(c + w) * LSB + k] = Op::conv(v[w]);
+        }
+        // the lane's 16 matrix entries: one aligned block, inside or outside the share
+        In a[16];
+        if (arow_ok && kb + 16 * g < k_hi) {
+            constexpr int NV = 16 * (int)sizeof(In) / 16;
+            const uint4 *src = reinterpret_cast<const uint4 *>(mrow + kb + 16 * g);
+            uint4 q[NV];
+#pragma unroll
+            for (int w = 0; w < NV; ++w) q[w] = src[w];
+            memcpy(a, q, sizeof a);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) a[e] = In(0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) {
+            In as[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) as[e] = a[4 * ss + e];
+#pragma unroll
+            for (int ct = 0; ct < NT; ++ct) {
+                In bv[4];
+                const In *src = bt + (ct * 16 + li) * LSB + 16 * g + 4 * ss;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) bv[e] = src[e];
+                Op::step(as, bv, acc[ct]);
+            }
+        }
+        __syncthreads();
+    }
+    if (nseg > 1) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+            const int c = ct * 16 + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = (int64_t)br.r0 + wave * 16 + Op::drow(lane, v);
+                if (row < br.r1 && c < K) part_y[((int64_t)seg * rows_all + row) * K + c] = acc[ct][v];
+            }
+        }
+        return;
+    }
+    // epilogue: store, and per-column sums of squares over the tile's rows
+    Acc part[NT];
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct) {
+        part[ct] = Acc{0.0, 0.0};
+        const int c = ct * 16 + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = (int64_t)br.r0 + wave * 16 + Op::drow(lane, v);
+            if (row < br.r1 && c < K) {
+                double yv = (double)acc[ct][v];
+                if constexpr (EPI == kBResid) yv = b[row * K + c] - yv;
+                if constexpr (EPI != kBNormOnly) y[row * K + c] = (X)yv;
+                const double q = (double)(X)yv;
+                acc_fma(part[ct], q, q);
+            }
+        }
+#pragma unroll
+        for (int off = 16; off < 64; off <<= 1) {
+            Acc o;
+            o.p = __shfl_xor(part[ct].p, off);
+            o.s = __shfl_xor(part[ct].s, off);
+            part[ct] = acc_merge(part[ct], o);
+        }
+    }
+    __shared__ Acc red[kBlock / 64][KP];
+    if (lane < 16) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) red[wave][ct * 16 + lane] = part[ct];
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc a = red[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
+        partials[((int64_t)slot * K + threadIdx.x) * cap + br.part] = make_double2(a.p, a.s);
+    }
+}
+
+// Sum of the column shares of k_bgemm (in share order) and the epilogue, per
+// 64-row tile: one lane per (row, column), K columns across the lanes.
+template <typename T, typename X, int K, int EPI>
+__global__ __launch_bounds__(kBlock) void k_bgemm_fin(const T *__restrict__ part_y,
+                                                       int32_t nseg, int64_t rows_all, X *y,
+                                                       const double *__restrict__ b,
+                                                       const BRange *__restrict__ blocks,
+                                                       Groups gs, double2 *partials, int64_t cap,
+                                                       int32_t slot, int32_t gate) {
+    constexpr int R = K >= 64 ? 1 : 64 / K;  // rows per wave
+    if (!bgate(gate, gs)) return;
+    const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1) return;
+    if (gate == kBRun && !gs.sys_active[br.sys]) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int c = lane % K, rsub = lane / K;
+    Acc part = {0.0, 0.0};
+    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
+        double v = 0.0;
+        for (int sg = 0; sg < nseg; ++sg) v += (double)part_y[((int64_t)sg * rows_all + row) * K + c];
+        if constexpr (EPI == kBResid) v = b[row * K + c] - v;
+        if constexpr (EPI != kBNormOnly) y[row * K + c] = (X)v;
+        const double q = (double)(X)v;
+        acc_fma(part, q, q);
+    }
+#pragma unroll
+    for (int off = K; off < 64; off <<= 1) {
+        Acc o;
+        o.p = __shfl_xor(part.p, off);
+        o.s = __shfl_xor(part.s, off);
+        part = acc_merge(part, o);
+    }
+    __shared__ Acc red[kBlock / 64][K];
+    if (lane < K) red[wave][lane] = part;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc a = red[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
+        partials[((int64_t)slot * K + threadIdx.x) * cap + br.part] = make_double2(a.p, a.s);
+    }
+}
+
 // Wave-level reduction of one slot over a block range, 8 loads in flight.
 __device__ double wave_slot_sum(const double2 *p, int32_t b0, int32_t b1) {
     const int lane = threadIdx.x & 63;
@@ -823,6 +1093,12 @@ struct BatchPlan {
     std::vector<int64_t> ro, co;  // row / column offsets of the systems (nsys + 1)
     std::vector<int32_t> h_arp, h_trp;  // host copies of the row pointers of A and A^T
     std::vector<uint8_t> square;        // 1 where system s has m_s == n_s
+    // dense batches (every system TA_DENSE_ROWMAJOR): packed padded copies of
+    // A and A^T (FP64, and the plan precision's copies), per-system layouts
+    bool dense = false;
+    double *d_val = nullptr, *dt_val = nullptr;
+    void *d_low = nullptr, *dt_low = nullptr;
+    DSys *d_sysA = nullptr, *d_sysT = nullptr;
     int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr;
     double *a_val = nullptr, *t_val = nullptr;
     void *a_low = nullptr, *t_low = nullptr;
@@ -835,10 +1111,88 @@ static void bplan_free(BatchPlan *P) {
     P->mem = nullptr;
 }
 
+// Transpose of one dense system: src (m x n, stride lds) -> dst (n x m, stride ldd).
+__global__ __launch_bounds__(kBlock) void k_dense_transpose(int64_t m, int64_t n,
+                                                             const double *__restrict__ src,
+                                                             int64_t lds, double *dst,
+                                                             int64_t ldd) {
+    __shared__ double tile[32][33];
+    const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8
+    for (int r = ty; r < 32; r += 8)
+        if (i0 + r < m && j0 + tx < n) tile[r][tx] = src[(i0 + r) * lds + j0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8)
+        if (j0 + r < n && i0 + tx < m) dst[(j0 + r) * ldd + i0 + tx] = tile[tx][r];
+}
+
+static int bplan_build_dense(int32_t nsys, const ta_mat *A, int32_t precision, hipStream_t s,
+                             BatchPlan *P) {
+    P->dense = true;
+    std::vector<DSys> ha(nsys), ht(nsys);
+    int64_t na = 0, nt = 0;
+    for (int32_t i = 0; i < nsys; ++i) {
+        const int64_t lda = cdivh(std::max<int64_t>(A[i].n, 1), 16) * 16;
+        const int64_t ldt = cdivh(std::max<int64_t>(A[i].m, 1), 16) * 16;
+        ha[i] = DSys{na, (int32_t)lda, (int32_t)A[i].n, (int32_t)P->co[i], (int32_t)P->ro[i]};
+        ht[i] = DSys{nt, (int32_t)ldt, (int32_t)A[i].m, (int32_t)P->ro[i], (int32_t)P->co[i]};
+        na += A[i].m * lda;
+        nt += A[i].n * ldt;
+    }
+    Workspace own(s);
+    own.reserve(&P->d_val, std::max<int64_t>(na, 1));
+    own.reserve(&P->dt_val, std::max<int64_t>(nt, 1));
+    own.reserve(&P->d_sysA, nsys);
+    own.reserve(&P->d_sysT, nsys);
+    float *al32 = nullptr, *tl32 = nullptr;
+    uint16_t *al16 = nullptr, *tl16 = nullptr;
+    if (precision == TA_FP32) {
+        own.reserve(&al32, std::max<int64_t>(na, 1));
+        own.reserve(&tl32, std::max<int64_t>(nt, 1));
+    } else if (precision == TA_BF16) {
+        own.reserve(&al16, std::max<int64_t>(na, 1));
+        own.reserve(&tl16, std::max<int64_t>(nt, 1));
+    }
+    int rc;
+    if ((rc = own.commit()) != TA_OK) return rc;
+    HIP_TRY(hipMemsetAsync(P->d_val, 0, sizeof(double) * (size_t)std::max<int64_t>(na, 1), s));
+    HIP_TRY(hipMemsetAsync(P->dt_val, 0, sizeof(double) * (size_t)std::max<int64_t>(nt, 1), s));
+    for (int32_t i = 0; i < nsys; ++i) {
+        if (A[i].m == 0 || A[i].n == 0) continue;
+        HIP_TRY(hipMemcpy2DAsync(P->d_val + ha[i].off, sizeof(double) * ha[i].ld, A[i].val,
+                                 sizeof(double) * A[i].ld, sizeof(double) * A[i].n, A[i].m,
+                                 hipMemcpyDeviceToDevice, s));
+        if (cdivh(A[i].m, 32) > 65535) return TA_ENOTSUP;
+        const dim3 grid((unsigned)cdivh(A[i].n, 32), (unsigned)cdivh(A[i].m, 32));
+        k_dense_transpose<<<grid, kBlock, 0, s>>>(A[i].m, A[i].n, P->d_val + ha[i].off, ha[i].ld,
+                                                   P->dt_val + ht[i].off, ht[i].ld);
+        HIP_TRY(hipGetLastError());
+    }
+    if (precision == TA_FP32) {
+        k_to_f32<<<grid_for(na), kBlock, 0, s>>>(na, P->d_val, al32);
+        k_to_f32<<<grid_for(nt), kBlock, 0, s>>>(nt, P->dt_val, tl32);
+        P->d_low = al32;
+        P->dt_low = tl32;
+    } else if (precision == TA_BF16) {
+        k_to_bf16<<<grid_for(na), kBlock, 0, s>>>(na, P->d_val, al16);
+        k_to_bf16<<<grid_for(nt), kBlock, 0, s>>>(nt, P->dt_val, tl16);
+        P->d_low = al16;
+        P->dt_low = tl16;
+    }
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(P->d_sysA, ha.data(), sizeof(DSys) * nsys, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(P->d_sysT, ht.data(), sizeof(DSys) * nsys, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    P->mem = own.release();
+    P->s_mem = s;
+    return TA_OK;
+}
+
 static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStream_t s,
                        BatchPlan *P) {
     if (nsys < 1 || A == nullptr) return TA_EINVAL;
     if (precision != TA_FP64 && precision != TA_FP32 && precision != TA_BF16) return TA_EINVAL;
+    const bool dense = A[0].kind == TA_DENSE_ROWMAJOR;
     P->nsys = nsys;
     P->precision = precision;
     P->ro.assign(nsys + 1, 0);
@@ -848,15 +1202,19 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
     for (int32_t i = 0; i < nsys; ++i) {
         int rc = validate_mat(&A[i]);
         if (rc != TA_OK) return rc;
-        if (A[i].kind != TA_CSR) return TA_EINVAL;
+        if (A[i].kind != (dense ? TA_DENSE_ROWMAJOR : TA_CSR)) return TA_EINVAL;
         P->ro[i + 1] = P->ro[i] + A[i].m;
         P->co[i + 1] = P->co[i] + A[i].n;
         P->square[i] = A[i].m == A[i].n;
-        nnz += A[i].nnz;
+        nnz += dense ? A[i].m * A[i].n : A[i].nnz;
     }
     P->M = P->ro[nsys];
     P->N = P->co[nsys];
     P->nnz = nnz;
+    if (dense) {
+        if (P->M >= INT32_MAX || P->N >= INT32_MAX) return TA_ENOTSUP;
+        return bplan_build_dense(nsys, A, precision, s, P);
+    }
     if (P->M >= INT32_MAX || P->N >= INT32_MAX || nnz >= INT32_MAX) return TA_ENOTSUP;
     const int64_t M = P->M, N = P->N, mx = std::max(M, N);
     Workspace own(s), tmp(s);
@@ -1030,6 +1388,23 @@ static void make_blocks(const std::vector<int64_t> &off, const std::vector<int32
         for (size_t i = 0; i < lists[x].size(); ++i) tab[i * kX + x] = lists[x][i];
 }
 
+// Block table of a dense batch: one entry per 64-row tile of every system
+// that takes part, in system order.
+static void make_dense_blocks(const std::vector<int64_t> &off, std::vector<BRange> &tab,
+                              std::vector<int32_t> &first, const int32_t *nrhs = nullptr) {
+    const size_t nsys = off.size() - 1;
+    tab.clear();
+    first.assign(off.size(), 0);
+    for (size_t sidx = 0; sidx < nsys; ++sidx) {
+        first[sidx] = (int32_t)tab.size();
+        if (nrhs != nullptr && nrhs[sidx] == 0) continue;
+        for (int64_t r = off[sidx]; r < off[sidx + 1]; r += 64)
+            tab.push_back(BRange{(int32_t)r, (int32_t)std::min<int64_t>(r + 64, off[sidx + 1]),
+                                 (int32_t)sidx, (int32_t)tab.size(), 0, 1, 64, 0});
+    }
+    first[nsys] = (int32_t)tab.size();
+}
+
 // Lanes per row: about a quarter of the nonzeros per row, within the lanes
 // the columns leave free.
 static int pick_row_lanes(int64_t nnz, int64_t rows, int KL) {
@@ -1055,6 +1430,43 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
                                                       b, tab, gs, partials, cap, slot, gate, L);
 }
 
+// One product of a batched solve: Y = M X (or B - M X for kBResid) with M = A
+// (trans = 0) or A^T (trans = 1) of the plan; V is the matrix element type
+// (double = the FP64 values, float / uint16_t = the plan's low-precision copy).
+// Dense products split over the matrix columns when there are few row tiles:
+// about 2048 workgroups in all, at most 16 shares.
+static int32_t dense_nseg(int32_t nblk) {
+    return (int32_t)std::min<int64_t>(16, std::max<int64_t>(1, cdivh(2048, std::max(nblk, 1))));
+}
+
+template <typename V, typename X, int K, int EPI>
+static void prod(const BatchPlan &P, int trans, const void *x, void *y, const double *b,
+                 const BRange *tab, int32_t nblk, const Groups &gs, double2 *partials,
+                 int64_t cap, int32_t slot, int32_t gate, int32_t L, hipStream_t s,
+                 void *scratch = nullptr) {
+    if (nblk <= 0) return;
+    const bool low = !std::is_same<V, double>::value;
+    if (P.dense) {
+        using T = typename MfmaOp<V>::AccT;
+        const void *m = low ? (trans ? P.dt_low : P.d_low)
+                            : (trans ? (const void *)P.dt_val : (const void *)P.d_val);
+        const int64_t rows_all = trans ? P.N : P.M;
+        const int32_t nseg = scratch != nullptr ? dense_nseg(nblk) : 1;
+        k_bgemm<V, X, K, EPI><<<(unsigned)(nblk * nseg), kBlock, 0, s>>>(
+            (const V *)m, trans ? P.d_sysT : P.d_sysA, (const X *)x, (X *)y, b, tab, gs, partials,
+            cap, slot, gate, nseg, (T *)scratch, rows_all);
+        if (nseg > 1)
+            k_bgemm_fin<T, X, K, EPI><<<nblk, kBlock, 0, s>>>((const T *)scratch, nseg, rows_all,
+                                                               (X *)y, b, tab, gs, partials, cap,
+                                                               slot, gate);
+        return;
+    }
+    const void *val = low ? (trans ? P.t_low : P.a_low)
+                          : (trans ? (const void *)P.t_val : (const void *)P.a_val);
+    spmm<V, X, K, EPI>(trans ? P.t_rp : P.a_rp, trans ? P.t_ci : P.a_ci, val, x, y, b, tab, nblk,
+                       gs, partials, cap, slot, gate, L, s);
+}
+
 // The per-K, per-precision pieces of one solve.
 template <typename V, typename X, int K>
 struct Engine {
@@ -1065,16 +1477,19 @@ struct Engine {
         const int32_t nsys = P.nsys, t = o->t;
         const int64_t M = P.M, N = P.N, G = (int64_t)nsys * K;
         const bool mixed = !std::is_same<V, double>::value;
-        const void *aval = mixed ? P.a_low : (const void *)P.a_val;
-        const void *tval = mixed ? P.t_low : (const void *)P.t_val;
 
         std::vector<BRange> ta_tab, tt_tab;
         std::vector<int32_t> a_first, t_first;
-        make_blocks(P.ro, P.h_arp, K, ta_tab, a_first, nrhs, P.square.data());
-        make_blocks(P.co, P.h_trp, K, tt_tab, t_first, nrhs, P.square.data());
         int64_t nnz_run = 0;
-        for (int32_t i = 0; i < nsys; ++i)
-            if (nrhs[i] > 0) nnz_run += P.h_arp[P.ro[i + 1]] - P.h_arp[P.ro[i]];
+        if (P.dense) {
+            make_dense_blocks(P.ro, ta_tab, a_first, nrhs);
+            make_dense_blocks(P.co, tt_tab, t_first, nrhs);
+        } else {
+            make_blocks(P.ro, P.h_arp, K, ta_tab, a_first, nrhs, P.square.data());
+            make_blocks(P.co, P.h_trp, K, tt_tab, t_first, nrhs, P.square.data());
+            for (int32_t i = 0; i < nsys; ++i)
+                if (nrhs[i] > 0) nnz_run += P.h_arp[P.ro[i + 1]] - P.h_arp[P.ro[i]];
+        }
         const int KLc = Lanes<X, K>::KL, KL64 = Lanes<double, K>::KL;
         int64_t m_run = 0, n_run = 0;
         for (int32_t i = 0; i < nsys; ++i)
@@ -1108,6 +1523,10 @@ struct Engine {
         ws.reserve(&Xc, N * K);
         ws.reserve(&RT, M * K);
         ws.reserve(&TN, N * K);
+        double *DS = nullptr;  // column shares of the dense products
+        if (P.dense)
+            ws.reserve(&DS, (int64_t)dense_nseg(std::max(std::min(na, nt), 1)) *
+                                std::max<int64_t>(std::max(M, N), 1) * K);
         ws.reserve(&partials, (int64_t)nslots * K * cap);
         ws.reserve(&d_ta, std::max(na, 1));
         ws.reserve(&d_tt, std::max(nt, 1));
@@ -1175,8 +1594,8 @@ struct Engine {
         if (na > 0) k_binit<X, K><<<na, kBlock, 0, s>>>(Bc, R, d_ta, partials, cap);
         const bool has_nab = o->tol_normal > 0.0;
         if (has_nab)
-            spmm<double, double, K, kBNormOnly>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt,
-                                                gs, partials, cap, 1, kBAlways, Lt64, s);
+            prod<double, double, K, kBNormOnly>(P, 1, Bc, TN, nullptr, d_tt, nt,
+                                                gs, partials, cap, 1, kBAlways, Lt64, s, DS);
         k_bstep_init<<<gw, kBlock, 0, s>>>(gs, partials, cap, has_nab ? 1 : 0);
         k_bsummary<<<1, kBlock, 0, s>>>(gs, 1);
         HIP_TRY(hipGetLastError());
@@ -1185,10 +1604,10 @@ struct Engine {
             for (int j = 0; j < t; ++j) {
                 const void *uj = j == 0 ? (const void *)R : (const void *)U[j];
                 X *wj = W[minnorm ? 0 : j];
-                spmm<V, X, K, kBNorm>(P.t_rp, P.t_ci, tval, uj, wj, nullptr, d_tt, nt, gs, partials,
-                                      cap, 2 * j, kBRun, Lt, s);
-                spmm<V, X, K, kBNorm>(P.a_rp, P.a_ci, aval, wj, U[j + 1], nullptr, d_ta, na, gs,
-                                      partials, cap, 2 * j + 1, kBRun, La, s);
+                prod<V, X, K, kBNorm>(P, 1, uj, wj, nullptr, d_tt, nt, gs, partials,
+                                      cap, 2 * j, kBRun, Lt, s, DS);
+                prod<V, X, K, kBNorm>(P, 0, wj, U[j + 1], nullptr, d_ta, na, gs,
+                                      partials, cap, 2 * j + 1, kBRun, La, s, DS);
             }
             k_bstep_gram<<<(unsigned)G, kBlock, 0, s>>>(gs, partials, cap);
             BVecs uv{};
@@ -1207,24 +1626,24 @@ struct Engine {
         auto tail = [&]() {
             // true-residual check for waiting groups (every running group when mixed)
             if (minnorm)
-                spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Y, Xc, nullptr, d_tt, nt, gs,
-                                                partials, cap, 1, kBCheck, Lt64, s);
-            spmm<double, double, K, kBResid>(P.a_rp, P.a_ci, P.a_val, Xc, RT, Bc, d_ta, na, gs,
-                                             partials, cap, 0, kBCheck, La64, s);
+                prod<double, double, K, kBNorm>(P, 1, Y, Xc, nullptr, d_tt, nt, gs,
+                                                partials, cap, 1, kBCheck, Lt64, s, DS);
+            prod<double, double, K, kBResid>(P, 0, Xc, RT, Bc, d_ta, na, gs,
+                                             partials, cap, 0, kBCheck, La64, s, DS);
             k_bstep_check<<<gw, kBlock, 0, s>>>(gs, partials, cap, products);
             if (na > 0) k_breplace<X, K><<<na, kBlock, 0, s>>>(RT, R, d_ta, gs);
             k_bsummary<<<1, kBlock, 0, s>>>(gs, 0);
             // exit diagnostics once every group has finished; x (y-form) and
             // b - A x are recomputed only if no check just produced them
             if (minnorm)
-                spmm<double, double, K, kBNorm>(P.t_rp, P.t_ci, P.t_val, Y, Xc, nullptr, d_tt, nt, gs,
-                                                partials, cap, 1, kBFinalNew, Lt64, s);
-            spmm<double, double, K, kBResid>(P.a_rp, P.a_ci, P.a_val, Xc, RT, Bc, d_ta, na, gs,
-                                             partials, cap, 0, kBFinalNew, La64, s);
-            spmm<double, double, K, kBNormOnly>(P.t_rp, P.t_ci, P.t_val, RT, TN, nullptr, d_tt, nt,
-                                                gs, partials, cap, 1, kBFinal, Lt64, s);
-            spmm<double, double, K, kBNormOnly>(P.t_rp, P.t_ci, P.t_val, Bc, TN, nullptr, d_tt, nt,
-                                                gs, partials, cap, 2, kBFinal, Lt64, s);
+                prod<double, double, K, kBNorm>(P, 1, Y, Xc, nullptr, d_tt, nt, gs,
+                                                partials, cap, 1, kBFinalNew, Lt64, s, DS);
+            prod<double, double, K, kBResid>(P, 0, Xc, RT, Bc, d_ta, na, gs,
+                                             partials, cap, 0, kBFinalNew, La64, s, DS);
+            prod<double, double, K, kBNormOnly>(P, 1, RT, TN, nullptr, d_tt, nt,
+                                                gs, partials, cap, 1, kBFinal, Lt64, s, DS);
+            prod<double, double, K, kBNormOnly>(P, 1, Bc, TN, nullptr, d_tt, nt,
+                                                gs, partials, cap, 2, kBFinal, Lt64, s, DS);
         };
 
         int32_t hflags[4] = {0, 0, 0, 0};
@@ -1368,8 +1787,11 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
     const int64_t rows = trans ? P.N : P.M, cols = trans ? P.M : P.N;
     std::vector<BRange> tab;
     std::vector<int32_t> first;
-    make_blocks(trans ? P.co : P.ro, trans ? P.h_trp : P.h_arp, K, tab, first, nullptr,
-                P.square.data());
+    if (P.dense)
+        make_dense_blocks(trans ? P.co : P.ro, tab, first);
+    else
+        make_blocks(trans ? P.co : P.ro, trans ? P.h_trp : P.h_arp, K, tab, first, nullptr,
+                    P.square.data());
     const int32_t nb = (int32_t)tab.size();
     const int L = pick_row_lanes(P.nnz, rows, Lanes<X, K>::KL);
     Workspace ws(s);
@@ -1383,6 +1805,8 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
     ws.reserve(&d_tab, std::max(nb, 1));
     ws.reserve(&gs.flags, 4);
     ws.reserve(&gs.sys_active, P.nsys);
+    double *DS = nullptr;
+    if (P.dense) ws.reserve(&DS, (int64_t)dense_nseg(std::max(nb, 1)) * std::max<int64_t>(rows, 1) * K);
     int rc = ws.commit();
     if (rc != TA_OK) return rc;
     HIP_TRY(hipMemcpyAsync(d_tab, tab.data(), sizeof(BRange) * nb, hipMemcpyHostToDevice, s));
@@ -1390,21 +1814,17 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
     HIP_TRY(hipMemsetAsync(gs.flags, 0, sizeof(int32_t) * 4, s));
     gs.nsys = P.nsys;
     gs.K = K;
-    const int32_t *rp = trans ? P.t_rp : P.a_rp;
-    const int32_t *ci = trans ? P.t_ci : P.a_ci;
-    const void *val = mixed ? (trans ? P.t_low : P.a_low) : (trans ? (const void *)P.t_val
-                                                                   : (const void *)P.a_val);
-    if (val == nullptr) return TA_EINVAL;
+    if (mixed && (P.dense ? P.d_low : P.a_low) == nullptr) return TA_EINVAL;
     const int64_t cap = std::max(nb, 1);
-    spmm<V, X, K, kBNorm>(rp, ci, val, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0,
-                          kBAlways, L, s);
+    prod<V, X, K, kBNorm>(P, trans, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0, kBAlways,
+                          L, s, DS);
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, s));
     for (int32_t i = 0; i < reps; ++i)
-        spmm<V, X, K, kBNorm>(rp, ci, val, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0,
-                              kBAlways, L, s);
+        prod<V, X, K, kBNorm>(P, trans, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0,
+                              kBAlways, L, s, DS);
     HIP_TRY(hipEventRecord(e1, s));
     HIP_TRY(hipEventSynchronize(e1));
     float ms = 0.f;

@@ -206,3 +206,88 @@ def test_uneven_batch_full_size_sampled():
             d = sp @ (xg[:, c] - xo)
             assert np.linalg.norm(d) <= (2e-6 + 1e-12) * np.linalg.norm(b[:, c]), (s, c)
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# dense systems: products on the matrix cores
+# ---------------------------------------------------------------------------
+def _dense_systems(seed=5):
+    g = np.random.default_rng(seed)
+    A = [g.standard_normal((40, 40)) + 8 * np.eye(40),   # well conditioned, square
+         g.standard_normal((70, 50)),                    # tall: least squares
+         g.standard_normal((30, 90)),                    # wide: minimum norm
+         g.standard_normal((17, 17)) + 5 * np.eye(17)]   # ragged tiles
+    ks = [3, 17, 64, 1]
+    B = []
+    for a, k in zip(A, ks):
+        B.append(a @ g.standard_normal((a.shape[1], k)))
+    B[1][:, 0] = g.standard_normal(70)  # inconsistent column
+    return A, B, ks
+
+
+@pytest.mark.parametrize("minnorm", [False, True], ids=["x_form", "y_form"])
+def test_dense_batched_fp64_matches_oracle(minnorm):
+    """FP64 matrix-core products are plain sums, so they agree with the
+    oracle's compensated sums to rounding: equal stop codes, iteration counts
+    within one, x within 1e-9 relative."""
+    A, B, ks = _dense_systems()
+    plan = P.BatchPlan(A, "fp64")
+    assert plan.dense
+    tol, t = 1e-8, 3
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=3000, minnorm=minnorm,
+                                   tol_normal=1e-10)
+    run = oracle.cta_minnorm if minnorm else oracle.cta
+    for s, (a, b) in enumerate(zip(A, B)):
+        xg = host(X[s])
+        for c in range(ks[s]):
+            xo, ho, io = run(a, b[:, c], tol=tol, t=t, max_iter=3000, tol_normal=1e-10)
+            ig = infos[s][c]
+            assert ig.stop == io.stop, (s, c, ig, io)
+            assert abs(ig.iters - io.iters) <= 1, (s, c, ig, io)
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-9 * max(np.linalg.norm(xo), 1e-300), (s, c)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_dense_batched_mixed_reaches_tolerance(prec):
+    """FP32 / BF16 matrix-core products with FP64 refinement: every consistent
+    column stops on the FP64 true residual at 1e-8, and x agrees with the FP64
+    oracle's x within what both residuals allow (||A d|| <= 2e-8 ||b||)."""
+    A, B, ks = _dense_systems()
+    plan = P.BatchPlan(A, prec)
+    tol = 1e-8
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=3, max_iter=2000, minnorm=True,
+                                   precision=prec, tol_normal=1e-10)
+    for s, (a, b) in enumerate(zip(A, B)):
+        xg = host(X[s])
+        for c in range(ks[s]):
+            ig = infos[s][c]
+            if s == 1 and c == 0:
+                # inconsistent: the low-precision products bound how far the
+                # normal-equation residual falls (about FP32 / BF16 rounding)
+                bound = 1e-4 if prec == "fp32" else 0.1
+                assert ig.stop in ("normal", "maxiter") and ig.rel_normal <= bound, ig
+                continue
+            assert ig.stop == "residual" and ig.rel_res <= tol, (s, c, ig)
+            rr = np.linalg.norm(b[:, c] - a @ xg[:, c]) / np.linalg.norm(b[:, c])
+            assert rr <= tol * (1 + 1e-6), (s, c, rr)
+            xo, _, io = oracle.cta_minnorm(a, b[:, c], tol=tol, t=3, max_iter=5000)
+            if io.stop == "residual":
+                d = a @ (xg[:, c] - xo)
+                assert np.linalg.norm(d) <= (2 * tol + 1e-12) * np.linalg.norm(b[:, c]), (s, c)
+    plan.close()
+
+
+def test_dense_batched_timing_hook():
+    A, _, _ = _dense_systems()
+    for prec in ("fp64", "fp32", "bf16"):
+        plan = P.BatchPlan(A, prec)
+        for trans in (False, True):
+            ms = P.batch_time_spmm(plan, 64, trans=trans, precision=prec, reps=3)
+            assert ms > 0
+        plan.close()
+
+
+def test_batch_rejects_mixed_kinds():
+    with pytest.raises(P.TaError):
+        P.BatchPlan([np.eye(4), csr_from_dense(np.eye(4))], "fp64")
