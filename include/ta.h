@@ -100,6 +100,9 @@ typedef struct ta_opts {
     double rho0;           /* ta_solve: initial radius (Algorithm 3 starts from 0) */
     int32_t fixed_rho;     /* ta_solve: 1 = Algorithm 2 (no radius growth, WITNESS exit) */
     int32_t chunk;         /* iterations per host poll of the stop flag; 0 = automatic */
+    int32_t launch_mode;   /* batched solves: 0 = each chunk of iterations is captured once
+                              as a HIP graph and replayed, 1 = kernels launched one by one;
+                              results are identical */
 } ta_opts;
 
 /* Result summary (host struct). */
@@ -211,8 +214,8 @@ int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts
  * true-residual check are FP64, and the true residual replaces the recurrence
  * residual after every chunk; stop codes and residuals refer to FP64.
  * Systems are advanced in groups of equal vector width (k_s rounded up to a
- * power of two), one group after another on `stream`; the results do not
- * depend on the grouping.
+ * power of two), one group after another on `stream`; every column keeps its
+ * own iteration, so the results do not depend on the grouping.
  */
 typedef struct ta_batch_plan ta_batch_plan;
 

@@ -22,6 +22,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -1099,6 +1100,10 @@ struct BatchPlan {
     double *d_val = nullptr, *dt_val = nullptr;
     void *d_low = nullptr, *dt_low = nullptr;
     DSys *d_sysA = nullptr, *d_sysT = nullptr;
+    // row lanes picked by timing for the low-precision products, per
+    // (K, value type, orientation); filled on first use
+    mutable std::mutex tune_mu;
+    mutable std::vector<std::pair<int64_t, int32_t>> tuned;
     int32_t *a_rp = nullptr, *a_ci = nullptr, *t_rp = nullptr, *t_ci = nullptr;
     double *a_val = nullptr, *t_val = nullptr;
     void *a_low = nullptr, *t_low = nullptr;
@@ -1467,6 +1472,64 @@ static void prod(const BatchPlan &P, int trans, const void *x, void *y, const do
                        gs, partials, cap, slot, gate, L, s);
 }
 
+// Autotuner of the SpMM's row lanes L (lanes sharing one row; rows per wave
+// = 64 / (K / CV * L)).  Every power of two from 1 to 64 / (K / CV) is timed
+// on the launch's own block table (one warm-up launch, then 3 timed ones
+// between HIP events), and the fastest is kept in the plan for this
+// (K, value type, orientation).  Dense plans and single candidates need no
+// timing.  x and y are scratch blocks of the launch's input and output shape.
+template <typename V, typename X, int K>
+static int tuned_lanes(const BatchPlan &P, int trans, const BRange *tab, int32_t nblk,
+                       const void *x, void *y, const Groups &gs, double2 *partials, int64_t cap,
+                       int32_t fallback, int32_t *L, hipStream_t s) {
+    *L = fallback;
+    constexpr int KL = Lanes<X, K>::KL;
+    if (P.dense || nblk <= 0 || 64 / KL < 2) return TA_OK;
+    const int64_t key = ((int64_t)K * 16 + (int64_t)sizeof(V)) * 2 + trans;
+    {
+        std::lock_guard<std::mutex> lk(P.tune_mu);
+        for (auto &e : P.tuned)
+            if (e.first == key) {
+                *L = e.second;
+                return TA_OK;
+            }
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 0.f;
+    int32_t best_l = fallback;
+    int rc = TA_OK;
+    for (int32_t l = 1; l <= 64 / KL; l <<= 1) {
+        prod<V, X, K, kBNorm>(P, trans, x, y, nullptr, tab, nblk, gs, partials, cap, 0, kBAlways,
+                              l, s);
+        hipError_t err = hipEventRecord(e0, s);
+        for (int r = 0; r < 3 && err == hipSuccess; ++r)
+            prod<V, X, K, kBNorm>(P, trans, x, y, nullptr, tab, nblk, gs, partials, cap, 0,
+                                  kBAlways, l, s);
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) {
+            hip_msg() = hipGetErrorString(err);
+            rc = TA_EHIP;
+            break;
+        }
+        if (l == 1 || ms < best) {
+            best = ms;
+            best_l = l;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != TA_OK) return rc;
+    *L = best_l;
+    std::lock_guard<std::mutex> lk(P.tune_mu);
+    P.tuned.emplace_back(key, best_l);
+    return TA_OK;
+}
+
 // The per-K, per-precision pieces of one solve.
 template <typename V, typename X, int K>
 struct Engine {
@@ -1497,7 +1560,7 @@ struct Engine {
                 m_run += P.ro[i + 1] - P.ro[i];
                 n_run += P.co[i + 1] - P.co[i];
             }
-        const int La = pick_row_lanes(nnz_run, m_run, KLc), Lt = pick_row_lanes(nnz_run, n_run, KLc);
+        int La = pick_row_lanes(nnz_run, m_run, KLc), Lt = pick_row_lanes(nnz_run, n_run, KLc);
         const int La64 = pick_row_lanes(nnz_run, m_run, KL64),
                   Lt64 = pick_row_lanes(nnz_run, n_run, KL64);
         const int32_t na = (int32_t)ta_tab.size(), nt = (int32_t)tt_tab.size();
@@ -1587,6 +1650,17 @@ struct Engine {
         gs.tol_normal = o->tol_normal;
         const unsigned gw = (unsigned)cdivh(G, 4);  // one wave per group
 
+        // row lanes of the low-precision chain: timed once per plan and K
+        if (mixed && M > 0 && N > 0) {
+            HIP_TRY(hipMemsetAsync(R, 0, sizeof(X) * (size_t)(M * K), s));
+            HIP_TRY(hipMemsetAsync(W[0], 0, sizeof(X) * (size_t)(N * K), s));
+            if ((rc = tuned_lanes<V, X, K>(P, 1, d_tt, nt, R, W[0], gs, partials, cap, Lt, &Lt,
+                                           s)) != TA_OK)
+                return rc;
+            if ((rc = tuned_lanes<V, X, K>(P, 0, d_ta, na, W[0], U[1], gs, partials, cap, La, &La,
+                                           s)) != TA_OK)
+                return rc;
+        }
         // initial state
         if (M > 0)
             k_pack<<<(unsigned)std::min<int64_t>(cdivh(M, 64), 4096), kBlock, 0, s>>>(
@@ -1600,60 +1674,104 @@ struct Engine {
         k_bsummary<<<1, kBlock, 0, s>>>(gs, 1);
         HIP_TRY(hipGetLastError());
 
+        // the stream the chunk's kernels go to: s, or the capture stream
+        hipStream_t cs = s;
         auto iteration = [&]() {
             for (int j = 0; j < t; ++j) {
                 const void *uj = j == 0 ? (const void *)R : (const void *)U[j];
                 X *wj = W[minnorm ? 0 : j];
                 prod<V, X, K, kBNorm>(P, 1, uj, wj, nullptr, d_tt, nt, gs, partials,
-                                      cap, 2 * j, kBRun, Lt, s, DS);
+                                      cap, 2 * j, kBRun, Lt, cs, DS);
                 prod<V, X, K, kBNorm>(P, 0, wj, U[j + 1], nullptr, d_ta, na, gs,
-                                      partials, cap, 2 * j + 1, kBRun, La, s, DS);
+                                      partials, cap, 2 * j + 1, kBRun, La, cs, DS);
             }
-            k_bstep_gram<<<(unsigned)G, kBlock, 0, s>>>(gs, partials, cap);
+            k_bstep_gram<<<(unsigned)G, kBlock, 0, cs>>>(gs, partials, cap);
             BVecs uv{};
             uv.p[0] = R;
             for (int j = 1; j <= t; ++j) uv.p[j] = U[j];
-            if (na > 0) k_bupdate_r<X, K><<<na, kBlock, 0, s>>>(uv, R, Y, d_ta, gs, partials, cap);
+            if (na > 0) k_bupdate_r<X, K><<<na, kBlock, 0, cs>>>(uv, R, Y, d_ta, gs, partials, cap);
             if (!minnorm && nt > 0) {
                 BVecs wv{};
                 for (int j = 0; j < t; ++j) wv.p[j] = W[j];
-                k_bupdate_x<X, K><<<nt, kBlock, 0, s>>>(wv, Xc, d_tt, gs);
+                k_bupdate_x<X, K><<<nt, kBlock, 0, cs>>>(wv, Xc, d_tt, gs);
             }
-            k_bstep_end<<<gw, kBlock, 0, s>>>(gs, partials, cap);
-            k_bsummary<<<1, kBlock, 0, s>>>(gs, 1);
+            k_bstep_end<<<gw, kBlock, 0, cs>>>(gs, partials, cap);
+            k_bsummary<<<1, kBlock, 0, cs>>>(gs, 1);
         };
         const int32_t products = minnorm ? 2 : 1;
         auto tail = [&]() {
             // true-residual check for waiting groups (every running group when mixed)
             if (minnorm)
                 prod<double, double, K, kBNorm>(P, 1, Y, Xc, nullptr, d_tt, nt, gs,
-                                                partials, cap, 1, kBCheck, Lt64, s, DS);
+                                                partials, cap, 1, kBCheck, Lt64, cs, DS);
             prod<double, double, K, kBResid>(P, 0, Xc, RT, Bc, d_ta, na, gs,
-                                             partials, cap, 0, kBCheck, La64, s, DS);
-            k_bstep_check<<<gw, kBlock, 0, s>>>(gs, partials, cap, products);
-            if (na > 0) k_breplace<X, K><<<na, kBlock, 0, s>>>(RT, R, d_ta, gs);
-            k_bsummary<<<1, kBlock, 0, s>>>(gs, 0);
+                                             partials, cap, 0, kBCheck, La64, cs, DS);
+            k_bstep_check<<<gw, kBlock, 0, cs>>>(gs, partials, cap, products);
+            if (na > 0) k_breplace<X, K><<<na, kBlock, 0, cs>>>(RT, R, d_ta, gs);
+            k_bsummary<<<1, kBlock, 0, cs>>>(gs, 0);
             // exit diagnostics once every group has finished; x (y-form) and
             // b - A x are recomputed only if no check just produced them
             if (minnorm)
                 prod<double, double, K, kBNorm>(P, 1, Y, Xc, nullptr, d_tt, nt, gs,
-                                                partials, cap, 1, kBFinalNew, Lt64, s, DS);
+                                                partials, cap, 1, kBFinalNew, Lt64, cs, DS);
             prod<double, double, K, kBResid>(P, 0, Xc, RT, Bc, d_ta, na, gs,
-                                             partials, cap, 0, kBFinalNew, La64, s, DS);
+                                             partials, cap, 0, kBFinalNew, La64, cs, DS);
             prod<double, double, K, kBNormOnly>(P, 1, RT, TN, nullptr, d_tt, nt,
-                                                gs, partials, cap, 1, kBFinal, Lt64, s, DS);
+                                                gs, partials, cap, 1, kBFinal, Lt64, cs, DS);
             prod<double, double, K, kBNormOnly>(P, 1, Bc, TN, nullptr, d_tt, nt,
-                                                gs, partials, cap, 2, kBFinal, Lt64, s, DS);
+                                                gs, partials, cap, 2, kBFinal, Lt64, cs, DS);
         };
 
         int32_t hflags[4] = {0, 0, 0, 0};
         int64_t chunk = o->chunk > 0 ? o->chunk : 4;
         const int64_t chunk_cap = o->chunk > 0 ? o->chunk : (mixed ? 8 : 64);
         std::vector<int64_t> kh(G), kh_prev(G, -1);
+        // Each chunk (iterations + tail) is captured once per length as a HIP
+        // graph on a private stream and replayed on s; launch_mode 1 launches
+        // the kernels one by one instead.
+        struct Graphs {
+            std::vector<std::pair<int64_t, hipGraphExec_t>> ex;
+            hipStream_t cap = nullptr;
+            ~Graphs() {
+                for (auto &e : ex) (void)hipGraphExecDestroy(e.second);
+                if (cap != nullptr) (void)hipStreamDestroy(cap);
+            }
+        } graphs;
+        const bool use_graph = o->launch_mode == 0;
+        auto run_chunk = [&](int64_t n) -> int {
+            if (!use_graph) {
+                cs = s;
+                for (int64_t i = 0; i < n; ++i) iteration();
+                tail();
+                HIP_TRY(hipGetLastError());
+                return TA_OK;
+            }
+            hipGraphExec_t ge = nullptr;
+            for (auto &e : graphs.ex)
+                if (e.first == n) ge = e.second;
+            if (ge == nullptr) {
+                if (graphs.cap == nullptr)
+                    HIP_TRY(hipStreamCreateWithFlags(&graphs.cap, hipStreamNonBlocking));
+                cs = graphs.cap;
+                HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                for (int64_t i = 0; i < n; ++i) iteration();
+                tail();
+                const hipError_t le = hipGetLastError();
+                hipGraph_t gr = nullptr;
+                const hipError_t ce = hipStreamEndCapture(cs, &gr);
+                cs = s;
+                HIP_TRY(le);
+                HIP_TRY(ce);
+                const hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                HIP_TRY(ie);
+                graphs.ex.emplace_back(n, ge);
+            }
+            HIP_TRY(hipGraphLaunch(ge, s));
+            return TA_OK;
+        };
         for (;;) {
-            for (int64_t i = 0; i < chunk; ++i) iteration();
-            tail();
-            HIP_TRY(hipGetLastError());
+            if ((rc = run_chunk(chunk)) != TA_OK) return rc;
             HIP_TRY(hipMemcpyAsync(hflags, gs.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (hflags[0]) break;
@@ -1729,6 +1847,7 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
     if (!(o->tol >= 0.0 && o->tol < 1.0) || !(o->tol_normal >= 0.0 && o->tol_normal < 1.0))
         return TA_EINVAL;
     if (o->t < 1 || o->t > kTMax || o->max_iter < 0 || o->chunk < 0) return TA_EINVAL;
+    if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
     if (minnorm && o->warm_start) return TA_EINVAL;
     if (o->precision != TA_FP64 && o->precision != P.precision) return TA_EINVAL;
     int32_t kmax = 0;
@@ -1745,6 +1864,9 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
     // Systems are run in groups of equal vector width K (the power of two
     // covering their right-hand-side count), narrowest first, so that a
     // system with few right-hand sides does not stream K - k padding columns.
+    // (Cutting wide counts further into power-of-two pieces, e.g. 40 = 32 + 8,
+    // streams fewer padding columns but measured slower: every extra group
+    // repeats the whole iteration sequence.)
     std::vector<int64_t> off(P.nsys);
     int64_t acc = 0;
     for (int32_t i = 0; i < P.nsys; ++i) {
@@ -1793,7 +1915,7 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
         make_blocks(trans ? P.co : P.ro, trans ? P.h_trp : P.h_arp, K, tab, first, nullptr,
                     P.square.data());
     const int32_t nb = (int32_t)tab.size();
-    const int L = pick_row_lanes(P.nnz, rows, Lanes<X, K>::KL);
+    int L = pick_row_lanes(P.nnz, rows, Lanes<X, K>::KL);
     Workspace ws(s);
     X *xin = nullptr, *yout = nullptr;
     double2 *partials = nullptr;
@@ -1816,6 +1938,9 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
     gs.K = K;
     if (mixed && (P.dense ? P.d_low : P.a_low) == nullptr) return TA_EINVAL;
     const int64_t cap = std::max(nb, 1);
+    if (mixed && (rc = tuned_lanes<V, X, K>(P, trans, d_tab, nb, xin, yout, gs, partials, cap, L,
+                                            &L, s)) != TA_OK)
+        return rc;
     prod<V, X, K, kBNorm>(P, trans, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0, kBAlways,
                           L, s, DS);
     hipEvent_t e0, e1;

@@ -47,6 +47,7 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (!(o->tol >= 0.0 && o->tol < 1.0)) return TA_EINVAL;
     if (!(o->tol_normal >= 0.0 && o->tol_normal < 1.0)) return TA_EINVAL;
     if (o->max_iter < 0 || o->replace_every < 0 || o->chunk < 0) return TA_EINVAL;
+    if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
     if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64
     if (solver == 0 || solver == 1) {
         if (o->t < 1 || o->t > kTMax) return TA_EINVAL;
