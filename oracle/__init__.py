@@ -72,6 +72,7 @@ def _load():
         lib.or_cta.restype = C.c_int
         lib.or_cta.argtypes = [C.POINTER(_Mat), P, P, C.POINTER(_Opts), C.c_int, P, C.c_int64,
                                C.POINTER(_Info)]
+        lib.or_csr_outer.argtypes = [C.POINTER(_Mat), P, P, C.c_double, P]
         lib.or_ta.restype = C.c_int
         lib.or_ta.argtypes = [C.POINTER(_Mat), P, P, C.POINTER(_Opts), P, C.c_int64,
                               C.POINTER(_Info)]
@@ -203,3 +204,42 @@ def ta(A, b, tol=1e-6, max_iter=100000, tol_normal=0.0, rho0=0.0, fixed_rho=Fals
     _load().or_ta(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), _ptr(hist), cap, C.byref(inf))
     info = _info(inf)
     return x, hist[:min(info.iters + 1, cap)], info
+
+
+def csr_outer(A, u, v, alpha=1.0) -> np.ndarray:
+    """out[k] = (alpha u_i) v_j for the k-th stored entry (i, j) of a CSR A."""
+    M = _MatRef(A)
+    if M.s.kind != 1:
+        raise ValueError("csr_outer takes a CSR matrix")
+    u, v = _f64(u), _f64(v)
+    out = np.empty(len(A.val))
+    _load().or_csr_outer(C.byref(M.s), _ptr(u), _ptr(v), float(alpha), _ptr(out))
+    return out
+
+
+def cta_grad(A, b, dldx_of_x, tol=1e-12, t=3, max_iter=100000):
+    """Forward solve and adjoint gradient of a loss of x(A, b) = A^{-1} b for a
+    square nonsingular CSR A (not in the paper; the derivative of the solution
+    map).  Algorithm 1 solves A x = b, then A^T lambda = dL/dx on the
+    transposed CSR (built with scipy), and the gradient is dL/db = lambda,
+    dL/da_ij = -lambda_i x_j on the stored pattern.  dldx_of_x maps x to dL/dx.
+    Returns (x, lambda, grad_vals, info_forward, info_adjoint)."""
+    import scipy.sparse as sps
+
+    sp = sps.csr_matrix((np.asarray(A.val, np.float64), np.asarray(A.col_idx),
+                         np.asarray(A.row_ptr)), shape=(A.m, A.n))
+    At = sp.T.tocsr()
+    At.sort_indices()
+
+    class _T:
+        pass
+
+    T = _T()
+    T.m, T.n = A.n, A.m
+    T.row_ptr = At.indptr.astype(np.int32)
+    T.col_idx = At.indices.astype(np.int32)
+    T.val = At.data.astype(np.float64)
+    x, _, fi = cta(A, b, tol=tol, t=t, max_iter=max_iter, hist_cap=1)
+    g = np.asarray(dldx_of_x(x), dtype=np.float64)
+    lam, _, ai = cta(T, g, tol=tol, t=t, max_iter=max_iter, hist_cap=1)
+    return x, lam, csr_outer(A, lam, x, -1.0), fi, ai

@@ -475,3 +475,19 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
     free(c);
     return 0;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Gradient of the solution map (not in the paper)                         */
+/* ---------------------------------------------------------------------- */
+/*
+ * For a square nonsingular A, x(A, b) = A^{-1} b is the limit of Algorithm 1
+ * (Theorem 1 (4) with range(A^T) = R^n).  A loss L(x) has
+ *   dL/db = lambda,   dL/da_ij = -lambda_i x_j,   where A^T lambda = dL/dx.
+ * or_csr_outer writes the second formula on the stored pattern of a CSR A:
+ * out[k] = (alpha * u[i]) * v[j] for the k-th stored entry (i, j).
+ */
+void or_csr_outer(const or_mat *A, const double *u, const double *v, double alpha, double *out) {
+    for (int64_t i = 0; i < A->m; ++i)
+        for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+            out[k] = (alpha * u[i]) * v[A->col_idx[k]];
+}
