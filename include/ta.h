@@ -282,6 +282,19 @@ int ta_transpose(const ta_mat *A, int32_t *at_row_ptr, int32_t *at_col_idx, doub
                  void *stream);
 
 /*
+ * ta_csr_outer - out[k] = (alpha * u[i]) * v[j] for the k-th stored entry
+ * (i, j) of a CSR A (u: m entries, v: n entries, out: nnz entries, all
+ * device).  Not in the paper: it is the gradient of a loss L of the solution
+ * map x(A, b) = A^{-1} b (square nonsingular A, the limit of Algorithm 1,
+ * Theorem 1 (4)) with respect to A's stored values, dL/da_ij = -lambda_i x_j
+ * where A^T lambda = dL/dx, taken with alpha = -1, u = lambda, v = x.  The
+ * CSR is checked on the device first (TA_EINVAL if malformed; this
+ * synchronises `stream`); the product is then enqueued on `stream`.
+ */
+int ta_csr_outer(const ta_mat *A, const double *u, const double *v, double alpha, double *out,
+                 void *stream);
+
+/*
  * ta_time_matvec - measurement hook: average duration (milliseconds, host
  * double *avg_ms) of one launch of the FP64 matrix-product kernel that the
  * solvers use for y = A x (trans = 0) or A^T x (trans = 1), with its fused

@@ -32,7 +32,7 @@ EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror",
            "ta_residual", "ta_transpose", "ta_time_matvec", "ta_plan_create", "ta_plan_destroy",
            "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
            "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched",
-           "ta_batch_time_spmm")
+           "ta_batch_time_spmm", "ta_csr_outer")
 
 
 class TaMat(C.Structure):
@@ -104,6 +104,8 @@ def load_library(path: str = LIB_PATH):
         lib.ta_residual.argtypes = [MP, P, P, P, P, P]
         lib.ta_transpose.restype = C.c_int
         lib.ta_transpose.argtypes = [MP, P, P, P, P]
+        lib.ta_csr_outer.restype = C.c_int
+        lib.ta_csr_outer.argtypes = [MP, P, P, C.c_double, P, P]
         lib.ta_time_matvec.restype = C.c_int
         lib.ta_time_matvec.argtypes = [MP, I32, P, P, I32, C.POINTER(C.c_double), P]
         _lib = lib
@@ -368,6 +370,21 @@ def transpose(A):
                           C.c_void_p(v.data_ptr()), _stream())
     _check(rc, "ta_transpose")
     return rp, ci[: dA.nnz], v[: dA.nnz]
+
+
+def csr_outer(A, u, v, alpha: float = 1.0):
+    """out[k] = (alpha u_i) v_j for the k-th stored entry (i, j) of a CSR A."""
+    import torch
+
+    lib = load_library()
+    dA = to_device(A)
+    ud, vd = _vec(u), _vec(v)
+    out = torch.empty(max(dA.nnz, 1), dtype=torch.float64, device=ud.device)
+    d = dA.desc()
+    rc = lib.ta_csr_outer(C.byref(d), C.c_void_p(ud.data_ptr()), C.c_void_p(vd.data_ptr()),
+                          float(alpha), C.c_void_p(out.data_ptr()), _stream())
+    _check(rc, "ta_csr_outer")
+    return out[: dA.nnz]
 
 
 def time_matvec(A, x, trans: bool = False, reps: int = 50) -> float:

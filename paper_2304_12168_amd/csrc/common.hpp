@@ -166,6 +166,8 @@ hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
                             const int32_t *ci, int32_t *flag, hipStream_t s);
 hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,
                                  int64_t cols, int32_t *seg, hipStream_t s);
+hipError_t launch_csr_outer(int64_t m, const int32_t *rp, const int32_t *ci, const double *u,
+                            const double *v, double alpha, double *out, hipStream_t s);
 hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                             const int32_t *ci, const double *val, int32_t *at_rp,
                             int32_t *at_ci, double *at_val, int32_t *work, int32_t *flag,

@@ -1016,4 +1016,29 @@ hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
     return hipGetLastError();
 }
 
+// out[k] = (alpha * u[i]) * v[j] for the k-th stored entry (i, j): the
+// sparse-pattern outer product of the gradient of the solution map
+// (dL/da_ij = -lambda_i x_j).  One thread per row, entries in storage order.
+__global__ __launch_bounds__(kBlock) void k_csr_outer(int64_t m, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const double *__restrict__ u,
+                                                       const double *__restrict__ v, double alpha,
+                                                       double *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+        const double a = alpha * u[i];
+        const int32_t e = rp[i + 1];
+        for (int32_t k = rp[i]; k < e; ++k) out[k] = a * v[ci[k]];
+    }
+}
+
+hipError_t launch_csr_outer(int64_t m, const int32_t *rp, const int32_t *ci, const double *u,
+                            const double *v, double alpha, double *out, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    const int64_t nb = (m + kBlock - 1) / kBlock;
+    const unsigned g = (unsigned)(nb < 65536 ? nb : 65536);
+    k_csr_outer<<<g, kBlock, 0, s>>>(m, rp, ci, u, v, alpha, out);
+    return hipGetLastError();
+}
+
 }  // namespace ta

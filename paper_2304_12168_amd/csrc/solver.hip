@@ -774,4 +774,22 @@ int ta_transpose(const ta_mat *A, int32_t *at_row_ptr, int32_t *at_col_idx, doub
     return h ? TA_ENOTSUP : TA_OK;
 }
 
+int ta_csr_outer(const ta_mat *A, const double *u, const double *v, double alpha, double *out,
+                 void *stream) {
+    int rc = ta::validate_mat(A);
+    if (rc != TA_OK) return rc;
+    if (A->kind != TA_CSR) return TA_EINVAL;
+    if (A->nnz > 0 && (u == nullptr || v == nullptr || out == nullptr)) return TA_EINVAL;
+    if (A->nnz == 0) return TA_OK;
+    hipStream_t s = (hipStream_t)stream;
+    ta::Workspace ws(s);
+    int32_t *flag = nullptr;
+    ws.reserve(&flag, 8);
+    if ((rc = ws.commit()) != TA_OK) return rc;
+    if ((rc = ta::check_csr_device(A, flag, s)) != TA_OK) return rc;
+    hipError_t e = ta::launch_csr_outer(A->m, A->row_ptr, A->col_idx, u, v, alpha, out, s);
+    if (e != hipSuccess) return ta::hip_fail(e, "csr outer product");
+    return TA_OK;
+}
+
 }  // extern "C"

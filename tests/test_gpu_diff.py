@@ -1,0 +1,120 @@
+"""Differentiable CTA (x(A, b) with the hand-written adjoint) on the GPU,
+against the oracle's adjoint gradient, central finite differences of the GPU's
+own forward solves, and the FP64 oracle for the FP32 forward/adjoint."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2304_12168_amd as P
+from paper_2304_12168_amd.diff import cta_solve_diff
+from workloads import perturbed_stencil
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.load_library()
+    oracle.build(force=False)
+
+
+def _setup(N, seed=0):
+    p = perturbed_stencil(N, sigma=0.1, seed=seed)
+    dev = torch.device("cuda")
+    vals = torch.tensor(p.A.val, dtype=torch.float64, device=dev, requires_grad=True)
+    b = torch.tensor(p.b, dtype=torch.float64, device=dev, requires_grad=True)
+    xt = torch.tensor(p.meta["x_target"], dtype=torch.float64, device=dev)
+    return p, vals, b, xt
+
+
+def test_csr_outer_bit_exact():
+    g = np.random.default_rng(2)
+    A = perturbed_stencil(33, seed=3).A
+    u, v = g.standard_normal(A.m), g.standard_normal(A.n)
+    out = P.csr_outer(A, u, v, -1.0).cpu().numpy()
+    assert np.array_equal(out, oracle.csr_outer(A, u, v, -1.0))
+
+
+def test_gradient_matches_oracle_n400():
+    """FP64, CTA-8 to 1e-10: forward and adjoint iteration counts equal the
+    oracle's, x and both gradients within 1e-9 relative."""
+    p, vals, b, xt = _setup(20)
+    log = []
+    x = cta_solve_diff(p.A, vals, b, tol=1e-10, t=8, max_iter=200000, log=log)
+    ((x - xt) ** 2).sum().backward()
+    xo, lam, gv, fi, ai = oracle.cta_grad(p.A, p.b, lambda z: 2 * (z - p.meta["x_target"]),
+                                          tol=1e-10, t=8, max_iter=200000)
+    (s0, f), (s1, a) = log
+    assert (s0, s1) == ("forward", "adjoint")
+    assert (f.stop, f.iters) == (fi.stop, fi.iters)
+    assert (a.stop, a.iters) == (ai.stop, ai.iters)
+    xg = x.detach().cpu().numpy()
+    assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+    gb = b.grad.cpu().numpy()
+    gA = vals.grad.cpu().numpy()
+    assert np.linalg.norm(gb - lam) <= 1e-9 * np.linalg.norm(lam)
+    assert np.linalg.norm(gA - gv) <= 1e-9 * np.linalg.norm(gv)
+
+
+def test_gradient_matches_central_differences():
+    """h = 1e-6 central differences of the GPU forward solve (CTA-3 to
+    1e-14) against the GPU adjoint gradient."""
+    p, vals, b, xt = _setup(4)
+    kw = dict(tol=1e-14, t=3, max_iter=100000)
+    x = cta_solve_diff(p.A, vals, b, **kw)
+    ((x - xt) ** 2).sum().backward()
+    h = 1e-6
+
+    def L(vv, bb):
+        with torch.no_grad():
+            z = cta_solve_diff(p.A, vv, bb, **kw)
+            return float(((z - xt) ** 2).sum())
+
+    v0, b0 = vals.detach().clone(), b.detach().clone()
+    for i in (0, 6, 15):
+        e = torch.zeros_like(b0)
+        e[i] = h
+        fd = (L(v0, b0 + e) - L(v0, b0 - e)) / (2 * h)
+        assert fd == pytest.approx(float(b.grad[i]), rel=1e-6, abs=1e-9)
+    for k in (0, 9, v0.numel() - 1):
+        d = torch.zeros_like(v0)
+        d[k] = h
+        fd = (L(v0 + d, b0) - L(v0 - d, b0)) / (2 * h)
+        assert fd == pytest.approx(float(vals.grad[k]), rel=1e-6, abs=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_low_precision_forward_adjoint(prec):
+    """FP32 / BF16 products with FP64 refinement for both solves (to 1e-9):
+    the gradients agree with the FP64 oracle's within the a posteriori bound
+    cond(A) x (residuals), here below 1e-4 relative."""
+    p, vals, b, xt = _setup(20)
+    log = []
+    x = cta_solve_diff(p.A, vals, b, tol=1e-9, t=8, max_iter=200000, precision=prec, log=log)
+    ((x - xt) ** 2).sum().backward()
+    assert all(i.stop == "residual" and i.rel_res <= 1e-9 for _, i in log)
+    xo, lam, gv, fi, ai = oracle.cta_grad(p.A, p.b, lambda z: 2 * (z - p.meta["x_target"]),
+                                          tol=1e-11, t=8, max_iter=400000)
+    gb = b.grad.cpu().numpy()
+    gA = vals.grad.cpu().numpy()
+    assert np.linalg.norm(gb - lam) <= 1e-4 * np.linalg.norm(lam)
+    assert np.linalg.norm(gA - gv) <= 1e-4 * np.linalg.norm(gv)
+
+
+@pytest.mark.slow
+def test_full_size_stencil_runs_to_budget():
+    """The 256 x 256 perturbed stencil (n = 65536): FP32 forward and adjoint
+    to an iteration budget (CTA does not reach 1e-6 there with H = A A^T);
+    the residuals fall and the gradients are finite and shaped like the
+    inputs."""
+    p, vals, b, xt = _setup(256)
+    log = []
+    x = cta_solve_diff(p.A, vals, b, tol=1e-6, t=3, max_iter=300, precision="fp32", log=log)
+    ((x - xt) ** 2).sum().backward()
+    assert [s for s, _ in log] == ["forward", "adjoint"]
+    assert all(i.stop == "maxiter" and i.rel_res < 0.5 for _, i in log)
+    assert vals.grad.shape == vals.shape and b.grad.shape == b.shape
+    assert torch.isfinite(vals.grad).all() and torch.isfinite(b.grad).all()
