@@ -272,6 +272,61 @@ def lp_shaped_bench(args, P, torch, dev):
             "speedup": rate / prate, "iterations": max(i.iters for i in inf)}
 
 
+def diff_bench(args, P, torch, dev):
+    """Secondary: the differentiable solve on the 256 x 256 perturbed stencil
+    (n = 65536): FP32 forward and adjoint CTA-3 with FP64 refinement to a
+    budget of 300 iterations each (they do not reach 1e-6 there), plus the
+    sparse-pattern outer product of the A gradient timed alone."""
+    from paper_2304_12168_amd.diff import cta_solve_diff
+    from workloads import perturbed_stencil
+
+    p = perturbed_stencil(256, sigma=0.1, seed=args.seed)
+    vals = torch.tensor(p.A.val, dtype=torch.float64, device=dev, requires_grad=True)
+    b = torch.tensor(p.b, dtype=torch.float64, device=dev, requires_grad=True)
+    xt = torch.tensor(p.meta["x_target"], dtype=torch.float64, device=dev)
+    budget = 300
+
+    def step():
+        vals.grad = None
+        b.grad = None
+        rec = []
+        x = cta_solve_diff(p.A, vals, b, tol=1e-6, t=3, max_iter=budget, precision="fp32",
+                           log=rec)
+        ((x - xt) ** 2).sum().backward()
+        return rec
+
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 2
+    for _ in range(reps):
+        solves = step()
+    torch.cuda.synchronize()
+    fb_ms = 1e3 * (time.perf_counter() - t0) / reps
+    iters = sum(i.iters for _, i in solves)
+    # one ta_csr_outer call (device CSR check, a host synchronisation, then the
+    # product kernel), on the current stream
+    A = P.to_device(p.A)
+    u = torch.randn(p.A.m, dtype=torch.float64, device=dev)
+    v = torch.randn(p.A.n, dtype=torch.float64, device=dev)
+    P.csr_outer(A, u, v, -1.0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        P.csr_outer(A, u, v, -1.0)
+    e1.record()
+    torch.cuda.synchronize()
+    outer_ms = e0.elapsed_time(e1) / 20
+    log(f"[bench] differentiable 256^2: forward+backward {fb_ms:.1f} ms ({iters} iterations), "
+        f"outer-product call {outer_ms * 1e3:.1f} us")
+    return {"workload": "perturbed 5-point stencil 256x256 (n=65536, sigma=0.1), loss "
+                        "||x - x_target||^2, FP32 forward + adjoint CTA-3 with FP64 refinement, "
+                        f"budget {budget} iterations each",
+            "forward_backward_ms": fb_ms, "iterations": iters,
+            "iterations_per_s": iters / (fb_ms * 1e-3),
+            "outer_product_call_us": outer_ms * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,6 +342,8 @@ def main():
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
     ap.add_argument("--lp-steps", type=int, default=5)
     ap.add_argument("--no-lp", action="store_true", help="skip the LP-shaped secondary block")
+    ap.add_argument("--no-diff", action="store_true",
+                    help="skip the differentiable-solve secondary block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -309,6 +366,8 @@ def main():
     res = batched_uneven_bench(args, P, torch, dev)
     if not args.no_lp:
         res["config"]["lp_shaped"] = lp_shaped_bench(args, P, torch, dev)
+    if not args.no_diff:
+        res["config"]["differentiable"] = diff_bench(args, P, torch, dev)
     out = {
         "metric": "solves/s and HBM GB/s to rel-residual 1e-6: CTA mixed+batched vs FP64 plain",
         "value": res["value"],

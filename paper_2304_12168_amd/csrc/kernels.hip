@@ -1018,17 +1018,33 @@ hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
 
 // out[k] = (alpha * u[i]) * v[j] for the k-th stored entry (i, j): the
 // sparse-pattern outer product of the gradient of the solution map
-// (dL/da_ij = -lambda_i x_j).  One thread per row, entries in storage order.
+// (dL/da_ij = -lambda_i x_j).  A block takes 256 consecutive rows, stages
+// their row pointers in LDS, and its threads walk the rows' entries in
+// storage order (coalesced index loads and stores); each finds its row by
+// binary search in LDS (the last row whose start is <= k).
 __global__ __launch_bounds__(kBlock) void k_csr_outer(int64_t m, const int32_t *__restrict__ rp,
                                                        const int32_t *__restrict__ ci,
                                                        const double *__restrict__ u,
                                                        const double *__restrict__ v, double alpha,
                                                        double *__restrict__ out) {
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
-         i += (int64_t)gridDim.x * kBlock) {
-        const double a = alpha * u[i];
-        const int32_t e = rp[i + 1];
-        for (int32_t k = rp[i]; k < e; ++k) out[k] = a * v[ci[k]];
+    __shared__ int32_t srp[kBlock + 1];
+    for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < m; r0 += (int64_t)gridDim.x * kBlock) {
+        const int rows = (int)((m - r0) < kBlock ? (m - r0) : kBlock);
+        for (int t = threadIdx.x; t <= rows; t += kBlock) srp[t] = rp[r0 + t];
+        __syncthreads();
+        const int32_t k1 = srp[rows];
+        for (int32_t k = srp[0] + threadIdx.x; k < k1; k += kBlock) {
+            int lo = 0, hi = rows - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (srp[mid] <= k)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            out[k] = (alpha * u[r0 + lo]) * v[ci[k]];
+        }
+        __syncthreads();
     }
 }
 

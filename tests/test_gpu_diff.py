@@ -38,6 +38,22 @@ def test_csr_outer_bit_exact():
     assert np.array_equal(out, oracle.csr_outer(A, u, v, -1.0))
 
 
+def test_csr_outer_empty_rows_ragged():
+    """Rows with no entries (runs of them, at block edges and at the end) and
+    a row count that is not a multiple of the block."""
+    from workloads import csr_from_coo
+
+    g = np.random.default_rng(8)
+    m, n = 1001, 700
+    rows = g.integers(0, m, 3000)
+    rows = rows[(rows % 7 != 0) & (rows < 990) & ((rows < 250) | (rows > 262))]
+    cols = g.integers(0, n, rows.size)
+    A = csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
+    u, v = g.standard_normal(m), g.standard_normal(n)
+    out = P.csr_outer(A, u, v, 0.37).cpu().numpy()
+    assert np.array_equal(out, oracle.csr_outer(A, u, v, 0.37))
+
+
 def test_gradient_matches_oracle_n400():
     """FP64, CTA-8 to 1e-10: forward and adjoint iteration counts equal the
     oracle's, x and both gradients within 1e-9 relative."""
