@@ -76,6 +76,9 @@ def _load():
         lib.or_ta.restype = C.c_int
         lib.or_ta.argtypes = [C.POINTER(_Mat), P, P, C.POINTER(_Opts), P, C.c_int64,
                               C.POINTER(_Info)]
+        lib.or_ta_minnorm.restype = C.c_int64
+        lib.or_ta_minnorm.argtypes = [C.POINTER(_Mat), P, P, P, C.POINTER(_Opts),
+                                      C.POINTER(_Info)]
         _lib = lib
     return _lib
 
@@ -192,14 +195,15 @@ def cta_minnorm(A, b, **kw):
 
 
 def ta(A, b, tol=1e-6, max_iter=100000, tol_normal=0.0, rho0=0.0, fixed_rho=False,
-       hist_cap: Optional[int] = None):
-    """Algorithm 3 (or Algorithm 2 with ``fixed_rho``).  Returns (x, hist, info)."""
+       hist_cap: Optional[int] = None, x0: Optional[np.ndarray] = None):
+    """Algorithm 3 (or Algorithm 2 with ``fixed_rho``), from x0 (b' = A x0) if
+    given, else from 0.  Returns (x, hist, info)."""
     M = _MatRef(A)
     b = _f64(b)
     cap = int(max_iter) + 1 if hist_cap is None else int(hist_cap)
     hist = np.full(max(cap, 1), np.nan)
-    x = np.zeros(M.n)
-    o = _opts(tol, tol_normal, 1, max_iter, 0, 0, rho0, fixed_rho)
+    x = np.zeros(M.n) if x0 is None else _f64(x0).copy()
+    o = _opts(tol, tol_normal, 1, max_iter, 0, x0 is not None, rho0, fixed_rho)
     inf = _Info()
     _load().or_ta(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), _ptr(hist), cap, C.byref(inf))
     info = _info(inf)
@@ -243,3 +247,17 @@ def cta_grad(A, b, dldx_of_x, tol=1e-12, t=3, max_iter=100000):
     g = np.asarray(dldx_of_x(x), dtype=np.float64)
     lam, _, ai = cta(T, g, tol=tol, t=t, max_iter=max_iter, hist_cap=1)
     return x, lam, csr_outer(A, lam, x, -1.0), fi, ai
+
+
+def ta_minnorm(A, b, x_eps, tol=1e-6, max_iter=100000, tol_normal=0.0):
+    """Algorithm 4: from an approximate solution x_eps, bisect on the radius
+    with Algorithm 2 tests.  Returns (x, info, tests); info.rho and
+    info.rho_lo are the final upper and lower bounds on the norm."""
+    M = _MatRef(A)
+    b, xe = _f64(b), _f64(x_eps)
+    x = np.zeros(M.n)
+    o = _opts(tol, tol_normal, 1, max_iter, 0, 0, 0.0, False)
+    inf = _Info()
+    tests = _load().or_ta_minnorm(C.byref(M.s), _ptr(b), _ptr(xe), _ptr(x), C.byref(o),
+                                   C.byref(inf))
+    return x, _info(inf), int(tests)

@@ -387,7 +387,7 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
 
     memset(info, 0, sizeof(*info));
     nb = sqrt(or_dot2(m, b, b));
-    memset(x, 0, sizeof(double) * (size_t)n);
+    if (!o->warm_start || nb == 0.0) memset(x, 0, sizeof(double) * (size_t)n);
     if (nb == 0.0) {
         if (hist_cap > 0) hist[0] = 0.0;
         info->stop = OR_RESIDUAL;
@@ -403,6 +403,10 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
     if (o->tol_normal > 0.0) {
         or_apply_t(A, b, c);
         nab = sqrt(or_dot2(n, c, c));
+        ++matvecs;
+    }
+    if (o->warm_start) {  /* start from the given x: b' = A x */
+        or_apply(A, x, bp);
         ++matvecs;
     }
     for (i = 0; i < m; ++i) r[i] = b[i] - bp[i];
@@ -490,4 +494,81 @@ void or_csr_outer(const or_mat *A, const double *u, const double *v, double alph
     for (int64_t i = 0; i < A->m; ++i)
         for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
             out[k] = (alpha * u[i]) * v[A->col_idx[k]];
+}
+
+/* ---------------------------------------------------------------------- */
+/* TA for an approximate minimum-norm solution (Algorithm 4, section 2.3)  */
+/* ---------------------------------------------------------------------- */
+/*
+ * Given x_eps with ||A x_eps - b|| <= tol ||b||, bisect on the radius rho of
+ * the ellipsoid E_{A, rho}: the upper bound starts at ||x_eps||, the lower
+ * bound at 0, and each test runs Algorithm 2 (TA with the fixed radius
+ * rho = midpoint) until it finds an approximate solution in the ball
+ * (the upper bound drops to rho, the solution is kept) or a witness (the
+ * lower bound rises to (b - b')^T b / ||c|| >= rho, Corollary 1).  Each test
+ * starts from the last witness's x (0 before the first witness).  The loop
+ * ends when upper - lower <= tol * ||x_eps||, when a test ends on the normal
+ * equation (its x is returned), or when the iteration budget o->max_iter,
+ * counted over all tests, runs out.  Corollary 1's bound holds for consistent
+ * systems; if a witness lifts the lower bound above the upper one by more
+ * than the gap tolerance, the input was not an approximate solution of a
+ * consistent system and the stop code is OR_WITNESS (x = the last solution
+ * found, or x_eps).  info: iters and matvecs summed over the tests, rho =
+ * upper bound, rho_lo = lower bound, rel_res / rel_normal of the returned x.
+ * Returns the number of tests.
+ */
+int64_t or_ta_minnorm(const or_mat *A, const double *b, const double *x_eps, double *x,
+                      const or_opts *o, or_info *info) {
+    const int64_t m = A->m, n = A->n;
+    double nb = sqrt(or_dot2(m, b, b));
+    double hi = sqrt(or_dot2(n, x_eps, x_eps)), lo = 0.0;
+    const double gap = o->tol * hi;
+    double *xt = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *xw = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    int have_w = 0, stop = OR_RESIDUAL;
+    int64_t tests = 0, iters = 0, matvecs = 0;
+
+    memset(info, 0, sizeof(*info));
+    memcpy(x, x_eps, sizeof(double) * (size_t)n);
+    if (nb == 0.0) {
+        memset(x, 0, sizeof(double) * (size_t)n);
+        hi = 0.0;
+    }
+    while (nb > 0.0 && hi - lo > gap) {
+        or_opts t = *o;
+        or_info ti;
+        const double rho = 0.5 * (hi + lo);
+        if (iters >= o->max_iter) { stop = OR_MAXITER; break; }
+        t.fixed_rho = 1;
+        t.rho0 = rho;
+        t.warm_start = have_w;
+        t.max_iter = o->max_iter - iters;
+        if (have_w) memcpy(xt, xw, sizeof(double) * (size_t)n);
+        or_ta(A, b, xt, &t, NULL, 0, &ti);
+        ++tests;
+        iters += ti.iters;
+        matvecs += ti.matvecs;
+        if (ti.stop == OR_RESIDUAL) {
+            hi = rho;
+            memcpy(x, xt, sizeof(double) * (size_t)n);
+        } else if (ti.stop == OR_WITNESS) {
+            lo = ti.rho_lo;
+            memcpy(xw, xt, sizeof(double) * (size_t)n);
+            have_w = 1;
+        } else {
+            if (ti.stop == OR_NORMAL) memcpy(x, xt, sizeof(double) * (size_t)n);
+            stop = ti.stop;
+            break;
+        }
+    }
+    if (stop == OR_RESIDUAL && lo - hi > gap) stop = OR_WITNESS;
+    info->iters = iters;
+    info->matvecs = matvecs;
+    info->stop = stop;
+    info->rho = hi;
+    info->rho_lo = lo;
+    if (nb > 0.0) exit_diagnostics(A, b, x, nb, &info->rel_res, &info->rel_normal);
+    free(xt);
+    free(xw);
+    return tests;
 }
