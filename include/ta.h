@@ -147,10 +147,35 @@ int cta_minnorm(const ta_mat *A, const double *b, double *x, const ta_opts *opts
  * Pivot v_rho = rho A c / ||c|| with c = A^T (b - b') (eq. vr), strict-pivot
  * test rho ||c|| >= (b - b')^T b (eq. eqlem2), step to the point of segment
  * [b', v_rho] nearest to b (Proposition prop1TA).  Arguments as cta_solve;
- * opts->t and opts->warm_start are ignored.
+ * opts->t is ignored.  opts->warm_start: start from the x passed in (b' = A x,
+ * one product more); b = 0 still returns x = 0.
  */
 int ta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
              int64_t hist_cap, ta_info *info, void *stream);
+
+/*
+ * ta_minnorm - Algorithm 4 (section 4.3, TA for an approximation to the
+ * minimum-norm solution): from x_eps (device, n doubles, an approximate
+ * solution: ||A x_eps - b|| <= tol ||b||) it bisects on the radius rho of
+ * the ellipsoid E_{A,rho}.  Upper bound hi = ||x_eps||, lower bound lo = 0;
+ * each test runs Algorithm 2 with rho = (hi + lo) / 2 from the last
+ * witness's x (0 before the first witness): an approximate solution in the
+ * ball lowers hi to rho (and becomes the answer), a witness raises lo to
+ * (b - b')^T b / ||c|| (Corollary 1).  Ends when hi - lo <= tol ||x_eps||
+ * (stop RESIDUAL), when a test ends on the normal equation (stop NORMAL, its
+ * x returned), or when opts->max_iter TA iterations (summed over the tests)
+ * are spent (stop MAXITER).  If a witness lifts lo above hi by more than the
+ * gap tolerance, x_eps was no approximate solution of a consistent system
+ * (Corollary 1 needs A x = b solvable): stop WITNESS.
+ *   x     : device, n doubles, output (the last solution found, or x_eps);
+ *   info  : iters / matvecs summed over the tests, rho = hi, rho_lo = lo,
+ *           rel_res / rel_normal of the returned x;
+ *   tests : host, may be NULL: number of Algorithm 2 tests run.
+ * opts->tol, tol_normal, max_iter and chunk are used; fixed_rho, rho0, t and
+ * warm_start are ignored.
+ */
+int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
+               const ta_opts *opts, ta_info *info, int64_t *tests, void *stream);
 
 /* ---- prepared operators (plans) ----
  *
@@ -179,6 +204,8 @@ int cta_minnorm_plan(const ta_plan *plan, const double *b, double *x, const ta_o
                      double *hist, int64_t hist_cap, ta_info *info, void *stream);
 int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
                   double *hist, int64_t hist_cap, ta_info *info, void *stream);
+int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, double *x,
+                    const ta_opts *opts, ta_info *info, int64_t *tests, void *stream);
 
 /* ---- batched solves: many systems, many right-hand sides, one set of kernels ----
  *

@@ -32,7 +32,7 @@ EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror",
            "ta_residual", "ta_transpose", "ta_time_matvec", "ta_plan_create", "ta_plan_destroy",
            "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
            "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched",
-           "ta_batch_time_spmm", "ta_csr_outer")
+           "ta_batch_time_spmm", "ta_csr_outer", "ta_minnorm", "ta_minnorm_plan")
 
 
 class TaMat(C.Structure):
@@ -104,6 +104,11 @@ def load_library(path: str = LIB_PATH):
         lib.ta_residual.argtypes = [MP, P, P, P, P, P]
         lib.ta_transpose.restype = C.c_int
         lib.ta_transpose.argtypes = [MP, P, P, P, P]
+        for name in ("ta_minnorm", "ta_minnorm_plan"):
+            f = getattr(lib, name)
+            f.restype = C.c_int
+            f.argtypes = [P if name.endswith("plan") else MP, P, P, P, OP, IP,
+                          C.POINTER(C.c_int64), P]
         lib.ta_csr_outer.restype = C.c_int
         lib.ta_csr_outer.argtypes = [MP, P, P, C.c_double, P, P]
         lib.ta_time_matvec.restype = C.c_int
@@ -294,10 +299,11 @@ def cta_minnorm(A, b, tol=1e-6, t=3, max_iter=100000, **kw):
     return _solve("cta_minnorm", A, b, tol=tol, t=t, max_iter=max_iter, **kw)
 
 
-def ta_solve(A, b, tol=1e-6, max_iter=100000, rho0=0.0, fixed_rho=False, **kw):
-    """Algorithm 3 (or Algorithm 2 with ``fixed_rho``).  Returns (x, hist, info)."""
-    return _solve("ta_solve", A, b, tol=tol, t=1, max_iter=max_iter, rho0=rho0,
-                  fixed_rho=fixed_rho, **kw)
+def ta_solve(A, b, tol=1e-6, max_iter=100000, rho0=0.0, fixed_rho=False, x0=None, **kw):
+    """Algorithm 3 (or Algorithm 2 with ``fixed_rho``), from x0 (b' = A x0) if
+    given, else from 0.  Returns (x, hist, info)."""
+    return _solve("ta_solve", A, b, x0=x0, tol=tol, t=1, max_iter=max_iter, rho0=rho0,
+                  fixed_rho=fixed_rho, warm_start=x0 is not None, **kw)
 
 
 def validate(A, solver: int = 0, **kw) -> int:
@@ -370,6 +376,34 @@ def transpose(A):
                           C.c_void_p(v.data_ptr()), _stream())
     _check(rc, "ta_transpose")
     return rp, ci[: dA.nnz], v[: dA.nnz]
+
+
+def ta_minnorm(A, b, x_eps, tol=1e-6, max_iter=100000, **kw):
+    """Algorithm 4 from an approximate solution x_eps.  Returns (x, info,
+    tests); info.rho and info.rho_lo are the final upper and lower bounds on
+    the norm of the minimum-norm solution."""
+    import torch
+
+    lib = load_library()
+    bd, xe = _vec(b), _vec(x_eps)
+    opts = make_opts(tol=tol, max_iter=max_iter, **kw)
+    info = TaInfo()
+    tests = C.c_int64(0)
+    if isinstance(A, Plan):
+        x = torch.zeros(A.n, dtype=torch.float64, device=bd.device)
+        rc = lib.ta_minnorm_plan(A.handle, C.c_void_p(bd.data_ptr()), C.c_void_p(xe.data_ptr()),
+                                 C.c_void_p(x.data_ptr()), C.byref(opts), C.byref(info),
+                                 C.byref(tests), _stream())
+        _check(rc, "ta_minnorm_plan")
+    else:
+        dA = to_device(A)
+        d = dA.desc()
+        x = torch.zeros(dA.n, dtype=torch.float64, device=bd.device)
+        rc = lib.ta_minnorm(C.byref(d), C.c_void_p(bd.data_ptr()), C.c_void_p(xe.data_ptr()),
+                            C.c_void_p(x.data_ptr()), C.byref(opts), C.byref(info),
+                            C.byref(tests), _stream())
+        _check(rc, "ta_minnorm")
+    return x, _info(info), int(tests.value)
 
 
 def csr_outer(A, u, v, alpha: float = 1.0):

@@ -72,6 +72,7 @@ enum Post : int32_t {
     kPostTaEnd,       // v0 = ||r||^2, v1 = r^T b after the step
     kPostTaCand,      // v0 = ||b - A x||^2 at a candidate stop
     kPostTaBp,        // v0 = ||r||^2, v1 = r^T b after b' = A x
+    kPostTaWarm,      // v0 = ||r||^2, v1 = r^T b after b' = A x0 (warm start): hist[0], loop top
 };
 
 // Which kernels of a chain run.
@@ -157,7 +158,8 @@ hipError_t launch_cta_update(int64_t m, int64_t n, int32_t t, int32_t minnorm, d
                              double *const *u, double *x, double *const *w, double *y,
                              const Out &o, hipStream_t s, int32_t *blocks);
 hipError_t launch_ta_init(int64_t m, int64_t n, const double *b, double *r, double *bp,
-                          double *x, const Out &o, hipStream_t s, int32_t *blocks);
+                          double *x, int32_t keep_x, const Out &o, hipStream_t s,
+                          int32_t *blocks);
 hipError_t launch_ta_update(int64_t m, int64_t n, const double *b, double *bp, const double *d,
                             double *r, double *x, const double *c, const Out &o, hipStream_t s,
                             int32_t *blocks);
@@ -166,6 +168,8 @@ hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
                             const int32_t *ci, int32_t *flag, hipStream_t s);
 hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,
                                  int64_t cols, int32_t *seg, hipStream_t s);
+hipError_t launch_norm2(int64_t n, const double *x, const Out &o, hipStream_t s,
+                        int32_t *blocks);
 hipError_t launch_csr_outer(int64_t m, const int32_t *rp, const int32_t *ci, const double *u,
                             const double *v, double alpha, double *out, hipStream_t s);
 hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,

@@ -199,6 +199,14 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
                 st->rejected = 1;
             }
             break;
+        case kPostTaWarm:  // warm start: b' = A x, r = b - b'
+            st->matvecs++;
+            st->rr = v[0];
+            st->rb = v[1];
+            st->have_c = 0;
+            put_hist(st, sp.hist);
+            loop_top(st);
+            break;
         case kPostTaBp:
             st->matvecs++;
             st->rr = v[0];
@@ -608,7 +616,8 @@ __global__ __launch_bounds__(kBlock) void k_cta_update(int64_t m, int64_t n, int
 
 __global__ __launch_bounds__(kBlock) void k_ta_init(int64_t m, int64_t n,
                                                      const double *__restrict__ b, double *r,
-                                                     double *bp, double *x, Out o) {
+                                                     double *bp, double *x, int32_t keep_x,
+                                                     Out o) {
     Acc v[1] = {};
     const int64_t N = m > n ? m : n;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
@@ -619,8 +628,17 @@ __global__ __launch_bounds__(kBlock) void k_ta_init(int64_t m, int64_t n,
             r[i] = bi - 0.0;
             acc_fma(v[0], bi, bi);
         }
-        if (i < n) x[i] = 0.0;
+        if (i < n && !keep_x) x[i] = 0.0;
     }
+    block_partials<1>(v, o);
+}
+
+// ||x||^2 as one compensated partial per block.
+__global__ __launch_bounds__(kBlock) void k_norm2(int64_t n, const double *__restrict__ x, Out o) {
+    Acc v[1] = {};
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBlock)
+        acc_fma(v[0], x[i], x[i]);
     block_partials<1>(v, o);
 }
 
@@ -945,10 +963,11 @@ hipError_t launch_cta_update(int64_t m, int64_t n, int32_t t, int32_t minnorm, d
 }
 
 hipError_t launch_ta_init(int64_t m, int64_t n, const double *b, double *r, double *bp,
-                          double *x, const Out &o, hipStream_t s, int32_t *blocks) {
+                          double *x, int32_t keep_x, const Out &o, hipStream_t s,
+                          int32_t *blocks) {
     const int64_t g = elementwise_blocks(m > n ? m : n);
     if (g > o.cap) return hipErrorInvalidValue;
-    k_ta_init<<<dim3((unsigned)g), kBlock, 0, s>>>(m, n, b, r, bp, x, o);
+    k_ta_init<<<dim3((unsigned)g), kBlock, 0, s>>>(m, n, b, r, bp, x, keep_x, o);
     if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }
@@ -1054,6 +1073,15 @@ hipError_t launch_csr_outer(int64_t m, const int32_t *rp, const int32_t *ci, con
     const int64_t nb = (m + kBlock - 1) / kBlock;
     const unsigned g = (unsigned)(nb < 65536 ? nb : 65536);
     k_csr_outer<<<g, kBlock, 0, s>>>(m, rp, ci, u, v, alpha, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm2(int64_t n, const double *x, const Out &o, hipStream_t s,
+                        int32_t *blocks) {
+    const int64_t g = elementwise_blocks(n);
+    if (g > o.cap) return hipErrorInvalidValue;
+    k_norm2<<<dim3((unsigned)g), kBlock, 0, s>>>(n, x, o);
+    if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }
 

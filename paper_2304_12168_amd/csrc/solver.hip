@@ -486,11 +486,19 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     if ((rc = upload_state(c.st, h0, s)) != TA_OK) return rc;
     int32_t g = 0, g2 = 0;
     // slots: 0 ||c||^2; 1, 2: r^T d, ||d||^2; 3, 4: ||r||^2, r^T b
-    HIP_TRY(launch_ta_init(m, n, b, r, bp, x, c.out(3, kGateAlways), s, &g));
-    HIP_TRY(c.step(3, {g}, kPostTaInit, 0, kGateAlways));
+    const int32_t warm = o->warm_start ? 1 : 0;
+    HIP_TRY(launch_ta_init(m, n, b, r, bp, x, warm, c.out(3, kGateAlways), s, &g));
+    HIP_TRY(c.step(3, {g}, kPostTaInit, warm, kGateAlways));
     if (o->tol_normal > 0.0) {
         HIP_TRY(launch_matvec(c.AT, b, cv, kEpiNorm, EpiArgs{}, c.out(0, kGateAlways), s, &g));
         HIP_TRY(c.step(0, {g}, kPostNab, 0, kGateAlways));
+    }
+    if (warm) {  // b' = A x0, r = b - b'
+        EpiArgs ew{};
+        ew.b = b;
+        ew.r_out = r;
+        HIP_TRY(launch_matvec(c.A, x, bp, kEpiTaBp, ew, c.out(3, kGateAlways), s, &g));
+        HIP_TRY(c.step(3, {g, g}, kPostTaWarm, 0, kGateAlways));
     }
 
     EpiArgs ed{};
@@ -532,8 +540,127 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
         }
         progress = h.k + h.matvecs;
     }
+    if (warm && h.nb == 0.0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
     fill_info(h, info);
     if (h.nb > 0.0) fill_diagnostics(h, info);
+    return TA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 4 (section 2.3): approximate minimum-norm solution from an
+// approximate solution x_eps, by bisection on the radius of E_{A, rho}
+// ---------------------------------------------------------------------------
+// ||v|| as one compensated sum (device), read back to the host.
+static int device_norm(Chain &c, int64_t n, const double *v, double *out, hipStream_t s) {
+    *out = 0.0;
+    if (n <= 0) return TA_OK;
+    HIP_TRY(hipMemsetAsync(c.st, 0, sizeof(State), s));
+    int32_t g = 0;
+    HIP_TRY(launch_norm2(n, v, c.out(0, kGateIgnoreDone), s, &g));
+    HIP_TRY(c.step(0, {g}, kPostStore, 0, kGateIgnoreDone, false));
+    State h;
+    int rc = read_state(c.st, h, s);
+    if (rc != TA_OK) return rc;
+    *out = sqrt(h.scratch[0]);
+    return TA_OK;
+}
+
+// Upper bound hi = ||x_eps||, lower bound lo = 0; each test runs Algorithm 2
+// (fixed radius rho = (hi + lo) / 2) from the last witness's x (0 before the
+// first): an approximate solution in the ball lowers hi to rho and is kept,
+// a witness raises lo to its Corollary 1 bound.  Stops when hi - lo <= tol
+// ||x_eps||, when a test ends on the normal equation (its x is returned), or
+// when the iteration budget (summed over the tests) runs out; crossed bounds
+// (lo - hi beyond the gap) mean the input was no approximate solution of a
+// consistent system: witness stop, x = the last solution found or x_eps.
+static int minnorm_run(const Plan &P, const double *b, const double *x_eps, double *x,
+                       const ta_opts *o, ta_info *info, int64_t *tests_out, hipStream_t s) {
+    const ta_mat *M = &P.desc;
+    int rc = check_solve_args(M, b, x, o, nullptr, 0, info, 2);
+    if (rc != TA_OK) return rc;
+    if (!P.has_t) return TA_EINVAL;
+    const int64_t m = M->m, n = M->n;
+    if (n > 0 && x_eps == nullptr) return TA_EINVAL;
+    if (tests_out != nullptr) *tests_out = 0;
+    if (m == 0 || n == 0) {
+        if (n > 0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        info->stop = TA_STOP_RESIDUAL;
+        return TA_OK;
+    }
+    Workspace ws(s);
+    Chain c;
+    c.s = s;
+    c.reserve(ws, P, 1);
+    double *xt = nullptr, *xw = nullptr;
+    ws.reserve(&xt, n);
+    ws.reserve(&xw, n);
+    if ((rc = ws.commit()) != TA_OK) return rc;
+    double nb = 0.0, hi = 0.0, lo = 0.0;
+    if ((rc = device_norm(c, m, b, &nb, s)) != TA_OK) return rc;
+    if ((rc = device_norm(c, n, x_eps, &hi, s)) != TA_OK) return rc;
+    const double gap = o->tol * hi;
+    HIP_TRY(hipMemcpyAsync(x, x_eps, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    if (nb == 0.0) {
+        HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
+        hi = 0.0;
+    }
+    int32_t stop = TA_STOP_RESIDUAL;
+    bool have_w = false;
+    int64_t tests = 0, iters = 0, matvecs = 0;
+    while (nb > 0.0 && hi - lo > gap) {
+        if (iters >= o->max_iter) {
+            stop = TA_STOP_MAXITER;
+            break;
+        }
+        ta_opts t = *o;
+        t.fixed_rho = 1;
+        t.rho0 = 0.5 * (hi + lo);
+        t.warm_start = have_w ? 1 : 0;
+        t.max_iter = o->max_iter - iters;
+        if (have_w)
+            HIP_TRY(hipMemcpyAsync(xt, xw, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        ta_info ti;
+        if ((rc = ta_run(P, b, xt, &t, nullptr, 0, &ti, s)) != TA_OK) return rc;
+        ++tests;
+        iters += ti.iters;
+        matvecs += ti.matvecs;
+        if (ti.stop == TA_STOP_RESIDUAL) {
+            hi = t.rho0;
+            HIP_TRY(hipMemcpyAsync(x, xt, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        } else if (ti.stop == TA_STOP_WITNESS) {
+            lo = ti.rho_lo;
+            HIP_TRY(hipMemcpyAsync(xw, xt, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+            have_w = true;
+        } else {
+            if (ti.stop == TA_STOP_NORMAL)
+                HIP_TRY(hipMemcpyAsync(x, xt, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice,
+                                       s));
+            stop = ti.stop;
+            break;
+        }
+    }
+    if (stop == TA_STOP_RESIDUAL && lo - hi > gap) stop = TA_STOP_WITNESS;
+    // diagnostics of the returned x (not counted): a TA start from x with no iteration
+    if (nb > 0.0) {
+        ta_opts d = *o;
+        d.fixed_rho = 0;
+        d.rho0 = 0.0;
+        d.warm_start = 1;
+        d.max_iter = 0;
+        HIP_TRY(hipMemcpyAsync(xt, x, sizeof(double) * (size_t)n, hipMemcpyDeviceToDevice, s));
+        ta_info di;
+        if ((rc = ta_run(P, b, xt, &d, nullptr, 0, &di, s)) != TA_OK) return rc;
+        info->rel_res = di.rel_res;
+        info->rel_normal = di.rel_normal;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    info->iters = iters;
+    info->matvecs = matvecs;
+    info->stop = stop;
+    info->rho = hi;
+    info->rho_lo = lo;
+    if (tests_out != nullptr) *tests_out = tests;
     return TA_OK;
 }
 
@@ -694,6 +821,23 @@ int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts
                   double *hist, int64_t hist_cap, ta_info *info, void *stream) {
     if (plan == nullptr) return TA_EINVAL;
     return ta::ta_run(plan->p, b, x, opts, hist, hist_cap, info, (hipStream_t)stream);
+}
+
+int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
+               const ta_opts *opts, ta_info *info, int64_t *tests, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    if (info == nullptr) return TA_EINVAL;
+    int rc = ta::check_solve_args(A, b, x, opts, nullptr, 0, info, 2);
+    if (rc != TA_OK) return rc;
+    return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
+        return ta::minnorm_run(P, b, x_eps, x, opts, info, tests, s);
+    });
+}
+
+int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, double *x,
+                    const ta_opts *opts, ta_info *info, int64_t *tests, void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    return ta::minnorm_run(plan->p, b, x_eps, x, opts, info, tests, (hipStream_t)stream);
 }
 
 int ta_validate(const ta_mat *A, const ta_opts *opts, int32_t solver) {
