@@ -266,10 +266,26 @@ def lp_shaped_bench(args, P, torch, dev):
     rate, prate = K * args.lp_steps / el, len(singles) / pl_s
     log(f"[bench] LP-shaped: mixed+batched {rate:.0f} columns/s, FP64 plain {prate:.0f} solves/s")
     bp.close()
+    # Algorithm 4 from an approximate solution that is not the minimum-norm one
+    # (the x-form from a seeded x0), to a certified gap of 1e-4 ||x_eps||
+    x0 = torch.from_numpy(0.05 * g.standard_normal(n)).to(dev)
+    b0 = blocks[0][:, 0].contiguous()
+    xe, _, _ = P.cta_solve(pl, b0, tol=1e-4, t=t, max_iter=100000, x0=x0, hist_cap=1)
+    P.ta_minnorm(pl, b0, xe, tol=1e-2, max_iter=200000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xm, im, tests = P.ta_minnorm(pl, b0, xe, tol=1e-4, max_iter=200000)
+    torch.cuda.synchronize()
+    a4_s = time.perf_counter() - t0
+    log(f"[bench] LP-shaped Algorithm 4: {tests} tests, {im.iters} TA iterations, {a4_s:.3f} s, "
+        f"norm bracket [{im.rho_lo:.6f}, {im.rho:.6f}]")
     return {"workload": "lp_shaped_minnorm m=10000 n=1000000 nnz/col=6 +I slack, CTA t=3 y-form, "
                         f"k={K} per step", "nnz": A.nnz,
             "mixed_batched_columns_per_s": rate, "fp64_plain_solves_per_s": prate,
-            "speedup": rate / prate, "iterations": max(i.iters for i in inf)}
+            "speedup": rate / prate, "iterations": max(i.iters for i in inf),
+            "algorithm4": {"tol": 1e-4, "stop": im.stop, "tests": tests, "ta_iterations": im.iters,
+                           "seconds": a4_s, "rho_lo": im.rho_lo, "rho_hi": im.rho,
+                           "ta_iterations_per_s": im.iters / a4_s}}
 
 
 def diff_bench(args, P, torch, dev):
