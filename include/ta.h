@@ -103,6 +103,9 @@ typedef struct ta_opts {
     int32_t launch_mode;   /* batched solves: 0 = each chunk of iterations is captured once
                               as a HIP graph and replayed, 1 = kernels launched one by one;
                               results are identical */
+    int32_t h_mode;        /* cta_solve: 0 = H = A A^T (section 5), 1 = H = A for a square
+                              symmetric positive semidefinite A (not checked): t products per
+                              iteration instead of 2t, phi_i = r^T A^i r.  Other solvers: 0 */
 } ta_opts;
 
 /* Result summary (host struct). */

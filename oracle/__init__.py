@@ -43,7 +43,7 @@ class _Mat(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_normal", C.c_double), ("t", C.c_int32),
                 ("max_iter", C.c_int64), ("replace_every", C.c_int32), ("warm_start", C.c_int32),
-                ("rho0", C.c_double), ("fixed_rho", C.c_int32)]
+                ("rho0", C.c_double), ("fixed_rho", C.c_int32), ("h_is_a", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -167,20 +167,27 @@ def gram_alpha(phi, t: int):
     return a, int(te)
 
 
-def _opts(tol, tol_normal, t, max_iter, replace_every, warm_start, rho0, fixed_rho):
+def _opts(tol, tol_normal, t, max_iter, replace_every, warm_start, rho0, fixed_rho,
+          h_is_a=False):
     return _Opts(float(tol), float(tol_normal), int(t), int(max_iter), int(replace_every),
-                 int(warm_start), float(rho0), int(fixed_rho))
+                 int(warm_start), float(rho0), int(fixed_rho), int(bool(h_is_a)))
 
 
 def cta(A, b, tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0,
-        x0: Optional[np.ndarray] = None, minnorm=False, hist_cap: Optional[int] = None):
-    """Algorithm 1 (CTA, H = A A^T).  Returns (x, hist, info)."""
+        x0: Optional[np.ndarray] = None, minnorm=False, hist_cap: Optional[int] = None,
+        h_is_a=False):
+    """Algorithm 1 (CTA, H = A A^T; with h_is_a, H = A for a square symmetric
+    positive semidefinite A, x-form only).  Returns (x, hist, info)."""
+    if h_is_a:
+        mm, nn = A.shape if isinstance(A, np.ndarray) else (A.m, A.n)
+        if minnorm or mm != nn:
+            raise ValueError("H = A takes a square A and the x-form")
     M = _MatRef(A)
     b = _f64(b)
     cap = int(max_iter) + 1 if hist_cap is None else int(hist_cap)
     hist = np.full(max(cap, 1), np.nan)
     x = np.zeros(M.n) if x0 is None else _f64(x0).copy()
-    o = _opts(tol, tol_normal, t, max_iter, replace_every, x0 is not None, 0.0, 0)
+    o = _opts(tol, tol_normal, t, max_iter, replace_every, x0 is not None, 0.0, 0, h_is_a)
     inf = _Info()
     rc = _load().or_cta(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), int(bool(minnorm)),
                         _ptr(hist), cap, C.byref(inf))

@@ -47,6 +47,7 @@ typedef struct {
     int32_t warm_start;    /* CTA x-form: start from the given x */
     double rho0;           /* TA: initial radius */
     int32_t fixed_rho;     /* TA: 1 = fixed radius, stop at a witness */
+    int32_t h_is_a;        /* CTA x-form: 1 = H = A (A square symmetric PSD), 0 = H = A A^T */
 } or_opts;
 
 typedef struct {
@@ -308,15 +309,30 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
         if (k >= o->max_iter) { stop = OR_MAXITER; break; }
 
         memcpy(u[0], r, sizeof(double) * (size_t)m);
-        for (int j = 0; j < t; ++j) {
-            or_apply_t(A, u[j], w[j]);
-            phi[2 * j + 1] = or_dot2(n, w[j], w[j]);
-            or_apply(A, w[j], u[j + 1]);
-            phi[2 * j + 2] = or_dot2(m, u[j + 1], u[j + 1]);
-            matvecs += 2;
+        if (o->h_is_a) {
+            /* H = A: u_{j+1} = A u_j, phi_{2j+1} = u_j^T A u_j, phi_{2j+2} = ||A u_j||^2 */
+            for (int j = 0; j < t; ++j) {
+                or_apply(A, u[j], u[j + 1]);
+                phi[2 * j + 1] = or_dot2(m, u[j], u[j + 1]);
+                phi[2 * j + 2] = or_dot2(m, u[j + 1], u[j + 1]);
+                matvecs += 1;
+            }
+        } else {
+            for (int j = 0; j < t; ++j) {
+                or_apply_t(A, u[j], w[j]);
+                phi[2 * j + 1] = or_dot2(n, w[j], w[j]);
+                or_apply(A, w[j], u[j + 1]);
+                phi[2 * j + 2] = or_dot2(m, u[j + 1], u[j + 1]);
+                matvecs += 2;
+            }
         }
         if (!finite_all(phi + 1, 2 * t)) { stop = OR_BREAKDOWN; break; }
-        if (sqrt(phi[1]) <= o->tol_normal * nab || phi[2] == 0.0) { stop = OR_NORMAL; break; }
+        /* normal-equation test on ||A^T r||: phi_1 for H = A A^T, phi_2 = ||A r||^2
+           (A symmetric) for H = A; phi_2 = 0 means H r = 0 (Example 1) */
+        if (sqrt(o->h_is_a ? phi[2] : phi[1]) <= o->tol_normal * nab || phi[2] == 0.0) {
+            stop = OR_NORMAL;
+            break;
+        }
         or_gram_alpha(phi, t, alpha);
         if (!finite_all(alpha, t)) { stop = OR_BREAKDOWN; break; }
 
@@ -325,6 +341,10 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
         if (minnorm) {
             for (int j = 0; j < t; ++j)
                 for (e = 0; e < m; ++e) y[e] = fma(alpha[j], u[j][e], y[e]);
+        } else if (o->h_is_a) {
+            /* r' = r - sum alpha_i A^i r = b - A (x + sum alpha_i A^{i-1} r) */
+            for (int j = 0; j < t; ++j)
+                for (e = 0; e < n; ++e) x[e] = fma(alpha[j], u[j][e], x[e]);
         } else {
             for (int j = 0; j < t; ++j)
                 for (e = 0; e < n; ++e) x[e] = fma(alpha[j], w[j][e], x[e]);

@@ -35,7 +35,7 @@ struct State {
     int32_t fixed_rho; // TA: Algorithm 2
     int32_t replace;   // a true-residual replacement is due
     int32_t rejected;  // TA: a candidate stop failed, b' = A x must be recomputed
-    int32_t pad0;
+    int32_t hmode;     // CTA: 1 = H = A (A symmetric positive semidefinite), 0 = H = A A^T
     int64_t k;         // iterations done
     int64_t max_iter;
     int64_t hist_cap;
@@ -93,12 +93,13 @@ enum Epi : int32_t {
     kEpiResid,     // y = b - A x (compensated);     v0 += y^2
     kEpiTaD,       // d = fma(gamma, v, -b');        v0 += r d, v1 += d^2
     kEpiTaBp,      // b' = v, r = b - b';            v0 += r^2, v1 += r b
+    kEpiNormDot,   // y = v (square M);              v0 += r y (r: the input), v1 += y^2
 };
 
 struct EpiArgs {
     const double *b;   // kEpiResid, kEpiTaBp
     const double *bp;  // kEpiTaD
-    const double *r;   // kEpiTaD
+    const double *r;   // kEpiTaD, kEpiNormDot
     double *r_out;     // kEpiTaBp
 };
 

@@ -83,13 +83,15 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
         case kPostGram: {
             const int t = st->t;
             for (int i = 0; i < 2 * t; ++i) st->phi[i + 1] = v[i];
-            st->matvecs += 2 * t;
+            // H = A A^T: 2t products, phi_1 = ||A^T r||^2; H = A: t products, phi_2 = ||A r||^2
+            st->matvecs += st->hmode ? t : 2 * t;
             for (int i = 1; i <= 2 * t; ++i)
                 if (!isfinite(st->phi[i])) {
                     finish(st, TA_STOP_BREAKDOWN);
                     return;
                 }
-            if (sqrt(st->phi[1]) <= st->tol_ne_nab || st->phi[2] == 0.0) {
+            const double nr = sqrt(st->hmode ? st->phi[2] : st->phi[1]);
+            if (nr <= st->tol_ne_nab || st->phi[2] == 0.0) {
                 finish(st, TA_STOP_NORMAL);
                 return;
             }
@@ -304,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_step(Step sp) {
 
 template <int EPI>
 struct EpiNV {
-    static constexpr int value = (EPI == kEpiTaD || EPI == kEpiTaBp) ? 2 : 1;
+    static constexpr int value = (EPI == kEpiTaD || EPI == kEpiTaBp || EPI == kEpiNormDot) ? 2 : 1;
 };
 
 // Epilogue for one output entry y_row = yv.
@@ -319,6 +321,10 @@ __device__ __forceinline__ void epilogue(int64_t row, double yv, double *y, cons
         y[row] = d;
         acc_fma(v[0], ea.r[row], d);
         acc_fma(v[1], d, d);
+    } else if constexpr (EPI == kEpiNormDot) {
+        y[row] = yv;
+        acc_fma(v[0], ea.r[row], yv);
+        acc_fma(v[1], yv, yv);
     } else {  // kEpiTaBp
         y[row] = yv;
         const double bv = ea.b[row];
@@ -933,6 +939,7 @@ hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t e
         case kEpiResid: launch_matvec_t<kEpiResid>(M, x, y, ea, o, s, grid); break;
         case kEpiTaD: launch_matvec_t<kEpiTaD>(M, x, y, ea, o, s, grid); break;
         case kEpiTaBp: launch_matvec_t<kEpiTaBp>(M, x, y, ea, o, s, grid); break;
+        case kEpiNormDot: launch_matvec_t<kEpiNormDot>(M, x, y, ea, o, s, grid); break;
         default: return hipErrorInvalidValue;
     }
     if (blocks != nullptr) *blocks = (int32_t)g;

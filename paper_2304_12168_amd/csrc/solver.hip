@@ -48,6 +48,8 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (!(o->tol_normal >= 0.0 && o->tol_normal < 1.0)) return TA_EINVAL;
     if (o->max_iter < 0 || o->replace_every < 0 || o->chunk < 0) return TA_EINVAL;
     if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
+    if (o->h_mode != 0 && o->h_mode != 1) return TA_EINVAL;
+    if (o->h_mode == 1 && (solver != 0 || A->m != A->n)) return TA_EINVAL;
     if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64
     if (solver == 0 || solver == 1) {
         if (o->t < 1 || o->t > kTMax) return TA_EINVAL;
@@ -246,6 +248,7 @@ static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
     h.tol_normal = o->tol_normal;
     h.rho = o->rho0;
     h.fixed_rho = o->fixed_rho;
+    h.hmode = o->h_mode;
     return h;
 }
 
@@ -352,11 +355,15 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     c.s = s;
     c.hist = hist;
     c.reserve(ws, P, 2 * t + 1);
+    // H = A (A square, symmetric positive semidefinite): the chain u_{j+1} =
+    // A u_j alone, phi_{2j+1} = u_j^T u_{j+1}, phi_{2j+2} = ||u_{j+1}||^2, and
+    // x += sum_i alpha_i u_{i-1} (the y-form update applied to x)
+    const bool ha = o->h_mode == 1;
     double *r = nullptr, *y = nullptr, *tmp_n = nullptr;
     double *u[kTMax + 1] = {}, *w[kTMax] = {};
     ws.reserve(&r, m);
     for (int j = 1; j <= t; ++j) ws.reserve(&u[j], m);
-    const int nw = minnorm ? 1 : t;
+    const int nw = ha ? 0 : (minnorm ? 1 : t);
     for (int j = 0; j < nw; ++j) ws.reserve(&w[j], n);
     if (minnorm) ws.reserve(&y, m);
     ws.reserve(&tmp_n, n);
@@ -389,6 +396,14 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     int32_t gphi[2 * kTMax] = {};
     auto enqueue_iteration = [&]() -> int {
         for (int j = 0; j < t; ++j) {
+            if (ha) {
+                EpiArgs ed{};
+                ed.r = u[j];
+                HIP_TRY(launch_matvec(c.A, u[j], u[j + 1], kEpiNormDot, ed,
+                                      c.out(2 * j, kGateAlways), s, &gphi[2 * j]));
+                gphi[2 * j + 1] = gphi[2 * j];
+                continue;
+            }
             double *wj = w[minnorm ? 0 : j];
             HIP_TRY(launch_matvec(c.AT, u[j], wj, kEpiNorm, EpiArgs{}, c.out(2 * j, kGateAlways), s,
                                   &gphi[2 * j]));
@@ -406,8 +421,8 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         sp.post = kPostGram;
         sp.gate = kGateAlways;
         HIP_TRY(launch_step(sp, s));
-        HIP_TRY(launch_cta_update(m, n, t, minnorm ? 1 : 0, r, u, x, w, y, c.out(R, kGateAlways), s,
-                                  &g));
+        HIP_TRY(launch_cta_update(m, n, t, (minnorm || ha) ? 1 : 0, r, u, x, w, ha ? x : y,
+                                  c.out(R, kGateAlways), s, &g));
         HIP_TRY(c.step(R, {g}, kPostCtaEnd, 0, kGateAlways));
         if (o->replace_every > 0) {
             if (minnorm)
