@@ -106,6 +106,10 @@ typedef struct ta_opts {
     int32_t h_mode;        /* cta_solve: 0 = H = A A^T (section 5), 1 = H = A for a square
                               symmetric positive semidefinite A (not checked): t products per
                               iteration instead of 2t, phi_i = r^T A^i r.  Other solvers: 0 */
+    int32_t t_cycle;       /* cta_solve / cta_minnorm: 1 = the order of iteration k (k = 0, 1,
+                              ...) cycles 1, 2, ..., t, t-1, ..., 2, 1, 2, ... (section 5.1's
+                              order cycling, read as a triangle wave of period 2(t-1)); 0 = the
+                              fixed order t.  Batched solves: 0 */
 } ta_opts;
 
 /* Result summary (host struct). */

@@ -48,7 +48,16 @@ typedef struct {
     double rho0;           /* TA: initial radius */
     int32_t fixed_rho;     /* TA: 1 = fixed radius, stop at a witness */
     int32_t h_is_a;        /* CTA x-form: 1 = H = A (A square symmetric PSD), 0 = H = A A^T */
+    int32_t t_cycle;       /* CTA: 1 = the order of iteration k is or_cycle_order(t, k) */
 } or_opts;
+
+/* Order cycling (section 5.1 cycles the order 1, ..., 5 and back), read as a
+ * triangle wave of period 2 (t - 1): 1, 2, ..., t, t - 1, ..., 2, 1, 2, ... */
+int or_cycle_order(int t, int64_t k) {
+    if (t <= 1) return 1;
+    const int64_t p = k % (2 * (int64_t)t - 2);
+    return (int)(p < t ? p + 1 : 2 * (int64_t)t - 1 - p);
+}
 
 typedef struct {
     int64_t iters, matvecs;
@@ -309,16 +318,17 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
         if (k >= o->max_iter) { stop = OR_MAXITER; break; }
 
         memcpy(u[0], r, sizeof(double) * (size_t)m);
+        const int tk = o->t_cycle ? or_cycle_order(t, k) : t; /* order of this iteration */
         if (o->h_is_a) {
             /* H = A: u_{j+1} = A u_j, phi_{2j+1} = u_j^T A u_j, phi_{2j+2} = ||A u_j||^2 */
-            for (int j = 0; j < t; ++j) {
+            for (int j = 0; j < tk; ++j) {
                 or_apply(A, u[j], u[j + 1]);
                 phi[2 * j + 1] = or_dot2(m, u[j], u[j + 1]);
                 phi[2 * j + 2] = or_dot2(m, u[j + 1], u[j + 1]);
                 matvecs += 1;
             }
         } else {
-            for (int j = 0; j < t; ++j) {
+            for (int j = 0; j < tk; ++j) {
                 or_apply_t(A, u[j], w[j]);
                 phi[2 * j + 1] = or_dot2(n, w[j], w[j]);
                 or_apply(A, w[j], u[j + 1]);
@@ -326,27 +336,27 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
                 matvecs += 2;
             }
         }
-        if (!finite_all(phi + 1, 2 * t)) { stop = OR_BREAKDOWN; break; }
+        if (!finite_all(phi + 1, 2 * tk)) { stop = OR_BREAKDOWN; break; }
         /* normal-equation test on ||A^T r||: phi_1 for H = A A^T, phi_2 = ||A r||^2
            (A symmetric) for H = A; phi_2 = 0 means H r = 0 (Example 1) */
         if (sqrt(o->h_is_a ? phi[2] : phi[1]) <= o->tol_normal * nab || phi[2] == 0.0) {
             stop = OR_NORMAL;
             break;
         }
-        or_gram_alpha(phi, t, alpha);
-        if (!finite_all(alpha, t)) { stop = OR_BREAKDOWN; break; }
+        or_gram_alpha(phi, tk, alpha);
+        if (!finite_all(alpha, tk)) { stop = OR_BREAKDOWN; break; }
 
-        for (int j = 0; j < t; ++j)
+        for (int j = 0; j < tk; ++j)
             for (e = 0; e < m; ++e) r[e] = fma(-alpha[j], u[j + 1][e], r[e]);
         if (minnorm) {
-            for (int j = 0; j < t; ++j)
+            for (int j = 0; j < tk; ++j)
                 for (e = 0; e < m; ++e) y[e] = fma(alpha[j], u[j][e], y[e]);
         } else if (o->h_is_a) {
             /* r' = r - sum alpha_i A^i r = b - A (x + sum alpha_i A^{i-1} r) */
-            for (int j = 0; j < t; ++j)
+            for (int j = 0; j < tk; ++j)
                 for (e = 0; e < n; ++e) x[e] = fma(alpha[j], u[j][e], x[e]);
         } else {
-            for (int j = 0; j < t; ++j)
+            for (int j = 0; j < tk; ++j)
                 for (e = 0; e < n; ++e) x[e] = fma(alpha[j], w[j][e], x[e]);
         }
         ++k;

@@ -81,6 +81,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             st->matvecs++;
             break;
         case kPostGram: {
+            if (sp.arg > 0) st->t = sp.arg;  // order of this iteration (order cycling)
             const int t = st->t;
             for (int i = 0; i < 2 * t; ++i) st->phi[i + 1] = v[i];
             // H = A A^T: 2t products, phi_1 = ||A^T r||^2; H = A: t products, phi_2 = ||A r||^2

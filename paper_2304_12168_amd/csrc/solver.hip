@@ -50,6 +50,7 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
     if (o->h_mode != 0 && o->h_mode != 1) return TA_EINVAL;
     if (o->h_mode == 1 && (solver != 0 || A->m != A->n)) return TA_EINVAL;
+    if (o->t_cycle != 0 && (o->t_cycle != 1 || solver == 2)) return TA_EINVAL;
     if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64
     if (solver == 0 || solver == 1) {
         if (o->t < 1 || o->t > kTMax) return TA_EINVAL;
@@ -394,8 +395,14 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     }
 
     int32_t gphi[2 * kTMax] = {};
-    auto enqueue_iteration = [&]() -> int {
-        for (int j = 0; j < t; ++j) {
+    // order of the iteration with index k: t, or the cycle 1, 2, ..., t, ..., 2
+    auto order_of = [&](int64_t k) -> int {
+        if (!o->t_cycle || t <= 1) return t;
+        const int64_t p = k % (2 * (int64_t)t - 2);
+        return (int)(p < t ? p + 1 : 2 * (int64_t)t - 1 - p);
+    };
+    auto enqueue_iteration = [&](int tk) -> int {
+        for (int j = 0; j < tk; ++j) {
             if (ha) {
                 EpiArgs ed{};
                 ed.r = u[j];
@@ -416,12 +423,13 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         sp.partials = c.partials;
         sp.cap = c.cap;
         sp.slot0 = 0;
-        sp.nslots = 2 * t;
-        for (int i = 0; i < 2 * t; ++i) sp.count[i] = gphi[i];
+        sp.nslots = 2 * tk;
+        for (int i = 0; i < 2 * tk; ++i) sp.count[i] = gphi[i];
         sp.post = kPostGram;
+        sp.arg = tk;
         sp.gate = kGateAlways;
         HIP_TRY(launch_step(sp, s));
-        HIP_TRY(launch_cta_update(m, n, t, (minnorm || ha) ? 1 : 0, r, u, x, w, ha ? x : y,
+        HIP_TRY(launch_cta_update(m, n, tk, (minnorm || ha) ? 1 : 0, r, u, x, w, ha ? x : y,
                                   c.out(R, kGateAlways), s, &g));
         HIP_TRY(c.step(R, {g}, kPostCtaEnd, 0, kGateAlways));
         if (o->replace_every > 0) {
@@ -439,11 +447,11 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     // only once the solve has finished).  One State read per chunk.
     Chunker ch(o->chunk);
     State h;
-    int64_t progress = -1;
+    int64_t progress = -1, k_done = 0;  // iterations done when the chunk starts
     for (;;) {
         const int64_t k = ch.take();
         for (int64_t i = 0; i < k; ++i)
-            if ((rc = enqueue_iteration()) != TA_OK) return rc;
+            if ((rc = enqueue_iteration(order_of(k_done + i))) != TA_OK) return rc;
         if (minnorm)
             HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateCandidate), s,
                                   nullptr));
@@ -455,6 +463,7 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         HIP_TRY(enqueue_exit_diagnostics(c, b, x, r, tmp_n));
         if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
         if (h.done && h.stop != kStopCandidate) break;
+        k_done = h.k;
         // every chunk advances k or checks a candidate until the solve stops
         if (h.k + h.matvecs == progress) {
             hip_msg() = "iteration chain made no progress";

@@ -71,3 +71,42 @@ def test_h_a_poisson_512_first_iterations():
     _, h2, i2 = P.cta_solve(A, b, tol=1e-12, t=3, max_iter=100)
     assert ig.matvecs * 2 == i2.matvecs
     assert float(hg[-1]) < float(h2[-1])
+
+
+CYCLE_CASES = {
+    "kac_101_t5": lambda: __import__("workloads").kac_clement(101),
+    "convdiff_8_t3": lambda: __import__("workloads").convection_diffusion(8),
+    "lp_200x5000_t4": lambda: __import__("workloads").lp_shaped(200, 5000, seed=3),
+}
+
+
+@pytest.mark.parametrize("case", list(CYCLE_CASES))
+@pytest.mark.parametrize("minnorm", [False, True], ids=["x_form", "y_form"])
+def test_order_cycling_matches_oracle(case, minnorm):
+    p = CYCLE_CASES[case]()
+    t = int(case.rsplit("_t", 1)[1])
+    run_g = P.cta_minnorm if minnorm else P.cta_solve
+    xg, hg, ig = run_g(p.A, p.b, tol=1e-8, t=t, max_iter=100000, t_cycle=True)
+    xo, ho, io = oracle.cta(p.A, p.b, tol=1e-8, t=t, max_iter=100000, t_cycle=True,
+                            minnorm=minnorm)
+    assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs)
+    np.testing.assert_allclose(hg.cpu().numpy(), ho, rtol=1e-10, atol=1e-300)
+    assert np.linalg.norm(xg.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_cycling_and_h_a_together():
+    A = poisson5(20)
+    b = np.random.default_rng(4).uniform(-1, 1, A.m)
+    xg, hg, ig = P.cta_solve(A, b, tol=1e-9, t=4, max_iter=100000, t_cycle=True, h_is_a=True)
+    xo, ho, io = oracle.cta(A, b, tol=1e-9, t=4, max_iter=100000, t_cycle=True, h_is_a=True)
+    assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs)
+    assert np.linalg.norm(xg.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_batched_rejects_variants():
+    plan = P.BatchPlan([poisson5(4)], "fp64")
+    with pytest.raises(P.TaError):
+        P.cta_solve_batched(plan, [np.ones((16, 1))], h_is_a=True)
+    with pytest.raises(P.TaError):
+        P.cta_solve_batched(plan, [np.ones((16, 1))], t_cycle=True)
+    plan.close()
