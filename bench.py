@@ -343,6 +343,43 @@ def diff_bench(args, P, torch, dev):
             "outer_product_call_us": outer_ms * 1e3}
 
 
+def variants_bench(args, P, torch, dev):
+    """Secondary: FP64 single-right-hand-side solves to 1e-6 with the CTA
+    variants -- Kac/Clement N = 10001 (fixed t = 3 as configured, and the
+    order cycling 1..5..1), and the 256 x 256 Poisson matrix (symmetric
+    positive definite: H = A A^T vs H = A, fixed and cycling)."""
+    import numpy as np
+
+    from workloads import kac_clement, poisson5
+
+    out = {}
+    kac = kac_clement(10001, seed=args.seed)
+    pois = poisson5(256)
+    bp = torch.from_numpy(np.random.default_rng([args.seed, 5]).uniform(0, 1, pois.m)).to(dev)
+    runs = [("kac_10001_t3", kac.A, torch.from_numpy(kac.b).to(dev), dict(t=3)),
+            ("kac_10001_cycle5", kac.A, torch.from_numpy(kac.b).to(dev), dict(t=5, t_cycle=True)),
+            ("poisson_256_AAt_t3", pois, bp, dict(t=3)),
+            ("poisson_256_A_t3", pois, bp, dict(t=3, h_is_a=True)),
+            ("poisson_256_A_cycle5", pois, bp, dict(t=5, t_cycle=True, h_is_a=True))]
+    plans = {}
+    for name, A, b, kw in runs:
+        key = id(A)
+        if key not in plans:
+            plans[key] = P.plan(A)
+        pl = plans[key]
+        P.cta_solve(pl, b, tol=1e-6, max_iter=20000, hist_cap=1, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = P.cta_solve(pl, b, tol=1e-6, max_iter=20000, hist_cap=1, **kw)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name] = {"stop": info.stop, "iterations": info.iters, "products": info.matvecs,
+                     "seconds": sec, "rel_res": info.rel_res}
+        log(f"[bench] {name}: {info.stop} after {info.iters} iterations, {info.matvecs} products, "
+            f"{sec * 1e3:.1f} ms")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +397,8 @@ def main():
     ap.add_argument("--no-lp", action="store_true", help="skip the LP-shaped secondary block")
     ap.add_argument("--no-diff", action="store_true",
                     help="skip the differentiable-solve secondary block")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the CTA-variants secondary block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -384,6 +423,8 @@ def main():
         res["config"]["lp_shaped"] = lp_shaped_bench(args, P, torch, dev)
     if not args.no_diff:
         res["config"]["differentiable"] = diff_bench(args, P, torch, dev)
+    if not args.no_variants:
+        res["config"]["variants"] = variants_bench(args, P, torch, dev)
     out = {
         "metric": "solves/s and HBM GB/s to rel-residual 1e-6: CTA mixed+batched vs FP64 plain",
         "value": res["value"],
