@@ -135,27 +135,15 @@ enum BEpi : int32_t { kBNorm = 0, kBResid = 1, kBNormOnly = 2 };
 
 // Column indices and values of one chunk of U nonzeros of a row (positions
 // k, k + L, ..., k + (U-1) L below the row end e) for the KL lanes that share
-// the row.  Unless TA_SPMM_LANE_LOADS is defined, the lanes load distinct
-// entries and pass them round with lane shuffles (KL times less load data
-// than every lane loading every entry); gbase is the group's first lane.
-// Entries past the row end come back as j = -1, a = 0.
+// the row: the lanes load distinct entries and pass them round with lane
+// shuffles (KL times less load data than every lane loading every entry);
+// gbase is the group's first lane.  Entries past the row end come back as
+// j = -1, a = 0.
 template <int U, int KL, typename V, typename T>
 __device__ __forceinline__ void load_chunk(const int32_t *__restrict__ ci,
                                            const V *__restrict__ val, int32_t k, int32_t e,
                                            int L, int cl, int gbase, T sgn, int32_t (&j)[U],
                                            T (&a)[U]) {
-#ifdef TA_SPMM_LANE_LOADS
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int32_t kk = k + u * L;
-        j[u] = -1;
-        a[u] = T(0);
-        if (kk < e) {
-            j[u] = ci[kk];
-            a[u] = sgn * (T)ldv(val, kk);
-        }
-    }
-#else
     constexpr int NL = (U + KL - 1) / KL;  // entries loaded per lane
     int32_t jl[NL];
     T al[NL];
@@ -175,7 +163,6 @@ __device__ __forceinline__ void load_chunk(const int32_t *__restrict__ ci,
         j[u] = __shfl(jl[u / KL], gbase + (u % KL));
         a[u] = __shfl(al[u / KL], gbase + (u % KL));
     }
-#endif
 }
 
 // ---------------------------------------------------------------------------

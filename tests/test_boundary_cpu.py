@@ -77,3 +77,20 @@ def test_minnorm_rejects_warm_start_and_ta_fixed_rho_needs_radius(lib):
 def test_null_descriptor(lib):
     o = P.make_opts()
     assert lib.ta_validate(None, C.byref(o), 0) == -1
+
+
+def test_validate_variant_options(lib):
+    import ctypes
+
+    sq = _csr_desc(m=8, n=8)
+    rect = _csr_desc(m=3, n=5)
+    assert P.validate(sq, 0, t=3, h_is_a=True) == 0
+    assert P.validate(rect, 0, t=2, h_is_a=True) == -1   # H = A needs a square A
+    assert P.validate(sq, 1, t=2, h_is_a=True) == -1     # x-form only
+    assert P.validate(sq, 2, h_is_a=True) == -1          # not for TA
+    assert P.validate(rect, 0, t=3, t_cycle=True) == 0
+    assert P.validate(rect, 1, t=3, t_cycle=True) == 0
+    assert P.validate(rect, 2, t_cycle=True) == -1       # TA has no order
+    o = P.make_opts(t=3)
+    o.launch_mode = 2
+    assert lib.ta_validate(ctypes.byref(sq), ctypes.byref(o), 0) == -1
