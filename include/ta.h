@@ -110,6 +110,14 @@ typedef struct ta_opts {
                               ...) cycles 1, 2, ..., t, t-1, ..., 2, 1, 2, ... (section 5.1's
                               order cycling, read as a triangle wave of period 2(t-1)); 0 = the
                               fixed order t.  Batched solves: 0 */
+    int32_t nonneg;        /* ta_solve: 1 = LP feasibility {A x = b, x >= 0} (section 6): the
+                              pivot uses c+ = max(A^T (b - b'), 0) in place of c (Proposition
+                              eq. vrend2), so x stays >= 0; stop NORMAL when ||c+|| <=
+                              tol_normal ||(A^T b)+|| (with b^T (b - b') > 0 this is a Farkas
+                              certificate of infeasibility).  Other solvers: 0 */
+    double rho_max;        /* ta_solve: > 0 = stop with WITNESS once the radius would grow
+                              beyond rho_max (the termination bound section 6 asks for);
+                              0 = no bound.  Other solvers: 0 */
 } ta_opts;
 
 /* Result summary (host struct). */

@@ -44,7 +44,7 @@ class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("tol_normal", C.c_double), ("t", C.c_int32),
                 ("max_iter", C.c_int64), ("replace_every", C.c_int32), ("warm_start", C.c_int32),
                 ("rho0", C.c_double), ("fixed_rho", C.c_int32), ("h_is_a", C.c_int32),
-                ("t_cycle", C.c_int32)]
+                ("t_cycle", C.c_int32), ("nonneg", C.c_int32), ("rho_max", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -169,10 +169,10 @@ def gram_alpha(phi, t: int):
 
 
 def _opts(tol, tol_normal, t, max_iter, replace_every, warm_start, rho0, fixed_rho,
-          h_is_a=False, t_cycle=False):
+          h_is_a=False, t_cycle=False, nonneg=False, rho_max=0.0):
     return _Opts(float(tol), float(tol_normal), int(t), int(max_iter), int(replace_every),
                  int(warm_start), float(rho0), int(fixed_rho), int(bool(h_is_a)),
-                 int(bool(t_cycle)))
+                 int(bool(t_cycle)), int(bool(nonneg)), float(rho_max))
 
 
 def cta(A, b, tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0,
@@ -206,15 +206,19 @@ def cta_minnorm(A, b, **kw):
 
 
 def ta(A, b, tol=1e-6, max_iter=100000, tol_normal=0.0, rho0=0.0, fixed_rho=False,
-       hist_cap: Optional[int] = None, x0: Optional[np.ndarray] = None):
+       hist_cap: Optional[int] = None, x0: Optional[np.ndarray] = None, nonneg=False,
+       rho_max=0.0):
     """Algorithm 3 (or Algorithm 2 with ``fixed_rho``), from x0 (b' = A x0) if
-    given, else from 0.  Returns (x, hist, info)."""
+    given, else from 0; with ``nonneg``, the LP-feasibility form (x >= 0, c
+    replaced by c+) and an optional radius bound ``rho_max``.  Returns
+    (x, hist, info)."""
     M = _MatRef(A)
     b = _f64(b)
     cap = int(max_iter) + 1 if hist_cap is None else int(hist_cap)
     hist = np.full(max(cap, 1), np.nan)
     x = np.zeros(M.n) if x0 is None else _f64(x0).copy()
-    o = _opts(tol, tol_normal, 1, max_iter, 0, x0 is not None, rho0, fixed_rho)
+    o = _opts(tol, tol_normal, 1, max_iter, 0, x0 is not None, rho0, fixed_rho,
+              nonneg=nonneg, rho_max=rho_max)
     inf = _Info()
     _load().or_ta(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), _ptr(hist), cap, C.byref(inf))
     info = _info(inf)

@@ -49,6 +49,8 @@ typedef struct {
     int32_t fixed_rho;     /* TA: 1 = fixed radius, stop at a witness */
     int32_t h_is_a;        /* CTA x-form: 1 = H = A (A square symmetric PSD), 0 = H = A A^T */
     int32_t t_cycle;       /* CTA: 1 = the order of iteration k is or_cycle_order(t, k) */
+    int32_t nonneg;        /* TA: 1 = x >= 0 (LP feasibility): c replaced by c+ = max(c, 0) */
+    double rho_max;        /* TA: > 0 = stop at a witness once the radius would exceed this */
 } or_opts;
 
 /* Order cycling (section 5.1 cycles the order 1, ..., 5 and back), read as a
@@ -432,6 +434,8 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
     c = (double *)malloc(sizeof(double) * (size_t)n);
     if (o->tol_normal > 0.0) {
         or_apply_t(A, b, c);
+        if (o->nonneg)
+            for (i = 0; i < n; ++i) c[i] = c[i] > 0.0 ? c[i] : 0.0;
         nab = sqrt(or_dot2(n, c, c));
         ++matvecs;
     }
@@ -459,6 +463,10 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
         if (k >= o->max_iter) { stop = OR_MAXITER; break; }
         if (!have_c) {
             or_apply_t(A, r, c);
+            /* LP feasibility (section 6): the best point of E_{A,rho} within the
+               cone x >= 0 uses c+ (Proposition eq. vrend2) */
+            if (o->nonneg)
+                for (i = 0; i < n; ++i) c[i] = c[i] > 0.0 ? c[i] : 0.0;
             nc = sqrt(or_dot2(n, c, c));
             ++matvecs;
             have_c = 1;
@@ -489,6 +497,10 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
             double q = rb / nc;
             if (o->fixed_rho) { rho_lo = q; stop = OR_WITNESS; break; }
             if (q > rho_lo) rho_lo = q;
+            if (o->rho_max > 0.0 && ((2.0 * rho >= q) ? 2.0 * rho : q) > o->rho_max) {
+                stop = OR_WITNESS;  /* no solution within the radius bound */
+                break;
+            }
             pass = (q >= 2.0 * rho);
             rho = (2.0 * rho >= q) ? 2.0 * rho : q;
         }

@@ -50,6 +50,7 @@ struct State {
     double gamma;      // TA: rho / ||c||
     double alpha_ta;   // TA: step length
     double rho, rho_lo;
+    double rho_max;    // TA: > 0 = witness stop once the radius would exceed it
     double phi[2 * kTMax + 2];  // phi[1..2t]
     double alpha[kTMax];
     double scratch[4];          // results of kernel-level reductions
@@ -94,6 +95,7 @@ enum Epi : int32_t {
     kEpiTaD,       // d = fma(gamma, v, -b');        v0 += r d, v1 += d^2
     kEpiTaBp,      // b' = v, r = b - b';            v0 += r^2, v1 += r b
     kEpiNormDot,   // y = v (square M);              v0 += r y (r: the input), v1 += y^2
+    kEpiNormPos,   // y = max(v, 0);                 v0 += y^2
 };
 
 struct EpiArgs {

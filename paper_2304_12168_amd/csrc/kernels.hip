@@ -161,6 +161,11 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
                     break;
                 }
                 if (q > st->rho_lo) st->rho_lo = q;
+                const double grown = (2.0 * st->rho >= q) ? 2.0 * st->rho : q;
+                if (st->rho_max > 0.0 && grown > st->rho_max) {
+                    finish(st, TA_STOP_WITNESS);  // no solution within the radius bound
+                    break;
+                }
                 st->pass = (q >= 2.0 * st->rho);
                 st->rho = (2.0 * st->rho >= q) ? 2.0 * st->rho : q;
                 st->k++;
@@ -322,6 +327,10 @@ __device__ __forceinline__ void epilogue(int64_t row, double yv, double *y, cons
         y[row] = d;
         acc_fma(v[0], ea.r[row], d);
         acc_fma(v[1], d, d);
+    } else if constexpr (EPI == kEpiNormPos) {
+        const double yp = yv > 0.0 ? yv : 0.0;
+        y[row] = yp;
+        acc_fma(v[0], yp, yp);
     } else if constexpr (EPI == kEpiNormDot) {
         y[row] = yv;
         acc_fma(v[0], ea.r[row], yv);
@@ -941,6 +950,7 @@ hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t e
         case kEpiTaD: launch_matvec_t<kEpiTaD>(M, x, y, ea, o, s, grid); break;
         case kEpiTaBp: launch_matvec_t<kEpiTaBp>(M, x, y, ea, o, s, grid); break;
         case kEpiNormDot: launch_matvec_t<kEpiNormDot>(M, x, y, ea, o, s, grid); break;
+        case kEpiNormPos: launch_matvec_t<kEpiNormPos>(M, x, y, ea, o, s, grid); break;
         default: return hipErrorInvalidValue;
     }
     if (blocks != nullptr) *blocks = (int32_t)g;

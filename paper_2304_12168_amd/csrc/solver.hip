@@ -51,6 +51,9 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (o->h_mode != 0 && o->h_mode != 1) return TA_EINVAL;
     if (o->h_mode == 1 && (solver != 0 || A->m != A->n)) return TA_EINVAL;
     if (o->t_cycle != 0 && (o->t_cycle != 1 || solver == 2)) return TA_EINVAL;
+    if (o->nonneg != 0 && (o->nonneg != 1 || solver != 2)) return TA_EINVAL;
+    if (!(o->rho_max >= 0.0) || !isfinite(o->rho_max) || (o->rho_max > 0.0 && solver != 2))
+        return TA_EINVAL;
     if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64
     if (solver == 0 || solver == 1) {
         if (o->t < 1 || o->t > kTMax) return TA_EINVAL;
@@ -250,6 +253,7 @@ static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
     h.rho = o->rho0;
     h.fixed_rho = o->fixed_rho;
     h.hmode = o->h_mode;
+    h.rho_max = o->rho_max;
     return h;
 }
 
@@ -513,8 +517,10 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     const int32_t warm = o->warm_start ? 1 : 0;
     HIP_TRY(launch_ta_init(m, n, b, r, bp, x, warm, c.out(3, kGateAlways), s, &g));
     HIP_TRY(c.step(3, {g}, kPostTaInit, warm, kGateAlways));
+    // LP feasibility (x >= 0): c = A^T r is replaced by its positive part
+    const int32_t epi_c = o->nonneg ? kEpiNormPos : kEpiNorm;
     if (o->tol_normal > 0.0) {
-        HIP_TRY(launch_matvec(c.AT, b, cv, kEpiNorm, EpiArgs{}, c.out(0, kGateAlways), s, &g));
+        HIP_TRY(launch_matvec(c.AT, b, cv, epi_c, EpiArgs{}, c.out(0, kGateAlways), s, &g));
         HIP_TRY(c.step(0, {g}, kPostNab, 0, kGateAlways));
     }
     if (warm) {  // b' = A x0, r = b - b'
@@ -529,7 +535,7 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     ed.bp = bp;
     ed.r = r;
     auto enqueue_iteration = [&]() -> int {
-        HIP_TRY(launch_matvec(c.AT, r, cv, kEpiNorm, EpiArgs{}, c.out(0, kGateNeedC), s, &g));
+        HIP_TRY(launch_matvec(c.AT, r, cv, epi_c, EpiArgs{}, c.out(0, kGateNeedC), s, &g));
         HIP_TRY(c.step(0, {g}, kPostTaC, 0, kGateNeedC));
         HIP_TRY(launch_matvec(c.A, cv, d, kEpiTaD, ed, c.out(1, kGatePivot), s, &g));
         HIP_TRY(c.step(1, {g, g}, kPostTaS, 0, kGatePivot));
@@ -605,6 +611,7 @@ static int minnorm_run(const Plan &P, const double *b, const double *x_eps, doub
     if (!P.has_t) return TA_EINVAL;
     const int64_t m = M->m, n = M->n;
     if (n > 0 && x_eps == nullptr) return TA_EINVAL;
+    if (o->nonneg || o->rho_max > 0.0) return TA_EINVAL;  // Algorithm 4 is stated without the cone
     if (tests_out != nullptr) *tests_out = 0;
     if (m == 0 || n == 0) {
         if (n > 0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
