@@ -279,13 +279,25 @@ def lp_shaped_bench(args, P, torch, dev):
     a4_s = time.perf_counter() - t0
     log(f"[bench] LP-shaped Algorithm 4: {tests} tests, {im.iters} TA iterations, {a4_s:.3f} s, "
         f"norm bracket [{im.rho_lo:.6f}, {im.rho:.6f}]")
+    # LP feasibility {A x = b, x >= 0} with b = A |x*| (feasible), TA with c+
+    bf = torch.from_numpy(sp @ np.abs(g.standard_normal(n))).to(dev)
+    P.ta_solve(pl, bf, tol=1e-2, max_iter=200000, nonneg=True, hist_cap=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xf, _, fi = P.ta_solve(pl, bf, tol=1e-4, max_iter=200000, nonneg=True, hist_cap=1)
+    torch.cuda.synchronize()
+    lf_s = time.perf_counter() - t0
+    log(f"[bench] LP-shaped feasibility (TA with c+): {fi.stop} after {fi.iters} iterations, "
+        f"{lf_s:.3f} s, min x = {float(xf.min()):.3g}")
     return {"workload": "lp_shaped_minnorm m=10000 n=1000000 nnz/col=6 +I slack, CTA t=3 y-form, "
                         f"k={K} per step", "nnz": A.nnz,
             "mixed_batched_columns_per_s": rate, "fp64_plain_solves_per_s": prate,
             "speedup": rate / prate, "iterations": max(i.iters for i in inf),
             "algorithm4": {"tol": 1e-4, "stop": im.stop, "tests": tests, "ta_iterations": im.iters,
                            "seconds": a4_s, "rho_lo": im.rho_lo, "rho_hi": im.rho,
-                           "ta_iterations_per_s": im.iters / a4_s}}
+                           "ta_iterations_per_s": im.iters / a4_s},
+            "lp_feasibility": {"tol": 1e-4, "stop": fi.stop, "iterations": fi.iters,
+                               "seconds": lf_s, "rel_res": fi.rel_res}}
 
 
 def diff_bench(args, P, torch, dev):
