@@ -749,51 +749,116 @@ struct BVecs {
     void *p[kTMax + 1];
 };
 
+// Vectors of CV consecutive entries, moved with 16-byte accesses.
+template <typename T, int CV>
+struct alignas(sizeof(T) * CV) VecT {
+    T v[CV];
+};
+template <typename T, int CV>
+__device__ __forceinline__ void vld(const T *p, double (&o)[CV]) {
+    const VecT<T, CV> w = *reinterpret_cast<const VecT<T, CV> *>(p);
+#pragma unroll
+    for (int v = 0; v < CV; ++v) o[v] = (double)w.v[v];
+}
+template <typename T, int CV>
+__device__ __forceinline__ void vst(T *p, const double (&o)[CV]) {
+    VecT<T, CV> w;
+#pragma unroll
+    for (int v = 0; v < CV; ++v) w.v[v] = (T)o[v];
+    *reinterpret_cast<VecT<T, CV> *>(p) = w;
+}
+
+// alpha of the block's system, [j][column], for the update kernels
+template <int K>
+__device__ __forceinline__ void load_alpha(const Groups &gs, int32_t sys, double (*sal)[K]) {
+    for (int i = threadIdx.x; i < kTMax * K; i += kBlock) {
+        const int j = i / K, c = i % K;
+        sal[j][c] = gs.alpha[((int64_t)sys * K + c) * kTMax + j];
+    }
+    __syncthreads();
+}
+
 // R -= sum alpha_j U_{j+1}; y-form: Y += alpha_1 R_old + sum alpha_j U_j.
-// Over the A-row table; partial ||R||^2 per (block, column) in slot 0.
+// Over the A-row table; partial ||R||^2 per (block, column) in slot 0.  A
+// lane covers CV consecutive columns of a row (16-byte accesses); every
+// column runs in FP64 and is rounded once to the vector type.
 template <typename X, int K>
 __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
                                                        const BRange *__restrict__ blocks,
                                                        Groups gs, double2 *partials,
                                                        int64_t cap) {
     if (gs.flags[0]) return;
-    constexpr int R = 64 / K;
+    constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
     const BRange br = blocks[blockIdx.x];
     if (br.r0 >= br.r1) return;
+    __shared__ double sal[kTMax][K];
+    load_alpha<K>(gs, br.sys, sal);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = lane % K, rsub = lane / K;
-    const int g = br.sys * K + c;
+    const int cl = lane % KL, rsub = lane / KL, c0 = cl * CV;
     const int t = gs.t;
-    Acc part = {0.0, 0.0};
-    if (gs.status[g] == kActive) {
-        double al[kTMax];
+    bool act[CV];
+    bool any = false;
 #pragma unroll
-        for (int j = 0; j < kTMax; ++j) al[j] = gs.alpha[(int64_t)g * kTMax + j];
+    for (int v = 0; v < CV; ++v) {
+        act[v] = gs.status[br.sys * K + c0 + v] == kActive;
+        any |= act[v];
+    }
+    Acc part[CV];
+#pragma unroll
+    for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
+    if (any) {
         for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
              it = brow_next(br, R, wave, rsub, it)) {
-            const int64_t e = (int64_t)it.row * K + c;
-            double ri = (double)r[e];
+            const int64_t e = (int64_t)it.row * K + c0;
+            double ri[CV], u[CV];
+            vld<X, CV>(r + e, ri);
             if (gs.minnorm) {
-                double yi = yv[e];
-                yi = __fma_rn(al[0], ri, yi);
-                for (int j = 1; j < t; ++j) yi = __fma_rn(al[j], (double)((const X *)U.p[j])[e], yi);
-                yv[e] = yi;
+                double yi[CV], y0[CV];
+                vld<double, CV>(yv + e, y0);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) yi[v] = __fma_rn(sal[0][c0 + v], ri[v], y0[v]);
+                for (int j = 1; j < t; ++j) {
+                    vld<X, CV>((const X *)U.p[j] + e, u);
+#pragma unroll
+                    for (int v = 0; v < CV; ++v) yi[v] = __fma_rn(sal[j][c0 + v], u[v], yi[v]);
+                }
+#pragma unroll
+                for (int v = 0; v < CV; ++v)
+                    if (!act[v]) yi[v] = y0[v];
+                vst<double, CV>(yv + e, yi);
             }
-            for (int j = 0; j < t; ++j) ri = __fma_rn(-al[j], (double)((const X *)U.p[j + 1])[e], ri);
-            const X rs = (X)ri;
-            r[e] = rs;
-            acc_fma(part, (double)rs, (double)rs);
+            double rn[CV];
+#pragma unroll
+            for (int v = 0; v < CV; ++v) rn[v] = ri[v];
+            for (int j = 0; j < t; ++j) {
+                vld<X, CV>((const X *)U.p[j + 1] + e, u);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) rn[v] = __fma_rn(-sal[j][c0 + v], u[v], rn[v]);
+            }
+#pragma unroll
+            for (int v = 0; v < CV; ++v) {
+                if (!act[v]) rn[v] = ri[v];
+                const double q = (double)(X)rn[v];
+                if (act[v]) acc_fma(part[v], q, q);
+            }
+            vst<X, CV>(r + e, rn);
         }
     }
 #pragma unroll
-    for (int off = K; off < 64; off <<= 1) {
-        Acc o;
-        o.p = __shfl_xor(part.p, off);
-        o.s = __shfl_xor(part.s, off);
-        part = acc_merge(part, o);
+    for (int off = KL; off < 64; off <<= 1) {
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+            Acc o;
+            o.p = __shfl_xor(part[v].p, off);
+            o.s = __shfl_xor(part[v].s, off);
+            part[v] = acc_merge(part[v], o);
+        }
     }
     __shared__ Acc red[kBlock / 64][K];
-    if (rsub == 0) red[wave][c] = part;
+    if (rsub == 0) {
+#pragma unroll
+        for (int v = 0; v < CV; ++v) red[wave][c0 + v] = part[v];
+    }
     __syncthreads();
     if (threadIdx.x < K) {
         Acc a = red[0][threadIdx.x];
@@ -802,28 +867,44 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
     }
 }
 
-// x-form: X += sum alpha_j W_{j-1}, over the A^T-row table.
+// x-form: X += sum alpha_j W_{j-1}, over the A^T-row table (CV columns per
+// lane as in k_bupdate_r).
 template <typename X, int K>
 __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, double *xv,
                                                        const BRange *__restrict__ blocks,
                                                        Groups gs) {
     if (gs.flags[0]) return;
-    constexpr int R = 64 / K;
+    constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
     const BRange br = blocks[blockIdx.x];
     if (br.r0 >= br.r1) return;
+    __shared__ double sal[kTMax][K];
+    load_alpha<K>(gs, br.sys, sal);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c = lane % K, rsub = lane / K;
-    const int g = br.sys * K + c;
-    if (gs.status[g] != kActive) return;
-    double al[kTMax];
+    const int cl = lane % KL, rsub = lane / KL, c0 = cl * CV;
+    bool act[CV];
+    bool any = false;
 #pragma unroll
-    for (int j = 0; j < kTMax; ++j) al[j] = gs.alpha[(int64_t)g * kTMax + j];
+    for (int v = 0; v < CV; ++v) {
+        act[v] = gs.status[br.sys * K + c0 + v] == kActive;
+        any |= act[v];
+    }
+    if (!any) return;
     for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
          it = brow_next(br, R, wave, rsub, it)) {
-        const int64_t e = (int64_t)it.row * K + c;
-        double xi = xv[e];
-        for (int j = 0; j < gs.t; ++j) xi = __fma_rn(al[j], (double)((const X *)W.p[j])[e], xi);
-        xv[e] = xi;
+        const int64_t e = (int64_t)it.row * K + c0;
+        double xi[CV], w[CV], x0[CV];
+        vld<double, CV>(xv + e, x0);
+#pragma unroll
+        for (int v = 0; v < CV; ++v) xi[v] = x0[v];
+        for (int j = 0; j < gs.t; ++j) {
+            vld<X, CV>((const X *)W.p[j] + e, w);
+#pragma unroll
+            for (int v = 0; v < CV; ++v) xi[v] = __fma_rn(sal[j][c0 + v], w[v], xi[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < CV; ++v)
+            if (!act[v]) xi[v] = x0[v];
+        vst<double, CV>(xv + e, xi);
     }
 }
 
