@@ -1354,16 +1354,17 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
     return TA_OK;
 }
 
-// Block table over the rows of every system, balanced by nonzeros: about
-// max(1024, nnz K / 2^18) blocks in all, shared out in proportion to each
-// system's nonzeros (at least one per system with rows).
 // Block table of one launch over the rows of the systems that take part
-// (nrhs[s] > 0, or all if nrhs is null).  About max(1024, nnz K / 2^18)
+// (nrhs[s] > 0, or all if nrhs is null).  About max(2048, nnz K / 2^16)
 // workgroups in all.  Each system is one unit, or for a system heavier than
 // 1/16 of the total (weight = nonzeros + rows) several units of contiguous
 // rows of about that weight; a unit gets workgroups in proportion to its
-// weight, which interleave over its rows in chunks (BRange).  `first[s]` is the index
-// of system s's first workgroup in system order.
+// weight (at most one per 8 rows), which interleave over its rows in chunks
+// (BRange).  `first[s]` is the index of system s's first workgroup in system
+// order.  The count is high enough that the workgroups one XCD holds at a
+// time cover about one system: a system whose gathers are scattered over its
+// whole input block (random sparsity) then has that block to itself in the
+// XCD's L2 while it runs.
 //
 // Dispatch order: workgroup b of a launch runs on XCD b mod 8, and each XCD
 // has its own L2.  The units are dealt to the 8 XCDs heaviest first, each to
@@ -1384,7 +1385,7 @@ static void make_blocks(const std::vector<int64_t> &off, const std::vector<int32
             total_nnz += rp[off[sidx + 1]] - rp[off[sidx]];
             total_w += weight(off[sidx], off[sidx + 1]);
         }
-    const int64_t target = std::max<int64_t>(1024, cdivh(total_nnz * K, 1 << 18));
+    const int64_t target = std::max<int64_t>(2048, cdivh(total_nnz * K, 1 << 16));
     struct Unit {
         int32_t r0, r1, sys;
         int64_t w, b0, nb;  // first workgroup (system order) and count
@@ -1414,7 +1415,7 @@ static void make_blocks(const std::vector<int64_t> &off, const std::vector<int32
             }
             Unit u{(int32_t)start, (int32_t)end, (int32_t)sidx, weight(start, end), nlog, 0};
             u.nb = std::max<int64_t>(1, std::min<int64_t>((target * u.w + total_w - 1) / total_w,
-                                                          end - start));
+                                                          (end - start) / 8));
             nlog += u.nb;
             units.push_back(u);
             start = end;
