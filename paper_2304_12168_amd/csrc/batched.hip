@@ -88,6 +88,7 @@ struct Groups {
     double *nb, *tol_nb, *tol_ne_nab, *rr, *phi, *alpha, *diag;
     int32_t *flags;  // [0] every group finished, [1] some group waits for a check
     int32_t *sys_active;   // per system: some group still running
+    int32_t *dirty;        // per system: its low-precision accumulator holds updates
     const int32_t *ksys;   // right-hand sides in use per system
     const int32_t *a_blk;  // per system: first block of the A-row table (nsys + 1)
     const int32_t *t_blk;  // per system: first block of the A^T-row table (nsys + 1)
@@ -781,9 +782,11 @@ __device__ __forceinline__ void load_alpha(const Groups &gs, int32_t sys, double
 // R -= sum alpha_j U_{j+1}; y-form: Y += alpha_1 R_old + sum alpha_j U_j.
 // Over the A-row table; partial ||R||^2 per (block, column) in slot 0.  A
 // lane covers CV consecutive columns of a row (16-byte accesses); every
-// column runs in FP64 and is rounded once to the vector type.
-template <typename X, int K>
-__global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
+// column runs in FP64 and is rounded once to the vector type.  Y is held in
+// YA: FP64, or (mixed precision) the low-precision accumulator of the
+// current chunk, folded into the FP64 Y by k_bfold.
+template <typename X, int K, typename YA>
+__global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
                                                        const BRange *__restrict__ blocks,
                                                        Groups gs, double2 *partials,
                                                        int64_t cap) {
@@ -806,6 +809,8 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
     Acc part[CV];
 #pragma unroll
     for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
+    if (!std::is_same<YA, double>::value && gs.minnorm && any && rsub == 0)
+        gs.dirty[br.sys] = 1;  // benign same-value stores
     if (any) {
         for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
              it = brow_next(br, R, wave, rsub, it)) {
@@ -814,7 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
             vld<X, CV>(r + e, ri);
             if (gs.minnorm) {
                 double yi[CV], y0[CV];
-                vld<double, CV>(yv + e, y0);
+                vld<YA, CV>(yv + e, y0);
 #pragma unroll
                 for (int v = 0; v < CV; ++v) yi[v] = __fma_rn(sal[0][c0 + v], ri[v], y0[v]);
                 for (int j = 1; j < t; ++j) {
@@ -825,7 +830,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
 #pragma unroll
                 for (int v = 0; v < CV; ++v)
                     if (!act[v]) yi[v] = y0[v];
-                vst<double, CV>(yv + e, yi);
+                vst<YA, CV>(yv + e, yi);
             }
             double rn[CV];
 #pragma unroll
@@ -868,9 +873,11 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, double *yv,
 }
 
 // x-form: X += sum alpha_j W_{j-1}, over the A^T-row table (CV columns per
-// lane as in k_bupdate_r).
-template <typename X, int K>
-__global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, double *xv,
+// lane as in k_bupdate_r).  X is held in XA: FP64, or (mixed precision) the
+// low-precision accumulator of the current chunk, folded into the FP64 X by
+// k_bfold.
+template <typename X, int K, typename XA>
+__global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, XA *xv,
                                                        const BRange *__restrict__ blocks,
                                                        Groups gs) {
     if (gs.flags[0]) return;
@@ -889,11 +896,12 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, double *xv,
         any |= act[v];
     }
     if (!any) return;
+    if (!std::is_same<XA, double>::value && rsub == 0) gs.dirty[br.sys] = 1;
     for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
          it = brow_next(br, R, wave, rsub, it)) {
         const int64_t e = (int64_t)it.row * K + c0;
         double xi[CV], w[CV], x0[CV];
-        vld<double, CV>(xv + e, x0);
+        vld<XA, CV>(xv + e, x0);
 #pragma unroll
         for (int v = 0; v < CV; ++v) xi[v] = x0[v];
         for (int j = 0; j < gs.t; ++j) {
@@ -904,8 +912,42 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, double *xv,
 #pragma unroll
         for (int v = 0; v < CV; ++v)
             if (!act[v]) xi[v] = x0[v];
-        vst<double, CV>(xv + e, xi);
+        vst<XA, CV>(xv + e, xi);
     }
+}
+
+// F += D, D = 0 over a table's rows, for the systems whose accumulator D
+// took updates since the last fold (every column: D is zero where nothing
+// was added).  Runs ungated at the end of every chunk, before anything reads
+// the FP64 block F.
+template <typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_bfold(X *d, double *f,
+                                                   const BRange *__restrict__ blocks,
+                                                   Groups gs) {
+    constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
+    const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1 || !gs.dirty[br.sys]) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane % KL, rsub = lane / KL, c0 = cl * CV;
+    for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+         it = brow_next(br, R, wave, rsub, it)) {
+        const int64_t e = (int64_t)it.row * K + c0;
+        double dv[CV], fv[CV];
+        vld<X, CV>(d + e, dv);
+        vld<double, CV>(f + e, fv);
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+            fv[v] += dv[v];
+            dv[v] = 0.0;
+        }
+        vst<double, CV>(f + e, fv);
+        vst<X, CV>(d + e, dv);
+    }
+}
+
+// after the fold: no accumulator holds updates
+__global__ __launch_bounds__(kBlock) void k_bdirty_clear(Groups gs) {
+    for (int sy = threadIdx.x; sy < gs.nsys; sy += kBlock) gs.dirty[sy] = 0;
 }
 
 // End of an iteration: ||r||^2 per group, k, loop-top tests.
@@ -1640,6 +1682,9 @@ struct Engine {
         double *Bc = nullptr, *Y = nullptr, *Xc = nullptr, *RT = nullptr, *TN = nullptr;
         X *R = nullptr;
         X *U[kTMax + 1] = {}, *W[kTMax] = {};
+        // mixed precision: the chunk's updates of X (x-form) or Y (y-form)
+        // accumulate in D and are folded into the FP64 block at its end
+        X *D = nullptr;
         double2 *partials = nullptr;
         BRange *d_ta = nullptr, *d_tt = nullptr;
         int32_t *d_afirst = nullptr, *d_tfirst = nullptr, *d_ksys = nullptr;
@@ -1653,6 +1698,7 @@ struct Engine {
         for (int j = 0; j < (minnorm ? 1 : t); ++j) ws.reserve(&W[j], N * K);
         if (minnorm) ws.reserve(&Y, M * K);
         ws.reserve(&Xc, N * K);
+        if (mixed) ws.reserve(&D, (minnorm ? M : N) * K);
         ws.reserve(&RT, M * K);
         ws.reserve(&TN, N * K);
         double *DS = nullptr;  // column shares of the dense products
@@ -1683,6 +1729,7 @@ struct Engine {
         ws.reserve(&gs.diag, G * 3);
         ws.reserve(&gs.flags, 4);
         ws.reserve(&gs.sys_active, nsys);
+        ws.reserve(&gs.dirty, nsys);
         int rc = ws.commit();
         if (rc != TA_OK) return rc;
 
@@ -1704,7 +1751,10 @@ struct Engine {
         HIP_TRY(hipMemcpyAsync(d_X, Xout, sizeof(double *) * nsys, hipMemcpyHostToDevice, s));
         HIP_TRY(hipMemsetAsync(gs.flags, 0, sizeof(int32_t) * 4, s));
         HIP_TRY(hipMemsetAsync(gs.sys_active, 0, sizeof(int32_t) * nsys, s));
+        HIP_TRY(hipMemsetAsync(gs.dirty, 0, sizeof(int32_t) * nsys, s));
         HIP_TRY(hipMemsetAsync(Xc, 0, sizeof(double) * (size_t)(N * K), s));
+        if (mixed)
+            HIP_TRY(hipMemsetAsync(D, 0, sizeof(X) * (size_t)((minnorm ? M : N) * K), s));
         if (minnorm) HIP_TRY(hipMemsetAsync(Y, 0, sizeof(double) * (size_t)(M * K), s));
         gs.ksys = d_ksys;
         gs.a_blk = d_afirst;
@@ -1758,17 +1808,32 @@ struct Engine {
             BVecs uv{};
             uv.p[0] = R;
             for (int j = 1; j <= t; ++j) uv.p[j] = U[j];
-            if (na > 0) k_bupdate_r<X, K><<<na, kBlock, 0, cs>>>(uv, R, Y, d_ta, gs, partials, cap);
+            if (na > 0) {
+                if (mixed)
+                    k_bupdate_r<X, K, X><<<na, kBlock, 0, cs>>>(uv, R, D, d_ta, gs, partials, cap);
+                else
+                    k_bupdate_r<X, K, double><<<na, kBlock, 0, cs>>>(uv, R, Y, d_ta, gs, partials,
+                                                                      cap);
+            }
             if (!minnorm && nt > 0) {
                 BVecs wv{};
                 for (int j = 0; j < t; ++j) wv.p[j] = W[j];
-                k_bupdate_x<X, K><<<nt, kBlock, 0, cs>>>(wv, Xc, d_tt, gs);
+                if (mixed)
+                    k_bupdate_x<X, K, X><<<nt, kBlock, 0, cs>>>(wv, D, d_tt, gs);
+                else
+                    k_bupdate_x<X, K, double><<<nt, kBlock, 0, cs>>>(wv, Xc, d_tt, gs);
             }
             k_bstep_end<<<gw, kBlock, 0, cs>>>(gs, partials, cap);
             k_bsummary<<<1, kBlock, 0, cs>>>(gs, 1);
         };
         const int32_t products = minnorm ? 2 : 1;
         auto tail = [&]() {
+            if (mixed) {
+                if (minnorm ? na > 0 : nt > 0)
+                    k_bfold<X, K><<<minnorm ? na : nt, kBlock, 0, cs>>>(D, minnorm ? Y : Xc,
+                                                                        minnorm ? d_ta : d_tt, gs);
+                k_bdirty_clear<<<1, kBlock, 0, cs>>>(gs);
+            }
             // true-residual check for waiting groups (every running group when mixed)
             if (minnorm)
                 prod<double, double, K, kBNorm>(P, 1, Y, Xc, nullptr, d_tt, nt, gs,
