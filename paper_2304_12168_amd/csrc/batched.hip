@@ -134,10 +134,54 @@ __device__ __forceinline__ float ldv(const uint16_t *v, int64_t k) {
 
 enum BEpi : int32_t { kBNorm = 0, kBResid = 1, kBNormOnly = 2 };
 
+// Value of lane S of the calling lane's group of KL consecutive lanes (KL a
+// power of two, groups aligned).  Groups inside one 16-lane DPP row use a
+// DPP broadcast (quad_perm within quads, row_newbcast within rows), which
+// needs no LDS round trip; wider groups use a lane shuffle.  Every lane of a
+// group is active or inactive together.
+template <int KL, int S>
+__device__ __forceinline__ int32_t grp_bcast(int32_t v, int lane) {
+    if constexpr (KL == 1) {
+        return v;
+    } else if constexpr (KL == 2) {
+        return __builtin_amdgcn_update_dpp(0, v, S | S << 2 | (2 + S) << 4 | (2 + S) << 6, 0xF,
+                                           0xF, false);
+    } else if constexpr (KL == 4) {
+        return __builtin_amdgcn_update_dpp(0, v, S * 0x55, 0xF, 0xF, false);
+    } else if constexpr (KL == 8) {
+        const int32_t lo = __builtin_amdgcn_update_dpp(0, v, 0x150 + S, 0xF, 0xF, false);
+        const int32_t hi = __builtin_amdgcn_update_dpp(0, v, 0x158 + S, 0xF, 0xF, false);
+        return (lane & 8) ? hi : lo;
+    } else if constexpr (KL == 16) {
+        return __builtin_amdgcn_update_dpp(0, v, 0x150 + S, 0xF, 0xF, false);
+    } else {
+        return __shfl(v, (lane & ~(KL - 1)) + S);
+    }
+}
+template <int KL, int S>
+__device__ __forceinline__ float grp_bcast(float v, int lane) {
+    return __int_as_float(grp_bcast<KL, S>(__float_as_int(v), lane));
+}
+template <int KL, int S>
+__device__ __forceinline__ double grp_bcast(double v, int lane) {
+    const int64_t w = __double_as_longlong(v);
+    const int32_t lo = grp_bcast<KL, S>((int32_t)(uint32_t)w, lane);
+    const int32_t hi = grp_bcast<KL, S>((int32_t)(w >> 32), lane);
+    return __longlong_as_double((int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 // Column indices and values of one chunk of U nonzeros of a row (positions
 // k, k + L, ..., k + (U-1) L below the row end e) for the KL lanes that share
-// the row: the lanes load distinct entries and pass them round with lane
-// shuffles (KL times less load data than every lane loading every entry);
+// the row: the lanes load distinct entries and pass them round with group
+// broadcasts (KL times less load data than every lane loading every entry);
 // gbase is the group's first lane.  Entries past the row end come back as
 // j = -1, a = 0.
 template <int U, int KL, typename V, typename T>
@@ -159,11 +203,12 @@ __device__ __forceinline__ void load_chunk(const int32_t *__restrict__ ci,
             al[q] = sgn * (T)ldv(val, kk);
         }
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        j[u] = __shfl(jl[u / KL], gbase + (u % KL));
-        a[u] = __shfl(al[u / KL], gbase + (u % KL));
-    }
+    const int lane = gbase + cl;
+    static_for<U>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        j[u] = grp_bcast<KL, u % KL>(jl[u / KL], lane);
+        a[u] = grp_bcast<KL, u % KL>(al[u / KL], lane);
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -174,6 +219,25 @@ __device__ __forceinline__ void load_chunk(const int32_t *__restrict__ ci,
 // kernels; L > 1: lane-strided terms merged by a fixed butterfly).  Per block
 // and column: partial sum of Y^2.
 // ---------------------------------------------------------------------------
+// Vectors of CV consecutive entries, moved with 16-byte accesses.
+template <typename T, int CV>
+struct alignas(sizeof(T) * CV) VecT {
+    T v[CV];
+};
+template <typename T, int CV>
+__device__ __forceinline__ void vld(const T *p, double (&o)[CV]) {
+    const VecT<T, CV> w = *reinterpret_cast<const VecT<T, CV> *>(p);
+#pragma unroll
+    for (int v = 0; v < CV; ++v) o[v] = (double)w.v[v];
+}
+template <typename T, int CV>
+__device__ __forceinline__ void vst(T *p, const double (&o)[CV]) {
+    VecT<T, CV> w;
+#pragma unroll
+    for (int v = 0; v < CV; ++v) w.v[v] = (T)o[v];
+    *reinterpret_cast<VecT<T, CV> *>(p) = w;
+}
+
 template <typename X, int CV>
 struct VecLoad;
 template <>
@@ -336,11 +400,16 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
             for (int v = 0; v < CV; ++v) yv[v] = (double)acc[v];
         }
         if (l == 0) {
+            if constexpr (EPI != kBNormOnly) vst<X, CV>(y + row * K + c0, yv);
 #pragma unroll
             for (int v = 0; v < CV; ++v) {
-                if constexpr (EPI != kBNormOnly) y[row * K + c0 + v] = (X)yv[v];
                 const double q = (double)(X)yv[v];
-                acc_fma(part[v], q, q);
+                // FP64 chains: compensated, as the single-vector kernels; the
+                // low-precision chain's FP32 outputs need only an FP64 sum
+                if constexpr (kF64)
+                    acc_fma(part[v], q, q);
+                else
+                    part[v].p = __fma_rn(q, q, part[v].p);
             }
         }
         s_cur = s_nxt;
@@ -749,25 +818,6 @@ __global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 
 struct BVecs {
     void *p[kTMax + 1];
 };
-
-// Vectors of CV consecutive entries, moved with 16-byte accesses.
-template <typename T, int CV>
-struct alignas(sizeof(T) * CV) VecT {
-    T v[CV];
-};
-template <typename T, int CV>
-__device__ __forceinline__ void vld(const T *p, double (&o)[CV]) {
-    const VecT<T, CV> w = *reinterpret_cast<const VecT<T, CV> *>(p);
-#pragma unroll
-    for (int v = 0; v < CV; ++v) o[v] = (double)w.v[v];
-}
-template <typename T, int CV>
-__device__ __forceinline__ void vst(T *p, const double (&o)[CV]) {
-    VecT<T, CV> w;
-#pragma unroll
-    for (int v = 0; v < CV; ++v) w.v[v] = (T)o[v];
-    *reinterpret_cast<VecT<T, CV> *>(p) = w;
-}
 
 // alpha of the block's system, [j][column], for the update kernels
 template <int K>
