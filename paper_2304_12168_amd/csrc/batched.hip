@@ -144,16 +144,16 @@ __device__ __forceinline__ int32_t grp_bcast(int32_t v, int lane) {
     if constexpr (KL == 1) {
         return v;
     } else if constexpr (KL == 2) {
-        return __builtin_amdgcn_update_dpp(0, v, S | S << 2 | (2 + S) << 4 | (2 + S) << 6, 0xF,
+        return __builtin_amdgcn_mov_dpp(v, S | S << 2 | (2 + S) << 4 | (2 + S) << 6, 0xF,
                                            0xF, false);
     } else if constexpr (KL == 4) {
-        return __builtin_amdgcn_update_dpp(0, v, S * 0x55, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, S * 0x55, 0xF, 0xF, false);
     } else if constexpr (KL == 8) {
-        const int32_t lo = __builtin_amdgcn_update_dpp(0, v, 0x150 + S, 0xF, 0xF, false);
-        const int32_t hi = __builtin_amdgcn_update_dpp(0, v, 0x158 + S, 0xF, 0xF, false);
+        const int32_t lo = __builtin_amdgcn_mov_dpp(v, 0x150 + S, 0xF, 0xF, false);
+        const int32_t hi = __builtin_amdgcn_mov_dpp(v, 0x158 + S, 0xF, 0xF, false);
         return (lane & 8) ? hi : lo;
     } else if constexpr (KL == 16) {
-        return __builtin_amdgcn_update_dpp(0, v, 0x150 + S, 0xF, 0xF, false);
+        return __builtin_amdgcn_mov_dpp(v, 0x150 + S, 0xF, 0xF, false);
     } else {
         return __shfl(v, (lane & ~(KL - 1)) + S);
     }
@@ -1589,8 +1589,10 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
 #ifdef TA_SPMM_UNROLL
     constexpr int kU = TA_SPMM_UNROLL;
 #else
-    // nonzeros per lane in flight: FP64 vectors hold twice the registers
-    constexpr int kU = sizeof(X) == 8 ? 4 : 8;
+    // nonzeros per lane in flight: FP64 vectors hold twice the registers.
+    // FP32: 6 keeps a 5-point stencil row to one round at 7 waves per SIMD
+    // (8: 6 waves; an 8-nonzero row then takes two rounds)
+    constexpr int kU = sizeof(X) == 8 ? 4 : 6;
 #endif
     k_bspmm<V, X, K, EPI, kU><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y,
                                                       b, tab, gs, partials, cap, slot, gate, L);
