@@ -51,6 +51,7 @@ typedef struct {
     int32_t t_cycle;       /* CTA: 1 = the order of iteration k is or_cycle_order(t, k) */
     int32_t nonneg;        /* TA: 1 = x >= 0 (LP feasibility): c replaced by c+ = max(c, 0) */
     double rho_max;        /* TA: > 0 = stop at a witness once the radius would exceed this */
+    int32_t enhanced;      /* CTA, t >= 2: the enhanced stop (section 3) */
 } or_opts;
 
 /* Order cycling (section 5.1 cycles the order 1, ..., 5 and back), read as a
@@ -268,6 +269,64 @@ static void exit_diagnostics(const or_mat *A, const double *b, const double *x, 
  * ||A^T r|| <= tol_normal ||A^T b||, or phi_2 = 0 (Example 1: H r = 0 means x
  * solves the normal equation).
  */
+/* The enhanced stop of section 3 (a variant of Algorithm 1 for t >= 2), taken
+ * literally with explicit vectors: from the current residual f_0 = r, the
+ * first-order steps f_j = F_1(f_{j-1}) = f_{j-1} - a_j H f_{j-1}, with
+ * a_j = phi_1(f_{j-1}) / phi_2(f_{j-1}) (Example 1's order-1 step), for
+ * j = 1, ..., t - 1; the first f_j that passes the normal-equation test (the
+ * quadratic form f^T H f of section 3, read as ||A^T f_j|| against
+ * tol_normal ||A^T b||; ||A f_j|| for H = A, as for the plain test) ends the
+ * solve at x^ = x + sum_{i<j} a_{i+1} A^T f_i (H = A A^T), whose residual is
+ * f_j.  For the y-form the increment is sum a_{i+1} f_i on y (x = A^T y); for
+ * H = A it is sum a_{i+1} f_i on x.  The products made here are the oracle's
+ * way of evaluating these quantities and are not counted as the method's:
+ * the method gets them from the iteration's phi_1..phi_2t.
+ * Returns 1 (and updates x or y and r) if some f_j passes, else 0. */
+static int or_enhanced(const or_mat *A, const or_opts *o, int minnorm, int t, double *r,
+                       double *xy, double nab) {
+    const int64_t m = A->m, n = A->n;
+    const int ha = o->h_is_a;
+    const int64_t ng = ha ? m : n;           /* length of g = A^T f (or A f) */
+    const int64_t nd = (minnorm || ha) ? m : n;
+    double *f = (double *)malloc(sizeof(double) * (size_t)m);
+    double *hf = (double *)malloc(sizeof(double) * (size_t)m);
+    double *g = (double *)malloc(sizeof(double) * (size_t)ng);
+    double *dx = (double *)calloc((size_t)nd, sizeof(double));
+    int hit = 0;
+    int64_t e;
+    memcpy(f, r, sizeof(double) * (size_t)m);
+    if (ha) or_apply(A, f, g); else or_apply_t(A, f, g);
+    for (int j = 1; j < t && !hit; ++j) {
+        double p1, p2, a;
+        if (ha) {
+            memcpy(hf, g, sizeof(double) * (size_t)m);   /* H f = A f */
+            p1 = or_dot2(m, f, hf);
+        } else {
+            or_apply(A, g, hf);                          /* H f = A (A^T f) */
+            p1 = or_dot2(n, g, g);
+        }
+        p2 = or_dot2(m, hf, hf);
+        if (!(p2 > 0.0) || !isfinite(p1) || !isfinite(p2)) break;
+        a = p1 / p2;
+        if (minnorm || ha)
+            for (e = 0; e < m; ++e) dx[e] = fma(a, f[e], dx[e]);
+        else
+            for (e = 0; e < n; ++e) dx[e] = fma(a, g[e], dx[e]);
+        for (e = 0; e < m; ++e) f[e] = fma(-a, hf[e], f[e]);
+        if (ha) or_apply(A, f, g); else or_apply_t(A, f, g);
+        if (sqrt(or_dot2(ng, g, g)) <= o->tol_normal * nab) hit = 1;
+    }
+    if (hit) {
+        for (e = 0; e < nd; ++e) xy[e] += dx[e];
+        memcpy(r, f, sizeof(double) * (size_t)m);
+    }
+    free(f);
+    free(hf);
+    free(g);
+    free(dx);
+    return hit;
+}
+
 int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int minnorm,
            double *hist, int64_t hist_cap, or_info *info) {
     const int64_t m = A->m, n = A->n;
@@ -342,6 +401,14 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
         /* normal-equation test on ||A^T r||: phi_1 for H = A A^T, phi_2 = ||A r||^2
            (A symmetric) for H = A; phi_2 = 0 means H r = 0 (Example 1) */
         if (sqrt(o->h_is_a ? phi[2] : phi[1]) <= o->tol_normal * nab || phi[2] == 0.0) {
+            stop = OR_NORMAL;
+            break;
+        }
+        if (o->enhanced && tk >= 2 && o->tol_normal > 0.0 &&
+            or_enhanced(A, o, minnorm, tk, r, minnorm ? y : x, nab)) {
+            ++k;
+            rr = or_dot2(m, r, r);
+            if (k < hist_cap) hist[k] = sqrt(rr) / nb;
             stop = OR_NORMAL;
             break;
         }
