@@ -358,8 +358,10 @@ def diff_bench(args, P, torch, dev):
 def variants_bench(args, P, torch, dev):
     """Secondary: FP64 single-right-hand-side solves to 1e-6 with the CTA
     variants -- Kac/Clement N = 10001 (fixed t = 3 as configured, and the
-    order cycling 1..5..1), and the 256 x 256 Poisson matrix (symmetric
-    positive definite: H = A A^T vs H = A, fixed and cycling)."""
+    order cycling 1..5..1), the same matrix with a random (inconsistent)
+    right-hand side to the normal-equation tolerance 1e-6, plain and with the
+    enhanced stop, and the 256 x 256 Poisson matrix (symmetric positive
+    definite: H = A A^T vs H = A, fixed and cycling)."""
     import numpy as np
 
     from workloads import kac_clement, poisson5
@@ -368,8 +370,12 @@ def variants_bench(args, P, torch, dev):
     kac = kac_clement(10001, seed=args.seed)
     pois = poisson5(256)
     bp = torch.from_numpy(np.random.default_rng([args.seed, 5]).uniform(0, 1, pois.m)).to(dev)
+    binc = torch.from_numpy(np.random.default_rng([args.seed, 6]).standard_normal(kac.A.m)).to(dev)
     runs = [("kac_10001_t3", kac.A, torch.from_numpy(kac.b).to(dev), dict(t=3)),
             ("kac_10001_cycle5", kac.A, torch.from_numpy(kac.b).to(dev), dict(t=5, t_cycle=True)),
+            ("kac_10001_inconsistent_t3", kac.A, binc, dict(t=3, tol_normal=1e-6)),
+            ("kac_10001_inconsistent_t3_enhanced", kac.A, binc,
+             dict(t=3, tol_normal=1e-6, enhanced=True)),
             ("poisson_256_AAt_t3", pois, bp, dict(t=3)),
             ("poisson_256_A_t3", pois, bp, dict(t=3, h_is_a=True)),
             ("poisson_256_A_cycle5", pois, bp, dict(t=5, t_cycle=True, h_is_a=True))]
@@ -386,7 +392,7 @@ def variants_bench(args, P, torch, dev):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         out[name] = {"stop": info.stop, "iterations": info.iters, "products": info.matvecs,
-                     "seconds": sec, "rel_res": info.rel_res}
+                     "seconds": sec, "rel_res": info.rel_res, "rel_normal": info.rel_normal}
         log(f"[bench] {name}: {info.stop} after {info.iters} iterations, {info.matvecs} products, "
             f"{sec * 1e3:.1f} ms")
     return out

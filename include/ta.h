@@ -118,6 +118,16 @@ typedef struct ta_opts {
     double rho_max;        /* ta_solve: > 0 = stop with WITNESS once the radius would grow
                               beyond rho_max (the termination bound section 6 asks for);
                               0 = no bound.  Other solvers: 0 */
+    int32_t enhanced;      /* cta_solve / cta_minnorm: 1 = the enhanced stop of section 3 (for
+                              t >= 2): in every iteration of order t >= 2 the j-fold first-order
+                              iterates f_j = F_1(f_{j-1}), f_0 = r, j = 1..t-1, are also tested,
+                              and the first with ||A^T f_j|| <= tol_normal ||A^T b|| (||A f_j||
+                              for h_mode 1) ends the solve with stop NORMAL at
+                              x^ = x + sum_{i<j} (phi_1(f_i) / phi_2(f_i)) A^T f_i (f_i for
+                              the y-form's y and for h_mode 1); that iteration counts.  The
+                              tests and x^ come from the iteration's phi_1..phi_2t, with no
+                              further products.  Needs tol_normal > 0 to act.  Other
+                              solvers: 0 */
 } ta_opts;
 
 /* Result summary (host struct). */

@@ -36,6 +36,8 @@ struct State {
     int32_t replace;   // a true-residual replacement is due
     int32_t rejected;  // TA: a candidate stop failed, b' = A x must be recomputed
     int32_t hmode;     // CTA: 1 = H = A (A symmetric positive semidefinite), 0 = H = A A^T
+    int32_t enhanced;  // CTA: the enhanced stop (first-order iterates tested too)
+    int32_t enh_hit;   // CTA: this iteration's update is x^; stop NORMAL after it
     int64_t k;         // iterations done
     int64_t max_iter;
     int64_t hist_cap;

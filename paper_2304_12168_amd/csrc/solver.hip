@@ -52,6 +52,7 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (o->h_mode == 1 && (solver != 0 || A->m != A->n)) return TA_EINVAL;
     if (o->t_cycle != 0 && (o->t_cycle != 1 || solver == 2)) return TA_EINVAL;
     if (o->nonneg != 0 && (o->nonneg != 1 || solver != 2)) return TA_EINVAL;
+    if (o->enhanced != 0 && (o->enhanced != 1 || solver == 2)) return TA_EINVAL;
     if (!(o->rho_max >= 0.0) || !isfinite(o->rho_max) || (o->rho_max > 0.0 && solver != 2))
         return TA_EINVAL;
     if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64
@@ -254,6 +255,7 @@ static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
     h.fixed_rho = o->fixed_rho;
     h.hmode = o->h_mode;
     h.rho_max = o->rho_max;
+    h.enhanced = o->enhanced;
     return h;
 }
 

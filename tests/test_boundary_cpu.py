@@ -91,6 +91,13 @@ def test_validate_variant_options(lib):
     assert P.validate(rect, 0, t=3, t_cycle=True) == 0
     assert P.validate(rect, 1, t=3, t_cycle=True) == 0
     assert P.validate(rect, 2, t_cycle=True) == -1       # TA has no order
+    assert P.validate(rect, 0, t=3, enhanced=True) == 0
+    assert P.validate(rect, 1, t=3, enhanced=True) == 0
+    assert P.validate(sq, 0, t=3, enhanced=True, h_is_a=True) == 0
+    assert P.validate(rect, 2, enhanced=True) == -1      # a CTA stop
+    oe = P.make_opts(t=3)
+    oe.enhanced = 2
+    assert lib.ta_validate(ctypes.byref(rect), ctypes.byref(oe), 0) == -1
     o = P.make_opts(t=3)
     o.launch_mode = 2
     assert lib.ta_validate(ctypes.byref(sq), ctypes.byref(o), 0) == -1

@@ -1,0 +1,111 @@
+"""The enhanced stop (section 3, CTA with t >= 2) through the C ABI, against
+the FP64 oracle.  The device derives the first-order iterates' tests and x^
+from the iteration's phi_1..phi_2t; the oracle forms the iterates with
+explicit products.  Cases where the stop fires by a margin (the tolerance
+sits between two iterates' test values, found in the eigenbasis of H): equal
+stop codes, iteration and product counts, x within 1e-9 relative.  A larger
+inconsistent sparse system: both stop NORMAL within one iteration of each
+other, with the true normal-equation residual within the tolerance."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2304_12168_amd as P
+from workloads import csr_from_dense, kac_clement
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.load_library()
+    oracle.build(force=False)
+
+
+def _tests(lam, V, r, steps, h_is_a):
+    """Test values of F_1^j(r), j = 1..steps, in the eigenbasis of H."""
+    c = V.T @ r
+    out = []
+    for _ in range(steps):
+        a = np.sum(lam * c * c) / np.sum(lam * lam * c * c)
+        c = c * (1.0 - a * lam)
+        out.append(np.sqrt(np.sum((lam * lam if h_is_a else lam) * c * c)))
+    return out
+
+
+def _window_case(h_is_a, t):
+    """A seeded small system and a tolerance that selects iterate j = t - 1
+    (the test values of j = t - 2 and j = t - 1 differ by at least 2x)."""
+    for seed in range(300):
+        g = np.random.default_rng(seed)
+        if h_is_a:
+            Q, _ = np.linalg.qr(g.standard_normal((12, 12)))
+            lam = np.concatenate([np.geomspace(1.0, 30.0, 9), np.zeros(3)])
+            A = (Q * lam) @ Q.T
+            b = g.standard_normal(12)
+            lamH, V = np.linalg.eigh(A)
+            nab = np.linalg.norm(A @ b)
+        else:
+            A = g.standard_normal((14, 10))
+            b = g.standard_normal(14)
+            lamH, V = np.linalg.eigh(A @ A.T)
+            nab = np.linalg.norm(A.T @ b)
+        q = [nab] + _tests(lamH, V, b, t - 1, h_is_a)
+        if q[-1] < 0.5 * q[-2]:
+            return A, b, np.sqrt(q[-1] * q[-2]) / nab
+    raise AssertionError("no window")
+
+
+@pytest.mark.parametrize("t", [2, 3, 4])
+@pytest.mark.parametrize("form", ["x_dense", "x_csr", "y_dense", "h_a"])
+def test_enhanced_window_matches_oracle(form, t):
+    A, b, tol_ne = _window_case(form == "h_a", t)
+    if form == "x_csr":
+        A = csr_from_dense(A)
+    kw = dict(tol=1e-12, t=t, max_iter=100, tol_normal=tol_ne, enhanced=True,
+              h_is_a=form == "h_a")
+    if form.startswith("y"):
+        kw.pop("h_is_a")
+        xg, hg, ig = P.cta_minnorm(A, b, **kw)
+        xo, ho, io = oracle.cta_minnorm(A, b, **kw)
+    else:
+        xg, hg, ig = P.cta_solve(A, b, **kw)
+        xo, ho, io = oracle.cta(A, b, **kw)
+    assert io.stop == "normal" and io.iters == 1
+    assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs)
+    xg = xg.cpu().numpy()
+    assert np.linalg.norm(xg - xo) <= 1e-9 * np.linalg.norm(xo)
+    np.testing.assert_allclose(hg.cpu().numpy(), ho, rtol=1e-9)
+    assert ig.rel_normal <= tol_ne * (1 + 1e-6)
+
+
+def test_no_hit_equals_plain_cta():
+    """A consistent system (b = A x*) and a normal-equation tolerance no
+    first-order iterate reaches before the residual stop: the enhanced run is
+    plain CTA's, bit for bit."""
+    prob = kac_clement(101)
+    A, b = prob.A, prob.b
+    kw = dict(tol=1e-8, t=3, max_iter=300, tol_normal=1e-14)
+    x0, h0, i0 = P.cta_solve(A, b, **kw)
+    x1, h1, i1 = P.cta_solve(A, b, enhanced=True, **kw)
+    assert i0 == i1
+    assert torch.equal(x0, x1) and torch.equal(h0, h1)
+
+
+@pytest.mark.parametrize("t", [2, 3])
+def test_inconsistent_kac(t):
+    """Kac-Clement N = 1001 is singular (eigenvalue 0); a random b makes the
+    system inconsistent, so CTA ends on the normal-equation test."""
+    A = kac_clement(1001).A
+    b = np.random.default_rng(11).standard_normal(1001)
+    kw = dict(tol=1e-10, t=t, max_iter=200000, tol_normal=1e-6, enhanced=True)
+    xg, _, ig = P.cta_solve(A, b, **kw)
+    xo, _, io = oracle.cta(A, b, **kw)
+    assert ig.stop == io.stop == "normal"
+    assert abs(ig.iters - io.iters) <= 1, (ig, io)
+    assert ig.rel_normal <= 1e-6 * (1 + 1e-6) and io.rel_normal <= 1e-6 * (1 + 1e-6)
+    _, _, ip = P.cta_solve(A, b, tol=1e-10, t=t, max_iter=200000, tol_normal=1e-6)
+    assert ip.stop == "normal" and ig.iters <= ip.iters
