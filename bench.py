@@ -398,6 +398,62 @@ def variants_bench(args, P, torch, dev):
     return out
 
 
+def hbm_sweep_bench(args, P, torch, dev):
+    """Secondary: bandwidth of the product kernels on HBM-resident sizes --
+    the LP-shaped generator at n = 1e6, 4e6, 1e7 (m = n / 100, 6 nonzeros per
+    column + slack: random gathers) and the Poisson 5-point matrix at
+    N^2 = 1024^2, 2048^2, 2896^2 (banded: gathers near the row's own index).
+    Single-vector FP64 A and A^T passes of the solvers (the prepared
+    operator's kernels) and the batched FP32 SpMM at K = 32, each timed with
+    HIP events by the library's hooks; algorithmic bytes as in csr_pass_bytes.
+    Past ~2e7 nonzeros the FP64 matrix (12 B per nonzero) no longer fits the
+    256 MB Infinity Cache."""
+    import numpy as np
+
+    from workloads import lp_shaped, poisson5
+
+    out = []
+    cases = [("lp_shaped", n) for n in (1_000_000, 4_000_000, 10_000_000)]
+    cases += [("poisson5", N) for N in (1024, 2048, 2896)]
+    for kind, size in cases:
+        t0 = time.perf_counter()
+        if kind == "lp_shaped":
+            Ah = lp_shaped(size // 100, size, per_col=6, seed=args.seed).A
+        else:
+            Ah = poisson5(size)
+        gen_s = time.perf_counter() - t0
+        m, n = Ah.m, Ah.n
+        A = P.to_device(Ah)
+        nnz = A.nnz
+        pl = P.plan(A)
+        g = np.random.default_rng([args.seed, 7])
+        x = torch.from_numpy(g.standard_normal(n)).to(dev)
+        u = torch.from_numpy(g.standard_normal(m)).to(dev)
+        ms_a = P.time_matvec(pl, x, trans=False, reps=args.reps)
+        ms_t = P.time_matvec(pl, u, trans=True, reps=args.reps)
+        by_a = csr_pass_bytes(m, n, nnz, 8, 4, 8)
+        by_t = csr_pass_bytes(n, m, nnz, 8, 4, 8)
+        bp = P.BatchPlan([A], "fp32")
+        ms_ba = P.batch_time_spmm(bp, 32, trans=False, precision="fp32", reps=args.reps)
+        ms_bt = P.batch_time_spmm(bp, 32, trans=True, precision="fp32", reps=args.reps)
+        bp.close()
+        by_ba = csr_pass_bytes(m, n, nnz, 4, 4, 4, 32)
+        by_bt = csr_pass_bytes(n, m, nnz, 4, 4, 4, 32)
+        row = {"matrix": kind, "size": size, "n": n, "m": m, "nnz": nnz,
+               "fp64_matrix_mb": nnz * 12 / 1e6, "generated_s": gen_s}
+        for key, by, ms in (("fp64_A", by_a, ms_a), ("fp64_AT", by_t, ms_t),
+                            ("fp32_k32_A", by_ba, ms_ba), ("fp32_k32_AT", by_bt, ms_bt)):
+            gbs = by / ms / 1e6
+            row[key] = {"us": ms * 1e3, "bytes": by, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+        out.append(row)
+        log(f"[bench] HBM sweep {kind} {size}: FP64 A {row['fp64_A']['GB_s']:.0f} GB/s, "
+            f"A^T {row['fp64_AT']['GB_s']:.0f} GB/s; FP32 K=32 A {row['fp32_k32_A']['GB_s']:.0f} "
+            f"GB/s, A^T {row['fp32_k32_AT']['GB_s']:.0f} GB/s")
+        del pl, A, x, u, Ah
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -417,6 +473,8 @@ def main():
                     help="skip the differentiable-solve secondary block")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the CTA-variants secondary block")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the HBM-resident size sweep of the product kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -443,6 +501,8 @@ def main():
         res["config"]["differentiable"] = diff_bench(args, P, torch, dev)
     if not args.no_variants:
         res["config"]["variants"] = variants_bench(args, P, torch, dev)
+    if not args.no_sweep:
+        res["config"]["hbm_sweep"] = hbm_sweep_bench(args, P, torch, dev)
     out = {
         "metric": "solves/s and HBM GB/s to rel-residual 1e-6: CTA mixed+batched vs FP64 plain",
         "value": res["value"],
