@@ -45,7 +45,7 @@ class _Opts(C.Structure):
                 ("max_iter", C.c_int64), ("replace_every", C.c_int32), ("warm_start", C.c_int32),
                 ("rho0", C.c_double), ("fixed_rho", C.c_int32), ("h_is_a", C.c_int32),
                 ("t_cycle", C.c_int32), ("nonneg", C.c_int32), ("rho_max", C.c_double),
-                ("enhanced", C.c_int32)]
+                ("enhanced", C.c_int32), ("normal_eq", C.c_int32)]
 
 
 class _Info(C.Structure):
@@ -170,10 +170,12 @@ def gram_alpha(phi, t: int):
 
 
 def _opts(tol, tol_normal, t, max_iter, replace_every, warm_start, rho0, fixed_rho,
-          h_is_a=False, t_cycle=False, nonneg=False, rho_max=0.0, enhanced=False):
+          h_is_a=False, t_cycle=False, nonneg=False, rho_max=0.0, enhanced=False,
+          normal_eq=False):
     return _Opts(float(tol), float(tol_normal), int(t), int(max_iter), int(replace_every),
                  int(warm_start), float(rho0), int(fixed_rho), int(bool(h_is_a)),
-                 int(bool(t_cycle)), int(bool(nonneg)), float(rho_max), int(bool(enhanced)))
+                 int(bool(t_cycle)), int(bool(nonneg)), float(rho_max), int(bool(enhanced)),
+                 int(bool(normal_eq)))
 
 
 def cta(A, b, tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0,
@@ -210,18 +212,19 @@ def cta_minnorm(A, b, **kw):
 
 def ta(A, b, tol=1e-6, max_iter=100000, tol_normal=0.0, rho0=0.0, fixed_rho=False,
        hist_cap: Optional[int] = None, x0: Optional[np.ndarray] = None, nonneg=False,
-       rho_max=0.0):
+       rho_max=0.0, normal_eq=False):
     """Algorithm 3 (or Algorithm 2 with ``fixed_rho``), from x0 (b' = A x0) if
     given, else from 0; with ``nonneg``, the LP-feasibility form (x >= 0, c
-    replaced by c+) and an optional radius bound ``rho_max``.  Returns
-    (x, hist, info)."""
+    replaced by c+) and an optional radius bound ``rho_max``; with
+    ``normal_eq``, on A^T A x = A^T b (the products are A^T (A v); the exit
+    diagnostics stay on (A, b)).  Returns (x, hist, info)."""
     M = _MatRef(A)
     b = _f64(b)
     cap = int(max_iter) + 1 if hist_cap is None else int(hist_cap)
     hist = np.full(max(cap, 1), np.nan)
     x = np.zeros(M.n) if x0 is None else _f64(x0).copy()
     o = _opts(tol, tol_normal, 1, max_iter, 0, x0 is not None, rho0, fixed_rho,
-              nonneg=nonneg, rho_max=rho_max)
+              nonneg=nonneg, rho_max=rho_max, normal_eq=normal_eq)
     inf = _Info()
     _load().or_ta(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), _ptr(hist), cap, C.byref(inf))
     info = _info(inf)
@@ -267,14 +270,15 @@ def cta_grad(A, b, dldx_of_x, tol=1e-12, t=3, max_iter=100000):
     return x, lam, csr_outer(A, lam, x, -1.0), fi, ai
 
 
-def ta_minnorm(A, b, x_eps, tol=1e-6, max_iter=100000, tol_normal=0.0):
+def ta_minnorm(A, b, x_eps, tol=1e-6, max_iter=100000, tol_normal=0.0, normal_eq=False):
     """Algorithm 4: from an approximate solution x_eps, bisect on the radius
-    with Algorithm 2 tests.  Returns (x, info, tests); info.rho and
-    info.rho_lo are the final upper and lower bounds on the norm."""
+    with Algorithm 2 tests (on A^T A x = A^T b with ``normal_eq``).  Returns
+    (x, info, tests); info.rho and info.rho_lo are the final upper and lower
+    bounds on the norm."""
     M = _MatRef(A)
     b, xe = _f64(b), _f64(x_eps)
     x = np.zeros(M.n)
-    o = _opts(tol, tol_normal, 1, max_iter, 0, 0, 0.0, False)
+    o = _opts(tol, tol_normal, 1, max_iter, 0, 0, 0.0, False, normal_eq=normal_eq)
     inf = _Info()
     tests = _load().or_ta_minnorm(C.byref(M.s), _ptr(b), _ptr(xe), _ptr(x), C.byref(o),
                                    C.byref(inf))

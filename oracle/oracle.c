@@ -52,6 +52,8 @@ typedef struct {
     int32_t nonneg;        /* TA: 1 = x >= 0 (LP feasibility): c replaced by c+ = max(c, 0) */
     double rho_max;        /* TA: > 0 = stop at a witness once the radius would exceed this */
     int32_t enhanced;      /* CTA, t >= 2: the enhanced stop (section 3) */
+    int32_t normal_eq;     /* TA: 1 = run on the normal equation A^T A x = A^T b (the
+                              rectangular hybrid's inputs for an inconsistent system) */
 } or_opts;
 
 /* Order cycling (section 5.1 cycles the order 1, ..., 5 and back), read as a
@@ -476,21 +478,86 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
  *   gamma = rho / ||c||, s = A c, d_i = fma(gamma, s_i, -b'_i) (= v_i - b'_i),
  *   b'_i = fma(alpha, d_i, b'_i), x_j = fma(alpha gamma, c_j, (1 - alpha) x_j).
  */
-int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double *hist,
+/* The operator TA works on: A itself, or M = A^T A (normal_eq), applied as
+ * A^T (A v) with the inner product A v rounded to FP64.  M is symmetric, so
+ * M^T = M; M's residual b~ - M x is b~ - A^T t, t = A x, one compensated sum
+ * of b~_j and the terms -a_ij t_i per column. */
+typedef struct {
+    const or_mat *A;
+    int ne;
+    double *tmp; /* m entries */
+} or_op;
+
+static void op_apply(const or_op *P, const double *v, double *y) {
+    if (P->ne) {
+        or_apply(P->A, v, P->tmp);
+        or_apply_t(P->A, P->tmp, y);
+    } else {
+        or_apply(P->A, v, y);
+    }
+}
+
+static void op_apply_t(const or_op *P, const double *v, double *y) {
+    if (P->ne)
+        op_apply(P, v, y);
+    else
+        or_apply_t(P->A, v, y);
+}
+
+static void op_residual(const or_op *P, const double *b, const double *x, double *r) {
+    const or_mat *A = P->A;
+    if (!P->ne) {
+        or_residual(A, b, x, r);
+        return;
+    }
+    acc2 *c = (acc2 *)calloc((size_t)A->n, sizeof(acc2));
+    or_apply(A, x, P->tmp);
+    for (int64_t j = 0; j < A->n; ++j) acc_add(&c[j], b[j], 1.0);
+    for (int64_t i = 0; i < A->m; ++i) {
+        if (A->kind == OR_CSR) {
+            for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k)
+                acc_add(&c[A->col_idx[k]], -A->val[k], P->tmp[i]);
+        } else {
+            const double *row = A->val + i * A->ld;
+            for (int64_t j = 0; j < A->n; ++j) acc_add(&c[j], -row[j], P->tmp[i]);
+        }
+    }
+    for (int64_t j = 0; j < A->n; ++j) r[j] = acc_value(c[j]);
+    free(c);
+}
+
+int or_ta(const or_mat *A, const double *b0, double *x, const or_opts *o, double *hist,
           int64_t hist_cap, or_info *info) {
-    const int64_t m = A->m, n = A->n;
+    /* normal_eq: the system is A^T A x = A^T b; m below is its row count n and
+       b its right-hand side A^T b; the exit diagnostics stay on (A, b) */
+    const int ne = o->normal_eq != 0;
+    const int64_t n = A->n, m = ne ? A->n : A->m;
+    const int pm = ne ? 2 : 1; /* passes over A per operator product */
+    double *btil = NULL;
+    or_op P = {A, ne, NULL};
+    const double *b = b0;
     int stop = 0, pass = 0, have_c = 0;
     int64_t k = 0, matvecs = 0, i;
     double nb, nab = 0.0, rr, rb, rho = o->rho0, rho_lo = 0.0, nc = 0.0;
     double *bp, *r, *c, *s, *d, *rt;
 
     memset(info, 0, sizeof(*info));
+    if (ne) {
+        P.tmp = (double *)malloc(sizeof(double) * (size_t)(A->m > 0 ? A->m : 1));
+        btil = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        or_apply_t(A, b0, btil);
+        b = btil;
+        ++matvecs;
+    }
     nb = sqrt(or_dot2(m, b, b));
     if (!o->warm_start || nb == 0.0) memset(x, 0, sizeof(double) * (size_t)n);
     if (nb == 0.0) {
         if (hist_cap > 0) hist[0] = 0.0;
         info->stop = OR_RESIDUAL;
         info->rho = rho;
+        info->matvecs = matvecs;
+        free(P.tmp);
+        free(btil);
         return 0;
     }
     bp = (double *)calloc((size_t)m, sizeof(double));
@@ -500,15 +567,15 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
     d = (double *)malloc(sizeof(double) * (size_t)m);
     c = (double *)malloc(sizeof(double) * (size_t)n);
     if (o->tol_normal > 0.0) {
-        or_apply_t(A, b, c);
+        op_apply_t(&P, b, c);
         if (o->nonneg)
             for (i = 0; i < n; ++i) c[i] = c[i] > 0.0 ? c[i] : 0.0;
         nab = sqrt(or_dot2(n, c, c));
-        ++matvecs;
+        matvecs += pm;
     }
     if (o->warm_start) {  /* start from the given x: b' = A x */
-        or_apply(A, x, bp);
-        ++matvecs;
+        op_apply(&P, x, bp);
+        matvecs += pm;
     }
     for (i = 0; i < m; ++i) r[i] = b[i] - bp[i];
     rr = or_dot2(m, r, r);
@@ -517,11 +584,11 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
 
     for (;;) {
         if (sqrt(rr) <= o->tol * nb) {
-            or_residual(A, b, x, rt);
-            ++matvecs;
+            op_residual(&P, b, x, rt);
+            matvecs += pm;
             if (sqrt(or_dot2(m, rt, rt)) <= o->tol * nb) { stop = OR_RESIDUAL; break; }
-            or_apply(A, x, bp);
-            ++matvecs;
+            op_apply(&P, x, bp);
+            matvecs += pm;
             for (i = 0; i < m; ++i) r[i] = b[i] - bp[i];
             rr = or_dot2(m, r, r);
             rb = or_dot2(m, r, b);
@@ -529,21 +596,21 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
         }
         if (k >= o->max_iter) { stop = OR_MAXITER; break; }
         if (!have_c) {
-            or_apply_t(A, r, c);
+            op_apply_t(&P, r, c);
             /* LP feasibility (section 6): the best point of E_{A,rho} within the
                cone x >= 0 uses c+ (Proposition eq. vrend2) */
             if (o->nonneg)
                 for (i = 0; i < n; ++i) c[i] = c[i] > 0.0 ? c[i] : 0.0;
             nc = sqrt(or_dot2(n, c, c));
-            ++matvecs;
+            matvecs += pm;
             have_c = 1;
         }
         if (!isfinite(nc) || !isfinite(rb)) { stop = OR_BREAKDOWN; break; }
         if (nc <= o->tol_normal * nab) { stop = OR_NORMAL; break; }
         if (pass || rho * nc >= rb) {
             double gamma = rho / nc, rd, dd, alpha, beta, a1;
-            or_apply(A, c, s);
-            ++matvecs;
+            op_apply(&P, c, s);
+            matvecs += pm;
             for (i = 0; i < m; ++i) d[i] = fma(gamma, s[i], -bp[i]);
             rd = or_dot2(m, r, d);
             dd = or_dot2(m, d, d);
@@ -579,12 +646,15 @@ int or_ta(const or_mat *A, const double *b, double *x, const or_opts *o, double 
     info->stop = stop;
     info->rho = rho;
     info->rho_lo = rho_lo;
-    exit_diagnostics(A, b, x, nb, &info->rel_res, &info->rel_normal);
+    exit_diagnostics(A, b0, x, sqrt(or_dot2(A->m, b0, b0)), &info->rel_res,
+                     &info->rel_normal);
     free(bp);
     free(r);
     free(rt);
     free(s);
     free(d);
+    free(P.tmp);
+    free(btil);
     free(c);
     return 0;
 }
