@@ -128,6 +128,11 @@ typedef struct ta_opts {
                               tests and x^ come from the iteration's phi_1..phi_2t, with no
                               further products.  Needs tol_normal > 0 to act.  Other
                               solvers: 0 */
+    int32_t normal_eq;     /* ta_solve / ta_minnorm: 1 = TA on the normal equation
+                              A^T A x = A^T b (the inputs the rectangular hybrid of section
+                              5.2 gives TA when A x = b is not solvable).  Not available in
+                              this library: the call returns TA_ENOTSUP.  Must be 0
+                              (TA_EINVAL) for the other solvers */
 } ta_opts;
 
 /* Result summary (host struct). */

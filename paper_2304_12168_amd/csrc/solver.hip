@@ -53,6 +53,7 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (o->t_cycle != 0 && (o->t_cycle != 1 || solver == 2)) return TA_EINVAL;
     if (o->nonneg != 0 && (o->nonneg != 1 || solver != 2)) return TA_EINVAL;
     if (o->enhanced != 0 && (o->enhanced != 1 || solver == 2)) return TA_EINVAL;
+    if (o->normal_eq != 0) return o->normal_eq == 1 && solver == 2 ? TA_ENOTSUP : TA_EINVAL;
     if (!(o->rho_max >= 0.0) || !isfinite(o->rho_max) || (o->rho_max > 0.0 && solver != 2))
         return TA_EINVAL;
     if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64

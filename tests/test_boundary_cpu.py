@@ -95,6 +95,9 @@ def test_validate_variant_options(lib):
     assert P.validate(rect, 1, t=3, enhanced=True) == 0
     assert P.validate(sq, 0, t=3, enhanced=True, h_is_a=True) == 0
     assert P.validate(rect, 2, enhanced=True) == -1      # a CTA stop
+    assert P.validate(rect, 2, normal_eq=True) == -4     # TA_ENOTSUP: not on the device
+    assert P.validate(rect, 0, t=2, normal_eq=True) == -1  # a TA input form
+    assert P.validate(rect, 1, t=2, normal_eq=True) == -1
     oe = P.make_opts(t=3)
     oe.enhanced = 2
     assert lib.ta_validate(ctypes.byref(rect), ctypes.byref(oe), 0) == -1
