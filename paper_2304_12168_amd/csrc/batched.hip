@@ -104,6 +104,7 @@ enum BGate : int32_t {
     kBFinal = 2,    // only when every group has finished
     kBAlways = 3,
     kBFinalNew = 4, // finished, and x and b - A x were not just computed by a check
+    kBDirty = 5,    // always, for the systems whose low-precision accumulator took updates
 };
 
 // flags: [0] every group finished, [1] a check is due, [2] a check ran in
@@ -299,6 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp
     // the iteration chain skips systems with no running group (their
     // partials are never read); checks and diagnostics cover every system
     if (gate == kBRun && !gs.sys_active[br.sys]) return;
+    if (gate == kBDirty && !gs.dirty[br.sys]) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cl = lane % KL, l = (lane / KL) % L, rsub = lane / (KL * L);
     const int RL = 64 / (KL * L);
@@ -538,6 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_bgemm(const V *__restrict__ mat,
     const BRange br = blocks[blockIdx.x / nseg];
     if (br.r0 >= br.r1) return;
     if (gate == kBRun && !gs.sys_active[br.sys]) return;
+    if (gate == kBDirty && !gs.dirty[br.sys]) return;
     const DSys ds = dsys[br.sys];
     const int32_t klen = ((ds.ld / 16 + nseg - 1) / nseg) * 16;
     const int32_t k_lo = min(seg * klen, ds.ld), k_hi = min(k_lo + klen, ds.ld);
@@ -681,6 +684,7 @@ __global__ __launch_bounds__(kBlock) void k_bgemm_fin(const T *__restrict__ part
     const BRange br = blocks[blockIdx.x];
     if (br.r0 >= br.r1) return;
     if (gate == kBRun && !gs.sys_active[br.sys]) return;
+    if (gate == kBDirty && !gs.dirty[br.sys]) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane % K, rsub = lane / K;
     Acc part = {0.0, 0.0};
@@ -829,17 +833,18 @@ __device__ __forceinline__ void load_alpha(const Groups &gs, int32_t sys, double
     __syncthreads();
 }
 
-// R -= sum alpha_j U_{j+1}; y-form: Y += alpha_1 R_old + sum alpha_j U_j.
-// Over the A-row table; partial ||R||^2 per (block, column) in slot 0.  A
-// lane covers CV consecutive columns of a row (16-byte accesses); every
-// column runs in FP64 and is rounded once to the vector type.  Y is held in
-// YA: FP64, or (mixed precision) the low-precision accumulator of the
-// current chunk, folded into the FP64 Y by k_bfold.
+// R -= sum alpha_j U_{j+1}; with acc_y, also Y += alpha_1 R_old + sum alpha_j
+// U_j (the y-form's y; in the mixed x-form the chunk's Z, x's increment
+// being A^T Z).  Over the A-row table; partial ||R||^2 per (block, column) in
+// slot 0.  A lane covers CV consecutive columns of a row (16-byte accesses);
+// every column runs in FP64 and is rounded once to the vector type.  Y is
+// held in YA: FP64, or (mixed precision) the low-precision accumulator of the
+// current chunk, folded into the FP64 iterate at the chunk's end.
 template <typename X, int K, typename YA>
 __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
                                                        const BRange *__restrict__ blocks,
                                                        Groups gs, double2 *partials,
-                                                       int64_t cap) {
+                                                       int64_t cap, int32_t acc_y) {
     if (gs.flags[0]) return;
     constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
     const BRange br = blocks[blockIdx.x];
@@ -859,7 +864,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
     Acc part[CV];
 #pragma unroll
     for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
-    if (!std::is_same<YA, double>::value && gs.minnorm && any && rsub == 0)
+    if (!std::is_same<YA, double>::value && acc_y && any && rsub == 0)
         gs.dirty[br.sys] = 1;  // benign same-value stores
     if (any) {
         for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
@@ -867,7 +872,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
             const int64_t e = (int64_t)it.row * K + c0;
             double ri[CV], u[CV];
             vld<X, CV>(r + e, ri);
-            if (gs.minnorm) {
+            if (acc_y) {
                 double yi[CV], y0[CV];
                 vld<YA, CV>(yv + e, y0);
 #pragma unroll
@@ -973,7 +978,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, XA *xv,
 template <typename X, int K>
 __global__ __launch_bounds__(kBlock) void k_bfold(X *d, double *f,
                                                    const BRange *__restrict__ blocks,
-                                                   Groups gs) {
+                                                   Groups gs, int32_t zero_d) {
     constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
     const BRange br = blocks[blockIdx.x];
     if (br.r0 >= br.r1 || !gs.dirty[br.sys]) return;
@@ -991,8 +996,23 @@ __global__ __launch_bounds__(kBlock) void k_bfold(X *d, double *f,
             dv[v] = 0.0;
         }
         vst<double, CV>(f + e, fv);
-        vst<X, CV>(d + e, dv);
+        if (zero_d) vst<X, CV>(d + e, dv);
     }
+}
+
+// D = 0 over a table's rows, for the systems whose accumulator took updates.
+template <typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_bzero(X *d, const BRange *__restrict__ blocks,
+                                                   Groups gs) {
+    constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
+    const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1 || !gs.dirty[br.sys]) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane % KL, rsub = lane / KL, c0 = cl * CV;
+    double z[CV] = {};
+    for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+         it = brow_next(br, R, wave, rsub, it))
+        vst<X, CV>(d + (int64_t)it.row * K + c0, z);
 }
 
 // after the fold: no accumulator holds updates
@@ -1734,8 +1754,9 @@ struct Engine {
         double *Bc = nullptr, *Y = nullptr, *Xc = nullptr, *RT = nullptr, *TN = nullptr;
         X *R = nullptr;
         X *U[kTMax + 1] = {}, *W[kTMax] = {};
-        // mixed precision: the chunk's updates of X (x-form) or Y (y-form)
-        // accumulate in D and are folded into the FP64 block at its end
+        // mixed precision: the chunk's increments accumulate in D (rows of A):
+        // the y-form's y, or in the x-form Z with x's increment A^T Z; at the
+        // chunk's end D is folded into the FP64 iterate
         X *D = nullptr;
         double2 *partials = nullptr;
         BRange *d_ta = nullptr, *d_tt = nullptr;
@@ -1747,10 +1768,12 @@ struct Engine {
         ws.reserve(&Bc, M * K);
         ws.reserve(&R, M * K);
         for (int j = 1; j <= t; ++j) ws.reserve(&U[j], M * K);
-        for (int j = 0; j < (minnorm ? 1 : t); ++j) ws.reserve(&W[j], N * K);
+        // W_j is kept for the x update only in the FP64 x-form
+        const bool one_w = minnorm || mixed;
+        for (int j = 0; j < (one_w ? 1 : t); ++j) ws.reserve(&W[j], N * K);
         if (minnorm) ws.reserve(&Y, M * K);
         ws.reserve(&Xc, N * K);
-        if (mixed) ws.reserve(&D, (minnorm ? M : N) * K);
+        if (mixed) ws.reserve(&D, M * K);
         ws.reserve(&RT, M * K);
         ws.reserve(&TN, N * K);
         double *DS = nullptr;  // column shares of the dense products
@@ -1805,8 +1828,7 @@ struct Engine {
         HIP_TRY(hipMemsetAsync(gs.sys_active, 0, sizeof(int32_t) * nsys, s));
         HIP_TRY(hipMemsetAsync(gs.dirty, 0, sizeof(int32_t) * nsys, s));
         HIP_TRY(hipMemsetAsync(Xc, 0, sizeof(double) * (size_t)(N * K), s));
-        if (mixed)
-            HIP_TRY(hipMemsetAsync(D, 0, sizeof(X) * (size_t)((minnorm ? M : N) * K), s));
+        if (mixed) HIP_TRY(hipMemsetAsync(D, 0, sizeof(X) * (size_t)(M * K), s));
         if (minnorm) HIP_TRY(hipMemsetAsync(Y, 0, sizeof(double) * (size_t)(M * K), s));
         gs.ksys = d_ksys;
         gs.a_blk = d_afirst;
@@ -1850,7 +1872,7 @@ struct Engine {
         auto iteration = [&]() {
             for (int j = 0; j < t; ++j) {
                 const void *uj = j == 0 ? (const void *)R : (const void *)U[j];
-                X *wj = W[minnorm ? 0 : j];
+                X *wj = W[one_w ? 0 : j];
                 prod<V, X, K, kBNorm>(P, 1, uj, wj, nullptr, d_tt, nt, gs, partials,
                                       cap, 2 * j, kBRun, Lt, cs, DS);
                 prod<V, X, K, kBNorm>(P, 0, wj, U[j + 1], nullptr, d_ta, na, gs,
@@ -1862,12 +1884,13 @@ struct Engine {
             for (int j = 1; j <= t; ++j) uv.p[j] = U[j];
             if (na > 0) {
                 if (mixed)
-                    k_bupdate_r<X, K, X><<<na, kBlock, 0, cs>>>(uv, R, D, d_ta, gs, partials, cap);
+                    k_bupdate_r<X, K, X><<<na, kBlock, 0, cs>>>(uv, R, D, d_ta, gs, partials, cap,
+                                                                 1);
                 else
                     k_bupdate_r<X, K, double><<<na, kBlock, 0, cs>>>(uv, R, Y, d_ta, gs, partials,
-                                                                      cap);
+                                                                      cap, minnorm ? 1 : 0);
             }
-            if (!minnorm && nt > 0) {
+            if (!minnorm && !mixed && nt > 0) {
                 BVecs wv{};
                 for (int j = 0; j < t; ++j) wv.p[j] = W[j];
                 if (mixed)
@@ -1881,9 +1904,15 @@ struct Engine {
         const int32_t products = minnorm ? 2 : 1;
         auto tail = [&]() {
             if (mixed) {
-                if (minnorm ? na > 0 : nt > 0)
-                    k_bfold<X, K><<<minnorm ? na : nt, kBlock, 0, cs>>>(D, minnorm ? Y : Xc,
-                                                                        minnorm ? d_ta : d_tt, gs);
+                if (minnorm) {
+                    if (na > 0) k_bfold<X, K><<<na, kBlock, 0, cs>>>(D, Y, d_ta, gs, 1);
+                } else {
+                    // x += A^T Z (the chunk's increment), Z = 0
+                    prod<V, X, K, kBNorm>(P, 1, D, W[0], nullptr, d_tt, nt, gs, partials, cap,
+                                          1, kBDirty, Lt, cs, DS);
+                    if (nt > 0) k_bfold<X, K><<<nt, kBlock, 0, cs>>>(W[0], Xc, d_tt, gs, 0);
+                    if (na > 0) k_bzero<X, K><<<na, kBlock, 0, cs>>>(D, d_ta, gs);
+                }
                 k_bdirty_clear<<<1, kBlock, 0, cs>>>(gs);
             }
             // true-residual check for waiting groups (every running group when mixed)
