@@ -45,7 +45,7 @@ class _Opts(C.Structure):
                 ("max_iter", C.c_int64), ("replace_every", C.c_int32), ("warm_start", C.c_int32),
                 ("rho0", C.c_double), ("fixed_rho", C.c_int32), ("h_is_a", C.c_int32),
                 ("t_cycle", C.c_int32), ("nonneg", C.c_int32), ("rho_max", C.c_double),
-                ("enhanced", C.c_int32), ("normal_eq", C.c_int32)]
+                ("enhanced", C.c_int32), ("normal_eq", C.c_int32), ("accel", C.c_double)]
 
 
 class _Info(C.Structure):
@@ -171,21 +171,22 @@ def gram_alpha(phi, t: int):
 
 def _opts(tol, tol_normal, t, max_iter, replace_every, warm_start, rho0, fixed_rho,
           h_is_a=False, t_cycle=False, nonneg=False, rho_max=0.0, enhanced=False,
-          normal_eq=False):
+          normal_eq=False, accel=0.0):
     return _Opts(float(tol), float(tol_normal), int(t), int(max_iter), int(replace_every),
                  int(warm_start), float(rho0), int(fixed_rho), int(bool(h_is_a)),
                  int(bool(t_cycle)), int(bool(nonneg)), float(rho_max), int(bool(enhanced)),
-                 int(bool(normal_eq)))
+                 int(bool(normal_eq)), float(accel))
 
 
 def cta(A, b, tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0,
         x0: Optional[np.ndarray] = None, minnorm=False, hist_cap: Optional[int] = None,
-        h_is_a=False, t_cycle=False, enhanced=False):
+        h_is_a=False, t_cycle=False, enhanced=False, accel=0.0):
     """Algorithm 1 (CTA, H = A A^T; with h_is_a, H = A for a square symmetric
     positive semidefinite A, x-form only; with t_cycle, the order of
     iteration k cycles 1, 2, ..., t, ..., 2, 1, ...; with enhanced, the
-    enhanced stop of section 3 on the j-fold first-order iterates).  Returns
-    (x, hist, info)."""
+    enhanced stop of section 3 on the j-fold first-order iterates; with accel
+    = theta in (0, 1), the convex-combination step of the first-order dynamics
+    theorem whenever ||r_{k+1}|| >= theta ||r_k||).  Returns (x, hist, info)."""
     if h_is_a:
         mm, nn = A.shape if isinstance(A, np.ndarray) else (A.m, A.n)
         if minnorm or mm != nn:
@@ -196,7 +197,7 @@ def cta(A, b, tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0,
     hist = np.full(max(cap, 1), np.nan)
     x = np.zeros(M.n) if x0 is None else _f64(x0).copy()
     o = _opts(tol, tol_normal, t, max_iter, replace_every, x0 is not None, 0.0, 0, h_is_a,
-              t_cycle, enhanced=enhanced)
+              t_cycle, enhanced=enhanced, accel=accel)
     inf = _Info()
     rc = _load().or_cta(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), int(bool(minnorm)),
                         _ptr(hist), cap, C.byref(inf))

@@ -54,6 +54,7 @@ typedef struct {
     int32_t enhanced;      /* CTA, t >= 2: the enhanced stop (section 3) */
     int32_t normal_eq;     /* TA: 1 = run on the normal equation A^T A x = A^T b (the
                               rectangular hybrid's inputs for an inconsistent system) */
+    double accel;          /* CTA: > 0 = convex-combination step when ||r_{k+1}|| >= accel ||r_k|| */
 } or_opts;
 
 /* Order cycling (section 5.1 cycles the order 1, ..., 5 and back), read as a
@@ -337,6 +338,11 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
     int64_t k = 0, matvecs = 0, i, e;
     double nb, nab = 0.0, rr, phi[17], alpha[8];
     double *r, *y = NULL, *u[9], *w[8], *rt;
+    /* convex-combination step (the theorem on the first-order dynamics,
+       section 3): the previous residual and iterate, and whether the current
+       iterate came from such a step */
+    double *rp = NULL, *xp = NULL;
+    int last_jump = 0;
 
     memset(info, 0, sizeof(*info));
     if (t < 1 || t > 8) return -1;
@@ -352,6 +358,10 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
     for (i = 0; i <= t; ++i) u[i] = (double *)malloc(sizeof(double) * (size_t)m);
     for (i = 0; i < t; ++i) w[i] = (double *)malloc(sizeof(double) * (size_t)n);
     if (minnorm) y = (double *)calloc((size_t)m, sizeof(double));
+    if (o->accel > 0.0) {
+        rp = (double *)malloc(sizeof(double) * (size_t)m);
+        xp = (double *)malloc(sizeof(double) * (size_t)(minnorm ? m : n));
+    }
 
     if (o->tol_normal > 0.0) {
         or_apply_t(A, b, w[0]);
@@ -417,6 +427,14 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
         or_gram_alpha(phi, tk, alpha);
         if (!finite_all(alpha, tk)) { stop = OR_BREAKDOWN; break; }
 
+        const double rr_prev = rr;
+        if (rp != NULL) {
+            memcpy(rp, r, sizeof(double) * (size_t)m);
+            if (minnorm)
+                memcpy(xp, y, sizeof(double) * (size_t)m);
+            else
+                memcpy(xp, x, sizeof(double) * (size_t)n);
+        }
         for (int j = 0; j < tk; ++j)
             for (e = 0; e < m; ++e) r[e] = fma(-alpha[j], u[j + 1][e], r[e]);
         if (minnorm) {
@@ -432,6 +450,25 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
         }
         ++k;
         rr = or_dot2(m, r, r);
+        /* Convex-combination step: when ||r_{k+1}|| / ||r_k|| = rho >= accel
+           (the residuals "do not differ by much"), the iterate becomes
+           a r_k + (1 - a) r_{k+1} (and the same combination of x or y) with
+           a = rho / (rho + 1), the weight that gives F_1(.) = 0 on a critical
+           line.  Not twice in a row: the pair must be two steps of F_t. */
+        if (rp != NULL) {
+            const double rho = rr_prev > 0.0 ? sqrt(rr / rr_prev) : 0.0;
+            if (!last_jump && rho >= o->accel) {
+                const double a = rho / (rho + 1.0), a1 = 1.0 - a;
+                double *xy = minnorm ? y : x;
+                const int64_t nxy = minnorm ? m : n;
+                for (e = 0; e < m; ++e) r[e] = fma(a, rp[e], a1 * r[e]);
+                for (e = 0; e < nxy; ++e) xy[e] = fma(a, xp[e], a1 * xy[e]);
+                rr = or_dot2(m, r, r);
+                last_jump = 1;
+            } else {
+                last_jump = 0;
+            }
+        }
         if (k < hist_cap) hist[k] = sqrt(rr) / nb;
         if (o->replace_every > 0 && k % o->replace_every == 0) {
             if (minnorm) { or_apply_t(A, y, x); ++matvecs; }
@@ -452,6 +489,8 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
     for (i = 0; i <= t; ++i) free(u[i]);
     for (i = 0; i < t; ++i) free(w[i]);
     free(y);
+    free(rp);
+    free(xp);
     return 0;
 }
 
