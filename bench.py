@@ -361,7 +361,9 @@ def variants_bench(args, P, torch, dev):
     order cycling 1..5..1), the same matrix with a random (inconsistent)
     right-hand side to the normal-equation tolerance 1e-6, plain and with the
     enhanced stop, and the 256 x 256 Poisson matrix (symmetric positive
-    definite: H = A A^T vs H = A, fixed and cycling)."""
+    definite: H = A A^T vs H = A, fixed and cycling); first-order and t = 3
+    runs with the convex-combination step at theta = 0.5 beside the plain
+    ones."""
     import numpy as np
 
     from workloads import kac_clement, poisson5
@@ -378,7 +380,13 @@ def variants_bench(args, P, torch, dev):
              dict(t=3, tol_normal=1e-6, enhanced=True)),
             ("poisson_256_AAt_t3", pois, bp, dict(t=3)),
             ("poisson_256_A_t3", pois, bp, dict(t=3, h_is_a=True)),
-            ("poisson_256_A_cycle5", pois, bp, dict(t=5, t_cycle=True, h_is_a=True))]
+            ("poisson_256_A_cycle5", pois, bp, dict(t=5, t_cycle=True, h_is_a=True)),
+            ("kac_10001_t1", kac.A, torch.from_numpy(kac.b).to(dev), dict(t=1)),
+            ("kac_10001_t1_accel0.5", kac.A, torch.from_numpy(kac.b).to(dev),
+             dict(t=1, accel=0.5)),
+            ("kac_10001_t3_accel0.5", kac.A, torch.from_numpy(kac.b).to(dev),
+             dict(t=3, accel=0.5)),
+            ("poisson_256_A_t3_accel0.5", pois, bp, dict(t=3, h_is_a=True, accel=0.5))]
     plans = {}
     for name, A, b, kw in runs:
         key = id(A)

@@ -133,6 +133,15 @@ typedef struct ta_opts {
                               5.2 gives TA when A x = b is not solvable).  Not available in
                               this library: the call returns TA_ENOTSUP.  Must be 0
                               (TA_EINVAL) for the other solvers */
+    double accel;          /* cta_solve / cta_minnorm: theta in (0, 1) = the convex-combination
+                              step of the theorem on the dynamics of first-order CTA (section
+                              3): after each step, if ||r_{k+1}|| >= theta ||r_k||, the iterate
+                              becomes a r_k + (1 - a) r_{k+1} (and the same combination of x,
+                              or y) with a = rho / (rho + 1), rho = ||r_{k+1}|| / ||r_k||, the
+                              weight for which F_1 of the combination vanishes on a critical
+                              line; never twice in a row; the step counts as one iteration and
+                              hist holds the combination's residual.  0 = off.  Other solvers
+                              and batched solves: 0 */
 } ta_opts;
 
 /* Result summary (host struct). */

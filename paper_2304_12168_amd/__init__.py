@@ -47,7 +47,7 @@ class TaOpts(C.Structure):
                 ("warm_start", C.c_int32), ("rho0", C.c_double), ("fixed_rho", C.c_int32),
                 ("chunk", C.c_int32), ("launch_mode", C.c_int32), ("h_mode", C.c_int32),
                 ("t_cycle", C.c_int32), ("nonneg", C.c_int32), ("rho_max", C.c_double),
-                ("enhanced", C.c_int32), ("normal_eq", C.c_int32)]
+                ("enhanced", C.c_int32), ("normal_eq", C.c_int32), ("accel", C.c_double)]
 
 
 class TaInfo(C.Structure):
@@ -205,12 +205,12 @@ def _info(i: TaInfo) -> Info:
 def make_opts(tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0, warm_start=False,
               rho0=0.0, fixed_rho=False, chunk=0, precision=TA_FP64, graph=True,
               h_is_a=False, t_cycle=False, nonneg=False, rho_max=0.0,
-              enhanced=False, normal_eq=False) -> TaOpts:
+              enhanced=False, normal_eq=False, accel=0.0) -> TaOpts:
     return TaOpts(float(tol), float(tol_normal), int(t), int(max_iter), int(precision),
                   int(replace_every), int(bool(warm_start)), float(rho0), int(bool(fixed_rho)),
                   int(chunk), 0 if graph else 1, 1 if h_is_a else 0, 1 if t_cycle else 0,
                   1 if nonneg else 0, float(rho_max), 1 if enhanced else 0,
-                  1 if normal_eq else 0)
+                  1 if normal_eq else 0, float(accel))
 
 
 class Plan:

@@ -2069,7 +2069,7 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
     if (o->t < 1 || o->t > kTMax || o->max_iter < 0 || o->chunk < 0) return TA_EINVAL;
     if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
     if (o->h_mode != 0 || o->t_cycle != 0 || o->nonneg != 0 || o->rho_max != 0.0 ||
-        o->enhanced != 0 || o->normal_eq != 0)
+        o->enhanced != 0 || o->normal_eq != 0 || o->accel != 0.0)
         return TA_EINVAL;  // batched: CTA with H = A A^T and a fixed t
     if (minnorm && o->warm_start) return TA_EINVAL;
     if (o->precision != TA_FP64 && o->precision != P.precision) return TA_EINVAL;

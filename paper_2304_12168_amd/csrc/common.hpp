@@ -38,6 +38,8 @@ struct State {
     int32_t hmode;     // CTA: 1 = H = A (A symmetric positive semidefinite), 0 = H = A A^T
     int32_t enhanced;  // CTA: the enhanced stop (first-order iterates tested too)
     int32_t enh_hit;   // CTA: this iteration's update is x^; stop NORMAL after it
+    int32_t jump;      // CTA: a convex-combination step follows this update
+    int32_t last_jump; // CTA: the current iterate came from one
     int64_t k;         // iterations done
     int64_t max_iter;
     int64_t hist_cap;
@@ -53,6 +55,8 @@ struct State {
     double alpha_ta;   // TA: step length
     double rho, rho_lo;
     double rho_max;    // TA: > 0 = witness stop once the radius would exceed it
+    double accel;      // CTA: > 0 = convex-combination step threshold on ||r_{k+1}|| / ||r_k||
+    double astar;      // CTA: its weight on r_k
     double phi[2 * kTMax + 2];  // phi[1..2t]
     double alpha[kTMax];
     double scratch[4];          // results of kernel-level reductions
@@ -66,7 +70,8 @@ enum Post : int32_t {
     kPostCtaWarm,     // v0 = ||b - A x0||^2 (warm start): rr, hist[0], loop-top tests
     kPostNab,         // v0 = ||A^T b||^2
     kPostGram,        // v[0..2t) = phi_1..phi_2t: normal-equation test and the step alpha
-    kPostCtaEnd,      // v0 = ||r||^2 after the update: k, hist, loop-top tests
+    kPostCtaEnd,      // v0 = ||r||^2 after the update: k, hist, convex-step decision, loop top
+    kPostCtaJump,     // v0 = ||r||^2 after a convex-combination step: hist, loop-top tests
     kPostCtaReplace,  // v0 = ||b - A x||^2 after a scheduled replacement (arg: products)
     kPostCtaCand,     // v0 = ||b - A x||^2 at a candidate stop: accept or replace (arg: products)
     kPostTaInit,      // v0 = ||b||^2
@@ -88,6 +93,7 @@ enum Gate : int32_t {
     kGateCandidate,   // only when the chain stopped at a candidate (true-residual check)
     kGateFinal,       // only when the solve has finished (final x, exit diagnostics)
     kGateRejected,    // unless done, and only after a rejected TA candidate
+    kGateJump,        // unless done, and only when a convex-combination step is due
 };
 
 // Epilogues of the matrix-product kernels.
@@ -159,9 +165,16 @@ hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t e
                          const EpiArgs &ea, const Out &o, hipStream_t s, int32_t *blocks);
 hipError_t launch_cta_init(int64_t m, const double *b, double *r, double *xy, int64_t nxy,
                            int32_t zero_xy, const Out &o, hipStream_t s, int32_t *blocks);
+// rb, yb (optional): the residual and the updated iterate (y, or x) before
+// the update, for a convex-combination step
 hipError_t launch_cta_update(int64_t m, int64_t n, int32_t t, int32_t minnorm, double *r,
                              double *const *u, double *x, double *const *w, double *y,
-                             const Out &o, hipStream_t s, int32_t *blocks);
+                             double *rb, double *yb, const Out &o, hipStream_t s,
+                             int32_t *blocks);
+// r = a rb + (1 - a) r, xy = a xyb + (1 - a) xy with a = state.astar (gate
+// kGateJump); v0 = ||r||^2
+hipError_t launch_cta_jump(int64_t m, int64_t nxy, double *r, const double *rb, double *xy,
+                           const double *xyb, const Out &o, hipStream_t s, int32_t *blocks);
 hipError_t launch_ta_init(int64_t m, int64_t n, const double *b, double *r, double *bp,
                           double *x, int32_t keep_x, const Out &o, hipStream_t s,
                           int32_t *blocks);

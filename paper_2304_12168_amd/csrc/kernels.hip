@@ -141,16 +141,40 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             for (int i = 0; i < t; ++i) st->alpha[i] = a[i];
             break;
         }
-        case kPostCtaEnd:
+        case kPostCtaEnd: {
+            const double rr_old = st->rr;
             st->rr = v[0];
             st->k++;
             put_hist(st, sp.hist);
-            if (st->enh_hit)
+            if (st->enh_hit) {
                 finish(st, TA_STOP_NORMAL);  // the update just applied x^ (enhanced stop)
-            else if (st->replace_every > 0 && st->k % st->replace_every == 0)
+                break;
+            }
+            // convex-combination step: ||r_{k+1}|| / ||r_k|| = rho >= accel, and
+            // the current pair is two steps of F_t (not after such a step)
+            int32_t jump = 0;
+            if (st->accel > 0.0) {
+                const double rho = rr_old > 0.0 ? sqrt(st->rr / rr_old) : 0.0;
+                if (!st->last_jump && rho >= st->accel) {
+                    jump = 1;
+                    st->astar = rho / (rho + 1.0);
+                } else {
+                    st->last_jump = 0;
+                }
+            }
+            st->jump = jump;
+            if (st->replace_every > 0 && st->k % st->replace_every == 0)
                 st->replace = 1;
-            else
+            else if (!jump)
                 loop_top(st);
+            break;
+        }
+        case kPostCtaJump:
+            st->rr = v[0];
+            st->jump = 0;
+            st->last_jump = 1;
+            put_hist(st, sp.hist);
+            if (!st->replace) loop_top(st);
             break;
         case kPostCtaReplace:
             st->rr = v[0];
@@ -275,6 +299,7 @@ __device__ __forceinline__ bool gate_open(int32_t gate, const State *st) {
     if (gate == kGatePivot && !st->pivot) return false;
     if (gate == kGateReplace && !st->replace) return false;
     if (gate == kGateRejected && !st->rejected) return false;
+    if (gate == kGateJump && !st->jump) return false;
     return true;
 }
 
@@ -635,7 +660,8 @@ struct VecPtrs {
 
 __global__ __launch_bounds__(kBlock) void k_cta_update(int64_t m, int64_t n, int32_t t,
                                                         int32_t minnorm, double *r, VecPtrs u,
-                                                        double *x, VecPtrs w, double *y, Out o) {
+                                                        double *x, VecPtrs w, double *y,
+                                                        double *rb, double *yb, Out o) {
     if (o.st->done) return;
     double al[kTMax];
 #pragma unroll
@@ -646,8 +672,10 @@ __global__ __launch_bounds__(kBlock) void k_cta_update(int64_t m, int64_t n, int
          i += (int64_t)gridDim.x * kBlock) {
         if (i < m) {
             double ri = r[i];
+            if (rb != nullptr) rb[i] = ri;
             if (minnorm) {
                 double yi = y[i];
+                if (yb != nullptr) yb[i] = yi;
                 yi = __fma_rn(al[0], ri, yi);
                 for (int j = 1; j < t; ++j) yi = __fma_rn(al[j], u.p[j][i], yi);
                 y[i] = yi;
@@ -658,9 +686,31 @@ __global__ __launch_bounds__(kBlock) void k_cta_update(int64_t m, int64_t n, int
         }
         if (!minnorm && i < n) {
             double xi = x[i];
+            if (yb != nullptr) yb[i] = xi;
             for (int j = 0; j < t; ++j) xi = __fma_rn(al[j], w.p[j][i], xi);
             x[i] = xi;
         }
+    }
+    block_partials<1>(v, o);
+}
+
+// Convex-combination step (the first-order dynamics theorem of section 3):
+// r = a r_k + (1 - a) r_{k+1}, and the same for the iterate, a = state.astar.
+__global__ __launch_bounds__(kBlock) void k_cta_jump(int64_t m, int64_t nxy, double *r,
+                                                      const double *__restrict__ rb, double *xy,
+                                                      const double *__restrict__ xyb, Out o) {
+    if (!producer_runs(o)) return;
+    const double a = o.st->astar, a1 = 1.0 - a;
+    Acc v[1] = {};
+    const int64_t N = m > nxy ? m : nxy;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * kBlock) {
+        if (i < m) {
+            const double ri = __fma_rn(a, rb[i], a1 * r[i]);
+            r[i] = ri;
+            acc_fma(v[0], ri, ri);
+        }
+        if (i < nxy) xy[i] = __fma_rn(a, xyb[i], a1 * xy[i]);
     }
     block_partials<1>(v, o);
 }
@@ -1003,14 +1053,25 @@ hipError_t launch_cta_init(int64_t m, const double *b, double *r, double *xy, in
 
 hipError_t launch_cta_update(int64_t m, int64_t n, int32_t t, int32_t minnorm, double *r,
                              double *const *u, double *x, double *const *w, double *y,
-                             const Out &o, hipStream_t s, int32_t *blocks) {
+                             double *rb, double *yb, const Out &o, hipStream_t s,
+                             int32_t *blocks) {
     VecPtrs U{}, Wp{};
     for (int j = 0; j <= t && j <= kTMax; ++j) U.p[j] = u[j];
     for (int j = 0; j < t && j < kTMax; ++j) Wp.p[j] = w ? w[j] : nullptr;
     const int64_t N = (minnorm || m > n) ? m : n;
     const int64_t g = elementwise_blocks(N);
     if (g > o.cap) return hipErrorInvalidValue;
-    k_cta_update<<<dim3((unsigned)g), kBlock, 0, s>>>(m, n, t, minnorm, r, U, x, Wp, y, o);
+    k_cta_update<<<dim3((unsigned)g), kBlock, 0, s>>>(m, n, t, minnorm, r, U, x, Wp, y, rb, yb,
+                                                      o);
+    if (blocks != nullptr) *blocks = (int32_t)g;
+    return hipGetLastError();
+}
+
+hipError_t launch_cta_jump(int64_t m, int64_t nxy, double *r, const double *rb, double *xy,
+                           const double *xyb, const Out &o, hipStream_t s, int32_t *blocks) {
+    const int64_t g = elementwise_blocks(m > nxy ? m : nxy);
+    if (g > o.cap) return hipErrorInvalidValue;
+    k_cta_jump<<<dim3((unsigned)g), kBlock, 0, s>>>(m, nxy, r, rb, xy, xyb, o);
     if (blocks != nullptr) *blocks = (int32_t)g;
     return hipGetLastError();
 }

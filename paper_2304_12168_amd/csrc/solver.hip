@@ -54,6 +54,8 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (o->nonneg != 0 && (o->nonneg != 1 || solver != 2)) return TA_EINVAL;
     if (o->enhanced != 0 && (o->enhanced != 1 || solver == 2)) return TA_EINVAL;
     if (o->normal_eq != 0) return o->normal_eq == 1 && solver == 2 ? TA_ENOTSUP : TA_EINVAL;
+    if (!(o->accel >= 0.0 && o->accel < 1.0) || (o->accel > 0.0 && solver == 2))
+        return TA_EINVAL;
     if (!(o->rho_max >= 0.0) || !isfinite(o->rho_max) || (o->rho_max > 0.0 && solver != 2))
         return TA_EINVAL;
     if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64
@@ -257,6 +259,7 @@ static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
     h.hmode = o->h_mode;
     h.rho_max = o->rho_max;
     h.enhanced = o->enhanced;
+    h.accel = o->accel;
     return h;
 }
 
@@ -375,6 +378,15 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     for (int j = 0; j < nw; ++j) ws.reserve(&w[j], n);
     if (minnorm) ws.reserve(&y, m);
     ws.reserve(&tmp_n, n);
+    // convex-combination step: the residual and the updated iterate (y, or x)
+    // before each update
+    const bool acc = o->accel > 0.0;
+    const int64_t nupd = minnorm ? m : n;
+    double *rb = nullptr, *xyb = nullptr;
+    if (acc) {
+        ws.reserve(&rb, m);
+        ws.reserve(&xyb, nupd);
+    }
     if ((rc = ws.commit()) != TA_OK) return rc;
 
     State h0 = initial_state(o, hist_cap, hist);
@@ -437,8 +449,14 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         sp.gate = kGateAlways;
         HIP_TRY(launch_step(sp, s));
         HIP_TRY(launch_cta_update(m, n, tk, (minnorm || ha) ? 1 : 0, r, u, x, w, ha ? x : y,
-                                  c.out(R, kGateAlways), s, &g));
+                                  rb, xyb, c.out(R, kGateAlways), s, &g));
         HIP_TRY(c.step(R, {g}, kPostCtaEnd, 0, kGateAlways));
+        if (acc) {
+            int32_t gj = 0;
+            HIP_TRY(launch_cta_jump(m, nupd, r, rb, minnorm ? y : x, xyb, c.out(R, kGateJump), s,
+                                    &gj));
+            HIP_TRY(c.step(R, {gj}, kPostCtaJump, 0, kGateJump));
+        }
         if (o->replace_every > 0) {
             if (minnorm)
                 HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateReplace), s,

@@ -98,6 +98,13 @@ def test_validate_variant_options(lib):
     assert P.validate(rect, 2, normal_eq=True) == -4     # TA_ENOTSUP: not on the device
     assert P.validate(rect, 0, t=2, normal_eq=True) == -1  # a TA input form
     assert P.validate(rect, 1, t=2, normal_eq=True) == -1
+    assert P.validate(rect, 0, t=3, accel=0.5) == 0
+    assert P.validate(rect, 1, t=1, accel=0.9) == 0
+    assert P.validate(sq, 0, t=2, accel=0.5, h_is_a=True) == 0
+    assert P.validate(rect, 2, accel=0.5) == -1          # a CTA step
+    assert P.validate(rect, 0, t=2, accel=1.0) == -1     # theta in [0, 1)
+    assert P.validate(rect, 0, t=2, accel=-0.1) == -1
+    assert P.validate(rect, 0, t=2, accel=float("nan")) == -1
     oe = P.make_opts(t=3)
     oe.enhanced = 2
     assert lib.ta_validate(ctypes.byref(rect), ctypes.byref(oe), 0) == -1
