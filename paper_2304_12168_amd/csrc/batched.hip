@@ -276,6 +276,12 @@ struct VecLoad<float, 4> {
     }
 };
 
+// Waves per SIMD asked of the SpMM: the low-precision chain at K = 64 fits
+// 64 VGPRs without spilling (8 waves instead of 7); the widths in between
+// would spill, and the FP64 chain keeps what its registers allow.
+template <typename X, int K>
+constexpr int kBspmmWaves = (sizeof(X) != 8 && K == 64) ? 8 : 1;
+
 template <typename X, int K>
 struct Lanes {
     static constexpr int CV0 = sizeof(X) == 8 ? 2 : 4;
@@ -284,7 +290,8 @@ struct Lanes {
 };
 
 template <typename V, typename X, int K, int EPI, int U>
-__global__ __launch_bounds__(kBlock) void k_bspmm(const int32_t *__restrict__ rp,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBspmmWaves<X, K>)))
+void k_bspmm(const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci,
                                                    const V *__restrict__ val,
                                                    const X *__restrict__ x, X *y,
@@ -870,31 +877,45 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
         for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
              it = brow_next(br, R, wave, rsub, it)) {
             const int64_t e = (int64_t)it.row * K + c0;
-            double ri[CV], u[CV];
-            vld<X, CV>(r + e, ri);
+            // every load of the row is issued before the first use: R, U_1..U_t
+            // (unrolled to the largest order, predicated on t) and Y
+            VecT<X, CV> uv[kTMax + 1];
+            uv[0] = *reinterpret_cast<const VecT<X, CV> *>(r + e);
+#pragma unroll
+            for (int j = 1; j <= kTMax; ++j)
+                if (j <= t) uv[j] = *reinterpret_cast<const VecT<X, CV> *>((const X *)U.p[j] + e);
+            VecT<YA, CV> yw;
+            if (acc_y) yw = *reinterpret_cast<const VecT<YA, CV> *>(yv + e);
+            double ri[CV];
+#pragma unroll
+            for (int v = 0; v < CV; ++v) ri[v] = (double)uv[0].v[v];
             if (acc_y) {
-                double yi[CV], y0[CV];
-                vld<YA, CV>(yv + e, y0);
-#pragma unroll
-                for (int v = 0; v < CV; ++v) yi[v] = __fma_rn(sal[0][c0 + v], ri[v], y0[v]);
-                for (int j = 1; j < t; ++j) {
-                    vld<X, CV>((const X *)U.p[j] + e, u);
-#pragma unroll
-                    for (int v = 0; v < CV; ++v) yi[v] = __fma_rn(sal[j][c0 + v], u[v], yi[v]);
-                }
+                double yi[CV];
 #pragma unroll
                 for (int v = 0; v < CV; ++v)
-                    if (!act[v]) yi[v] = y0[v];
+                    yi[v] = __fma_rn(sal[0][c0 + v], ri[v], (double)yw.v[v]);
+#pragma unroll
+                for (int j = 1; j < kTMax; ++j)
+                    if (j < t) {
+#pragma unroll
+                        for (int v = 0; v < CV; ++v)
+                            yi[v] = __fma_rn(sal[j][c0 + v], (double)uv[j].v[v], yi[v]);
+                    }
+#pragma unroll
+                for (int v = 0; v < CV; ++v)
+                    if (!act[v]) yi[v] = (double)yw.v[v];
                 vst<YA, CV>(yv + e, yi);
             }
             double rn[CV];
 #pragma unroll
             for (int v = 0; v < CV; ++v) rn[v] = ri[v];
-            for (int j = 0; j < t; ++j) {
-                vld<X, CV>((const X *)U.p[j + 1] + e, u);
 #pragma unroll
-                for (int v = 0; v < CV; ++v) rn[v] = __fma_rn(-sal[j][c0 + v], u[v], rn[v]);
-            }
+            for (int j = 0; j < kTMax; ++j)
+                if (j < t) {
+#pragma unroll
+                    for (int v = 0; v < CV; ++v)
+                        rn[v] = __fma_rn(-sal[j][c0 + v], (double)uv[j + 1].v[v], rn[v]);
+                }
 #pragma unroll
             for (int v = 0; v < CV; ++v) {
                 if (!act[v]) rn[v] = ri[v];
@@ -952,18 +973,26 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, XA *xv,
     }
     if (!any) return;
     if (!std::is_same<XA, double>::value && rsub == 0) gs.dirty[br.sys] = 1;
+    const int t = gs.t;
     for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
          it = brow_next(br, R, wave, rsub, it)) {
         const int64_t e = (int64_t)it.row * K + c0;
-        double xi[CV], w[CV], x0[CV];
+        // all loads of the row first: W_0..W_{t-1} (predicated on t) and X
+        VecT<X, CV> wv[kTMax];
+#pragma unroll
+        for (int j = 0; j < kTMax; ++j)
+            if (j < t) wv[j] = *reinterpret_cast<const VecT<X, CV> *>((const X *)W.p[j] + e);
+        double xi[CV], x0[CV];
         vld<XA, CV>(xv + e, x0);
 #pragma unroll
         for (int v = 0; v < CV; ++v) xi[v] = x0[v];
-        for (int j = 0; j < gs.t; ++j) {
-            vld<X, CV>((const X *)W.p[j] + e, w);
 #pragma unroll
-            for (int v = 0; v < CV; ++v) xi[v] = __fma_rn(sal[j][c0 + v], w[v], xi[v]);
-        }
+        for (int j = 0; j < kTMax; ++j)
+            if (j < t) {
+#pragma unroll
+                for (int v = 0; v < CV; ++v)
+                    xi[v] = __fma_rn(sal[j][c0 + v], (double)wv[j].v[v], xi[v]);
+            }
 #pragma unroll
         for (int v = 0; v < CV; ++v)
             if (!act[v]) xi[v] = x0[v];
