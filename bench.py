@@ -44,8 +44,8 @@ HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy
 # kernel); see profiles/.  Keyed by (kernel, precision, K, pass); None when the
 # kernel has changed since the counters were taken.
-MEASURED_TRAFFIC: dict = {("k_bspmm", "fp32", 64, "A"): 6.0755e9,
-                          ("k_bspmm", "fp32", 64, "AT"): 6.2150e9}
+MEASURED_TRAFFIC: dict = {("k_bspmm", "fp32", 64, "A"): 6.1486e9,
+                          ("k_bspmm", "fp32", 64, "AT"): 6.3013e9}
 
 
 def log(*a):
