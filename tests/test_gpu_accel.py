@@ -114,3 +114,26 @@ def test_accel_rejected_by_batched_engine():
     B = [np.asarray(p.b)]
     with pytest.raises(P.TaError, match="EINVAL"):
         P.cta_solve_batched(plan, B, tol=1e-8, t=2, accel=0.5)
+
+
+@pytest.mark.parametrize("t", [3, 5])
+def test_with_order_cycling_matches_oracle(t):
+    p = kac_clement(101)
+    kw = dict(tol=1e-8, t=t, max_iter=20_000, accel=0.5, t_cycle=True)
+    _compare(P.cta_solve(p.A, p.b, **kw), oracle.cta(p.A, p.b, **kw))
+
+
+@pytest.mark.parametrize("t,theta", [(2, 0.5), (3, 0.8)])
+def test_with_enhanced_stop(t, theta):
+    """Inconsistent Kac-Clement N = 1001: both sides stop NORMAL; the
+    enhanced test's moment sums may decide one iteration apart (as without
+    the step), so the counts agree within one and the true normal-equation
+    residual meets the tolerance."""
+    A = kac_clement(1001).A
+    b = np.random.default_rng(11).standard_normal(1001)
+    kw = dict(tol=1e-10, t=t, max_iter=200_000, tol_normal=1e-6, enhanced=True, accel=theta)
+    _, _, ig = P.cta_solve(A, b, **kw)
+    _, _, io = oracle.cta(A, b, **kw)
+    assert ig.stop == io.stop == "normal"
+    assert abs(ig.iters - io.iters) <= 1, (ig, io)
+    assert ig.rel_normal <= 1e-6 * (1 + 1e-6)
