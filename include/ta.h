@@ -222,8 +222,14 @@ int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
  * built on the device, and for matrices with long rows (more than 16
  * nonzeros per row on average) and at least 131072 columns, a copy of A with
  * sorted columns split into 8 column slices so that each XCD of the MI355X
- * gathers from its own eighth of x.  Solving many right-hand sides with one
- * matrix builds them once.  The plan refers to A's device arrays (row_ptr,
+ * gathers from its own eighth of x.  A or A^T with short rows (16 or fewer
+ * nonzeros on average) whose 64-row slices pad the entries by at most a
+ * quarter is also copied into SELL-64 form (each slice stored position by
+ * position, padded to its widest row), so its products need no row bounds
+ * and make contiguous index loads; the sums keep the CSR order, so results
+ * are unchanged.  The one-shot solvers build the same; the one-shot
+ * products (ta_spmv, ta_residual, ta_time_matvec) do not.  Solving many
+ * right-hand sides with one matrix builds them once.  The plan refers to A's device arrays (row_ptr,
  * col_idx, val, or the dense val): they must stay allocated and unchanged
  * while the plan lives.  A plan is read-only once created and may serve
  * calls on several streams at the same time.  Its device memory is taken
@@ -235,6 +241,14 @@ typedef struct ta_plan ta_plan;
 
 int ta_plan_create(const ta_mat *A, ta_plan **plan, void *stream);
 int ta_plan_destroy(ta_plan *plan);
+
+/* Storage the plan's products use for A (trans = 0) or A^T (trans = 1):
+ * TA_FMT_CSR_ROWS, TA_FMT_DENSE_ROWS, TA_FMT_DENSE_COLS, TA_FMT_CSR_SLICED
+ * (column slices) or TA_FMT_SELL64, written to *format (host).  TA_EINVAL for
+ * a NULL argument. */
+enum { TA_FMT_CSR_ROWS = 0, TA_FMT_DENSE_ROWS = 1, TA_FMT_DENSE_COLS = 2,
+       TA_FMT_CSR_SLICED = 3, TA_FMT_SELL64 = 4 };
+int ta_plan_format(const ta_plan *plan, int32_t trans, int32_t *format);
 
 /* The solvers above on a prepared operator; other arguments as there. */
 int cta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,

@@ -32,7 +32,9 @@ EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror",
            "ta_residual", "ta_transpose", "ta_time_matvec", "ta_plan_create", "ta_plan_destroy",
            "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
            "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched",
-           "ta_batch_time_spmm", "ta_csr_outer", "ta_minnorm", "ta_minnorm_plan")
+           "ta_batch_time_spmm", "ta_csr_outer", "ta_minnorm", "ta_minnorm_plan", "ta_plan_format")
+# storage of a plan's products (ta_plan_format)
+FORMATS = {0: "csr_rows", 1: "dense_rows", 2: "dense_cols", 3: "csr_sliced", 4: "sell64"}
 
 
 class TaMat(C.Structure):
@@ -84,6 +86,8 @@ def load_library(path: str = LIB_PATH):
         lib.ta_plan_create.argtypes = [MP, C.POINTER(C.c_void_p), P]
         lib.ta_plan_destroy.restype = C.c_int
         lib.ta_plan_destroy.argtypes = [P]
+        lib.ta_plan_format.restype = C.c_int
+        lib.ta_plan_format.argtypes = [P, I32, C.POINTER(C.c_int32)]
         lib.ta_batch_plan_create.restype = C.c_int
         lib.ta_batch_plan_create.argtypes = [I32, P, I32, C.POINTER(C.c_void_p), P]
         lib.ta_batch_plan_destroy.restype = C.c_int
@@ -215,7 +219,8 @@ def make_opts(tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0, w
 
 class Plan:
     """A prepared operator (ta_plan): A^T and, for long rows, the XCD column
-    slices of A, built once on the device.  Keeps the matrix alive."""
+    slices of A; for short even rows, SELL-64 copies of A and A^T.  Built once
+    on the device.  Keeps the matrix alive."""
 
     def __init__(self, A):
         lib = load_library()
@@ -228,6 +233,13 @@ class Plan:
     @property
     def m(self):
         return self.A.m
+
+    def format(self, trans: bool = False) -> str:
+        """Storage the products of A (or A^T) use: a FORMATS value."""
+        f = C.c_int32(-1)
+        _check(load_library().ta_plan_format(self.handle, int(bool(trans)), C.byref(f)),
+               "ta_plan_format")
+        return FORMATS[f.value]
 
     @property
     def n(self):

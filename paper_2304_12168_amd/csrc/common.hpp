@@ -144,6 +144,7 @@ enum MatKind : int32_t {
     kDenseRows = 1,  // dense row-major, rows of M, 64 lanes per row
     kDenseCols = 2,  // dense row-major A viewed as M = A^T: one thread per column of A
     kCsrSliced = 3,  // CSR with columns sorted, split into kSlices column slices (one per XCD)
+    kCsrSell = 4,    // CSR copied into 64-row slices (SELL-64), one thread per row
 };
 
 constexpr int kSlices = 8;  // XCDs of the part; blocks b with b % 8 == s take column slice s
@@ -158,9 +159,19 @@ struct MatView {
     int32_t lanes;       // kCsrRows: 1 = one thread per row, else lanes per row
     const int32_t *seg;  // kCsrSliced: rows x (kSlices + 1) slice starts inside each row
     double2 *ypart;      // kCsrSliced: kSlices x rows compensated partial sums (workspace)
+    // kCsrSell: slice s (rows 64 s .. 64 s + 63) holds slots [so[s], so[s + 1]),
+    // position k of row 64 s + i at slot so[s] + 64 k + i; a row's entries keep
+    // their CSR order, and the slots past its end hold column -1, value 0
+    const int64_t *so;
+    const int32_t *sc;
+    const double *sv;
 };
 
 // ---- launchers (kernels.hip); each returns the grid size it used in *blocks ----
+// SELL-64 construction: the widest row of each 64-row slice, then the slots
+hipError_t launch_sell_widths(int64_t rows, const int32_t *rp, int32_t *w, hipStream_t s);
+hipError_t launch_sell_fill(int64_t rows, const int32_t *rp, const int32_t *ci, const double *val,
+                            const int64_t *so, int32_t *sc, double *sv, hipStream_t s);
 hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t epi,
                          const EpiArgs &ea, const Out &o, hipStream_t s, int32_t *blocks);
 hipError_t launch_cta_init(int64_t m, const double *b, double *r, double *xy, int64_t nxy,

@@ -472,6 +472,98 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(MatView M, const double *
 }
 
 // ---------------------------------------------------------------------------
+// SELL-64: one thread per row, the 64 rows of a slice in one wave.  A slice's
+// entries are stored position by position (64 slots each), so every column
+// index and value load of the wave is one contiguous access and no row bound
+// is loaded.  Terms are added in storage order with the compensated steps of
+// k_csr_stream, so both give the same bits.  Up to 6 positions are loaded
+// before the first gather (the width is uniform over the wave).
+// ---------------------------------------------------------------------------
+template <int EPI>
+__global__ __launch_bounds__(kBlock) void k_sell(MatView M, const double *__restrict__ x,
+                                                  double *y, EpiArgs ea, Out o) {
+    if (!producer_runs(o)) return;
+    constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
+    constexpr int UN = 6;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t row = blk * kBlock + threadIdx.x;
+    const int64_t slice = row >> 6;
+    const int lane = threadIdx.x & 63;
+    Acc acc = {0.0, 0.0};
+    if constexpr (EPI == kEpiResid) {
+        if (row < M.rows) acc.p = ea.b[row];
+    }
+    if (slice < ((M.rows + 63) >> 6)) {
+        const int64_t off = M.so[slice];
+        const int32_t w = (int32_t)((M.so[slice + 1] - off) >> 6);
+        const int32_t *__restrict__ c = M.sc + off + lane;
+        const double *__restrict__ a = M.sv + off + lane;
+        for (int32_t k = 0; k < w; k += UN) {
+            int32_t cc[UN];
+            double aa[UN], xv[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                cc[u] = -1;
+                aa[u] = 0.0;
+                if (k + u < w) {
+                    cc[u] = c[(int64_t)(k + u) * 64];
+                    aa[u] = a[(int64_t)(k + u) * 64];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UN; ++u) xv[u] = cc[u] >= 0 ? x[cc[u]] : 0.0;
+#pragma unroll
+            for (int u = 0; u < UN; ++u)
+                if (cc[u] >= 0) acc_fma(acc, sgn * aa[u], xv[u]);
+        }
+    }
+    Acc v[EpiNV<EPI>::value] = {};
+    if (row < M.rows) epilogue<EPI>(row, acc_val(acc), y, ea, o.st, v);
+    block_partials<EpiNV<EPI>::value>(v, o);
+}
+
+// widest row of each 64-row slice (one wave per slice)
+__global__ __launch_bounds__(kBlock) void k_sell_widths(int64_t rows,
+                                                         const int32_t *__restrict__ rp,
+                                                         int32_t *w) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int32_t len = r < rows ? rp[r + 1] - rp[r] : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off));
+    if ((threadIdx.x & 63) == 0 && r < rows) w[r >> 6] = len;
+}
+
+// every slot of every slice written once: a row's entries, then padding
+__global__ __launch_bounds__(kBlock) void k_sell_fill(int64_t rows,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci,
+                                                       const double *__restrict__ val,
+                                                       const int64_t *__restrict__ so,
+                                                       int32_t *sc, double *sv) {
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = r >> 6;
+    if (s >= ((rows + 63) >> 6)) return;
+    const int lane = (int)(r & 63);
+    const int64_t off = so[s];
+    const int32_t w = (int32_t)((so[s + 1] - off) >> 6);
+    int32_t k0 = 0, len = 0;
+    if (r < rows) {
+        k0 = rp[r];
+        len = rp[r + 1] - k0;
+    }
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t e = off + (int64_t)k * 64 + lane;
+        if (k < len) {
+            sc[e] = ci[k0 + k];
+            sv[e] = val[k0 + k];
+        } else {
+            sc[e] = -1;
+            sv[e] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // W lanes per row (CSR with long rows, or the rows of a dense matrix).
 // ---------------------------------------------------------------------------
 template <int W, int EPI>
@@ -968,6 +1060,7 @@ int64_t matvec_blocks(const MatView &M) {
         case kDenseCols: return cdiv(rows, kBlock);
         case kDenseRows: return cdiv(rows, kBlock / 64);
         case kCsrSliced: return elementwise_blocks(rows);  // the combine kernel
+        case kCsrSell: return cdiv(rows, kBlock);
         default: return M.lanes > 1 ? cdiv(rows, kBlock / M.lanes) : cdiv(rows, kBlock);
     }
 }
@@ -1015,6 +1108,7 @@ static void launch_matvec_t(const MatView &M, const double *x, double *y, const 
             launch_sliced<EPI>(M, x, ea, o, s);
             k_slices_combine<EPI><<<grid, kBlock, 0, s>>>(M, y, ea, o);
             break;
+        case kCsrSell: k_sell<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
         default:
             if (M.lanes > 1)
                 launch_vec_lanes<EPI>(M, grid, x, y, ea, o, s);
@@ -1022,6 +1116,21 @@ static void launch_matvec_t(const MatView &M, const double *x, double *y, const 
                 k_csr_stream<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o);
             break;
     }
+}
+
+hipError_t launch_sell_widths(int64_t rows, const int32_t *rp, int32_t *w, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    const int64_t g = cdiv(((rows + 63) >> 6) * 64, kBlock);
+    k_sell_widths<<<dim3((unsigned)g), kBlock, 0, s>>>(rows, rp, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_sell_fill(int64_t rows, const int32_t *rp, const int32_t *ci, const double *val,
+                            const int64_t *so, int32_t *sc, double *sv, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    const int64_t g = cdiv(((rows + 63) >> 6) * 64, kBlock);
+    k_sell_fill<<<dim3((unsigned)g), kBlock, 0, s>>>(rows, rp, ci, val, so, sc, sv);
+    return hipGetLastError();
 }
 
 hipError_t launch_matvec(const MatView &M, const double *x, double *y, int32_t epi,

@@ -113,15 +113,78 @@ struct Plan {
     MatView A{}, AT{};
     bool has_t = false;
     void *mem = nullptr;
+    void *mem_sell = nullptr;  // SELL-64 copies of the views that take them
     hipStream_t s_mem = nullptr;
 };
 
 static void plan_free(Plan *P) {
     if (P->mem != nullptr) (void)hipFreeAsync(P->mem, P->s_mem);
+    if (P->mem_sell != nullptr) (void)hipFreeAsync(P->mem_sell, P->s_mem);
     P->mem = nullptr;
+    P->mem_sell = nullptr;
 }
 
-static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P) {
+// SELL-64 copies for the one-thread-per-row CSR views whose 64-row slices
+// pad the entries by at most a quarter (rows of even length: stencils,
+// banded and degree-bounded sparse matrices).  Widths come back to the host
+// for the slice offsets; the slots are filled on the device.
+static int plan_sell(Plan *P, int64_t nnz, hipStream_t s) {
+    MatView *vs[2] = {&P->A, P->has_t ? &P->AT : nullptr};
+    int64_t nsl[2] = {0, 0};
+    for (int i = 0; i < 2; ++i)
+        if (vs[i] != nullptr && vs[i]->kind == kCsrRows && vs[i]->lanes == 1 && vs[i]->rows > 0)
+            nsl[i] = (vs[i]->rows + 63) / 64;
+    if (nsl[0] + nsl[1] == 0 || nnz <= 0) return TA_OK;
+    Workspace wt(s);
+    int32_t *dw = nullptr;
+    wt.reserve(&dw, nsl[0] + nsl[1]);
+    int rc = wt.commit();
+    if (rc != TA_OK) return rc;
+    for (int i = 0; i < 2; ++i)
+        if (nsl[i] > 0) HIP_TRY(launch_sell_widths(vs[i]->rows, vs[i]->rp, dw + (i ? nsl[0] : 0), s));
+    std::vector<int32_t> hw((size_t)(nsl[0] + nsl[1]));
+    HIP_TRY(hipMemcpyAsync(hw.data(), dw, sizeof(int32_t) * hw.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    std::vector<int64_t> so[2];
+    bool use[2] = {false, false};
+    for (int i = 0; i < 2; ++i) {
+        if (nsl[i] == 0) continue;
+        so[i].assign((size_t)nsl[i] + 1, 0);
+        for (int64_t q = 0; q < nsl[i]; ++q)
+            so[i][q + 1] = so[i][q] + 64 * (int64_t)hw[(size_t)((i ? nsl[0] : 0) + q)];
+        use[i] = so[i][nsl[i]] <= nnz + nnz / 4;
+    }
+    if (!use[0] && !use[1]) return TA_OK;
+    Workspace sw(s);
+    int64_t *d_so[2] = {nullptr, nullptr};
+    int32_t *d_sc[2] = {nullptr, nullptr};
+    double *d_sv[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i)
+        if (use[i]) {
+            sw.reserve(&d_so[i], nsl[i] + 1);
+            sw.reserve(&d_sc[i], so[i][nsl[i]]);
+            sw.reserve(&d_sv[i], so[i][nsl[i]]);
+        }
+    if ((rc = sw.commit()) != TA_OK) return rc;
+    for (int i = 0; i < 2; ++i)
+        if (use[i]) {
+            HIP_TRY(hipMemcpyAsync(d_so[i], so[i].data(), sizeof(int64_t) * so[i].size(),
+                                   hipMemcpyHostToDevice, s));
+            HIP_TRY(launch_sell_fill(vs[i]->rows, vs[i]->rp, vs[i]->ci, vs[i]->val, d_so[i],
+                                     d_sc[i], d_sv[i], s));
+            vs[i]->kind = kCsrSell;
+            vs[i]->so = d_so[i];
+            vs[i]->sc = d_sc[i];
+            vs[i]->sv = d_sv[i];
+        }
+    HIP_TRY(hipStreamSynchronize(s));  // the host offsets are read before they go
+    P->mem_sell = sw.release();
+    return TA_OK;
+}
+
+// sell: also build SELL-64 copies (plans and solves; not the one-shot
+// products, which would spend more on the copy than they save)
+static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool sell = false) {
     int rc = validate_mat(M);
     if (rc != TA_OK) return rc;
     P->desc = *M;
@@ -191,6 +254,7 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P) {
     }
     P->mem = own.release();
     P->s_mem = s;
+    if (sell) return plan_sell(P, nnz, s);
     return TA_OK;
 }
 
@@ -783,9 +847,9 @@ static int time_run(const Plan &P, int32_t trans, const double *x, double *y, in
 
 // One-shot calls: a transient plan on the call's stream.
 template <class F>
-static int with_plan(const ta_mat *M, bool need_t, hipStream_t s, F &&f) {
+static int with_plan(const ta_mat *M, bool need_t, hipStream_t s, F &&f, bool sell = false) {
     Plan P;
-    int rc = plan_build(M, need_t, s, &P);
+    int rc = plan_build(M, need_t, s, &P, sell);
     if (rc == TA_OK) rc = f(P);
     plan_free(&P);
     return rc;
@@ -810,7 +874,7 @@ int cta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, 
     if (rc != TA_OK) return rc;
     return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
         return ta::cta_run(P, b, x, opts, hist, hist_cap, info, s, false);
-    });
+    }, true);
 }
 
 int cta_minnorm(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
@@ -821,7 +885,7 @@ int cta_minnorm(const ta_mat *A, const double *b, double *x, const ta_opts *opts
     if (rc != TA_OK) return rc;
     return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
         return ta::cta_run(P, b, x, opts, hist, hist_cap, info, s, true);
-    });
+    }, true);
 }
 
 int ta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
@@ -832,7 +896,7 @@ int ta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, d
     if (rc != TA_OK) return rc;
     return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
         return ta::ta_run(P, b, x, opts, hist, hist_cap, info, s);
-    });
+    }, true);
 }
 
 int ta_plan_create(const ta_mat *A, ta_plan **plan, void *stream) {
@@ -840,13 +904,23 @@ int ta_plan_create(const ta_mat *A, ta_plan **plan, void *stream) {
     *plan = nullptr;
     ta_plan *p = new (std::nothrow) ta_plan;
     if (p == nullptr) return TA_ENOMEM;
-    int rc = ta::plan_build(A, true, (hipStream_t)stream, &p->p);
+    int rc = ta::plan_build(A, true, (hipStream_t)stream, &p->p, true);
     if (rc != TA_OK) {
         ta::plan_free(&p->p);
         delete p;
         return rc;
     }
     *plan = p;
+    return TA_OK;
+}
+
+int ta_plan_format(const ta_plan *plan, int32_t trans, int32_t *format) {
+    if (plan == nullptr || format == nullptr) return TA_EINVAL;
+    static_assert(ta::kCsrRows == TA_FMT_CSR_ROWS && ta::kDenseRows == TA_FMT_DENSE_ROWS &&
+                      ta::kDenseCols == TA_FMT_DENSE_COLS && ta::kCsrSliced == TA_FMT_CSR_SLICED &&
+                      ta::kCsrSell == TA_FMT_SELL64,
+                  "storage kinds");
+    *format = trans ? plan->p.AT.kind : plan->p.A.kind;
     return TA_OK;
 }
 
@@ -883,7 +957,7 @@ int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
     if (rc != TA_OK) return rc;
     return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
         return ta::minnorm_run(P, b, x_eps, x, opts, info, tests, s);
-    });
+    }, true);
 }
 
 int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, double *x,
