@@ -22,10 +22,12 @@
 #include <string.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.hpp"
@@ -1742,13 +1744,42 @@ static int tuned_lanes(const BatchPlan &P, int trans, const BRange *tab, int32_t
     return TA_OK;
 }
 
+// Groups of one batched solve run side by side, one host thread and stream
+// each.  The row-lane autotuner times kernels, so tuning is done one group
+// at a time (tune), and no group starts iterating before every group has
+// tuned (pending reaches 0): the timings see a quiet GPU.
+struct GroupSync {
+    std::mutex tune, m;
+    std::condition_variable cv;
+    int pending = 0;
+    void arrive() {
+        std::lock_guard<std::mutex> lk(m);
+        if (--pending == 0) cv.notify_all();
+    }
+    void wait() {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] { return pending <= 0; });
+    }
+};
+// Arrives once: explicitly after tuning, or on any early return.
+struct Arrival {
+    GroupSync *g;
+    bool done = false;
+    void now() {
+        if (g != nullptr && !done) g->arrive();
+        done = true;
+    }
+    ~Arrival() { now(); }
+};
+
 // The per-K, per-precision pieces of one solve.
 template <typename V, typename X, int K>
 struct Engine {
     // info[info_off[s] + c] receives the result of column c of system s.
     static int run(const BatchPlan &P, const int32_t *nrhs, const double *const *B,
                    double *const *Xout, const ta_opts *o, int32_t minnorm, ta_info *info,
-                   const int64_t *info_off, hipStream_t s) {
+                   const int64_t *info_off, hipStream_t s, GroupSync *sync = nullptr) {
+        Arrival arrival{sync};
         const int32_t nsys = P.nsys, t = o->t;
         const int64_t M = P.M, N = P.N, G = (int64_t)nsys * K;
         const bool mixed = !std::is_same<V, double>::value;
@@ -1874,6 +1905,8 @@ struct Engine {
 
         // row lanes of the low-precision chain: timed once per plan and K
         if (mixed && M > 0 && N > 0) {
+            std::unique_lock<std::mutex> lk;
+            if (sync != nullptr) lk = std::unique_lock<std::mutex>(sync->tune);
             HIP_TRY(hipMemsetAsync(R, 0, sizeof(X) * (size_t)(M * K), s));
             HIP_TRY(hipMemsetAsync(W[0], 0, sizeof(X) * (size_t)(N * K), s));
             if ((rc = tuned_lanes<V, X, K>(P, 1, d_tt, nt, R, W[0], gs, partials, cap, Lt, &Lt,
@@ -1882,6 +1915,11 @@ struct Engine {
             if ((rc = tuned_lanes<V, X, K>(P, 0, d_ta, na, W[0], U[1], gs, partials, cap, La, &La,
                                            s)) != TA_OK)
                 return rc;
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        if (sync != nullptr) {
+            arrival.now();
+            sync->wait();
         }
         // initial state
         if (M > 0)
@@ -2070,15 +2108,15 @@ struct Engine {
 template <typename V, typename X>
 static int run_k(int K, const BatchPlan &P, const int32_t *nrhs, const double *const *B,
                  double *const *Xo, const ta_opts *o, int32_t minnorm, ta_info *info,
-                 const int64_t *off, hipStream_t s) {
+                 const int64_t *off, hipStream_t s, GroupSync *g) {
     switch (K) {
-        case 1: return Engine<V, X, 1>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
-        case 2: return Engine<V, X, 2>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
-        case 4: return Engine<V, X, 4>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
-        case 8: return Engine<V, X, 8>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
-        case 16: return Engine<V, X, 16>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
-        case 32: return Engine<V, X, 32>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
-        default: return Engine<V, X, 64>::run(P, nrhs, B, Xo, o, minnorm, info, off, s);
+        case 1: return Engine<V, X, 1>::run(P, nrhs, B, Xo, o, minnorm, info, off, s, g);
+        case 2: return Engine<V, X, 2>::run(P, nrhs, B, Xo, o, minnorm, info, off, s, g);
+        case 4: return Engine<V, X, 4>::run(P, nrhs, B, Xo, o, minnorm, info, off, s, g);
+        case 8: return Engine<V, X, 8>::run(P, nrhs, B, Xo, o, minnorm, info, off, s, g);
+        case 16: return Engine<V, X, 16>::run(P, nrhs, B, Xo, o, minnorm, info, off, s, g);
+        case 32: return Engine<V, X, 32>::run(P, nrhs, B, Xo, o, minnorm, info, off, s, g);
+        default: return Engine<V, X, 64>::run(P, nrhs, B, Xo, o, minnorm, info, off, s, g);
     }
 }
 
@@ -2114,40 +2152,95 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
     }
     if (kmax == 0) return TA_OK;
     // Systems are run in groups of equal vector width K (the power of two
-    // covering their right-hand-side count), narrowest first, so that a
-    // system with few right-hand sides does not stream K - k padding columns.
-    // (Cutting wide counts further into power-of-two pieces, e.g. 40 = 32 + 8,
-    // streams fewer padding columns but measured slower: every extra group
-    // repeats the whole iteration sequence.)
+    // covering their right-hand-side count), so that a system with few
+    // right-hand sides does not stream K - k padding columns.  (Cutting wide
+    // counts further into power-of-two pieces, e.g. 40 = 32 + 8, streams fewer
+    // padding columns but measured slower: every extra group repeats the
+    // whole iteration sequence.)  The groups run side by side, each on its
+    // own host thread and stream, after everything queued on s.
     std::vector<int64_t> off(P.nsys);
     int64_t acc = 0;
     for (int32_t i = 0; i < P.nsys; ++i) {
         off[i] = acc;
         acc += nrhs[i];
     }
-    std::vector<int32_t> part(P.nsys);
+    std::vector<int> widths;
+    std::vector<std::vector<int32_t>> parts;
     for (int K = 1; K <= kwidth(kmax); K <<= 1) {
+        std::vector<int32_t> part(P.nsys);
         bool any = false;
         for (int32_t i = 0; i < P.nsys; ++i) {
             part[i] = (nrhs[i] > 0 && kwidth(nrhs[i]) == K) ? nrhs[i] : 0;
             any = any || part[i] > 0;
         }
         if (!any) continue;
-        int rc;
+        widths.push_back(K);
+        parts.push_back(std::move(part));
+    }
+    auto run_group = [&](size_t j, hipStream_t gsm, GroupSync *g) -> int {
         switch (o->precision) {
             case TA_FP32:
-                rc = run_k<float, float>(K, P, part.data(), B, Xo, o, minnorm, info, off.data(), s);
-                break;
+                return run_k<float, float>(widths[j], P, parts[j].data(), B, Xo, o, minnorm, info,
+                                           off.data(), gsm, g);
             case TA_BF16:
-                rc = run_k<uint16_t, float>(K, P, part.data(), B, Xo, o, minnorm, info, off.data(),
-                                            s);
-                break;
+                return run_k<uint16_t, float>(widths[j], P, parts[j].data(), B, Xo, o, minnorm,
+                                              info, off.data(), gsm, g);
             default:
-                rc = run_k<double, double>(K, P, part.data(), B, Xo, o, minnorm, info, off.data(),
-                                           s);
+                return run_k<double, double>(widths[j], P, parts[j].data(), B, Xo, o, minnorm,
+                                             info, off.data(), gsm, g);
         }
-        if (rc != TA_OK) return rc;
+    };
+    const size_t ng = widths.size();
+    if (ng == 1) return run_group(0, s, nullptr);
+    struct Streams {
+        std::vector<hipStream_t> v;
+        hipEvent_t ev = nullptr;
+        ~Streams() {
+            for (hipStream_t x : v) (void)hipStreamDestroy(x);
+            if (ev != nullptr) (void)hipEventDestroy(ev);
+        }
+    } st;
+    HIP_TRY(hipEventCreateWithFlags(&st.ev, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(st.ev, s));
+    for (size_t j = 0; j < ng; ++j) {
+        hipStream_t x = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        st.v.push_back(x);
+        HIP_TRY(hipStreamWaitEvent(x, st.ev, 0));
     }
+    int dev = 0;  // the caller's device, made current on every group thread
+    HIP_TRY(hipGetDevice(&dev));
+    GroupSync g;
+    g.pending = (int)ng;
+    std::vector<int> rcs(ng, TA_OK);
+    std::vector<std::string> msgs(ng);
+    std::vector<std::thread> th;
+    th.reserve(ng);
+    size_t started = 0;
+    try {
+        for (; started < ng; ++started) {
+            const size_t j = started;
+            th.emplace_back([&, j] {
+                const hipError_t e = hipSetDevice(dev);
+                rcs[j] = e == hipSuccess ? run_group(j, st.v[j], &g) : hip_fail(e, "hipSetDevice");
+                if (e != hipSuccess) g.arrive();
+                msgs[j] = hip_msg();
+            });
+        }
+    } catch (...) {
+        // groups that never started still count at the barrier
+        for (size_t j = started; j < ng; ++j) {
+            rcs[j] = TA_ENOMEM;
+            msgs[j] = "could not start a host thread";
+            g.arrive();
+        }
+    }
+    for (auto &x : th) x.join();
+    for (size_t j = 0; j < ng; ++j)
+        if (rcs[j] != TA_OK) {
+            hip_msg() = msgs[j];
+            return rcs[j];
+        }
     return TA_OK;
 }
 
