@@ -278,6 +278,10 @@ struct VecLoad<float, 4> {
     }
 };
 
+// nonzeros per lane in flight in the low-precision SpMM (its U): a row of up
+// to this many nonzeros takes one round of gathers
+constexpr int64_t kRoundNnz = 6;
+
 // Waves per SIMD asked of the SpMM: the low-precision chain at K = 64 fits
 // 64 VGPRs without spilling (8 waves instead of 7); the widths in between
 // would spill, and the FP64 chain keeps what its registers allow.
@@ -1644,6 +1648,7 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
     // FP32: 6 keeps a 5-point stencil row to one round at 7 waves per SIMD
     // (8: 6 waves; an 8-nonzero row then takes two rounds)
     constexpr int kU = sizeof(X) == 8 ? 4 : 6;
+    static_assert(sizeof(X) == 8 || kU == kRoundNnz, "the group split follows the FP32 round");
 #endif
     k_bspmm<V, X, K, EPI, kU><<<nblk, kBlock, 0, s>>>(rp, ci, (const V *)val, (const X *)x, (X *)y,
                                                       b, tab, gs, partials, cap, slot, gate, L);
@@ -2156,8 +2161,9 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
     // right-hand sides does not stream K - k padding columns.  (Cutting wide
     // counts further into power-of-two pieces, e.g. 40 = 32 + 8, streams fewer
     // padding columns but measured slower: every extra group repeats the
-    // whole iteration sequence.)  The groups run side by side, each on its
-    // own host thread and stream, after everything queued on s.
+    // whole iteration sequence.)  The groups (and their parts, below) run
+    // side by side, each on its own host thread and stream, after everything
+    // queued on s.
     std::vector<int64_t> off(P.nsys);
     int64_t acc = 0;
     for (int32_t i = 0; i < P.nsys; ++i) {
@@ -2174,8 +2180,41 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
             any = any || part[i] > 0;
         }
         if (!any) continue;
-        widths.push_back(K);
-        parts.push_back(std::move(part));
+        // low-precision chains: each group split once more by row length,
+        // systems whose rows fit one round of the SpMM's gathers (at most
+        // kRoundNnz nonzeros per row on average) and the rest.  The parts
+        // iterate independently, so short-row systems (stencils:
+        // latency-bound passes) overlap long-row ones (gather-bound) and
+        // neither waits for the other's iteration count.  (The FP64 chain,
+        // 4 nonzeros per round, measured slower split this way.)
+        if (o->precision == TA_FP64) {
+            widths.push_back(K);
+            parts.push_back(std::move(part));
+            continue;
+        }
+        std::vector<int32_t> pa(P.nsys, 0), pb(P.nsys, 0);
+        bool ha = false, hb = false;
+        for (int32_t i = 0; i < P.nsys; ++i) {
+            if (part[i] == 0) continue;
+            const int64_t rows = P.ro[i + 1] - P.ro[i];
+            const int64_t nz = P.dense ? rows * (P.co[i + 1] - P.co[i])
+                                       : (int64_t)P.h_arp[P.ro[i + 1]] - P.h_arp[P.ro[i]];
+            if (nz <= kRoundNnz * rows) {
+                pa[i] = part[i];
+                ha = true;
+            } else {
+                pb[i] = part[i];
+                hb = true;
+            }
+        }
+        if (ha) {
+            widths.push_back(K);
+            parts.push_back(std::move(pa));
+        }
+        if (hb) {
+            widths.push_back(K);
+            parts.push_back(std::move(pb));
+        }
     }
     auto run_group = [&](size_t j, hipStream_t gsm, GroupSync *g) -> int {
         switch (o->precision) {
