@@ -42,10 +42,13 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel on this workload, from two
 # rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy
-# kernel); see profiles/.  Keyed by (kernel, precision, K, pass); None when the
-# kernel has changed since the counters were taken.
-MEASURED_TRAFFIC: dict = {("k_bspmm", "fp32", 64, "A"): 6.1486e9,
-                          ("k_bspmm", "fp32", 64, "AT"): 6.3013e9}
+# kernel); see profiles/.  Keyed by (kernel, precision, K, pass, part); the
+# roofline's traffic is None unless every part's figure is here, and entries
+# are removed when the kernel changes.
+MEASURED_TRAFFIC: dict = {("k_bspmm", "fp32", 64, "A", 0): 1.3778e9,
+                          ("k_bspmm", "fp32", 64, "AT", 0): 1.3780e9,
+                          ("k_bspmm", "fp32", 64, "A", 1): 4.6727e9,
+                          ("k_bspmm", "fp32", 64, "AT", 1): 4.8692e9}
 
 
 def log(*a):
@@ -154,22 +157,47 @@ def batched_uneven_bench(args, P, torch, dev):
         f"{plain_conv} converged: {plain_rate:.1f} columns/s")
 
     # dominant kernel: the SpMM of the widest group (K = 64), A and A^T passes,
-    # timed on a plan over exactly that group's systems (the launch the solve makes)
+    # launched as the solve launches it: the library runs a group's low-precision
+    # chain in two parts, systems with at most 6 nonzeros per row on average (one
+    # round of the kernel's gathers) and the rest, so each part is timed on a
+    # plan over exactly its systems and a product of the group is one launch of
+    # each part
     Kd = max(kwidth(k) for k in ks)
     grp = [s for s, k in enumerate(ks) if kwidth(k) == Kd]
-    gp = P.BatchPlan([systems[s] for s in grp], args.precision)
-    gm = sum(bt.systems[s].m for s in grp)
-    gnnz = sum(bt.systems[s].nnz for s in grp)
+    split = args.precision != "fp64"
+    parts = [[s for s in grp if bt.systems[s].nnz <= 6 * bt.systems[s].m],
+             [s for s in grp if bt.systems[s].nnz > 6 * bt.systems[s].m]] if split else [grp]
+    parts = [q for q in parts if q]
     vb = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
     xb = 8 if args.precision == "fp64" else 4
-    ms_a = P.batch_time_spmm(gp, Kd, trans=False, precision=args.precision, reps=args.reps)
-    ms_at = P.batch_time_spmm(gp, Kd, trans=True, precision=args.precision, reps=args.reps)
-    by = csr_pass_bytes(gm, gm, gnnz, vb, 4, xb, Kd)
-    log(f"[bench] SpMM K={Kd} {args.precision} over {len(grp)} systems: A {ms_a * 1e3:.1f} us, "
-        f"A^T {ms_at * 1e3:.1f} us, {by / 1e9:.3f} GB per pass")
+    gm = sum(bt.systems[s].m for s in grp)
+    gnnz = sum(bt.systems[s].nnz for s in grp)
+    part_rows = []
+    for q in parts:
+        gp = P.BatchPlan([systems[s] for s in q], args.precision)
+        qm = sum(bt.systems[s].m for s in q)
+        qnnz = sum(bt.systems[s].nnz for s in q)
+        qa = P.batch_time_spmm(gp, Kd, trans=False, precision=args.precision, reps=args.reps)
+        qt = P.batch_time_spmm(gp, Kd, trans=True, precision=args.precision, reps=args.reps)
+        gp.close()
+        qby = csr_pass_bytes(qm, qm, qnnz, vb, 4, xb, Kd)
+        part_rows.append({"systems": len(q), "rows": qm, "nnz": qnnz, "bytes_per_launch": qby,
+                          "A_us": qa * 1e3, "AT_us": qt * 1e3})
+        log(f"[bench] SpMM K={Kd} {args.precision} part of {len(q)} systems ({qnnz / qm:.2f} "
+            f"nonzeros/row): A {qa * 1e3:.1f} us, A^T {qt * 1e3:.1f} us, {qby / 1e9:.3f} GB")
+    ms_a = sum(r["A_us"] for r in part_rows) * 1e-3
+    ms_at = sum(r["AT_us"] for r in part_rows) * 1e-3
+    by = sum(r["bytes_per_launch"] for r in part_rows)
+    log(f"[bench] SpMM K={Kd} {args.precision} over {len(grp)} systems in {len(parts)} launches: "
+        f"A {ms_a * 1e3:.1f} us, A^T {ms_at * 1e3:.1f} us, {by / 1e9:.3f} GB per product")
     trans = ms_at > ms_a
     kms = max(ms_a, ms_at)
-    gp.close()
+    orient = "AT" if trans else "A"
+    traffic = None
+    if all(("k_bspmm", args.precision, Kd, orient, i) in MEASURED_TRAFFIC
+           for i in range(len(parts))):
+        traffic = sum(MEASURED_TRAFFIC[("k_bspmm", args.precision, Kd, orient, i)]
+                      for i in range(len(parts)))
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -210,15 +238,14 @@ def batched_uneven_bench(args, P, torch, dev):
             "speedup_vs_fp64_batched": value / (conv64 / b64_s) if conv64 else None},
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_bspmm<{args.precision}, K={Kd}> {'A^T' if trans else 'A'} pass over the "
-                      f"{len(grp)} systems with {Kd // 2 + 1}-{Kd} right-hand sides "
-                      f"({gm} rows, {gnnz} nonzeros)",
+            "kernel": f"k_bspmm<{args.precision}, K={Kd}> {'A^T' if trans else 'A'} product over "
+                      f"the {len(grp)} systems with {Kd // 2 + 1}-{Kd} right-hand sides "
+                      f"({gm} rows, {gnnz} nonzeros), one launch per row-length part",
             "achieved": by / (kms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-            "traffic": MEASURED_TRAFFIC.get(("k_bspmm", args.precision, Kd,
-                                             "AT" if trans else "A")),
+            "traffic": traffic,
             "bytes_per_launch": by, "avg_launch_us": kms * 1e3,
-            "other_pass_us": min(ms_a, ms_at) * 1e3},
+            "other_pass_us": min(ms_a, ms_at) * 1e3, "parts": part_rows},
         "cpu_baseline": cpu,
     }
     return res

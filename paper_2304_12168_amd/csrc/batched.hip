@@ -1700,11 +1700,12 @@ static void prod(const BatchPlan &P, int trans, const void *x, void *y, const do
 template <typename V, typename X, int K>
 static int tuned_lanes(const BatchPlan &P, int trans, const BRange *tab, int32_t nblk,
                        const void *x, void *y, const Groups &gs, double2 *partials, int64_t cap,
-                       int32_t fallback, int32_t *L, hipStream_t s) {
+                       int32_t fallback, int32_t *L, hipStream_t s, int32_t short_rows) {
     *L = fallback;
     constexpr int KL = Lanes<X, K>::KL;
     if (P.dense || nblk <= 0 || 64 / KL < 2) return TA_OK;
-    const int64_t key = ((int64_t)K * 16 + (int64_t)sizeof(V)) * 2 + trans;
+    // per row-length class too: the two parts of a group keep their own lanes
+    const int64_t key = (((int64_t)K * 16 + (int64_t)sizeof(V)) * 2 + trans) * 2 + short_rows;
     {
         std::lock_guard<std::mutex> lk(P.tune_mu);
         for (auto &e : P.tuned)
@@ -1914,11 +1915,12 @@ struct Engine {
             if (sync != nullptr) lk = std::unique_lock<std::mutex>(sync->tune);
             HIP_TRY(hipMemsetAsync(R, 0, sizeof(X) * (size_t)(M * K), s));
             HIP_TRY(hipMemsetAsync(W[0], 0, sizeof(X) * (size_t)(N * K), s));
+            const int32_t short_rows = nnz_run <= kRoundNnz * m_run ? 1 : 0;
             if ((rc = tuned_lanes<V, X, K>(P, 1, d_tt, nt, R, W[0], gs, partials, cap, Lt, &Lt,
-                                           s)) != TA_OK)
+                                           s, short_rows)) != TA_OK)
                 return rc;
             if ((rc = tuned_lanes<V, X, K>(P, 0, d_ta, na, W[0], U[1], gs, partials, cap, La, &La,
-                                           s)) != TA_OK)
+                                           s, short_rows)) != TA_OK)
                 return rc;
             HIP_TRY(hipStreamSynchronize(s));
         }
@@ -2322,8 +2324,9 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
     gs.K = K;
     if (mixed && (P.dense ? P.d_low : P.a_low) == nullptr) return TA_EINVAL;
     const int64_t cap = std::max(nb, 1);
+    const int32_t short_rows = P.nnz <= kRoundNnz * rows ? 1 : 0;
     if (mixed && (rc = tuned_lanes<V, X, K>(P, trans, d_tab, nb, xin, yout, gs, partials, cap, L,
-                                            &L, s)) != TA_OK)
+                                            &L, s, short_rows)) != TA_OK)
         return rc;
     prod<V, X, K, kBNorm>(P, trans, xin, yout, nullptr, d_tab, nb, gs, partials, cap, 0, kBAlways,
                           L, s, DS);
