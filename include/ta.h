@@ -138,10 +138,12 @@ typedef struct ta_opts {
                               3): after each step, if ||r_{k+1}|| >= theta ||r_k||, the iterate
                               becomes a r_k + (1 - a) r_{k+1} (and the same combination of x,
                               or y) with a = rho / (rho + 1), rho = ||r_{k+1}|| / ||r_k||, the
-                              weight for which F_1 of the combination vanishes on a critical
-                              line; never twice in a row; the step counts as one iteration and
-                              hist holds the combination's residual.  0 = off.  Other solvers
-                              and batched solves: 0 */
+                              weight that makes the combination an eigenvector on a critical
+                              line, so that the next step solves such a system; never twice in
+                              a row.  The combination takes no product and is not counted as an
+                              iteration; hist[k] holds the combined residual.  0 = off; a value
+                              outside [0, 1) is TA_EINVAL.  Other solvers and batched solves:
+                              0 */
 } ta_opts;
 
 /* Result summary (host struct). */
