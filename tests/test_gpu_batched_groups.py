@@ -6,7 +6,9 @@ each system must get what it gets when solved alone.
 FP64: equal stop codes, iteration and product counts, x within 1e-12
 relative (the row lanes, and so the order of the compensated sums, may
 differ with the group's composition).  FP32 products with FP64 refinement:
-every column stops on the FP64 true residual, as when solved alone."""
+every column stops as when solved alone.  The iteration cap sits far from
+every column's count: the stencils stop at it, the random systems converge
+in under 60 iterations."""
 import numpy as np
 import pytest
 
@@ -55,7 +57,7 @@ def _solve(A, B, prec, **kw):
 @pytest.mark.parametrize("minnorm", [False, True], ids=["x_form", "y_form"])
 def test_fp64_side_by_side_equals_alone(minnorm):
     A, B = _batch()
-    kw = dict(tol=1e-8, t=3, max_iter=3000, minnorm=minnorm)
+    kw = dict(tol=1e-8, t=3, max_iter=1500, minnorm=minnorm)
     X, infos = _solve(A, B, "fp64", **kw)
     for s in range(len(A)):
         Xs, inf_s = _solve([A[s]], [B[s]], "fp64", **kw)
@@ -67,7 +69,7 @@ def test_fp64_side_by_side_equals_alone(minnorm):
 
 def test_fp32_side_by_side_reaches_tolerance():
     A, B = _batch()
-    kw = dict(tol=1e-6, t=3, max_iter=3000)
+    kw = dict(tol=1e-6, t=3, max_iter=1500)
     X, infos = _solve(A, B, "fp32", **kw)
     for s in range(len(A)):
         _, inf_s = _solve([A[s]], [B[s]], "fp32", **kw)
