@@ -294,8 +294,8 @@ int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, d
  * rounding of the plain matrix-core sums.  TA_FP32 / TA_BF16: products of the Krylov chain use the low
  * precision copies and FP32 vectors; Gram entries, steps, x (or y) and every
  * true-residual check are FP64, and the true residual replaces the recurrence
- * residual after every chunk (4, 8, 16, then 32 iterations with TA_FP32, 4
- * then 8 with TA_BF16, unless opts->chunk fixes it); a column can stop only
+ * residual after every chunk (4, 8, 16, 32, then 64 iterations with TA_FP32,
+ * 4 then 8 with TA_BF16, unless opts->chunk fixes it); a column can stop only
  * at a chunk's end; stop codes and residuals refer to FP64.
  * Systems are advanced in groups of equal vector width (k_s rounded up to a
  * power of two), one group after another on `stream`; every column keeps its

@@ -2014,11 +2014,11 @@ struct Engine {
         int32_t hflags[4] = {0, 0, 0, 0};
         int64_t chunk = o->chunk > 0 ? o->chunk : 4;
         // mixed precision: a chunk ends with the FP64 true-residual pass, and a
-        // group can stop only there; up to 32 iterations between checks with
+        // group can stop only there; up to 64 iterations between checks with
         // FP32 products, 8 with BF16 (whose recurrence drifts from the true
         // residual within a few dozen iterations)
         const int64_t chunk_cap =
-            o->chunk > 0 ? o->chunk : (mixed ? (sizeof(V) == 2 ? 8 : 32) : 64);
+            o->chunk > 0 ? o->chunk : (mixed ? (sizeof(V) == 2 ? 8 : 64) : 64);
         std::vector<int64_t> kh(G), kh_prev(G, -1);
         // Each chunk (iterations + tail) is captured once per length as a HIP
         // graph on a private stream and replayed on s; launch_mode 1 launches
