@@ -881,7 +881,7 @@ __device__ int32_t block_scan_excl(int32_t v, int32_t *sh, int32_t &total) {
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < kBlock; off <<= 1) {
-        const int32_t t = threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        const int32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
         __syncthreads();
         sh[threadIdx.x] += t;
         __syncthreads();
