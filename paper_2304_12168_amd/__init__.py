@@ -14,7 +14,7 @@ from __future__ import annotations
 import ctypes as C
 import dataclasses
 import os
-from typing import Optional, Union
+from typing import Optional
 
 import numpy as np
 

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import paper_2304_12168_amd as P
-from workloads import (convection_diffusion, dense_gaussian, csr_from_dense, kac_clement,
+from workloads import (convection_diffusion, csr_from_dense, kac_clement,
                        lp_shaped, poisson5, random_diag_dominant)
 
 pytestmark = pytest.mark.gpu

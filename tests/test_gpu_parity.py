@@ -8,7 +8,6 @@ Bars:
     within 1e-10 relative, x within 1e-10 relative (the tolerance the FP64
     path is held to).
 """
-import math
 
 import numpy as np
 import pytest
@@ -16,7 +15,7 @@ import pytest
 import oracle
 import paper_2304_12168_amd as P
 from workloads import (Csr, convection_diffusion, csr_from_coo, csr_from_dense, dense_gaussian,
-                       kac_clement, lp_shaped, poisson5, random_diag_dominant)
+                       kac_clement, lp_shaped, random_diag_dominant)
 
 pytestmark = pytest.mark.gpu
 
