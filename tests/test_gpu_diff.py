@@ -123,12 +123,17 @@ def test_low_precision_forward_adjoint(prec):
 @pytest.mark.slow
 def test_full_size_stencil_runs_to_budget():
     """The 256 x 256 perturbed stencil (n = 65536): FP32 forward and adjoint
-    to an iteration budget (CTA does not reach 1e-6 there with H = A A^T);
-    the residuals fall and the gradients are finite and shaped like the
-    inputs."""
+    to an iteration budget (CTA does not reach 1e-6 there with H = A A^T).
+    This is a run-to-budget check, not gradient coverage: the solves stop
+    short, so the call must refuse them unless told to accept them, and the
+    accepted x and gradients are only checked to be finite and shaped like
+    the inputs."""
     p, vals, b, xt = _setup(256)
+    with pytest.raises(P.TaError, match="maxiter"):
+        cta_solve_diff(p.A, vals, b, tol=1e-6, t=3, max_iter=20, precision="fp32")
     log = []
-    x = cta_solve_diff(p.A, vals, b, tol=1e-6, t=3, max_iter=300, precision="fp32", log=log)
+    x = cta_solve_diff(p.A, vals, b, tol=1e-6, t=3, max_iter=300, precision="fp32", log=log,
+                       allow_unconverged=True)
     ((x - xt) ** 2).sum().backward()
     assert [s for s, _ in log] == ["forward", "adjoint"]
     assert all(i.stop == "maxiter" and i.rel_res < 0.5 for _, i in log)
