@@ -195,7 +195,7 @@ int ta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, d
              int64_t hist_cap, ta_info *info, void *stream);
 
 /*
- * ta_minnorm - Algorithm 4 (section 4.3, TA for an approximation to the
+ * ta_minnorm - Algorithm 4 (section 4.4, TA for an approximation to the
  * minimum-norm solution): from x_eps (device, n doubles, an approximate
  * solution: ||A x_eps - b|| <= tol ||b||) it bisects on the radius rho of
  * the ellipsoid E_{A,rho}.  Upper bound hi = ||x_eps||, lower bound lo = 0;

@@ -184,7 +184,7 @@ def cta(A, b, tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0,
     """Algorithm 1 (CTA, H = A A^T; with h_is_a, H = A for a square symmetric
     positive semidefinite A, x-form only; with t_cycle, the order of
     iteration k cycles 1, 2, ..., t, ..., 2, 1, ...; with enhanced, the
-    enhanced stop of section 3 on the j-fold first-order iterates; with accel
+    enhanced stop of section 3.2 on the j-fold first-order iterates; with accel
     = theta in (0, 1), the convex-combination step of the first-order dynamics
     theorem whenever ||r_{k+1}|| >= theta ||r_k||).  Returns (x, hist, info)."""
     if h_is_a:

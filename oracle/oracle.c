@@ -51,7 +51,7 @@ typedef struct {
     int32_t t_cycle;       /* CTA: 1 = the order of iteration k is or_cycle_order(t, k) */
     int32_t nonneg;        /* TA: 1 = x >= 0 (LP feasibility): c replaced by c+ = max(c, 0) */
     double rho_max;        /* TA: > 0 = stop at a witness once the radius would exceed this */
-    int32_t enhanced;      /* CTA, t >= 2: the enhanced stop (section 3) */
+    int32_t enhanced;      /* CTA, t >= 2: the enhanced stop (section 3.2) */
     int32_t normal_eq;     /* TA: 1 = run on the normal equation A^T A x = A^T b (the
                               rectangular hybrid's inputs for an inconsistent system) */
     double accel;          /* CTA: > 0 = convex-combination step when ||r_{k+1}|| >= accel ||r_k|| */
@@ -272,12 +272,12 @@ static void exit_diagnostics(const or_mat *A, const double *b, const double *x, 
  * ||A^T r|| <= tol_normal ||A^T b||, or phi_2 = 0 (Example 1: H r = 0 means x
  * solves the normal equation).
  */
-/* The enhanced stop of section 3 (a variant of Algorithm 1 for t >= 2), taken
+/* The enhanced stop of section 3.2 (a variant of Algorithm 1 for t >= 2), taken
  * literally with explicit vectors: from the current residual f_0 = r, the
  * first-order steps f_j = F_1(f_{j-1}) = f_{j-1} - a_j H f_{j-1}, with
  * a_j = phi_1(f_{j-1}) / phi_2(f_{j-1}) (Example 1's order-1 step), for
  * j = 1, ..., t - 1; the first f_j that passes the normal-equation test (the
- * quadratic form f^T H f of section 3, read as ||A^T f_j|| against
+ * quadratic form f^T H f of section 3.2, read as ||A^T f_j|| against
  * tol_normal ||A^T b||; ||A f_j|| for H = A, as for the plain test) ends the
  * solve at x^ = x + sum_{i<j} a_{i+1} A^T f_i (H = A A^T), whose residual is
  * f_j.  For the y-form the increment is sum a_{i+1} f_i on y (x = A^T y); for
@@ -339,7 +339,7 @@ int or_cta(const or_mat *A, const double *b, double *x, const or_opts *o, int mi
     double nb, nab = 0.0, rr, phi[17], alpha[8];
     double *r, *y = NULL, *u[9], *w[8], *rt;
     /* convex-combination step (the theorem on the first-order dynamics,
-       section 3): the previous residual and iterate, and whether the current
+       section 3.4): the previous residual and iterate, and whether the current
        iterate came from such a step */
     double *rp = NULL, *xp = NULL;
     int last_jump = 0;
@@ -715,7 +715,7 @@ void or_csr_outer(const or_mat *A, const double *u, const double *v, double alph
 }
 
 /* ---------------------------------------------------------------------- */
-/* TA for an approximate minimum-norm solution (Algorithm 4, section 2.3)  */
+/* TA for an approximate minimum-norm solution (Algorithm 4, section 4.4)  */
 /* ---------------------------------------------------------------------- */
 /*
  * Given x_eps with ||A x_eps - b|| <= tol ||b||, bisect on the radius rho of

@@ -99,7 +99,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             double phi[2 * kTMax + 2];
             for (int i = 0; i <= 2 * t; ++i) phi[i] = st->phi[i];
             double a[kTMax];
-            // Enhanced stop (section 3, t >= 2): the first-order iterates
+            // Enhanced stop (section 3.2, t >= 2): the first-order iterates
             // f_j = F_1(f_{j-1}), f_0 = r, lie in r + span{H r, ..., H^j r}:
             // f_j = sum_k c_k H^k r, so f^T H^p f = sum_{k,l} c_k c_l phi_{k+l+p}
             // needs phi up to 2j + 2 <= 2t.  a_j = (f^T H f) / (f^T H^2 f);
@@ -786,7 +786,7 @@ __global__ __launch_bounds__(kBlock) void k_cta_update(int64_t m, int64_t n, int
     block_partials<1>(v, o);
 }
 
-// Convex-combination step (the first-order dynamics theorem of section 3):
+// Convex-combination step (the first-order dynamics theorem of section 3.4):
 // r = a r_k + (1 - a) r_{k+1}, and the same for the iterate, a = state.astar.
 __global__ __launch_bounds__(kBlock) void k_cta_jump(int64_t m, int64_t nxy, double *r,
                                                       const double *__restrict__ rb, double *xy,

@@ -662,7 +662,7 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
 }
 
 // ---------------------------------------------------------------------------
-// Algorithm 4 (section 2.3): approximate minimum-norm solution from an
+// Algorithm 4 (section 4.4): approximate minimum-norm solution from an
 // approximate solution x_eps, by bisection on the radius of E_{A, rho}
 // ---------------------------------------------------------------------------
 // ||v|| as one compensated sum (device), read back to the host.

@@ -1,6 +1,6 @@
 """Writes the stored expected values under tests/golden/.
 
-critical_line.json: Theorem (dynamics of F_1) (iv) of the paper (section 3.3):
+critical_line.json: Theorem (dynamics of F_1) (iv) of the paper (section 3.4):
 for H = diag(lam_i, lam_j), lam_i < lam_j, starting on the ij-critical line at
 r+ = (sqrt(lam_j/(lam_i+lam_j)), sqrt(lam_i/(lam_i+lam_j))) (unit norm), the
 k-th residual of first-order CTA has norm rho_ij^k with
@@ -19,7 +19,7 @@ def critical_line():
         rho = (lj - li) / (lj + li)
         cases.append({"lam_i": li, "lam_j": lj, "rho_ij": rho,
                       "expected_rel_res": [rho ** k for k in range(K + 1)]})
-    return {"source": "Theorem on the dynamics of F_1, part (iv), section 3.3 (eqs. c-two, c-three)",
+    return {"source": "Theorem on the dynamics of F_1, part (iv), section 3.4 (eqs. c-two, c-three)",
             "cases": cases}
 
 

@@ -1,4 +1,4 @@
-"""The enhanced stop (section 3, CTA with t >= 2) through the C ABI, against
+"""The enhanced stop (section 3.2, CTA with t >= 2) through the C ABI, against
 the FP64 oracle.  The device derives the first-order iterates' tests and x^
 from the iteration's phi_1..phi_2t; the oracle forms the iterates with
 explicit products.  Cases where the stop fires by a margin (the tolerance

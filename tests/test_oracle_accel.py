@@ -1,5 +1,5 @@
 """Pins of the oracle's convex-combination step (the theorem on the dynamics
-of first-order CTA, section 3): when ||r_{k+1}|| >= theta ||r_k||, the
+of first-order CTA, section 3.4): when ||r_{k+1}|| >= theta ||r_k||, the
 iterate becomes a r_k + (1 - a) r_{k+1} with a = rho / (rho + 1),
 rho = ||r_{k+1}|| / ||r_k||.
 

@@ -1,4 +1,4 @@
-"""Pins of the oracle's enhanced stop (section 3: for t >= 2, the j-fold
+"""Pins of the oracle's enhanced stop (section 3.2: for t >= 2, the j-fold
 first-order iterates F_1^j(r), j < t, are tested as well, and the first that
 passes the normal-equation test ends the solve at x^).
 

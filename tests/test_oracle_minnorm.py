@@ -1,5 +1,5 @@
 """Pins of the oracle's Algorithm 4 (TA for an approximate minimum-norm
-solution, section 2.3) and of TA's warm start: a case worked by hand, and on
+solution, section 4.4) and of TA's warm start: a case worked by hand, and on
 random systems the facts the paper and linear algebra fix -- Corollary 1's
 lower bound, the residual and gap conditions of Definition 1, the bisection
 count of the theorem after Algorithm 4, and a distance bound to pinv(A) b."""

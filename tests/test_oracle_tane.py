@@ -1,5 +1,5 @@
 """Pins of the oracle's TA on the normal equation A^T A x = A^T b (the inputs
-the rectangular hybrid of section 5.2 gives TA when the system is not
+the rectangular hybrid of section 5.3 gives TA when the system is not
 solvable): the limit is a least-squares solution, from x = 0 the
 minimum-norm one (pinv), within the bound the normal-equation residual
 allows; Algorithm 4 in this form certifies a bracket around ||pinv(A) b||,

@@ -14,7 +14,7 @@ Shapes follow the workloads the solvers are measured on:
   paper's convection-diffusion experiment discretises, section 5.1.8);
 * the Kac / Clement tridiagonal matrix (section 5.1.6 uses Clement matrices);
 * an LP-shaped wide sparse matrix, m x n with n >> m, six nonzeros per column
-  plus an identity slack block (the m = 1e4, n up to 1e6 class of section 5.2);
+  plus an identity slack block (the m = 1e4, n up to 1e6 class of section 5.3);
 * batches of uneven Poisson stencils and diagonally dominant random sparse
   systems with several right-hand sides each;
 * a randomly perturbed Poisson stencil.
