@@ -42,6 +42,8 @@ extern "C" {
 #define TA_ENOMEM (-2)  /* device allocation failed */
 #define TA_EHIP (-3)    /* a HIP runtime call failed; ta_strerror(TA_EHIP) has the text */
 #define TA_ENOTSUP (-4) /* input outside what the kernels support (see ta_mat) */
+#define TA_ESCRATCH (-5) /* cta_solve_plan_noalloc: the solve needs more device memory than
+                            its fixed buffer holds (see there) */
 
 /* ---- matrix kinds ---- */
 #define TA_DENSE_ROWMAJOR 0
@@ -261,6 +263,30 @@ int ta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opts
                   double *hist, int64_t hist_cap, ta_info *info, void *stream);
 int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, double *x,
                     const ta_opts *opts, ta_info *info, int64_t *tests, void *stream);
+
+/*
+ * cta_solve_plan_noalloc - cta_solve_plan for callers that cannot allocate
+ * device memory (code that must not call hipMalloc, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, same kernels, same
+ * results bit for bit.  The call allocates nothing: its workspace (the
+ * Krylov vectors, the residual, the per-block partial sums, the solver
+ * state) is carved from one fixed device buffer of TA_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each GPU it runs on until the process ends; the
+ * State is set from a kernel argument and read back into host stack memory.
+ * The plan itself is made beforehand with ta_plan_create (which allocates).
+ *   Limit: the workspace is 8 (t + 1) (m + n) bytes (8 (m + n) more with
+ *   accel, 128 m or 128 n more for a plan with column slices) plus the
+ *   per-block partial sums; a solve that needs more than the buffer returns
+ *   TA_ESCRATCH before any device work.  For t = 3 and m = n that is
+ *   n up to about 1e6.
+ *   Sharing: every call on one GPU uses that GPU's buffer, so calls that
+ *   overlap in time on one GPU (from several host threads or streams) race
+ *   and must be serialised by the caller.  Each call initialises what it
+ *   reads; the buffer keeps the last call's contents.
+ */
+#define TA_NOALLOC_SCRATCH_BYTES (64u << 20)
+int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                           double *hist, int64_t hist_cap, ta_info *info, void *stream);
 
 /* ---- batched solves: many systems, many right-hand sides, one set of kernels ----
  *

@@ -25,14 +25,15 @@ TA_DENSE_ROWMAJOR = 0
 TA_CSR = 1
 TA_FP64, TA_FP32, TA_BF16 = 0, 1, 2
 STOP_NAMES = {0: "none", 1: "residual", 2: "normal", 3: "witness", 4: "maxiter", 5: "breakdown"}
-ERRORS = {-1: "TA_EINVAL", -2: "TA_ENOMEM", -3: "TA_EHIP", -4: "TA_ENOTSUP"}
+ERRORS = {-1: "TA_EINVAL", -2: "TA_ENOMEM", -3: "TA_EHIP", -4: "TA_ENOTSUP", -5: "TA_ESCRATCH"}
 
 # every symbol the header declares
 EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror", "ta_spmv",
            "ta_residual", "ta_transpose", "ta_time_matvec", "ta_plan_create", "ta_plan_destroy",
            "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
            "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched",
-           "ta_batch_time_spmm", "ta_csr_outer", "ta_minnorm", "ta_minnorm_plan", "ta_plan_format")
+           "ta_batch_time_spmm", "ta_csr_outer", "ta_minnorm", "ta_minnorm_plan", "ta_plan_format",
+           "cta_solve_plan_noalloc")
 # storage of a plan's products (ta_plan_format)
 FORMATS = {0: "csr_rows", 1: "dense_rows", 2: "dense_cols", 3: "csr_sliced", 4: "sell64"}
 
@@ -78,7 +79,8 @@ def load_library(path: str = LIB_PATH):
             f = getattr(lib, name)
             f.restype = C.c_int
             f.argtypes = [MP, P, P, OP, P, I64, IP, P]
-        for name in ("cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan"):
+        for name in ("cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan",
+                     "cta_solve_plan_noalloc"):
             f = getattr(lib, name)
             f.restype = C.c_int
             f.argtypes = [P, P, P, OP, P, I64, IP, P]
@@ -285,7 +287,7 @@ def _solve(name, A, b, x0=None, hist_cap=None, **kw):
     return x, hist[: min(inf.iters + 1, cap)], inf
 
 
-def _solve_plan(name, pl, b, x0=None, hist_cap=None, **kw):
+def _solve_plan(name, pl, b, x0=None, hist_cap=None, _suffix="_plan", **kw):
     import torch
 
     lib = load_library()
@@ -297,10 +299,10 @@ def _solve_plan(name, pl, b, x0=None, hist_cap=None, **kw):
     cap = int(opts.max_iter) + 1 if hist_cap is None else int(hist_cap)
     hist = torch.full((max(cap, 1),), float("nan"), dtype=torch.float64, device=bd.device)
     info = TaInfo()
-    rc = getattr(lib, name + "_plan")(pl.handle, C.c_void_p(bd.data_ptr()),
+    rc = getattr(lib, name + _suffix)(pl.handle, C.c_void_p(bd.data_ptr()),
                                       C.c_void_p(x.data_ptr()), C.byref(opts),
                                       C.c_void_p(hist.data_ptr()), cap, C.byref(info), _stream())
-    _check(rc, name + "_plan")
+    _check(rc, name + _suffix)
     inf = _info(info)
     return x, hist[: min(inf.iters + 1, cap)], inf
 
@@ -310,6 +312,17 @@ def cta_solve(A, b, tol=1e-6, t=3, max_iter=100000, x0=None, **kw):
     else from 0.  Returns (x, hist, info)."""
     return _solve("cta_solve", A, b, x0=x0, tol=tol, t=t, max_iter=max_iter,
                   warm_start=x0 is not None, **kw)
+
+
+def cta_solve_noalloc(pl: "Plan", b, tol=1e-6, t=3, max_iter=100000, x0=None, **kw):
+    """cta_solve on a prepared operator through ``cta_solve_plan_noalloc``:
+    the library takes its workspace from a fixed per-GPU device buffer and
+    allocates nothing (the output tensors here are allocated by torch, as for
+    every binding call).  Returns (x, hist, info)."""
+    if not isinstance(pl, Plan):
+        raise TaError("cta_solve_noalloc takes a Plan")
+    return _solve_plan("cta_solve", pl, b, x0=x0, tol=tol, t=t, max_iter=max_iter,
+                       warm_start=x0 is not None, _suffix="_plan_noalloc", **kw)
 
 
 def cta_minnorm(A, b, tol=1e-6, t=3, max_iter=100000, **kw):

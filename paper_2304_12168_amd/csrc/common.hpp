@@ -193,6 +193,8 @@ hipError_t launch_ta_update(int64_t m, int64_t n, const double *b, double *bp, c
                             double *r, double *x, const double *c, const Out &o, hipStream_t s,
                             int32_t *blocks);
 hipError_t launch_step(const Step &sp, hipStream_t s);
+// *d = h, from a kernel argument
+hipError_t launch_state_set(State *d, const State &h, hipStream_t s);
 hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                             const int32_t *ci, int32_t *flag, hipStream_t s);
 hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,

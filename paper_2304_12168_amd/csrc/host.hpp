@@ -39,16 +39,33 @@ inline int hip_fail(hipError_t e, const char *what) {
 class Workspace {
    public:
     explicit Workspace(hipStream_t s) : s_(s) {}
+    // Carve from a caller-owned device buffer of `cap` bytes instead of
+    // allocating: commit() then calls no allocator and fails with
+    // TA_ESCRATCH if the pieces do not fit; nothing is freed.
+    Workspace(hipStream_t s, void *ext, size_t cap) : s_(s), ext_(ext), ext_cap_(cap) {}
     ~Workspace() {
-        if (base_ != nullptr) (void)hipFreeAsync(base_, s_);
+        if (base_ != nullptr && ext_ == nullptr) (void)hipFreeAsync(base_, s_);
     }
+    // pieces are recorded in a fixed table (no host allocation either)
     template <class T>
     void reserve(T **slot, int64_t count) {
-        reqs_.push_back({reinterpret_cast<void **>(slot), (size_t)std::max<int64_t>(count, 1) * sizeof(T)});
+        if (nreq_ == kMaxReqs) {
+            overflow_ = true;
+            return;
+        }
+        reqs_[nreq_++] = {reinterpret_cast<void **>(slot),
+                          (size_t)std::max<int64_t>(count, 1) * sizeof(T)};
     }
     int commit() {
+        if (overflow_) return TA_EINVAL;
         size_t total = 0;
-        for (auto &r : reqs_) total += (r.bytes + 255) & ~size_t(255);
+        for (int i = 0; i < nreq_; ++i) total += (reqs_[i].bytes + 255) & ~size_t(255);
+        if (ext_ != nullptr) {
+            if (total > ext_cap_) return TA_ESCRATCH;
+            base_ = ext_;
+            carve();
+            return TA_OK;
+        }
         static thread_local bool pool_set = false;
         if (!pool_set) {
             int dev = 0;
@@ -60,28 +77,37 @@ class Workspace {
             pool_set = true;
         }
         HIP_TRY(hipMallocAsync(&base_, total, s_));
-        char *p = static_cast<char *>(base_);
-        for (auto &r : reqs_) {
-            *r.slot = p;
-            p += (r.bytes + 255) & ~size_t(255);
-        }
+        carve();
         return TA_OK;
     }
     // hand the allocation to the caller (it is not freed by the destructor)
     void *release() {
-        void *b = base_;
+        void *b = ext_ == nullptr ? base_ : nullptr;
         base_ = nullptr;
         return b;
     }
+    bool external() const { return ext_ != nullptr; }
 
    private:
+    void carve() {
+        char *p = static_cast<char *>(base_);
+        for (int i = 0; i < nreq_; ++i) {
+            *reqs_[i].slot = p;
+            p += (reqs_[i].bytes + 255) & ~size_t(255);
+        }
+    }
     struct Req {
         void **slot;
         size_t bytes;
     };
+    static constexpr int kMaxReqs = 64;
     hipStream_t s_;
     void *base_ = nullptr;
-    std::vector<Req> reqs_;
+    void *ext_ = nullptr;
+    size_t ext_cap_ = 0;
+    Req reqs_[kMaxReqs];
+    int nreq_ = 0;
+    bool overflow_ = false;
 };
 
 inline int validate_mat(const ta_mat *A) {

@@ -1220,6 +1220,16 @@ hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
     return hipGetLastError();
 }
 
+// The whole State from a kernel argument (no host staging buffer).
+__global__ void k_state_set(State *d, State h) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *d = h;
+}
+
+hipError_t launch_state_set(State *d, const State &h, hipStream_t s) {
+    k_state_set<<<1, 64, 0, s>>>(d, h);
+    return hipGetLastError();
+}
+
 hipError_t launch_step(const Step &sp, hipStream_t s) {
     if (sp.nslots < 0 || sp.nslots > kMaxSlots) return hipErrorInvalidValue;
     for (int i = 0; i < sp.nslots; ++i)

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <initializer_list>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -30,7 +31,13 @@ static State *host_state() {
     return h;
 }
 
-static int read_state(State *d, State &out, hipStream_t s) {
+// noalloc: into `out` directly (pageable host memory, no pinned buffer)
+static int read_state(State *d, State &out, hipStream_t s, bool noalloc = false) {
+    if (noalloc) {
+        HIP_TRY(hipMemcpyAsync(&out, d, sizeof(State), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return TA_OK;
+    }
     State *h = host_state();
     if (h == nullptr) return hip_fail(hipErrorOutOfMemory, "hipHostMalloc");
     HIP_TRY(hipMemcpyAsync(h, d, sizeof(State), hipMemcpyDeviceToHost, s));
@@ -330,7 +337,11 @@ static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
 // One State upload from a pinned buffer of its own.  Every solve ends with a
 // synchronising State read, so when the next solve of this host thread
 // starts, the previous upload from the buffer has completed.
-static int upload_state(State *d, const State &h, hipStream_t s) {
+static int upload_state(State *d, const State &h, hipStream_t s, bool noalloc = false) {
+    if (noalloc) {  // from a kernel argument: no pinned staging buffer
+        HIP_TRY(launch_state_set(d, h, s));
+        return TA_OK;
+    }
     static thread_local State *up = nullptr;
     if (up == nullptr &&
         hipHostMalloc(reinterpret_cast<void **>(&up), sizeof(State)) != hipSuccess) {
@@ -415,8 +426,11 @@ static int solve_empty(const ta_mat *M, double *x, double *hist, int64_t hist_ca
 // ---------------------------------------------------------------------------
 // CTA (x-form and y-form)
 // ---------------------------------------------------------------------------
+// ext, ext_cap: a caller-held device buffer to carve the workspace from
+// (cta_solve_plan_noalloc); nullptr = allocate stream-ordered
 static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, double *hist,
-                   int64_t hist_cap, ta_info *info, hipStream_t s, bool minnorm) {
+                   int64_t hist_cap, ta_info *info, hipStream_t s, bool minnorm,
+                   void *ext = nullptr, size_t ext_cap = 0) {
     const ta_mat *M = &P.desc;
     int rc = check_solve_args(M, b, x, o, hist, hist_cap, info, minnorm ? 1 : 0);
     if (rc != TA_OK) return rc;
@@ -425,7 +439,8 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     const int t = o->t;
     if (m == 0) return solve_empty(M, x, hist, hist_cap, info, 0.0, s);
 
-    Workspace ws(s);
+    const bool noalloc = ext != nullptr;
+    Workspace ws = noalloc ? Workspace(s, ext, ext_cap) : Workspace(s);
     Chain c;
     c.s = s;
     c.hist = hist;
@@ -454,7 +469,7 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     if ((rc = ws.commit()) != TA_OK) return rc;
 
     State h0 = initial_state(o, hist_cap, hist);
-    if ((rc = upload_state(c.st, h0, s)) != TA_OK) return rc;
+    if ((rc = upload_state(c.st, h0, s, noalloc)) != TA_OK) return rc;
     u[0] = r;
     double *const xy = minnorm ? y : x;
     const int64_t nxy = minnorm ? m : n;
@@ -550,7 +565,7 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
             HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateFinal), s,
                                   nullptr));
         HIP_TRY(enqueue_exit_diagnostics(c, b, x, r, tmp_n));
-        if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
+        if ((rc = read_state(c.st, h, s, noalloc)) != TA_OK) return rc;
         if (h.done && h.stop != kStopCandidate) break;
         k_done = h.k;
         // every chunk advances k or checks a candidate until the solve stops
@@ -855,6 +870,35 @@ static int with_plan(const ta_mat *M, bool need_t, hipStream_t s, F &&f, bool se
     return rc;
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device buffer of cta_solve_plan_noalloc: one copy on every GPU the
+// library is loaded on, held until the process ends.  In host code the name
+// `scratch` is a host-side stand-in, never a device address: each device's
+// address comes from hipGetSymbolAddress, taken once with that device
+// current, and only that address is passed on.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[TA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+static int scratch_address(void **out) {
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return TA_EINVAL;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (p == nullptr) return hip_fail(hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return TA_OK;
+}
+
 }  // namespace ta
 
 struct ta_plan {
@@ -937,6 +981,16 @@ int cta_solve_plan(const ta_plan *plan, const double *b, double *x, const ta_opt
     return ta::cta_run(plan->p, b, x, opts, hist, hist_cap, info, (hipStream_t)stream, false);
 }
 
+int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                           double *hist, int64_t hist_cap, ta_info *info, void *stream) {
+    if (plan == nullptr) return TA_EINVAL;
+    void *buf = nullptr;
+    const int rc = ta::scratch_address(&buf);
+    if (rc != TA_OK) return rc;
+    return ta::cta_run(plan->p, b, x, opts, hist, hist_cap, info, (hipStream_t)stream, false, buf,
+                       TA_NOALLOC_SCRATCH_BYTES);
+}
+
 int cta_minnorm_plan(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
                      double *hist, int64_t hist_cap, ta_info *info, void *stream) {
     if (plan == nullptr) return TA_EINVAL;
@@ -979,6 +1033,9 @@ const char *ta_strerror(int code) {
         case TA_ENOMEM: return "device allocation failed";
         case TA_EHIP: return ta::hip_msg().empty() ? "HIP error" : ta::hip_msg().c_str();
         case TA_ENOTSUP: return "input not supported (a column of A holds more than 8192 entries)";
+        case TA_ESCRATCH:
+            return "the solve needs more device memory than the fixed buffer of "
+                   "cta_solve_plan_noalloc holds (64 MiB)";
         default: return "unknown error";
     }
 }
