@@ -132,9 +132,13 @@ typedef struct ta_opts {
                               solvers: 0 */
     int32_t normal_eq;     /* ta_solve / ta_minnorm: 1 = TA on the normal equation
                               A^T A x = A^T b (the inputs the rectangular hybrid of section
-                              5.2 gives TA when A x = b is not solvable).  Not available in
-                              this library: the call returns TA_ENOTSUP.  Must be 0
-                              (TA_EINVAL) for the other solvers */
+                              5.3 gives TA when A x = b is not solvable): the operator
+                              M = A^T A is applied as A^T (A v) with A v rounded to FP64
+                              (two passes, counted as two products; A^T b one more), the
+                              true residual is A^T b - A^T (A x) as one compensated sum per
+                              entry, hist[k] is relative to ||A^T b||, and rel_res /
+                              rel_normal stay on (A, b).  Must be 0 (TA_EINVAL) for the
+                              other solvers */
     double accel;          /* cta_solve / cta_minnorm: theta in (0, 1) = the convex-combination
                               step of the theorem on the dynamics of first-order CTA (section
                               3): after each step, if ||r_{k+1}|| >= theta ||r_k||, the iterate

@@ -40,7 +40,10 @@ struct State {
     int32_t enh_hit;   // CTA: this iteration's update is x^; stop NORMAL after it
     int32_t jump;      // CTA: a convex-combination step follows this update
     int32_t last_jump; // CTA: the current iterate came from one
+    int32_t pm;        // matrix passes per operator product: 1, or 2 for TA on the normal
+                       // equation (M v = A^T (A v))
     int64_t k;         // iterations done
+    int64_t rejects;   // candidate stops the true residual rejected
     int64_t max_iter;
     int64_t hist_cap;
     int64_t matvecs;

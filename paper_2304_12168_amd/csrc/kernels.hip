@@ -78,7 +78,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
         case kPostNab:
             st->nab = sqrt(v[0]);
             st->tol_ne_nab = st->tol_normal * st->nab;
-            st->matvecs++;
+            st->matvecs += st->pm;
             break;
         case kPostGram: {
             if (sp.arg > 0) st->t = sp.arg;  // order of this iteration (order cycling)
@@ -190,6 +190,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             } else {
                 st->done = 0;
                 st->stop = 0;
+                st->rejects++;
                 if (st->k >= st->max_iter) finish(st, TA_STOP_MAXITER);
             }
             break;
@@ -197,7 +198,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             if (computed) {
                 st->nc = sqrt(v[0]);
                 st->have_c = 1;
-                st->matvecs++;
+                st->matvecs += st->pm;
             }
             const double nc = st->nc, rb = st->rb;
             if (!isfinite(nc) || !isfinite(rb)) {
@@ -234,7 +235,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             break;
         }
         case kPostTaS: {
-            st->matvecs++;
+            st->matvecs += st->pm;
             const double rd = v[0], dd = v[1];
             if (!(dd > 0.0) || !isfinite(rd) || !isfinite(dd)) {
                 finish(st, TA_STOP_BREAKDOWN);
@@ -257,17 +258,18 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             loop_top(st);
             break;
         case kPostTaCand:
-            st->matvecs++;
+            st->matvecs += st->pm;
             if (sqrt(v[0]) <= st->tol_nb) {
                 finish(st, TA_STOP_RESIDUAL);
             } else {
                 st->done = 0;
                 st->stop = 0;
                 st->rejected = 1;
+                st->rejects++;
             }
             break;
         case kPostTaWarm:  // warm start: b' = A x, r = b - b'
-            st->matvecs++;
+            st->matvecs += st->pm;
             st->rr = v[0];
             st->rb = v[1];
             st->have_c = 0;
@@ -275,7 +277,7 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             loop_top(st);
             break;
         case kPostTaBp:
-            st->matvecs++;
+            st->matvecs += st->pm;
             st->rr = v[0];
             st->rb = v[1];
             st->have_c = 0;
@@ -715,11 +717,14 @@ __global__ __launch_bounds__(kBlock) void k_dense_cols(MatView M, const double *
                                                         double *y, EpiArgs ea, Out o) {
     if (!producer_runs(o)) return;
     // M = A^T: M.rows = columns of A, M.cols = rows of A
+    constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
     const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     Acc acc = {0.0, 0.0};
     if (j < M.rows) {
+        // the residual form b_j - (M x)_j is one compensated sum starting at b_j
+        if constexpr (EPI == kEpiResid) acc.p = ea.b[j];
         const double *a = M.val + j;
-        for (int64_t i = 0; i < M.cols; ++i) acc_fma(acc, a[i * M.ld], x[i]);
+        for (int64_t i = 0; i < M.cols; ++i) acc_fma(acc, sgn * a[i * M.ld], x[i]);
     }
     Acc v[EpiNV<EPI>::value] = {};
     if (j < M.rows) epilogue<EPI>(j, acc_val(acc), y, ea, o.st, v);

@@ -60,7 +60,7 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
     if (o->t_cycle != 0 && (o->t_cycle != 1 || solver == 2)) return TA_EINVAL;
     if (o->nonneg != 0 && (o->nonneg != 1 || solver != 2)) return TA_EINVAL;
     if (o->enhanced != 0 && (o->enhanced != 1 || solver == 2)) return TA_EINVAL;
-    if (o->normal_eq != 0) return o->normal_eq == 1 && solver == 2 ? TA_ENOTSUP : TA_EINVAL;
+    if (o->normal_eq != 0 && (o->normal_eq != 1 || solver != 2)) return TA_EINVAL;
     if (!(o->accel >= 0.0 && o->accel < 1.0) || (o->accel > 0.0 && solver == 2))
         return TA_EINVAL;
     if (!(o->rho_max >= 0.0) || !isfinite(o->rho_max) || (o->rho_max > 0.0 && solver != 2))
@@ -331,6 +331,7 @@ static State initial_state(const ta_opts *o, int64_t hist_cap, double *hist) {
     h.rho_max = o->rho_max;
     h.enhanced = o->enhanced;
     h.accel = o->accel;
+    h.pm = 1;
     return h;
 }
 
@@ -356,11 +357,13 @@ static int upload_state(State *d, const State &h, hipStream_t s, bool noalloc = 
 // Exit diagnostics, enqueued behind every chunk and run only once the solve
 // has finished: ||b - A x||^2, ||A^T (b - A x)||^2 and ||A^T b||^2 of the
 // final x into State.scratch[0..2].
+// with_nb: also ||b||^2 into State.scratch[3] (TA on the normal equation,
+// whose State.nb is ||A^T b||); needs a fourth partials slot.
 static hipError_t enqueue_exit_diagnostics(const Chain &c, const double *b, const double *x,
-                                           double *tmp_m, double *tmp_n) {
+                                           double *tmp_m, double *tmp_n, bool with_nb = false) {
     EpiArgs ea{};
     ea.b = b;
-    int32_t g0 = 0, g1 = 0, g2 = 0;
+    int32_t g0 = 0, g1 = 0, g2 = 0, g3 = 0;
     hipError_t e;
     if ((e = launch_matvec(c.A, x, tmp_m, kEpiResid, ea, c.out(0, kGateFinal), c.s, &g0)) !=
         hipSuccess)
@@ -371,13 +374,17 @@ static hipError_t enqueue_exit_diagnostics(const Chain &c, const double *b, cons
     if ((e = launch_matvec(c.AT, b, tmp_n, kEpiNorm, EpiArgs{}, c.out(2, kGateFinal), c.s, &g2)) !=
         hipSuccess)
         return e;
-    return c.step(0, {g0, g1, g2}, kPostStore, 0, kGateFinal, false);
+    if (!with_nb) return c.step(0, {g0, g1, g2}, kPostStore, 0, kGateFinal, false);
+    if ((e = launch_norm2(c.A.rows, b, c.out(3, kGateFinal), c.s, &g3)) != hipSuccess) return e;
+    return c.step(0, {g0, g1, g2, g3}, kPostStore, 0, kGateFinal, false);
 }
 
-static void fill_diagnostics(const State &h, ta_info *info) {
-    info->rel_res = h.nb > 0.0 ? sqrt(h.scratch[0]) / h.nb : 0.0;
+// nb_scratch: ||b|| is in State.scratch[3] rather than State.nb
+static void fill_diagnostics(const State &h, ta_info *info, bool nb_scratch = false) {
+    const double nb = nb_scratch ? sqrt(h.scratch[3]) : h.nb;
+    info->rel_res = nb > 0.0 ? sqrt(h.scratch[0]) / nb : 0.0;
     const double nab = sqrt(h.scratch[2]);
-    info->rel_normal = (h.nb > 0.0 && nab > 0.0) ? sqrt(h.scratch[1]) / nab : 0.0;
+    info->rel_normal = (nb > 0.0 && nab > 0.0) ? sqrt(h.scratch[1]) / nab : 0.0;
 }
 
 static void fill_info(const State &h, ta_info *info) {
@@ -422,6 +429,22 @@ static int solve_empty(const ta_mat *M, double *x, double *hist, int64_t hist_ca
     info->rho = rho0;
     return TA_OK;
 }
+
+// Host loop guard shared by the chains.  Every chunk either finishes the
+// solve or advances the iteration count, except a chunk that ends on a
+// candidate check right at its start (the next chunk then runs at least one
+// iteration, since a rejected candidate is not re-tested before the next
+// step).  Two chunks in a row without progress therefore mean a broken
+// chain: the call returns an error instead of polling forever.
+struct Progress {
+    int64_t k_last = -1;
+    int stalls = 0;
+    bool stalled(const State &h) {
+        stalls = h.k == k_last ? stalls + 1 : 0;
+        k_last = h.k;
+        return stalls >= 2;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // CTA (x-form and y-form)
@@ -546,21 +569,38 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         return TA_OK;
     };
 
-    // Each chunk: k iterations, then a candidate check (runs only if the chain
-    // stopped at a candidate), then the final x and the exit diagnostics (run
-    // only once the solve has finished).  One State read per chunk.
-    Chunker ch(o->chunk);
-    State h;
-    int64_t progress = -1, k_done = 0;  // iterations done when the chunk starts
-    for (;;) {
-        const int64_t k = ch.take();
-        for (int64_t i = 0; i < k; ++i)
-            if ((rc = enqueue_iteration(order_of(k_done + i))) != TA_OK) return rc;
+    // the candidate check (runs only if the chain stopped at a candidate):
+    // x = A^T y in the y-form, then the true residual, accepted or taken as
+    // the new recurrence residual
+    auto enqueue_check = [&]() -> int {
         if (minnorm)
             HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateCandidate), s,
                                   nullptr));
         HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateCandidate), s, &g));
         HIP_TRY(c.step(R, {g}, kPostCtaCand, products, kGateCandidate));
+        return TA_OK;
+    };
+
+    // Each chunk: k iterations, then a candidate check, then the final x and
+    // the exit diagnostics (run only once the solve has finished).  One State
+    // read per chunk.  After the first rejected candidate the recurrence is
+    // near the true residual's floor, where candidates can come every
+    // iteration: from then on each iteration is followed by the (gated)
+    // check, so no chunk stalls on one.
+    Chunker ch(o->chunk);
+    State h;
+    Progress prog;
+    bool inline_checks = false;
+    int64_t k_done = 0;  // iterations done when the chunk starts
+    for (;;) {
+        const int64_t k = ch.take();
+        for (int64_t i = 0; i < k; ++i) {
+            // the order of an iteration is its index's; a chunk that runs into
+            // a candidate resumes the schedule from the state's count
+            if ((rc = enqueue_iteration(order_of(k_done + i))) != TA_OK) return rc;
+            if (inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
+        }
+        if (!inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
         if (minnorm)
             HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateFinal), s,
                                   nullptr));
@@ -568,12 +608,11 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         if ((rc = read_state(c.st, h, s, noalloc)) != TA_OK) return rc;
         if (h.done && h.stop != kStopCandidate) break;
         k_done = h.k;
-        // every chunk advances k or checks a candidate until the solve stops
-        if (h.k + h.matvecs == progress) {
-            hip_msg() = "iteration chain made no progress";
+        inline_checks = inline_checks || h.rejects > 0;
+        if (prog.stalled(h)) {
+            hip_msg() = "CTA iteration chain made no progress";
             return TA_EHIP;
         }
-        progress = h.k + h.matvecs;
     }
     fill_info(h, info);
     if (h.nb == 0.0) {
@@ -586,7 +625,8 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
 }
 
 // ---------------------------------------------------------------------------
-// TA (Algorithm 3, or Algorithm 2 with a fixed radius)
+// TA (Algorithm 3, or Algorithm 2 with a fixed radius), on A x = b or on the
+// normal equation A^T A x = A^T b
 // ---------------------------------------------------------------------------
 static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, double *hist,
                   int64_t hist_cap, ta_info *info, hipStream_t s) {
@@ -596,38 +636,68 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     if (!P.has_t) return TA_EINVAL;
     const int64_t m = M->m, n = M->n;
     if (m == 0) return solve_empty(M, x, hist, hist_cap, info, o->rho0, s);
+    // normal equation: the operator is A^T A (n x n, symmetric), applied as
+    // A^T t with t = A v rounded to FP64; the right-hand side is A^T b
+    const bool ne = o->normal_eq == 1;
+    const int64_t mo = ne ? n : m;  // rows of the operator
 
     Workspace ws(s);
     Chain c;
     c.s = s;
     c.hist = hist;
-    c.reserve(ws, P, 5);
-    double *r = nullptr, *bp = nullptr, *cv = nullptr, *d = nullptr, *tmp_m = nullptr;
-    ws.reserve(&r, m);
-    ws.reserve(&bp, m);
-    ws.reserve(&d, m);
-    ws.reserve(&tmp_m, m);
+    c.reserve(ws, P, 6);  // slot 5: sink for the partial sums of inner passes
+    double *r = nullptr, *bp = nullptr, *cv = nullptr, *d = nullptr, *rt = nullptr,
+           *tA = nullptr, *bt = nullptr;
+    ws.reserve(&r, mo);
+    ws.reserve(&bp, mo);
+    ws.reserve(&d, mo);
+    ws.reserve(&rt, mo);
     ws.reserve(&cv, n);
+    ws.reserve(&tA, m);
+    if (ne) ws.reserve(&bt, n);
     if ((rc = ws.commit()) != TA_OK) return rc;
 
     State h0 = initial_state(o, hist_cap, hist);
+    h0.pm = ne ? 2 : 1;
+    h0.matvecs = ne ? 1 : 0;  // A^T b
     if ((rc = upload_state(c.st, h0, s)) != TA_OK) return rc;
-    int32_t g = 0, g2 = 0;
+    int32_t g = 0;
+    // y = Op v with the epilogue of the outer pass (gate and slot of `out`)
+    auto op_apply = [&](const double *v, double *y, int32_t epi, const EpiArgs &ea, const Out &out,
+                        int32_t *blocks) -> hipError_t {
+        if (!ne) return launch_matvec(c.A, v, y, epi, ea, out, s, blocks);
+        Out inner = out;
+        inner.slot = 5;
+        hipError_t e = launch_matvec(c.A, v, tA, kEpiNorm, EpiArgs{}, inner, s, nullptr);
+        if (e != hipSuccess) return e;
+        return launch_matvec(c.AT, tA, y, epi, ea, out, s, blocks);
+    };
+    // y = Op^T v (Op^T = Op on the normal equation)
+    auto op_apply_t = [&](const double *v, double *y, int32_t epi, const Out &out,
+                          int32_t *blocks) -> hipError_t {
+        if (!ne) return launch_matvec(c.AT, v, y, epi, EpiArgs{}, out, s, blocks);
+        return op_apply(v, y, epi, EpiArgs{}, out, blocks);
+    };
+    const double *be = b;  // the right-hand side the iteration works on
+    if (ne) {
+        HIP_TRY(launch_matvec(c.AT, b, bt, kEpiNorm, EpiArgs{}, c.out(5, kGateAlways), s, nullptr));
+        be = bt;
+    }
     // slots: 0 ||c||^2; 1, 2: r^T d, ||d||^2; 3, 4: ||r||^2, r^T b
     const int32_t warm = o->warm_start ? 1 : 0;
-    HIP_TRY(launch_ta_init(m, n, b, r, bp, x, warm, c.out(3, kGateAlways), s, &g));
+    HIP_TRY(launch_ta_init(mo, n, be, r, bp, x, warm, c.out(3, kGateAlways), s, &g));
     HIP_TRY(c.step(3, {g}, kPostTaInit, warm, kGateAlways));
     // LP feasibility (x >= 0): c = A^T r is replaced by its positive part
     const int32_t epi_c = o->nonneg ? kEpiNormPos : kEpiNorm;
     if (o->tol_normal > 0.0) {
-        HIP_TRY(launch_matvec(c.AT, b, cv, epi_c, EpiArgs{}, c.out(0, kGateAlways), s, &g));
+        HIP_TRY(op_apply_t(be, cv, epi_c, c.out(0, kGateAlways), &g));
         HIP_TRY(c.step(0, {g}, kPostNab, 0, kGateAlways));
     }
+    EpiArgs ebp{};
+    ebp.b = be;
+    ebp.r_out = r;
     if (warm) {  // b' = A x0, r = b - b'
-        EpiArgs ew{};
-        ew.b = b;
-        ew.r_out = r;
-        HIP_TRY(launch_matvec(c.A, x, bp, kEpiTaBp, ew, c.out(3, kGateAlways), s, &g));
+        HIP_TRY(op_apply(x, bp, kEpiTaBp, ebp, c.out(3, kGateAlways), &g));
         HIP_TRY(c.step(3, {g, g}, kPostTaWarm, 0, kGateAlways));
     }
 
@@ -635,44 +705,55 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     ed.bp = bp;
     ed.r = r;
     auto enqueue_iteration = [&]() -> int {
-        HIP_TRY(launch_matvec(c.AT, r, cv, epi_c, EpiArgs{}, c.out(0, kGateNeedC), s, &g));
+        HIP_TRY(op_apply_t(r, cv, epi_c, c.out(0, kGateNeedC), &g));
         HIP_TRY(c.step(0, {g}, kPostTaC, 0, kGateNeedC));
-        HIP_TRY(launch_matvec(c.A, cv, d, kEpiTaD, ed, c.out(1, kGatePivot), s, &g));
+        HIP_TRY(op_apply(cv, d, kEpiTaD, ed, c.out(1, kGatePivot), &g));
         HIP_TRY(c.step(1, {g, g}, kPostTaS, 0, kGatePivot));
-        HIP_TRY(launch_ta_update(m, n, b, bp, d, r, x, cv, c.out(3, kGatePivot), s, &g));
+        HIP_TRY(launch_ta_update(mo, n, be, bp, d, r, x, cv, c.out(3, kGatePivot), s, &g));
         HIP_TRY(c.step(3, {g, g}, kPostTaEnd, 0, kGatePivot));
         return TA_OK;
     };
-
     EpiArgs eres{};
-    eres.b = b;
-    EpiArgs ebp{};
-    ebp.b = b;
-    ebp.r_out = r;
+    eres.b = be;
+    // the candidate check (true residual; on the normal equation
+    // A^T b - A^T (A x) as one compensated sum per entry) and, after a
+    // rejection, b' = Op x and r = b - b'; both run only when due
+    auto enqueue_check = [&]() -> int {
+        int32_t gc = 0, gb = 0;
+        HIP_TRY(op_apply(x, rt, kEpiResid, eres, c.out(3, kGateCandidate), &gc));
+        HIP_TRY(c.step(3, {gc}, kPostTaCand, 0, kGateCandidate));
+        HIP_TRY(op_apply(x, bp, kEpiTaBp, ebp, c.out(3, kGateRejected), &gb));
+        HIP_TRY(c.step(3, {gb, gb}, kPostTaBp, 0, kGateRejected));
+        return TA_OK;
+    };
+
+    // Once a candidate has been rejected the recurrence runs close to the
+    // true residual's floor, where candidates can come every iteration; from
+    // then on every iteration is followed by the (gated) check, so a chunk
+    // never stalls on one.
     Chunker ch(o->chunk);
     State h;
-    int64_t progress = -1;
+    Progress prog;
+    bool inline_checks = false;
     for (;;) {
         const int64_t k = ch.take();
-        for (int64_t i = 0; i < k; ++i)
+        for (int64_t i = 0; i < k; ++i) {
             if ((rc = enqueue_iteration()) != TA_OK) return rc;
-        // candidate check; on rejection b' = A x and r = b - b' are recomputed
-        HIP_TRY(launch_matvec(c.A, x, tmp_m, kEpiResid, eres, c.out(3, kGateCandidate), s, &g));
-        HIP_TRY(c.step(3, {g}, kPostTaCand, 0, kGateCandidate));
-        HIP_TRY(launch_matvec(c.A, x, bp, kEpiTaBp, ebp, c.out(3, kGateRejected), s, &g2));
-        HIP_TRY(c.step(3, {g2, g2}, kPostTaBp, 0, kGateRejected));
-        HIP_TRY(enqueue_exit_diagnostics(c, b, x, tmp_m, cv));
+            if (inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
+        }
+        if (!inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
+        HIP_TRY(enqueue_exit_diagnostics(c, b, x, tA, cv, ne));
         if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
         if (h.done && h.stop != kStopCandidate) break;
-        if (h.k + h.matvecs == progress) {
-            hip_msg() = "iteration chain made no progress";
+        inline_checks = inline_checks || h.rejects > 0;
+        if (prog.stalled(h)) {
+            hip_msg() = "TA iteration chain made no progress";
             return TA_EHIP;
         }
-        progress = h.k + h.matvecs;
     }
     if (warm && h.nb == 0.0) HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * (size_t)n, s));
     fill_info(h, info);
-    if (h.nb > 0.0) fill_diagnostics(h, info);
+    if (h.nb > 0.0) fill_diagnostics(h, info, ne);
     return TA_OK;
 }
 

@@ -95,7 +95,7 @@ def test_validate_variant_options(lib):
     assert P.validate(rect, 1, t=3, enhanced=True) == 0
     assert P.validate(sq, 0, t=3, enhanced=True, h_is_a=True) == 0
     assert P.validate(rect, 2, enhanced=True) == -1      # a CTA stop
-    assert P.validate(rect, 2, normal_eq=True) == -4     # TA_ENOTSUP: not on the device
+    assert P.validate(rect, 2, normal_eq=True) == 0      # TA on the normal equation
     assert P.validate(rect, 0, t=2, normal_eq=True) == -1  # a TA input form
     assert P.validate(rect, 1, t=2, normal_eq=True) == -1
     assert P.validate(rect, 0, t=3, accel=0.5) == 0

@@ -1,12 +1,16 @@
 """TA and Algorithm 4 on the normal equation A^T A x = A^T b (the rectangular
 hybrid's inputs for an unsolvable system) through the C ABI, against the FP64
-oracle: equal stop codes, iteration and pass counts, histories within 1e-10,
-x within 1e-9 relative; Algorithm 4's tests and bracket equal.
+oracle: equal stop codes, iteration and product counts, histories within
+1e-10, x within 1e-9 relative; Algorithm 4's tests and bracket equal.
 
-The device path is switched off: its first run on the GPU (the dense
-rank-deficient case below) did not finish within the time limit and no cause
-has been found by reading the code, so the library rejects normal_eq with
-TA_ENOTSUP and the parity tests are skipped until the cause is found."""
+The first device implementation never finished on the dense rank-deficient
+case: the dense transposed product ignored the residual form of its epilogue
+(it returned A^T t instead of A^T b - A^T t), so every candidate stop was
+rejected and the chain advanced one iteration per host poll.  The dense
+kernel now forms the residual like the other product kernels (the dense
+cases below reach the oracle's RESIDUAL stop with its exact counts only if
+the true residual is right), and after a first rejection the chains check
+candidates after every iteration."""
 import numpy as np
 import pytest
 
@@ -40,11 +44,6 @@ def _full_tall(seed):
     return g.standard_normal((14, 10)), g.standard_normal(14)
 
 
-_OFF = pytest.mark.skip(reason="device normal_eq path switched off: its first GPU run did not "
-                                "finish and no cause has been found; the library returns "
-                                "TA_ENOTSUP")
-
-
 def _compare(g, o):
     x, hist, info = g
     xo, ho, io = o
@@ -55,7 +54,6 @@ def _compare(g, o):
     assert info.rel_normal == pytest.approx(io.rel_normal, rel=1e-6, abs=1e-18)
 
 
-@_OFF
 @pytest.mark.parametrize("kind", ["dense", "csr"])
 @pytest.mark.parametrize("case,tol", [("rank_deficient", 1e-6), ("full_tall", 1e-3)])
 def test_ta_normal_eq_matches_oracle(kind, case, tol):
@@ -65,7 +63,6 @@ def test_ta_normal_eq_matches_oracle(kind, case, tol):
              oracle.ta(M, b, tol=tol, max_iter=200_000, normal_eq=True))
 
 
-@_OFF
 def test_ta_normal_eq_tall_sparse():
     """The transpose of an LP-shaped matrix (5000 x 200, sparse, full column
     rank) with a random, inconsistent right-hand side."""
@@ -78,7 +75,6 @@ def test_ta_normal_eq_tall_sparse():
              oracle.ta(A, b, tol=1e-3, max_iter=100_000, normal_eq=True))
 
 
-@_OFF
 def test_algorithm4_on_normal_eq():
     A, b = _rank_deficient(0)
     xp = np.linalg.pinv(A) @ b
@@ -92,10 +88,10 @@ def test_algorithm4_on_normal_eq():
     assert ig.rho_lo <= np.linalg.norm(xp) <= ig.rho + 1e-3 * np.linalg.norm(xe)
 
 
-def test_normal_eq_rejected_before_any_device_work():
-    """Host-side validation: TA_ENOTSUP for TA, TA_EINVAL for CTA."""
+def test_normal_eq_is_a_ta_option_only():
+    """Host-side validation: CTA takes no normal_eq (TA_EINVAL)."""
     A, b = _full_tall(0)
-    with pytest.raises(P.TaError, match="ENOTSUP"):
-        P.ta_solve(A, b, normal_eq=True)
     with pytest.raises(P.TaError, match="EINVAL"):
         P.cta_solve(A, b, normal_eq=True)
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.cta_minnorm(A, b, normal_eq=True)
