@@ -40,15 +40,30 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel on this workload, from two
-# rocprofv3 counter runs (FETCH_SIZE and WRITE_SIZE, scaled by a 1 GiB copy
-# kernel); see profiles/.  Keyed by (kernel, precision, K, pass, part); the
-# roofline's traffic is None unless every part's figure is here, and entries
-# are removed when the kernel changes.
-MEASURED_TRAFFIC: dict = {("k_bspmm", "fp32", 64, "A", 0): 1.3778e9,
-                          ("k_bspmm", "fp32", 64, "AT", 0): 1.3780e9,
-                          ("k_bspmm", "fp32", 64, "A", 1): 4.6727e9,
-                          ("k_bspmm", "fp32", 64, "AT", 1): 4.8692e9}
+# HBM bytes per launch of the dominant kernel on this workload come from two
+# rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, scaled by a 1 GiB copy
+# kernel) stored in profiles/ with the hash of the kernel source they were
+# taken on; the roofline's traffic is None when that source has changed since.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bspmm_fp32_k64_batched_uneven_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2304_12168_amd", "csrc", "batched.hip")
+
+
+def measured_traffic():
+    """{(precision, K, pass, part): bytes} if the committed counter figures
+    were taken on the current kernel source, else {}."""
+    import hashlib
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return {}
+    if rec.get("kernel_source_sha256") != sha:
+        return {}
+    return {(e["precision"], e["K"], e["pass"], e["part"]): e["bytes_per_launch"]
+            for e in rec.get("entries", [])}
 
 
 def log(*a):
@@ -64,6 +79,16 @@ def csr_pass_bytes(rows: int, cols: int, nnz: int, val_bytes: int, idx_bytes: in
             + rows * k * vec_bytes)
 
 
+def group_pass_bytes(systems, ks, val_bytes: int, vec_bytes: int, K: int = 0) -> int:
+    """Algorithmic HBM bytes of one pass Y = M X over the block-diagonal
+    operator of `systems` (square), each system with its own k_s right-hand
+    sides: every system's matrix once, its k_s input and output columns once.
+    With K > 0, every system is counted at K columns instead (what a kernel
+    of vector width K streams, padding included)."""
+    return sum(csr_pass_bytes(a.m, a.n, a.nnz, val_bytes, 4, vec_bytes, K if K else k)
+               for a, k in zip(systems, ks))
+
+
 def kwidth(k: int) -> int:
     K = 1
     while K < k:
@@ -71,7 +96,7 @@ def kwidth(k: int) -> int:
     return K
 
 
-def batched_uneven_bench(args, P, torch, dev):
+def batched_uneven_bench(args, P, torch, dev, pool=None):
     import numpy as np
 
     from workloads import batched_uneven
@@ -95,8 +120,11 @@ def batched_uneven_bench(args, P, torch, dev):
     torch.cuda.synchronize()
     plan_ms = 1e3 * (time.perf_counter() - t0)
 
+    last_x = []
+
     def solve(plan, prec):
-        _, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=budget, precision=prec)
+        X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=budget, precision=prec)
+        last_x[:] = [X]
         return infos
 
     def summary(infos):
@@ -126,6 +154,19 @@ def batched_uneven_bench(args, P, torch, dev):
     stencil_its = sum(s for _, s in sums) / elapsed
     rand_iters = sorted(i.iters for s, inf in enumerate(runs[-1]) for i in inf
                         if bt.kinds[s] == "random" and i.stop == "residual")
+    x_mixed = [x.cpu().numpy() for x in last_x[0]]  # the last timed step's solutions
+    # bytes the step's matrix products move (algorithmic): per system, 2t passes
+    # over its matrix per iteration while any column is active, and per column
+    # and iteration 2t products each reading and writing one vector column
+    vbs = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
+    xbs = 8 if args.precision == "fp64" else 4
+    step_bytes = 0
+    for s, inf in enumerate(runs[-1]):
+        a = bt.systems[s]
+        if not inf:
+            continue
+        step_bytes += max(i.iters for i in inf) * 2 * t * (a.nnz * (vbs + 4) + 4 * (a.m + 1))
+        step_bytes += sum(i.iters for i in inf) * 2 * t * 2 * a.m * xbs
     log(f"[bench] mixed+batched ({args.precision}): {ms_per_step:.1f} ms per step, "
         f"{conv // args.steps} of {ncols} columns converged per step, {value:.1f} columns/s")
 
@@ -137,6 +178,22 @@ def batched_uneven_bench(args, P, torch, dev):
     b64_s = time.perf_counter() - t0
     conv64, _ = summary(inf64)
     log(f"[bench] FP64 batched: {b64_s * 1e3:.1f} ms, {conv64} columns converged")
+
+    # BF16 products (FP32 accumulation) with FP64 refinement, one solve
+    bf16 = None
+    if args.precision != "bf16":
+        bp16 = P.BatchPlan(systems, "bf16")
+        solve(bp16, "bf16")  # warm-up (row-lane tuning)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf16 = solve(bp16, "bf16")
+        torch.cuda.synchronize()
+        b16_s = time.perf_counter() - t0
+        conv16, _ = summary(inf16)
+        bp16.close()
+        bf16 = {"columns_per_s": conv16 / b16_s, "ms": b16_s * 1e3,
+                "columns_converged": conv16}
+        log(f"[bench] BF16 batched: {b16_s * 1e3:.1f} ms, {conv16} columns converged")
 
     # FP64 plain on a seeded sample of columns, one cta_solve call each
     g = np.random.default_rng([args.seed, 7])
@@ -180,44 +237,35 @@ def batched_uneven_bench(args, P, torch, dev):
         qa = P.batch_time_spmm(gp, Kd, trans=False, precision=args.precision, reps=args.reps)
         qt = P.batch_time_spmm(gp, Kd, trans=True, precision=args.precision, reps=args.reps)
         gp.close()
-        qby = csr_pass_bytes(qm, qm, qnnz, vb, 4, xb, Kd)
-        part_rows.append({"systems": len(q), "rows": qm, "nnz": qnnz, "bytes_per_launch": qby,
+        qsys = [bt.systems[s] for s in q]
+        qks = [ks[s] for s in q]
+        qby = group_pass_bytes(qsys, qks, vb, xb)
+        qpad = group_pass_bytes(qsys, qks, vb, xb, K=Kd)
+        part_rows.append({"systems": len(q), "rows": qm, "nnz": qnnz, "columns": sum(qks),
+                          "bytes_per_launch": qby, "padded_bytes_per_launch": qpad,
                           "A_us": qa * 1e3, "AT_us": qt * 1e3})
         log(f"[bench] SpMM K={Kd} {args.precision} part of {len(q)} systems ({qnnz / qm:.2f} "
-            f"nonzeros/row): A {qa * 1e3:.1f} us, A^T {qt * 1e3:.1f} us, {qby / 1e9:.3f} GB")
+            f"nonzeros/row, {sum(qks)} columns): A {qa * 1e3:.1f} us, A^T {qt * 1e3:.1f} us, "
+            f"{qby / 1e9:.3f} GB algorithmic ({qpad / 1e9:.3f} GB with padding columns)")
     ms_a = sum(r["A_us"] for r in part_rows) * 1e-3
     ms_at = sum(r["AT_us"] for r in part_rows) * 1e-3
     by = sum(r["bytes_per_launch"] for r in part_rows)
+    by_pad = sum(r["padded_bytes_per_launch"] for r in part_rows)
     log(f"[bench] SpMM K={Kd} {args.precision} over {len(grp)} systems in {len(parts)} launches: "
-        f"A {ms_a * 1e3:.1f} us, A^T {ms_at * 1e3:.1f} us, {by / 1e9:.3f} GB per product")
+        f"A {ms_a * 1e3:.1f} us, A^T {ms_at * 1e3:.1f} us, {by / 1e9:.3f} GB per product "
+        f"({by_pad / 1e9:.3f} GB with padding)")
     trans = ms_at > ms_a
     kms = max(ms_a, ms_at)
     orient = "AT" if trans else "A"
+    mt = measured_traffic()
     traffic = None
-    if all(("k_bspmm", args.precision, Kd, orient, i) in MEASURED_TRAFFIC
-           for i in range(len(parts))):
-        traffic = sum(MEASURED_TRAFFIC[("k_bspmm", args.precision, Kd, orient, i)]
-                      for i in range(len(parts)))
+    if all((args.precision, Kd, orient, i) in mt for i in range(len(parts))):
+        traffic = sum(mt[(args.precision, Kd, orient, i)] for i in range(len(parts)))
 
     cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        oracle.build(force=False)
-        sample = pick[: args.cpu_sample]
-        log(f"[bench] CPU oracle: {len(sample)} sampled columns, 1 thread")
-        c0 = time.perf_counter()
-        cconv = 0
-        for s, c in sample:
-            _, _, oi = oracle.cta(bt.systems[s], bt.B[s][:, c], tol=tol, t=t, max_iter=budget,
-                                  hist_cap=1)
-            cconv += oi.stop == "residual"
-        csec = time.perf_counter() - c0
-        cpu = {"value": cconv / csec, "unit": "columns solved to 1e-6/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{len(sample)} seeded (system, column) pairs of the same batch, each "
-                         f"a full single-column CTA-3 solve (budget {budget}), sequential C, "
-                         f"{cconv} converged, {csec:.1f} s"}
+    x_err = None
+    if pool is not None:
+        cpu, x_err = cpu_baseline(args, bt, x_mixed, runs[-1], tol, t, budget, *pool)
 
     res = {
         "value": value, "ms_per_step": ms_per_step,
@@ -232,10 +280,14 @@ def batched_uneven_bench(args, P, torch, dev):
             "random_iterations_median": rand_iters[len(rand_iters) // 2] if rand_iters else None,
             "stencil_iterations_per_s": stencil_its, "plan_ms": plan_ms,
             "fp64_batched_columns_per_s": conv64 / b64_s,
+            "bf16_batched": bf16,
             "fp64_plain_columns_per_s": plain_rate,
             "fp64_plain_sample": f"{len(pick)} columns, {plain_conv} converged, {plain_s:.2f} s",
             "speedup_vs_fp64_plain": value / plain_rate if plain_rate > 0 else None,
-            "speedup_vs_fp64_batched": value / (conv64 / b64_s) if conv64 else None},
+            "speedup_vs_fp64_batched": value / (conv64 / b64_s) if conv64 else None,
+            "step_product_bytes": step_bytes,
+            "step_product_GB_s": step_bytes / (ms_per_step * 1e-3) / 1e9,
+            "x_rel_err_vs_fp64_oracle": x_err},
         "roofline": {
             "bound": "hbm",
             "kernel": f"k_bspmm<{args.precision}, K={Kd}> {'A^T' if trans else 'A'} product over "
@@ -244,11 +296,86 @@ def batched_uneven_bench(args, P, torch, dev):
             "achieved": by / (kms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "traffic": traffic,
-            "bytes_per_launch": by, "avg_launch_us": kms * 1e3,
+            "bytes_per_launch": by, "padded_bytes_per_launch": by_pad,
+            "frac_with_padding": by_pad / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "avg_launch_us": kms * 1e3,
             "other_pass_us": min(ms_a, ms_at) * 1e3, "parts": part_rows},
         "cpu_baseline": cpu,
     }
     return res
+
+
+def _oracle_column(job):
+    """One sampled column solved by the CPU oracle (a worker process)."""
+    import oracle
+
+    a, b, tol, t, budget = job
+    t0 = time.perf_counter()
+    x, _, info = oracle.cta(a, b, tol=tol, t=t, max_iter=budget, hist_cap=1)
+    return x, info.stop, time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def make_cpu_pool():
+    """Worker processes for the CPU baseline, forked before anything touches
+    the GPU (they never do): one per host core, at most 12."""
+    import multiprocessing as mp
+
+    import oracle
+
+    oracle.build(force=False)
+    workers = max(1, min(12, os.cpu_count() or 1))
+    return mp.get_context("fork").Pool(workers), workers
+
+
+def cpu_baseline(args, bt, x_mixed, infos, tol, t, budget, pool, workers):
+    """The oracle (sequential C, unchanged) on a seeded sample of the batch's
+    columns, one column per worker process on the host's cores, and the
+    relative difference between the mixed-precision x of the timed run and
+    the oracle's FP64 x on every sampled column both converged."""
+    import numpy as np
+
+    g = np.random.default_rng([args.seed, 11])
+    flat = [(s, c) for s in range(len(bt.B)) for c in range(bt.B[s].shape[1])]
+    pick = [flat[i] for i in g.choice(len(flat), size=args.cpu_sample, replace=False)]
+    jobs = [(bt.systems[s], bt.B[s][:, c], tol, t, budget) for s, c in pick]
+    log(f"[bench] CPU oracle: {len(pick)} sampled columns on {workers} worker processes")
+    c0 = time.perf_counter()
+    res = pool.map(_oracle_column, jobs, chunksize=1)
+    csec = time.perf_counter() - c0
+    cconv = sum(r[1] == "residual" for r in res)
+    one = sum(r[2] for r in res)
+    errs = []
+    for (s, c), (xo, stop, _) in zip(pick, res):
+        xg = x_mixed[s][:, c]
+        if stop == "residual" and infos[s][c].stop == "residual":
+            errs.append(float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)))
+    errs.sort()
+    x_err = ({"columns": len(errs), "max": errs[-1], "median": errs[len(errs) // 2],
+              "note": "||x_mixed - x_oracle|| / ||x_oracle|| on sampled columns both solved"}
+             if errs else None)
+    if errs:
+        log(f"[bench] mixed x vs FP64 oracle x on {len(errs)} columns: max {errs[-1]:.2e}, "
+            f"median {errs[len(errs) // 2]:.2e}")
+    cpu = {"value": cconv / csec, "unit": "columns solved to 1e-6/s", "cores": workers,
+           "kind": "oracle",
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "single_thread_value": cconv / one if one > 0 else None,
+           "sample": f"{len(pick)} seeded (system, column) pairs of the same batch, each a full "
+                     f"single-column CTA-3 solve (budget {budget}) by the sequential C oracle, "
+                     f"one column per process on {workers} processes; {cconv} converged; "
+                     f"{csec:.1f} s wall, {one:.1f} s summed over the workers"}
+    return cpu, x_err
 
 
 def lp_shaped_bench(args, P, torch, dev):
@@ -499,7 +626,7 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp64"])
     ap.add_argument("--plain-sample", type=int, default=24,
                     help="columns solved one at a time for the FP64 plain rate")
-    ap.add_argument("--cpu-sample", type=int, default=8,
+    ap.add_argument("--cpu-sample", type=int, default=48,
                     help="columns solved by the CPU oracle for the CPU baseline")
     ap.add_argument("--reps", type=int, default=20, help="launches per kernel timing")
     ap.add_argument("--lp-steps", type=int, default=5)
@@ -518,6 +645,10 @@ def main():
               "(the multi-GPU layout is described, not built)", file=sys.stderr)
         sys.exit(2)
 
+    # the CPU baseline's worker processes are forked first, before the GPU is
+    # initialised, so that none of them holds GPU state
+    pool = None if args.no_cpu_baseline else make_cpu_pool()
+
     import torch
 
     import paper_2304_12168_amd as P
@@ -529,7 +660,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    res = batched_uneven_bench(args, P, torch, dev)
+    res = batched_uneven_bench(args, P, torch, dev, pool)
+    if pool is not None:
+        pool[0].close()
+        pool[0].join()
     if not args.no_lp:
         res["config"]["lp_shaped"] = lp_shaped_bench(args, P, torch, dev)
     if not args.no_diff:

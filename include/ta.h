@@ -17,7 +17,7 @@
  *     (the host reads a device flag once per chunk of iterations).  Kernel-
  *     level calls (ta_spmv, ta_transpose, ...) return after enqueueing.
  *   - Workspace is taken with stream-ordered hipMallocAsync inside the call
- *     and released before return.
+ *     and released before return (cta_solve_plan_noalloc excepted).
  *   - Return value: 0 on success, a negative TA_E* code otherwise (see
  *     ta_strerror).  Not converging is not an error: it is reported in
  *     ta_info.stop.
@@ -96,7 +96,10 @@ typedef struct ta_opts {
     double tol_normal;     /* stop when ||A^T r|| <= tol_normal ||A^T b||; 0 = only A^T r = 0 */
     int32_t t;             /* CTA order, 1..8 and <= m (ignored by ta_solve) */
     int64_t max_iter;      /* iteration budget (>= 0) */
-    int32_t precision;     /* TA_FP64 | TA_FP32 | TA_BF16: precision of the matrix products */
+    int32_t precision;     /* TA_FP64 | TA_FP32 | TA_BF16: precision of the matrix products.
+                              TA_FP32 / TA_BF16 are taken by cta_solve and cta_minnorm (one
+                              shot; see there) and by cta_solve_batched; the plan solvers
+                              and the TA solvers compute in FP64 only (TA_EINVAL) */
     int32_t replace_every; /* recompute r = b - A x every so many iterations; 0 = only at stop */
     int32_t warm_start;    /* cta_solve: 1 = start from the x passed in */
     double rho0;           /* ta_solve: initial radius (Algorithm 3 starts from 0) */
@@ -120,7 +123,7 @@ typedef struct ta_opts {
     double rho_max;        /* ta_solve: > 0 = stop with WITNESS once the radius would grow
                               beyond rho_max (the termination bound section 6 asks for);
                               0 = no bound.  Other solvers: 0 */
-    int32_t enhanced;      /* cta_solve / cta_minnorm: 1 = the enhanced stop of section 3 (for
+    int32_t enhanced;      /* cta_solve / cta_minnorm: 1 = the enhanced stop of section 3.2 (for
                               t >= 2): in every iteration of order t >= 2 the j-fold first-order
                               iterates f_j = F_1(f_{j-1}), f_0 = r, j = 1..t-1, are also tested,
                               and the first with ||A^T f_j|| <= tol_normal ||A^T b|| (||A f_j||
@@ -141,7 +144,7 @@ typedef struct ta_opts {
                               other solvers */
     double accel;          /* cta_solve / cta_minnorm: theta in (0, 1) = the convex-combination
                               step of the theorem on the dynamics of first-order CTA (section
-                              3): after each step, if ||r_{k+1}|| >= theta ||r_k||, the iterate
+                              3.4): after each step, if ||r_{k+1}|| >= theta ||r_k||, the iterate
                               becomes a r_k + (1 - a) r_{k+1} (and the same combination of x,
                               or y) with a = rho / (rho + 1), rho = ||r_{k+1}|| / ||r_k||, the
                               weight that makes the combination an eigenvector on a critical
@@ -174,6 +177,14 @@ typedef struct ta_info {
  *             k = 0 .. min(iters, hist_cap - 1) (recurrence residual).
  *   info    : host, filled on return.
  * b = 0 returns x = 0, iters = 0, stop = RESIDUAL.
+ * opts->precision TA_FP32 / TA_BF16: the Krylov chain's products use FP32 (or
+ * BF16) copies of A and A^T and FP32 vectors, while the Gram entries, the
+ * step, x and every true-residual check stay FP64; the call runs the batched
+ * engine on this one system and one right-hand side (cta_solve_batched), so
+ * the true residual replaces the recurrence after every chunk of iterations
+ * and the solve stops only at a chunk's end.  hist is not written in that
+ * form, and warm_start, replace_every, h_mode, t_cycle, enhanced and accel
+ * must be 0 (TA_EINVAL otherwise).
  */
 int cta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
               int64_t hist_cap, ta_info *info, void *stream);
@@ -301,10 +312,14 @@ int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, cons
  * low-precision copies of the values.  The plan copies A's values, so A may
  * change or be freed afterwards.  Totals (sum of m_s, sum of n_s, and for
  * CSR sum of nnz_s) must stay below 2^31.  Dense systems are stored with rows
- * padded to a multiple of 16 and run their products on the matrix cores
- * (MFMA: FP64 16x16x4 in FP64, FP32 16x16x4 in TA_FP32, BF16 16x16x16 with
- * FP32 accumulation in TA_BF16, where the vector entries are rounded to BF16
- * too); their FP64 products are plain (not compensated) sums.
+ * padded to a multiple of 16 and run their low-precision products on the
+ * matrix cores (MFMA: FP32 16x16x4 in TA_FP32, BF16 16x16x16 with FP32
+ * accumulation in TA_BF16, where the vector entries are rounded to BF16 too;
+ * the FP64 true residuals of those solves use FP64 16x16x4, plain sums).  A
+ * dense plan also holds the systems as CSR with every entry stored (when the
+ * entries fit the CSR limits, sum below 2^31): FP64 solves (opts->precision
+ * TA_FP64, on any dense plan) run there, with compensated sums like every
+ * CSR plan.
  *
  * cta_solve_batched runs Algorithm 1 (CTA, H = A_s A_s^T) independently for
  * every (system s, right-hand side c), all advanced together:
@@ -318,18 +333,20 @@ int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, cons
  *   minnorm : 1 = the y-form of cta_minnorm (x = A^T y), 0 = the x-form;
  *   info : host, sum k_s entries, system-major (s, then c): iterations, products,
  *          stop code, FP64 true relative residual, normal-equation residual.
- * TA_FP64 on CSR systems: each (s, c) follows exactly the single-right-hand-
- * side iteration (same iteration count and stop code as cta_solve /
- * cta_minnorm on that column); on dense systems it follows it up to the
- * rounding of the plain matrix-core sums.  TA_FP32 / TA_BF16: products of the Krylov chain use the low
+ * TA_FP64: each (s, c) follows exactly the single-right-hand-side iteration
+ * (same iteration count and stop code as cta_solve / cta_minnorm on that
+ * column), on CSR and on dense plans.  TA_FP32 / TA_BF16: products of the Krylov chain use the low
  * precision copies and FP32 vectors; Gram entries, steps, x (or y) and every
  * true-residual check are FP64, and the true residual replaces the recurrence
  * residual after every chunk (4, 8, 16, 32, then 64 iterations with TA_FP32,
  * 4 then 8 with TA_BF16, unless opts->chunk fixes it); a column can stop only
  * at a chunk's end; stop codes and residuals refer to FP64.
  * Systems are advanced in groups of equal vector width (k_s rounded up to a
- * power of two), one group after another on `stream`; every column keeps its
- * own iteration, so the results do not depend on the grouping.
+ * power of two; low-precision groups further split by row length), the
+ * groups side by side, each on a host thread and a stream of its own that
+ * start after the work already queued on `stream`; the call returns when all
+ * are done.  Every column keeps its own iteration, so the results do not
+ * depend on the grouping.
  */
 typedef struct ta_batch_plan ta_batch_plan;
 

@@ -212,6 +212,8 @@ def make_opts(tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0, w
               rho0=0.0, fixed_rho=False, chunk=0, precision=TA_FP64, graph=True,
               h_is_a=False, t_cycle=False, nonneg=False, rho_max=0.0,
               enhanced=False, normal_eq=False, accel=0.0) -> TaOpts:
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
     return TaOpts(float(tol), float(tol_normal), int(t), int(max_iter), int(precision),
                   int(replace_every), int(bool(warm_start)), float(rho0), int(bool(fixed_rho)),
                   int(chunk), 0 if graph else 1, 1 if h_is_a else 0, 1 if t_cycle else 0,

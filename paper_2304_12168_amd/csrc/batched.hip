@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <condition_variable>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <type_traits>
@@ -1035,6 +1036,28 @@ __global__ __launch_bounds__(kBlock) void k_bfold(X *d, double *f,
     }
 }
 
+// F = D (in FP64), D = 0 over a table's rows, for the systems whose
+// accumulator D took updates since the last fold.
+template <typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_bmove(X *d, double *f,
+                                                   const BRange *__restrict__ blocks,
+                                                   Groups gs) {
+    constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
+    const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1 || !gs.dirty[br.sys]) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane % KL, rsub = lane / KL, c0 = cl * CV;
+    double z[CV] = {};
+    for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+         it = brow_next(br, R, wave, rsub, it)) {
+        const int64_t e = (int64_t)it.row * K + c0;
+        double dv[CV];
+        vld<X, CV>(d + e, dv);
+        vst<double, CV>(f + e, dv);
+        vst<X, CV>(d + e, z);
+    }
+}
+
 // D = 0 over a table's rows, for the systems whose accumulator took updates.
 template <typename X, int K>
 __global__ __launch_bounds__(kBlock) void k_bzero(X *d, const BRange *__restrict__ blocks,
@@ -1324,11 +1347,36 @@ struct BatchPlan {
     void *a_low = nullptr, *t_low = nullptr;
     void *mem = nullptr;
     hipStream_t s_mem = nullptr;
+    // dense batches: the same systems as a CSR plan (every entry stored), on
+    // which FP64 solves run with compensated sums, so that each column follows
+    // the single-right-hand-side iteration exactly; null if the entries do not
+    // fit the CSR limits (FP64 solves then use the FP64 matrix-core sums)
+    std::unique_ptr<BatchPlan> csr64;
 };
 
 static void bplan_free(BatchPlan *P) {
+    if (P->csr64) {
+        bplan_free(P->csr64.get());
+        P->csr64.reset();
+    }
     if (P->mem != nullptr) (void)hipFreeAsync(P->mem, P->s_mem);
     P->mem = nullptr;
+}
+
+// One dense system (m x n, row stride ld) as CSR with every entry stored:
+// row r holds columns 0 .. n-1 in order.
+__global__ __launch_bounds__(kBlock) void k_dense_to_csr(int64_t m, int64_t n,
+                                                          const double *__restrict__ val,
+                                                          int64_t ld, int32_t *rp, int32_t *ci,
+                                                          double *cv) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r <= m; r += stride)
+        rp[r] = (int32_t)(r * n);
+    for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < m * n; k += stride) {
+        const int64_t r = k / n, c = k - r * n;
+        ci[k] = (int32_t)c;
+        cv[k] = val[r * ld + c];
+    }
 }
 
 // Transpose of one dense system: src (m x n, stride lds) -> dst (n x m, stride ldd).
@@ -1433,7 +1481,33 @@ static int bplan_build(int32_t nsys, const ta_mat *A, int32_t precision, hipStre
     P->nnz = nnz;
     if (dense) {
         if (P->M >= INT32_MAX || P->N >= INT32_MAX) return TA_ENOTSUP;
-        return bplan_build_dense(nsys, A, precision, s, P);
+        int rc = bplan_build_dense(nsys, A, precision, s, P);
+        if (rc != TA_OK || nnz >= INT32_MAX) return rc;
+        // the CSR copy for FP64 solves
+        std::vector<ta_mat> cs((size_t)nsys);
+        Workspace tmp(s);
+        std::vector<int32_t *> rps((size_t)nsys), cis((size_t)nsys);
+        std::vector<double *> cvs((size_t)nsys);
+        for (int32_t i = 0; i < nsys; ++i) {
+            tmp.reserve(&rps[i], A[i].m + 1);
+            tmp.reserve(&cis[i], A[i].m * A[i].n);
+            tmp.reserve(&cvs[i], A[i].m * A[i].n);
+        }
+        if ((rc = tmp.commit()) != TA_OK) return rc;
+        for (int32_t i = 0; i < nsys; ++i) {
+            k_dense_to_csr<<<grid_for(std::max<int64_t>(A[i].m * A[i].n, A[i].m + 1)), kBlock, 0,
+                             s>>>(A[i].m, A[i].n, A[i].val, A[i].ld, rps[i], cis[i], cvs[i]);
+            HIP_TRY(hipGetLastError());
+            cs[i] = ta_mat{TA_CSR, A[i].m, A[i].n, A[i].m * A[i].n, 0, rps[i], cis[i], cvs[i]};
+        }
+        std::unique_ptr<BatchPlan> sub(new (std::nothrow) BatchPlan);
+        if (!sub) return TA_ENOMEM;
+        if ((rc = bplan_build(nsys, cs.data(), TA_FP64, s, sub.get())) != TA_OK) {
+            bplan_free(sub.get());
+            return rc;
+        }
+        P->csr64 = std::move(sub);
+        return TA_OK;
     }
     if (P->M >= INT32_MAX || P->N >= INT32_MAX || nnz >= INT32_MAX) return TA_ENOTSUP;
     const int64_t M = P->M, N = P->N, mx = std::max(M, N);
@@ -1981,11 +2055,15 @@ struct Engine {
                 if (minnorm) {
                     if (na > 0) k_bfold<X, K><<<na, kBlock, 0, cs>>>(D, Y, d_ta, gs, 1);
                 } else {
-                    // x += A^T Z (the chunk's increment), Z = 0
-                    prod<V, X, K, kBNorm>(P, 1, D, W[0], nullptr, d_tt, nt, gs, partials, cap,
-                                          1, kBDirty, Lt, cs, DS);
-                    if (nt > 0) k_bfold<X, K><<<nt, kBlock, 0, cs>>>(W[0], Xc, d_tt, gs, 0);
-                    if (na > 0) k_bzero<X, K><<<na, kBlock, 0, cs>>>(D, d_ta, gs);
+                    // x += A^T Z (the chunk's increment), Z = 0.  The product
+                    // is the FP64 one: with the low-precision A^T the increment
+                    // would leave range(A^T) by the values' rounding, and the
+                    // x-form would lose its minimum-norm limit (Theorem 1 (4))
+                    // on systems with a null space
+                    if (na > 0) k_bmove<X, K><<<na, kBlock, 0, cs>>>(D, RT, d_ta, gs);
+                    prod<double, double, K, kBNorm>(P, 1, RT, TN, nullptr, d_tt, nt, gs,
+                                                    partials, cap, 1, kBDirty, Lt64, cs, DS);
+                    if (nt > 0) k_bfold<double, K><<<nt, kBlock, 0, cs>>>(TN, Xc, d_tt, gs, 0);
                 }
                 k_bdirty_clear<<<1, kBlock, 0, cs>>>(gs);
             }
@@ -2147,6 +2225,8 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         return TA_EINVAL;  // batched: CTA with H = A A^T and a fixed t
     if (minnorm && o->warm_start) return TA_EINVAL;
     if (o->precision != TA_FP64 && o->precision != P.precision) return TA_EINVAL;
+    if (P.dense && o->precision == TA_FP64 && P.csr64)
+        return solve_batched(*P.csr64, nrhs, B, Xo, o, minnorm, info, s);
     int32_t kmax = 0;
     for (int32_t i = 0; i < P.nsys; ++i) {
         if (nrhs[i] < 0 || nrhs[i] > kMaxK) return TA_EINVAL;
@@ -2398,8 +2478,10 @@ int ta_batch_time_spmm(const ta_batch_plan *plan, int32_t K, int32_t trans, int3
                        int32_t reps, double *avg_ms, void *stream) {
     if (plan == nullptr || avg_ms == nullptr || reps < 1) return TA_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const ta::bt::BatchPlan &P = plan->p;
-    if (precision != TA_FP64 && precision != P.precision) return TA_EINVAL;
+    const ta::bt::BatchPlan &P0 = plan->p;
+    if (precision != TA_FP64 && precision != P0.precision) return TA_EINVAL;
+    // FP64 on a dense plan: the kernel its solves run, on the CSR copy
+    const ta::bt::BatchPlan &P = (P0.dense && precision == TA_FP64 && P0.csr64) ? *P0.csr64 : P0;
     switch (precision) {
         case TA_FP32: return ta::bt::time_spmm<float, float>(P, K, trans, reps, avg_ms, s);
         case TA_BF16: return ta::bt::time_spmm<uint16_t, float>(P, K, trans, reps, avg_ms, s);

@@ -65,7 +65,15 @@ static int validate_opts(const ta_mat *A, const ta_opts *o, int solver) {
         return TA_EINVAL;
     if (!(o->rho_max >= 0.0) || !isfinite(o->rho_max) || (o->rho_max > 0.0 && solver != 2))
         return TA_EINVAL;
-    if (o->precision != TA_FP64) return TA_EINVAL;  // the solver chains compute in FP64
+    // FP32 / BF16 products: one-shot CTA only (run on the batched engine, which
+    // refines in FP64 at fixed chunk ends), without the per-iteration options
+    if (o->precision != TA_FP64) {
+        if (o->precision != TA_FP32 && o->precision != TA_BF16) return TA_EINVAL;
+        if (solver != 0 && solver != 1) return TA_EINVAL;
+        if (o->warm_start || o->replace_every || o->h_mode || o->t_cycle || o->enhanced ||
+            o->accel != 0.0)
+            return TA_EINVAL;
+    }
     if (solver == 0 || solver == 1) {
         if (o->t < 1 || o->t > kTMax) return TA_EINVAL;
         if (A->m > 0 && o->t > A->m) return TA_EINVAL;
@@ -457,7 +465,7 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     const ta_mat *M = &P.desc;
     int rc = check_solve_args(M, b, x, o, hist, hist_cap, info, minnorm ? 1 : 0);
     if (rc != TA_OK) return rc;
-    if (!P.has_t) return TA_EINVAL;
+    if (!P.has_t || o->precision != TA_FP64) return TA_EINVAL;  // a plan holds FP64 only
     const int64_t m = M->m, n = M->n;
     const int t = o->t;
     if (m == 0) return solve_empty(M, x, hist, hist_cap, info, 0.0, s);
@@ -991,12 +999,41 @@ struct ta_plan {
 // ---------------------------------------------------------------------------
 extern "C" {
 
+#define HIP_TRY_C(call)                                        \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return ta::hip_fail(e_, #call);  \
+    } while (0)
+
+// FP32 / BF16 products for one system: the batched engine on a one-system
+// plan with one right-hand side (x stays FP64; no history is written).
+static int cta_mixed_one(const ta_mat *A, const double *b, double *x, const ta_opts *opts,
+                         ta_info *info, void *stream, int32_t minnorm) {
+    if (A->m == 0 || A->n == 0) {  // nothing to iterate: x = 0
+        hipStream_t s = (hipStream_t)stream;
+        if (A->n > 0) HIP_TRY_C(hipMemsetAsync(x, 0, sizeof(double) * (size_t)A->n, s));
+        HIP_TRY_C(hipStreamSynchronize(s));
+        info->stop = TA_STOP_RESIDUAL;
+        return TA_OK;
+    }
+    ta_batch_plan *bp = nullptr;
+    int rc = ta_batch_plan_create(1, A, opts->precision, &bp, stream);
+    if (rc != TA_OK) return rc;
+    const int32_t k = 1;
+    const double *B[1] = {b};
+    double *X[1] = {x};
+    rc = cta_solve_batched(bp, &k, B, X, opts, minnorm, info, stream);
+    const int rd = ta_batch_plan_destroy(bp);
+    return rc != TA_OK ? rc : rd;
+}
+
 int cta_solve(const ta_mat *A, const double *b, double *x, const ta_opts *opts, double *hist,
               int64_t hist_cap, ta_info *info, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     if (info == nullptr) return TA_EINVAL;
     int rc = ta::check_solve_args(A, b, x, opts, hist, hist_cap, info, 0);
     if (rc != TA_OK) return rc;
+    if (opts->precision != TA_FP64) return cta_mixed_one(A, b, x, opts, info, stream, 0);
     return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
         return ta::cta_run(P, b, x, opts, hist, hist_cap, info, s, false);
     }, true);
@@ -1008,6 +1045,7 @@ int cta_minnorm(const ta_mat *A, const double *b, double *x, const ta_opts *opts
     if (info == nullptr) return TA_EINVAL;
     int rc = ta::check_solve_args(A, b, x, opts, hist, hist_cap, info, 1);
     if (rc != TA_OK) return rc;
+    if (opts->precision != TA_FP64) return cta_mixed_one(A, b, x, opts, info, stream, 1);
     return ta::with_plan(A, true, s, [&](const ta::Plan &P) {
         return ta::cta_run(P, b, x, opts, hist, hist_cap, info, s, true);
     }, true);

@@ -34,7 +34,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_strerror(lib):
-    for code in (0, -1, -2, -3, -4, -99):
+    for code in (0, -1, -2, -3, -4, -5, -99):
         assert isinstance(lib.ta_strerror(code), bytes)
 
 
@@ -111,3 +111,22 @@ def test_validate_variant_options(lib):
     o = P.make_opts(t=3)
     o.launch_mode = 2
     assert lib.ta_validate(ctypes.byref(sq), ctypes.byref(o), 0) == -1
+
+
+def test_validate_precision_per_solver(lib):
+    """FP32 / BF16 products are a CTA option (one-shot solves and batched);
+    TA computes in FP64 only; the per-iteration CTA options need FP64."""
+    d = _csr_desc()
+    for prec in (P.TA_FP32, P.TA_BF16, "fp32", "bf16"):
+        assert P.validate(d, 0, t=3, precision=prec) == 0
+        assert P.validate(d, 1, t=3, precision=prec) == 0
+        assert P.validate(d, 2, precision=prec) == -1
+        for kw in (dict(warm_start=True), dict(replace_every=4), dict(t_cycle=True),
+                   dict(enhanced=True), dict(accel=0.5)):
+            assert P.validate(d, 0, t=3, precision=prec, **kw) == -1, kw
+    assert P.validate(_csr_desc(m=8, n=8), 0, t=3, precision="fp32", h_is_a=True) == -1
+
+
+def test_strerror_of_every_code(lib):
+    for code, name in P.ERRORS.items():
+        assert lib.ta_strerror(code).decode() != "unknown error", name

@@ -101,11 +101,12 @@ def test_mixed_precision_reaches_fp64_tolerance(prec, minnorm):
         # the FP64 true residual of x itself
         r = Bm[:, c] - p.A.to_scipy() @ xg[:, c]
         assert np.linalg.norm(r) <= tol * np.linalg.norm(Bm[:, c]) * (1 + 1e-6)
-        if minnorm:
-            xo, _, io = run(p.A, Bm[:, c], tol=tol, t=3, max_iter=2000)
-            # both are within tol of the minimum-norm solution's residual;
-            # on range(A^T) the map is well conditioned here
-            assert np.linalg.norm(xg[:, c] - xo) <= 1e-6 * np.linalg.norm(xo)
+        # both forms keep x in range(A^T) (the x-form folds A^T Z into x), so
+        # both converge to the minimum-norm solution, as the FP64 oracle does;
+        # on range(A^T) the map is well conditioned here
+        xo, _, io = run(p.A, Bm[:, c], tol=tol, t=3, max_iter=2000)
+        assert io.stop == "residual"
+        assert np.linalg.norm(xg[:, c] - xo) <= 1e-6 * np.linalg.norm(xo), c
     plan.close()
 
 
@@ -152,13 +153,12 @@ def test_uneven_batch_full_size_sampled():
     right-hand sides each (about 8.5e3 columns).
 
     FP64, two iterations: sampled columns equal the oracle's.  FP32 products
-    with FP64 refinement, 400 iterations: every column reported converged has
-    an FP64 true relative residual <= 1e-6, recomputed here on the host from
-    the returned x; at least 98% of the random-system columns converge (the
-    stencil systems need far more iterations than any budget here, with
-    H = A A^T); and on sampled columns the FP64 oracle converges to an x whose
-    difference d from the GPU x satisfies ||A d|| <= 2e-6 ||b|| + rounding (both
-    residuals are <= 1e-6 ||b||)."""
+    with FP64 refinement (the benchmark's x-form), 1600 iterations: every
+    column reported converged has relative residual <= 1e-6, every column of
+    the random systems converges (the stencil systems need far more iterations
+    than any budget here, with H = A A^T), and on every column of sampled
+    random systems x agrees with the FP64 oracle's x within 1e-6 relative and
+    within the rigorous a-posteriori bound of diagonal dominance."""
     import scipy.sparse  # noqa: F401  (the Csr helper converts through it)
 
     bt = _uneven(256, 1024, 65536, 64, seed=0)
@@ -176,35 +176,46 @@ def test_uneven_batch_full_size_sampled():
         assert ig.rel_res == pytest.approx(io.rel_res, rel=1e-8)
     plan.close()
     del X
-    budget = 400
+    # FP32 products with FP64 refinement (the configuration the benchmark
+    # times), with a budget every random column meets (the slowest need
+    # about 1.2e3 iterations; the median is about 110)
+    budget = 1600
     plan = P.BatchPlan(bt.systems, "fp32")
     X, infos = P.cta_solve_batched(plan, bt.B, tol=1e-6, t=3, max_iter=budget, precision="fp32")
-    n_rand = n_conv = 0
     for s, kind in enumerate(bt.kinds):
-        for i in infos[s]:
-            assert i.stop in ("residual", "maxiter"), (s, i)
+        for c, i in enumerate(infos[s]):
+            assert i.stop in ("residual", "maxiter"), (s, c, i)
             if i.stop == "residual":
-                assert i.rel_res <= 1e-6, (s, i)
+                assert i.rel_res <= 1e-6, (s, c, i)
             if kind == "random":
-                n_rand += 1
-                n_conv += i.stop == "residual"
-    assert n_conv >= 0.98 * n_rand, (n_conv, n_rand)
-    rand = [s for s, kind in enumerate(bt.kinds) if kind == "random"]
-    for s in rng.choice(rand, size=6, replace=False):
+                assert i.stop == "residual", (s, c, i)
+    # every column of sampled random systems against the FP64 oracle:
+    #  - the FP64 true residual of the returned x, recomputed on the host;
+    #  - x within 1e-6 relative of the oracle's x (mixed-mode bar);
+    #  - a rigorous a-posteriori bound: the rows are diagonally dominant with
+    #    gap g = min_i (|a_ii| - sum_{j != i} |a_ij|) > 0, so ||A^-1||_inf <=
+    #    1 / g (Varah) and ||x - x_o||_inf <= ||r - r_o||_inf / g
+    rand = [s for s, kind in enumerate(bt.kinds)
+            if kind == "random" and bt.B[s].shape[1] <= 12 and bt.systems[s].n <= 40000]
+    worst = 0.0
+    for s in rng.choice(rand, size=4, replace=False):
         a, b = bt.systems[s], bt.B[s]
         sp = a.to_scipy()
         xg = host(X[s])
+        diag = np.abs(sp.diagonal())
+        gap = np.min(2 * diag - np.asarray(abs(sp).sum(axis=1)).ravel())
+        assert gap > 0
         for c in range(b.shape[1]):
-            if infos[s][c].stop == "residual":
-                rr = np.linalg.norm(b[:, c] - sp @ xg[:, c]) / np.linalg.norm(b[:, c])
-                assert rr <= 1e-6 * (1 + 1e-6), (s, c, rr)
-        c = int(rng.integers(b.shape[1]))
-        xo, ho, io = oracle.cta(a, b[:, c], tol=1e-6, t=3, max_iter=budget)
-        if io.stop == "residual" and io.iters <= budget // 2:
-            assert infos[s][c].stop == "residual", (s, c, infos[s][c], io)
-        if io.stop == infos[s][c].stop == "residual":
-            d = sp @ (xg[:, c] - xo)
-            assert np.linalg.norm(d) <= (2e-6 + 1e-12) * np.linalg.norm(b[:, c]), (s, c)
+            r = b[:, c] - sp @ xg[:, c]
+            assert np.linalg.norm(r) <= 1e-6 * (1 + 1e-6) * np.linalg.norm(b[:, c]), (s, c)
+            xo, _, io = oracle.cta(a, b[:, c], tol=1e-6, t=3, max_iter=budget, hist_cap=1)
+            assert io.stop == "residual", (s, c, io)
+            ro = b[:, c] - sp @ xo
+            err = np.linalg.norm(xg[:, c] - xo) / np.linalg.norm(xo)
+            worst = max(worst, err)
+            assert err <= 1e-6, (s, c, err)
+            assert np.max(np.abs(xg[:, c] - xo)) <= np.max(np.abs(r - ro)) / gap * (1 + 1e-9)
+    print(f"mixed x-form vs FP64 oracle: largest relative x difference {worst:.2e}")
     plan.close()
 
 
@@ -227,9 +238,9 @@ def _dense_systems(seed=5):
 
 @pytest.mark.parametrize("minnorm", [False, True], ids=["x_form", "y_form"])
 def test_dense_batched_fp64_matches_oracle(minnorm):
-    """FP64 matrix-core products are plain sums, so they agree with the
-    oracle's compensated sums to rounding: equal stop codes, iteration counts
-    within one, x within 1e-9 relative."""
+    """FP64 solves on a dense batch run on the plan's CSR copy with
+    compensated sums, so every column follows the oracle's iteration: equal
+    stop codes, iteration and product counts, x within 1e-10 relative."""
     A, B, ks = _dense_systems()
     plan = P.BatchPlan(A, "fp64")
     assert plan.dense
@@ -242,9 +253,24 @@ def test_dense_batched_fp64_matches_oracle(minnorm):
         for c in range(ks[s]):
             xo, ho, io = run(a, b[:, c], tol=tol, t=t, max_iter=3000, tol_normal=1e-10)
             ig = infos[s][c]
-            assert ig.stop == io.stop, (s, c, ig, io)
-            assert abs(ig.iters - io.iters) <= 1, (s, c, ig, io)
-            assert np.linalg.norm(xg[:, c] - xo) <= 1e-9 * max(np.linalg.norm(xo), 1e-300), (s, c)
+            assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), (s, c, ig, io)
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-10 * max(np.linalg.norm(xo), 1e-300), (s, c)
+            assert ig.rel_res == pytest.approx(io.rel_res, rel=1e-8, abs=1e-300)
+    plan.close()
+
+
+def test_dense_batched_fp64_inside_a_mixed_plan():
+    """A dense plan made for FP32 products still solves in FP64 on request,
+    on the same CSR copy: the same counts as the oracle."""
+    A, B, ks = _dense_systems(seed=4)
+    plan = P.BatchPlan(A, "fp32")
+    X, infos = P.cta_solve_batched(plan, B, tol=1e-8, t=2, max_iter=3000, precision="fp64")
+    for s, (a, b) in enumerate(zip(A, B)):
+        for c in range(ks[s]):
+            xo, _, io = oracle.cta(a, b[:, c], tol=1e-8, t=2, max_iter=3000)
+            ig = infos[s][c]
+            assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), (s, c)
+            assert np.linalg.norm(host(X[s])[:, c] - xo) <= 1e-10 * np.linalg.norm(xo)
     plan.close()
 
 
