@@ -341,9 +341,11 @@ int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, cons
  * residual after every chunk (4, 8, 16, 32, then 64 iterations with TA_FP32,
  * 4 then 8 with TA_BF16, unless opts->chunk fixes it); a column can stop only
  * at a chunk's end; stop codes and residuals refer to FP64.
- * Systems are advanced in groups of equal vector width (k_s rounded up to a
- * power of two; low-precision groups further split by row length), the
- * groups side by side, each on a host thread and a stream of its own that
+ * Systems are advanced in groups of equal vector width, a power of two: a
+ * system's k_s columns form one piece (k_s rounded up to a power of two) or,
+ * when that would pad more than a quarter, two (the widest power of two
+ * K1 <= k_s and the rest, rounded up); low-precision groups are further split
+ * by row length.  The groups run side by side, each on a host thread and a stream of its own that
  * start after the work already queued on `stream`; the call returns when all
  * are done.  Every column keeps its own iteration, so the results do not
  * depend on the grouping.

@@ -2205,6 +2205,13 @@ static int run_k(int K, const BatchPlan &P, const int32_t *nrhs, const double *c
     }
 }
 
+// Cut a system's right-hand sides into two power-of-two pieces (see
+// solve_batched); 0 = one piece padded to the next power of two.
+#ifndef TA_SPLIT_COLUMNS
+#define TA_SPLIT_COLUMNS 1
+#endif
+constexpr int kSplitColumns = TA_SPLIT_COLUMNS;
+
 static int kwidth(int32_t k) {
     int K = 1;
     while (K < k) K <<= 1;
@@ -2238,29 +2245,77 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         kmax = std::max(kmax, nrhs[i]);
     }
     if (kmax == 0) return TA_OK;
-    // Systems are run in groups of equal vector width K (the power of two
-    // covering their right-hand-side count), so that a system with few
-    // right-hand sides does not stream K - k padding columns.  (Cutting wide
-    // counts further into power-of-two pieces, e.g. 40 = 32 + 8, streams fewer
-    // padding columns but measured slower: every extra group repeats the
-    // whole iteration sequence.)  The groups (and their parts, below) run
-    // side by side, each on its own host thread and stream, after everything
-    // queued on s.
+    // Systems are run in groups of equal vector width K (a power of two), so
+    // that a system with few right-hand sides does not stream K - k padding
+    // columns.  A system's k columns are cut into at most two pieces: the
+    // widest power of two K1 <= k, and the rest k - K1 in the group of the
+    // power of two covering it, when that is narrower than K1 (40 = 32 + 8,
+    // 44 = 32 + 12 -> 16 wide; 56 stays one piece of 64).  Padding is then
+    // below a quarter of the columns instead of up to half; the price is one
+    // more pass over the system's matrix per product, cheap beside the vector
+    // blocks at these widths.  Columns are
+    // contiguous in the column-major B and X, so a piece is a pointer offset.
+    // The groups (and their parts, below) run side by side, each on its own
+    // host thread and stream, after everything queued on s.
     std::vector<int64_t> off(P.nsys);
     int64_t acc = 0;
     for (int32_t i = 0; i < P.nsys; ++i) {
         off[i] = acc;
         acc += nrhs[i];
     }
-    std::vector<int> widths;
-    std::vector<std::vector<int32_t>> parts;
-    for (int K = 1; K <= kwidth(kmax); K <<= 1) {
-        std::vector<int32_t> part(P.nsys);
-        bool any = false;
-        for (int32_t i = 0; i < P.nsys; ++i) {
-            part[i] = (nrhs[i] > 0 && kwidth(nrhs[i]) == K) ? nrhs[i] : 0;
-            any = any || part[i] > 0;
+    struct Piece {
+        int32_t c0 = 0, k = 0;  // first column and width of the system's piece in a group
+    };
+    // pieces[K][s]
+    std::vector<std::vector<Piece>> pieces(8, std::vector<Piece>(P.nsys));
+    auto log2i = [](int K) {
+        int l = 0;
+        while ((1 << l) < K) ++l;
+        return l;
+    };
+    for (int32_t i = 0; i < P.nsys; ++i) {
+        const int32_t k = nrhs[i];
+        if (k <= 0) continue;
+        int32_t K1 = 1;
+        while (2 * K1 <= k) K1 <<= 1;
+        // a rest wider than K1 / 2 pads to K1 itself: then one piece of 2 K1
+        if (K1 == k || !kSplitColumns || kwidth(k - K1) == K1) {
+            pieces[log2i(kwidth(k))][i] = Piece{0, k};
+        } else {
+            pieces[log2i(K1)][i] = Piece{0, K1};
+            pieces[log2i(kwidth(k - K1))][i] = Piece{K1, k - K1};
         }
+    }
+    struct GroupArgs {
+        int K;
+        std::vector<int32_t> nrhs;
+        std::vector<const double *> B;
+        std::vector<double *> X;
+        std::vector<int64_t> off;
+    };
+    std::vector<GroupArgs> groups;
+    auto add_group = [&](int K, const std::vector<Piece> &pc, const std::vector<uint8_t> &take) {
+        GroupArgs ga;
+        ga.K = K;
+        ga.nrhs.assign(P.nsys, 0);
+        ga.B.assign(P.nsys, nullptr);
+        ga.X.assign(P.nsys, nullptr);
+        ga.off.assign(P.nsys, 0);
+        for (int32_t i = 0; i < P.nsys; ++i) {
+            if (!take[i] || pc[i].k == 0) continue;
+            const int64_t m = P.ro[i + 1] - P.ro[i], n = P.co[i + 1] - P.co[i];
+            ga.nrhs[i] = pc[i].k;
+            ga.B[i] = B[i] + (int64_t)pc[i].c0 * m;
+            ga.X[i] = Xo[i] + (int64_t)pc[i].c0 * n;
+            ga.off[i] = off[i] + pc[i].c0;
+        }
+        groups.push_back(std::move(ga));
+    };
+    for (int l = 0; (1 << l) <= kwidth(kmax); ++l) {
+        const int K = 1 << l;
+        const std::vector<Piece> &pc = pieces[l];
+        bool any = false;
+        for (int32_t i = 0; i < P.nsys; ++i) any = any || pc[i].k > 0;
         if (!any) continue;
         // low-precision chains: each group split once more by row length,
         // systems whose rows fit one round of the SpMM's gathers (at most
@@ -2270,48 +2325,42 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         // neither waits for the other's iteration count.  (The FP64 chain,
         // 4 nonzeros per round, measured slower split this way.)
         if (o->precision == TA_FP64) {
-            widths.push_back(K);
-            parts.push_back(std::move(part));
+            add_group(K, pc, std::vector<uint8_t>(P.nsys, 1));
             continue;
         }
-        std::vector<int32_t> pa(P.nsys, 0), pb(P.nsys, 0);
+        std::vector<uint8_t> ta(P.nsys, 0), tb(P.nsys, 0);
         bool ha = false, hb = false;
         for (int32_t i = 0; i < P.nsys; ++i) {
-            if (part[i] == 0) continue;
+            if (pc[i].k == 0) continue;
             const int64_t rows = P.ro[i + 1] - P.ro[i];
             const int64_t nz = P.dense ? rows * (P.co[i + 1] - P.co[i])
                                        : (int64_t)P.h_arp[P.ro[i + 1]] - P.h_arp[P.ro[i]];
             if (nz <= kRoundNnz * rows) {
-                pa[i] = part[i];
+                ta[i] = 1;
                 ha = true;
             } else {
-                pb[i] = part[i];
+                tb[i] = 1;
                 hb = true;
             }
         }
-        if (ha) {
-            widths.push_back(K);
-            parts.push_back(std::move(pa));
-        }
-        if (hb) {
-            widths.push_back(K);
-            parts.push_back(std::move(pb));
-        }
+        if (ha) add_group(K, pc, ta);
+        if (hb) add_group(K, pc, tb);
     }
     auto run_group = [&](size_t j, hipStream_t gsm, GroupSync *g) -> int {
+        const GroupArgs &ga = groups[j];
         switch (o->precision) {
             case TA_FP32:
-                return run_k<float, float>(widths[j], P, parts[j].data(), B, Xo, o, minnorm, info,
-                                           off.data(), gsm, g);
+                return run_k<float, float>(ga.K, P, ga.nrhs.data(), ga.B.data(), ga.X.data(), o,
+                                           minnorm, info, ga.off.data(), gsm, g);
             case TA_BF16:
-                return run_k<uint16_t, float>(widths[j], P, parts[j].data(), B, Xo, o, minnorm,
-                                              info, off.data(), gsm, g);
+                return run_k<uint16_t, float>(ga.K, P, ga.nrhs.data(), ga.B.data(), ga.X.data(),
+                                              o, minnorm, info, ga.off.data(), gsm, g);
             default:
-                return run_k<double, double>(widths[j], P, parts[j].data(), B, Xo, o, minnorm,
-                                             info, off.data(), gsm, g);
+                return run_k<double, double>(ga.K, P, ga.nrhs.data(), ga.B.data(), ga.X.data(),
+                                             o, minnorm, info, ga.off.data(), gsm, g);
         }
     };
-    const size_t ng = widths.size();
+    const size_t ng = groups.size();
     if (ng == 1) return run_group(0, s, nullptr);
     struct Streams {
         std::vector<hipStream_t> v;
