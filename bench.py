@@ -96,6 +96,20 @@ def kwidth(k: int) -> int:
     return K
 
 
+def column_pieces(k: int):
+    """[(K, width)]: how the batched solve splits a system's k right-hand
+    sides into width groups (the widest power of two K1 <= k and the rest,
+    when the rest rounds up to less than K1; else one piece of kwidth(k))."""
+    if k <= 0:
+        return []
+    K1 = 1
+    while 2 * K1 <= k:
+        K1 *= 2
+    if K1 == k or kwidth(k - K1) == K1:
+        return [(kwidth(k), k)]
+    return [(K1, K1), (kwidth(k - K1), k - K1)]
+
+
 def batched_uneven_bench(args, P, torch, dev, pool=None):
     import numpy as np
 
@@ -163,9 +177,11 @@ def batched_uneven_bench(args, P, torch, dev, pool=None):
     step_bytes = 0
     for s, inf in enumerate(runs[-1]):
         a = bt.systems[s]
-        if not inf:
-            continue
-        step_bytes += max(i.iters for i in inf) * 2 * t * (a.nnz * (vbs + 4) + 4 * (a.m + 1))
+        c0 = 0
+        for _, w in column_pieces(len(inf)):  # each piece reads the matrix on its own
+            step_bytes += (max(i.iters for i in inf[c0:c0 + w]) * 2 * t *
+                           (a.nnz * (vbs + 4) + 4 * (a.m + 1)))
+            c0 += w
         step_bytes += sum(i.iters for i in inf) * 2 * t * 2 * a.m * xbs
     log(f"[bench] mixed+batched ({args.precision}): {ms_per_step:.1f} ms per step, "
         f"{conv // args.steps} of {ncols} columns converged per step, {value:.1f} columns/s")
@@ -213,54 +229,66 @@ def batched_uneven_bench(args, P, torch, dev, pool=None):
     log(f"[bench] FP64 plain: {len(pick)} sampled columns in {plain_s:.2f} s, "
         f"{plain_conv} converged: {plain_rate:.1f} columns/s")
 
-    # dominant kernel: the SpMM of the widest group (K = 64), A and A^T passes,
-    # launched as the solve launches it: the library runs a group's low-precision
-    # chain in two parts, systems with at most 6 nonzeros per row on average (one
-    # round of the kernel's gathers) and the rest, so each part is timed on a
-    # plan over exactly its systems and a product of the group is one launch of
-    # each part
-    Kd = max(kwidth(k) for k in ks)
-    grp = [s for s, k in enumerate(ks) if kwidth(k) == Kd]
+    # dominant kernel: the SpMM of the width group whose product takes longest,
+    # A and A^T passes, launched as the solve launches it.  The library cuts a
+    # system's columns into pieces (column_pieces) and runs a group's
+    # low-precision chain in two parts, systems with at most 6 nonzeros per row
+    # on average (one round of the kernel's gathers) and the rest, so each part
+    # is timed on a plan over exactly its systems and a product of the group is
+    # one launch of each part.  Every group is timed and listed.
     split = args.precision != "fp64"
-    parts = [[s for s in grp if bt.systems[s].nnz <= 6 * bt.systems[s].m],
-             [s for s in grp if bt.systems[s].nnz > 6 * bt.systems[s].m]] if split else [grp]
-    parts = [q for q in parts if q]
     vb = {"fp32": 4, "bf16": 2, "fp64": 8}[args.precision]
     xb = 8 if args.precision == "fp64" else 4
-    gm = sum(bt.systems[s].m for s in grp)
-    gnnz = sum(bt.systems[s].nnz for s in grp)
-    part_rows = []
-    for q in parts:
-        gp = P.BatchPlan([systems[s] for s in q], args.precision)
-        qm = sum(bt.systems[s].m for s in q)
-        qnnz = sum(bt.systems[s].nnz for s in q)
-        qa = P.batch_time_spmm(gp, Kd, trans=False, precision=args.precision, reps=args.reps)
-        qt = P.batch_time_spmm(gp, Kd, trans=True, precision=args.precision, reps=args.reps)
-        gp.close()
-        qsys = [bt.systems[s] for s in q]
-        qks = [ks[s] for s in q]
-        qby = group_pass_bytes(qsys, qks, vb, xb)
-        qpad = group_pass_bytes(qsys, qks, vb, xb, K=Kd)
-        part_rows.append({"systems": len(q), "rows": qm, "nnz": qnnz, "columns": sum(qks),
-                          "bytes_per_launch": qby, "padded_bytes_per_launch": qpad,
-                          "A_us": qa * 1e3, "AT_us": qt * 1e3})
-        log(f"[bench] SpMM K={Kd} {args.precision} part of {len(q)} systems ({qnnz / qm:.2f} "
-            f"nonzeros/row, {sum(qks)} columns): A {qa * 1e3:.1f} us, A^T {qt * 1e3:.1f} us, "
-            f"{qby / 1e9:.3f} GB algorithmic ({qpad / 1e9:.3f} GB with padding columns)")
-    ms_a = sum(r["A_us"] for r in part_rows) * 1e-3
-    ms_at = sum(r["AT_us"] for r in part_rows) * 1e-3
-    by = sum(r["bytes_per_launch"] for r in part_rows)
-    by_pad = sum(r["padded_bytes_per_launch"] for r in part_rows)
-    log(f"[bench] SpMM K={Kd} {args.precision} over {len(grp)} systems in {len(parts)} launches: "
-        f"A {ms_a * 1e3:.1f} us, A^T {ms_at * 1e3:.1f} us, {by / 1e9:.3f} GB per product "
-        f"({by_pad / 1e9:.3f} GB with padding)")
+    members = {}
+    for s_, k in enumerate(ks):
+        for K, w in column_pieces(k):
+            members.setdefault(K, []).append((s_, w))
+    groups = []
+    for K in sorted(members, reverse=True):
+        grp = members[K]
+        parts = ([[(s_, w) for s_, w in grp if bt.systems[s_].nnz <= 6 * bt.systems[s_].m],
+                  [(s_, w) for s_, w in grp if bt.systems[s_].nnz > 6 * bt.systems[s_].m]]
+                 if split else [grp])
+        part_rows = []
+        for q in [q for q in parts if q]:
+            gp = P.BatchPlan([systems[s_] for s_, _ in q], args.precision)
+            qa = P.batch_time_spmm(gp, K, trans=False, precision=args.precision, reps=args.reps)
+            qt = P.batch_time_spmm(gp, K, trans=True, precision=args.precision, reps=args.reps)
+            gp.close()
+            qsys = [bt.systems[s_] for s_, _ in q]
+            qks = [w for _, w in q]
+            qm = sum(a.m for a in qsys)
+            qnnz = sum(a.nnz for a in qsys)
+            part_rows.append({"systems": len(q), "rows": qm, "nnz": qnnz, "columns": sum(qks),
+                              "bytes_per_launch": group_pass_bytes(qsys, qks, vb, xb),
+                              "padded_bytes_per_launch": group_pass_bytes(qsys, qks, vb, xb, K=K),
+                              "A_us": qa * 1e3, "AT_us": qt * 1e3})
+        ms_a = sum(r["A_us"] for r in part_rows) * 1e-3
+        ms_at = sum(r["AT_us"] for r in part_rows) * 1e-3
+        by = sum(r["bytes_per_launch"] for r in part_rows)
+        by_pad = sum(r["padded_bytes_per_launch"] for r in part_rows)
+        groups.append({"K": K, "systems": len(grp), "columns": sum(w for _, w in grp),
+                       "A_us": ms_a * 1e3, "AT_us": ms_at * 1e3, "bytes_per_launch": by,
+                       "padded_bytes_per_launch": by_pad,
+                       "frac": by / (max(ms_a, ms_at) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                       "parts": part_rows})
+        log(f"[bench] SpMM K={K} {args.precision}: {len(grp)} systems, "
+            f"{sum(w for _, w in grp)} columns, {len(part_rows)} launches: A {ms_a * 1e3:.1f} us, "
+            f"A^T {ms_at * 1e3:.1f} us, {by / 1e9:.3f} GB algorithmic "
+            f"({by_pad / 1e9:.3f} GB with padding), frac {groups[-1]['frac']:.3f}")
+    dom = max(groups, key=lambda g_: max(g_["A_us"], g_["AT_us"]))
+    Kd, part_rows = dom["K"], dom["parts"]
+    ms_a, ms_at = dom["A_us"] * 1e-3, dom["AT_us"] * 1e-3
+    by, by_pad = dom["bytes_per_launch"], dom["padded_bytes_per_launch"]
+    gm = sum(r["rows"] for r in part_rows)
+    gnnz = sum(r["nnz"] for r in part_rows)
     trans = ms_at > ms_a
     kms = max(ms_a, ms_at)
     orient = "AT" if trans else "A"
     mt = measured_traffic()
     traffic = None
-    if all((args.precision, Kd, orient, i) in mt for i in range(len(parts))):
-        traffic = sum(mt[(args.precision, Kd, orient, i)] for i in range(len(parts)))
+    if all((args.precision, Kd, orient, i) in mt for i in range(len(part_rows))):
+        traffic = sum(mt[(args.precision, Kd, orient, i)] for i in range(len(part_rows)))
 
     cpu = None
     x_err = None
@@ -291,15 +319,17 @@ def batched_uneven_bench(args, P, torch, dev, pool=None):
         "roofline": {
             "bound": "hbm",
             "kernel": f"k_bspmm<{args.precision}, K={Kd}> {'A^T' if trans else 'A'} product over "
-                      f"the {len(grp)} systems with {Kd // 2 + 1}-{Kd} right-hand sides "
-                      f"({gm} rows, {gnnz} nonzeros), one launch per row-length part",
+                      f"the {dom['systems']} system pieces of width {Kd // 2 + 1}-{Kd} "
+                      f"({gm} rows, {gnnz} nonzeros, {dom['columns']} columns), one launch per "
+                      f"row-length part",
             "achieved": by / (kms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": by / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "traffic": traffic,
             "bytes_per_launch": by, "padded_bytes_per_launch": by_pad,
             "frac_with_padding": by_pad / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "avg_launch_us": kms * 1e3,
-            "other_pass_us": min(ms_a, ms_at) * 1e3, "parts": part_rows},
+            "other_pass_us": min(ms_a, ms_at) * 1e3, "parts": part_rows,
+            "groups": [{k_: v for k_, v in g_.items() if k_ != "parts"} for g_ in groups]},
         "cpu_baseline": cpu,
     }
     return res
@@ -560,6 +590,60 @@ def variants_bench(args, P, torch, dev):
     return out
 
 
+def iteration_bytes(m, n, nnz, t, dense=False, ta=False):
+    """Algorithmic FP64 bytes of one iteration: CTA-t makes t A passes and t
+    A^T passes (matrix once each, input and output vectors once) and streams
+    (t + 2) residual-length and (t + 2) iterate-length vectors in the update;
+    TA makes one pass of each and about four vector streams."""
+    mat = m * n * 8 if dense else nnz * 12 + 4 * (max(m, n) + 1)
+    a_pass = mat + 8 * (m + n)
+    if ta:
+        return 2 * a_pass + 4 * 8 * (m + n)
+    return 2 * t * a_pass + (t + 2) * 8 * (m + n)
+
+
+def configs_bench(args, P, torch, dev):
+    """Secondary: the dense and convection-diffusion configurations, FP64,
+    one system each, run to an iteration budget (neither reaches its
+    tolerance in seconds: dense Gaussian 500 x 500 needs ~1e6-1e7 CTA-2
+    iterations to 1e-8, convection-diffusion 512^2 ~1e8 CTA-3 iterations to
+    1e-6).  Reported: iterations/s, algorithmic GB/s (iteration_bytes), the
+    relative residual reached."""
+    import numpy as np
+
+    from workloads import convection_diffusion, dense_gaussian
+
+    out = {}
+    c1 = dense_gaussian(500, seed=args.seed)
+    c2 = convection_diffusion(512, seed=args.seed)
+    a1 = P.to_device(np.ascontiguousarray(c1.A))
+    runs = [("dense_gaussian_500_cta2", a1, c1.b, 2, False, 1e-8, 20000, (500, 500, 250000, True)),
+            ("dense_gaussian_500_ta", a1, c1.b, 1, True, 1e-8, 20000, (500, 500, 250000, True)),
+            ("convdiff_512_cta3", c2.A, c2.b, 3, False, 1e-6, 2000,
+             (c2.A.m, c2.A.n, c2.A.nnz, False))]
+    for name, A, b, t, ta, tol, budget, (m, n, nnz, dense) in runs:
+        pl = P.plan(A)
+        bd = torch.from_numpy(np.asarray(b)).to(dev)
+        solve = (lambda: P.ta_solve(pl, bd, tol=tol, max_iter=budget, hist_cap=1)) if ta else \
+            (lambda: P.cta_solve(pl, bd, tol=tol, t=t, max_iter=budget, hist_cap=1))
+        solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, info = solve()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        pl.close()
+        ib = iteration_bytes(m, n, nnz, t, dense=dense, ta=ta)
+        out[name] = {"stop": info.stop, "iterations": info.iters, "seconds": sec,
+                     "iterations_per_s": info.iters / sec, "bytes_per_iteration": ib,
+                     "GB_s": ib * info.iters / sec / 1e9, "rel_res": info.rel_res,
+                     "tol": tol, "budget": budget}
+        log(f"[bench] {name}: {info.stop} after {info.iters} iterations in {sec * 1e3:.1f} ms "
+            f"({info.iters / sec:.0f} it/s, {ib * info.iters / sec / 1e9:.0f} GB/s), "
+            f"rel res {info.rel_res:.3e}")
+    return out
+
+
 def hbm_sweep_bench(args, P, torch, dev):
     """Secondary: bandwidth of the product kernels on HBM-resident sizes --
     the LP-shaped generator at n = 1e6, 4e6, 1e7 (m = n / 100, 6 nonzeros per
@@ -670,6 +754,7 @@ def main():
         res["config"]["differentiable"] = diff_bench(args, P, torch, dev)
     if not args.no_variants:
         res["config"]["variants"] = variants_bench(args, P, torch, dev)
+        res["config"]["configs"] = configs_bench(args, P, torch, dev)
     if not args.no_sweep:
         res["config"]["hbm_sweep"] = hbm_sweep_bench(args, P, torch, dev)
     out = {

@@ -2211,6 +2211,11 @@ static int run_k(int K, const BatchPlan &P, const int32_t *nrhs, const double *c
 #define TA_SPLIT_COLUMNS 1
 #endif
 constexpr int kSplitColumns = TA_SPLIT_COLUMNS;
+// 1 = run the width groups one after another on the caller's stream (a
+// measurement build: kernel durations without other groups beside them)
+#ifndef TA_SERIAL_GROUPS
+#define TA_SERIAL_GROUPS 0
+#endif
 
 static int kwidth(int32_t k) {
     int K = 1;
@@ -2362,6 +2367,14 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
     };
     const size_t ng = groups.size();
     if (ng == 1) return run_group(0, s, nullptr);
+#if TA_SERIAL_GROUPS
+    // measurement build: the groups one after another on s
+    for (size_t j = 0; j < ng; ++j) {
+        const int rc = run_group(j, s, nullptr);
+        if (rc != TA_OK) return rc;
+    }
+    return TA_OK;
+#endif
     struct Streams {
         std::vector<hipStream_t> v;
         hipEvent_t ev = nullptr;
