@@ -105,9 +105,10 @@ typedef struct ta_opts {
     double rho0;           /* ta_solve: initial radius (Algorithm 3 starts from 0) */
     int32_t fixed_rho;     /* ta_solve: 1 = Algorithm 2 (no radius growth, WITNESS exit) */
     int32_t chunk;         /* iterations per host poll of the stop flag; 0 = automatic */
-    int32_t launch_mode;   /* batched solves: 0 = each chunk of iterations is captured once
-                              as a HIP graph and replayed, 1 = kernels launched one by one;
-                              results are identical */
+    int32_t launch_mode;   /* 0 = each chunk of iterations is captured once as a HIP graph
+                              and replayed (single-system solves: from the second chunk on,
+                              not with t_cycle, not in cta_solve_plan_noalloc), 1 = kernels
+                              launched one by one; results are identical */
     int32_t h_mode;        /* cta_solve: 0 = H = A A^T (section 5), 1 = H = A for a square
                               symmetric positive semidefinite A (not checked): t products per
                               iteration instead of 2t, phi_i = r^T A^i r.  Other solvers: 0 */
@@ -238,7 +239,7 @@ int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
 /* ---- prepared operators (plans) ----
  *
  * A plan holds what the solvers derive from A alone: A^T as a canonical CSR
- * built on the device, and for matrices with long rows (more than 16
+ * built on the device (for a dense A, a row-major copy of A^T), and for matrices with long rows (more than 16
  * nonzeros per row on average) and at least 131072 columns, a copy of A with
  * sorted columns split into 8 column slices so that each XCD of the MI355X
  * gathers from its own eighth of x.  A or A^T with short rows (16 or fewer

@@ -215,6 +215,38 @@ __device__ __forceinline__ void load_chunk(const int32_t *__restrict__ ci,
     });
 }
 
+// The two halves of load_chunk, for a loop that issues the loads of one
+// row's first chunk before the previous row's gathers are consumed: the raw
+// per-lane loads, then (once they have arrived) the group broadcasts.
+template <int U, int KL, typename V, typename T>
+__device__ __forceinline__ void chunk_raw(const int32_t *__restrict__ ci,
+                                          const V *__restrict__ val, int32_t k, int32_t e, int L,
+                                          int cl, int32_t (&jl)[(U + KL - 1) / KL],
+                                          T (&al)[(U + KL - 1) / KL]) {
+    constexpr int NL = (U + KL - 1) / KL;
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+        const int idx = cl + q * KL;
+        const int32_t kk = k + idx * L;
+        jl[q] = -1;
+        al[q] = T(0);
+        if (idx < U && kk < e) {
+            jl[q] = ci[kk];
+            al[q] = (T)ldv(val, kk);
+        }
+    }
+}
+template <int U, int KL, typename T>
+__device__ __forceinline__ void chunk_bcast(const int32_t (&jl)[(U + KL - 1) / KL],
+                                            const T (&al)[(U + KL - 1) / KL], int lane,
+                                            int32_t (&j)[U], T (&a)[U]) {
+    static_for<U>([&](auto uc) {
+        constexpr int u = decltype(uc)::value;
+        j[u] = grp_bcast<KL, u % KL>(jl[u / KL], lane);
+        a[u] = grp_bcast<KL, u % KL>(al[u / KL], lane);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // SpMM: Y = M X (or B - M X) over a block table of M's rows.  A lane covers
 // CV consecutive columns with one 16-byte load of the input row (2 doubles or
@@ -289,6 +321,13 @@ constexpr int64_t kRoundNnz = 6;
 template <typename X, int K>
 constexpr int kBspmmWaves = (sizeof(X) != 8 && K == 64) ? 8 : 1;
 
+// Widths whose low-precision SpMM runs the row loop software-pipelined (see
+// k_bspmm): measured faster at K = 8, 16, 32; at K = 64 the lookahead's
+// registers spill (the kernel is held to 64 VGPRs), at K <= 4 the narrow
+// groups load a whole chunk per lane and lose occupancy.
+template <typename X, int K>
+constexpr bool kSpmmPipe = sizeof(X) != 8 && (K == 8 || K == 16 || K == 32);
+
 template <typename X, int K>
 struct Lanes {
     static constexpr int CV0 = sizeof(X) == 8 ? 2 : 4;
@@ -322,11 +361,109 @@ void k_bspmm(const int32_t *__restrict__ rp,
     Acc part[CV];
 #pragma unroll
     for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
-    // Rows are visited tile by tile (see BRange); the bounds of a lane's next
-    // row are loaded before the current row's nonzeros so that their latency
-    // overlaps the gathers.  Nonzeros go in chunks of U per lane, each chunk
-    // predicated on the row end: a short row issues all its column-index and
-    // x loads in one round.
+    // Rows are visited tile by tile (see BRange).  Nonzeros go in chunks of U
+    // per lane, each chunk predicated on the row end: a short row issues all
+    // its column-index and x loads in one round.
+    if constexpr (kSpmmPipe<X, K>) {
+        // Low precision: a lane's rows are software-pipelined one deep.  The
+        // column indices and values of the next row's first chunk, and the
+        // bounds of the row after it, are loaded right after the current
+        // row's gathers are issued, so that for short rows each row waits on
+        // one memory latency (the gathers) instead of two (indices, then
+        // gathers).  The arithmetic is that of the plain loop.
+        constexpr int NL = (U + KL - 1) / KL;
+        BIter it = brow_first(br, RL, wave, rsub);
+        int32_t s_cur = 0, e_cur = 0, s_nxt = 0, e_nxt = 0;
+        if (it.row >= 0) {
+            s_cur = rp[it.row];
+            e_cur = rp[it.row + 1];
+        }
+        int32_t jl[NL];
+        float al[NL];
+        chunk_raw<U, KL>(ci, val, s_cur + l, e_cur, L, cl, jl, al);
+        BIter nit = it.row >= 0 ? brow_next(br, RL, wave, rsub, it) : it;
+        if (nit.row >= 0) {
+            s_nxt = rp[nit.row];
+            e_nxt = rp[nit.row + 1];
+        }
+        while (it.row >= 0) {
+            const int64_t row = it.row;
+            int32_t j[U];
+            float a[U], xv[U][CV];
+            chunk_bcast<U, KL>(jl, al, gbase + cl, j, a);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (j[u] >= 0) {
+                    VecLoad<float, CV>::ld((const float *)x + (int64_t)j[u] * K + c0, xv[u]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < CV; ++v) xv[u][v] = 0.0f;
+                }
+            }
+            // the next row's first chunk and the bounds of the row after it
+            chunk_raw<U, KL>(ci, val, s_nxt + l, e_nxt, L, cl, jl, al);
+            const BIter nnit = nit.row >= 0 ? brow_next(br, RL, wave, rsub, nit) : nit;
+            int32_t s_nn = 0, e_nn = 0;
+            if (nnit.row >= 0) {
+                s_nn = rp[nnit.row];
+                e_nn = rp[nnit.row + 1];
+            }
+            float acc[CV];
+#pragma unroll
+            for (int v = 0; v < CV; ++v) acc[v] = 0.0f;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (j[u] >= 0) {
+#pragma unroll
+                    for (int v = 0; v < CV; ++v) acc[v] = fmaf(a[u], xv[u][v], acc[v]);
+                }
+            // the rest of a row longer than one chunk, as in the plain loop
+            for (int32_t k = s_cur + l + U * L; k < e_cur; k += U * L) {
+                int32_t j2[U];
+                float a2[U], xv2[U][CV];
+                load_chunk<U, KL>(ci, val, k, e_cur, L, cl, gbase, 1.0f, j2, a2);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (j2[u] >= 0) {
+                        VecLoad<float, CV>::ld((const float *)x + (int64_t)j2[u] * K + c0,
+                                               xv2[u]);
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < CV; ++v) xv2[u][v] = 0.0f;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j2[u] >= 0) {
+#pragma unroll
+                        for (int v = 0; v < CV; ++v) acc[v] = fmaf(a2[u], xv2[u][v], acc[v]);
+                    }
+            }
+            for (int off = KL; off < KL * L; off <<= 1) {
+#pragma unroll
+                for (int v = 0; v < CV; ++v) acc[v] += __shfl_xor(acc[v], off);
+            }
+            if (l == 0) {
+                double yv[CV];
+#pragma unroll
+                for (int v = 0; v < CV; ++v) yv[v] = (double)acc[v];
+                if constexpr (EPI != kBNormOnly) vst<X, CV>(y + row * K + c0, yv);
+#pragma unroll
+                for (int v = 0; v < CV; ++v) {
+                    const double q = (double)(X)yv[v];
+                    part[v].p = __fma_rn(q, q, part[v].p);
+                }
+            }
+            s_cur = s_nxt;
+            e_cur = e_nxt;
+            s_nxt = s_nn;
+            e_nxt = e_nn;
+            it = nit;
+            nit = nnit;
+        }
+    } else {
+    // The plain loop: the bounds of a lane's next row are loaded before the
+    // current row's nonzeros so that their latency overlaps the gathers.
     BIter it = brow_first(br, RL, wave, rsub);
     int32_t s_cur = 0, e_cur = 0;
     if (it.row >= 0) {
@@ -431,6 +568,7 @@ void k_bspmm(const int32_t *__restrict__ rp,
         s_cur = s_nxt;
         e_cur = e_nxt;
         it = nit;
+    }
     }
     // reduce over the rows of the block for each column
     for (int off = KL; off < 64; off <<= 1) {

@@ -196,6 +196,9 @@ hipError_t launch_ta_update(int64_t m, int64_t n, const double *b, double *bp, c
                             double *r, double *x, const double *c, const Out &o, hipStream_t s,
                             int32_t *blocks);
 hipError_t launch_step(const Step &sp, hipStream_t s);
+// dst (n x m, row stride ldd) = src^T (m x n, row stride lds), FP64
+hipError_t launch_dense_transpose(int64_t m, int64_t n, const double *src, int64_t lds,
+                                  double *dst, int64_t ldd, hipStream_t s);
 // *d = h, from a kernel argument
 hipError_t launch_state_set(State *d, const State &h, hipStream_t s);
 hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,

@@ -1225,6 +1225,31 @@ hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
     return hipGetLastError();
 }
 
+// Dense transpose through a 32 x 33 LDS tile: dst (n x m, row stride ldd)
+// = src^T (m x n, row stride lds).
+__global__ __launch_bounds__(kBlock) void k_dense_transpose64(int64_t m, int64_t n,
+                                                               const double *__restrict__ src,
+                                                               int64_t lds, double *dst,
+                                                               int64_t ldd) {
+    __shared__ double tile[32][33];
+    const int64_t i0 = (int64_t)blockIdx.y * 32, j0 = (int64_t)blockIdx.x * 32;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;  // 32 x 8
+    for (int r = ty; r < 32; r += 8)
+        if (i0 + r < m && j0 + tx < n) tile[r][tx] = src[(i0 + r) * lds + j0 + tx];
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8)
+        if (j0 + r < n && i0 + tx < m) dst[(j0 + r) * ldd + i0 + tx] = tile[tx][r];
+}
+
+hipError_t launch_dense_transpose(int64_t m, int64_t n, const double *src, int64_t lds,
+                                  double *dst, int64_t ldd, hipStream_t s) {
+    if (m <= 0 || n <= 0) return hipSuccess;
+    if ((m + 31) / 32 > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32));
+    k_dense_transpose64<<<grid, kBlock, 0, s>>>(m, n, src, lds, dst, ldd);
+    return hipGetLastError();
+}
+
 // The whole State from a kernel argument (no host staging buffer).
 __global__ void k_state_set(State *d, State h) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *d = h;

@@ -206,9 +206,22 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
     const int64_t m = M->m, n = M->n;
     P->has_t = need_t;
     if (M->kind == TA_DENSE_ROWMAJOR) {
+        // A^T as a row-major copy, so that both products run 64 lanes per row
+        // (the column view of A, one thread per column of A, leaves most of
+        // the chip idle on a few hundred columns)
         P->A = MatView{kDenseRows, m, n, M->ld, nullptr, nullptr, M->val, 64, nullptr, nullptr};
         P->AT = MatView{kDenseCols, n, m, M->ld, nullptr, nullptr, M->val, 1, nullptr, nullptr};
         P->has_t = true;
+        if (m > 0 && n > 0 && need_t && (m + 31) / 32 <= 65535) {
+            Workspace own(s);
+            double *at = nullptr;
+            own.reserve(&at, n * m);
+            if ((rc = own.commit()) != TA_OK) return rc;
+            HIP_TRY(launch_dense_transpose(m, n, M->val, M->ld, at, m, s));
+            P->AT = MatView{kDenseRows, n, m, m, nullptr, nullptr, at, 64, nullptr, nullptr};
+            P->mem = own.release();
+            P->s_mem = s;
+        }
         return TA_OK;
     }
     const int64_t nnz = M->nnz;
@@ -438,6 +451,56 @@ static int solve_empty(const ta_mat *M, double *x, double *hist, int64_t hist_ca
     return TA_OK;
 }
 
+// Chunks of a chain captured once as HIP graphs and replayed.  Every kernel
+// of a chain takes its state from device memory (State, vectors, partials)
+// and its launch arguments are fixed for the whole solve, so a replay does
+// exactly the work of the launches it was captured from; a chunk's launches
+// depend only on its length and on whether candidate checks follow every
+// iteration (the key).  Not used with order cycling (the order of each
+// iteration depends on its index) or by the no-allocation entry point
+// (instantiating a graph allocates).
+struct ChunkGraphs {
+    hipStream_t cap = nullptr;
+    std::vector<std::pair<int64_t, hipGraphExec_t>> ex;
+    ChunkGraphs() = default;
+    ChunkGraphs(const ChunkGraphs &) = delete;
+    ChunkGraphs &operator=(const ChunkGraphs &) = delete;
+    ~ChunkGraphs() {
+        for (auto &e : ex) (void)hipGraphExecDestroy(e.second);
+        if (cap != nullptr) (void)hipStreamDestroy(cap);
+    }
+};
+
+// Enqueue one chunk on s: body() enqueues on c.s; with g, it runs once on a
+// capture stream for each key and the graph is launched on s.
+template <class F>
+static int enqueue_chunk(ChunkGraphs *g, int64_t key, Chain &c, hipStream_t s, F &&body) {
+    c.s = s;
+    if (g == nullptr) return body();
+    hipGraphExec_t ge = nullptr;
+    for (auto &e : g->ex)
+        if (e.first == key) ge = e.second;
+    if (ge == nullptr) {
+        if (g->cap == nullptr) HIP_TRY(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+        c.s = g->cap;
+        HIP_TRY(hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal));
+        const int rc = body();
+        hipGraph_t gr = nullptr;
+        const hipError_t ce = hipStreamEndCapture(g->cap, &gr);
+        c.s = s;
+        if (rc != TA_OK || ce != hipSuccess) {
+            if (gr != nullptr) (void)hipGraphDestroy(gr);
+            return rc != TA_OK ? rc : hip_fail(ce, "hipStreamEndCapture");
+        }
+        const hipError_t ie = hipGraphInstantiate(&ge, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        HIP_TRY(ie);
+        g->ex.emplace_back(key, ge);
+    }
+    HIP_TRY(hipGraphLaunch(ge, s));
+    return TA_OK;
+}
+
 // Host loop guard shared by the chains.  Every chunk either finishes the
 // solve or advances the iteration count, except a chunk that ends on a
 // candidate check right at its start (the next chunk then runs at least one
@@ -536,15 +599,15 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
                 EpiArgs ed{};
                 ed.r = u[j];
                 HIP_TRY(launch_matvec(c.A, u[j], u[j + 1], kEpiNormDot, ed,
-                                      c.out(2 * j, kGateAlways), s, &gphi[2 * j]));
+                                      c.out(2 * j, kGateAlways), c.s, &gphi[2 * j]));
                 gphi[2 * j + 1] = gphi[2 * j];
                 continue;
             }
             double *wj = w[minnorm ? 0 : j];
-            HIP_TRY(launch_matvec(c.AT, u[j], wj, kEpiNorm, EpiArgs{}, c.out(2 * j, kGateAlways), s,
+            HIP_TRY(launch_matvec(c.AT, u[j], wj, kEpiNorm, EpiArgs{}, c.out(2 * j, kGateAlways), c.s,
                                   &gphi[2 * j]));
             HIP_TRY(launch_matvec(c.A, wj, u[j + 1], kEpiNorm, EpiArgs{},
-                                  c.out(2 * j + 1, kGateAlways), s, &gphi[2 * j + 1]));
+                                  c.out(2 * j + 1, kGateAlways), c.s, &gphi[2 * j + 1]));
         }
         Step sp;
         memset(&sp, 0, sizeof sp);
@@ -557,21 +620,21 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
         sp.post = kPostGram;
         sp.arg = tk;
         sp.gate = kGateAlways;
-        HIP_TRY(launch_step(sp, s));
+        HIP_TRY(launch_step(sp, c.s));
         HIP_TRY(launch_cta_update(m, n, tk, (minnorm || ha) ? 1 : 0, r, u, x, w, ha ? x : y,
-                                  rb, xyb, c.out(R, kGateAlways), s, &g));
+                                  rb, xyb, c.out(R, kGateAlways), c.s, &g));
         HIP_TRY(c.step(R, {g}, kPostCtaEnd, 0, kGateAlways));
         if (acc) {
             int32_t gj = 0;
-            HIP_TRY(launch_cta_jump(m, nupd, r, rb, minnorm ? y : x, xyb, c.out(R, kGateJump), s,
+            HIP_TRY(launch_cta_jump(m, nupd, r, rb, minnorm ? y : x, xyb, c.out(R, kGateJump), c.s,
                                     &gj));
             HIP_TRY(c.step(R, {gj}, kPostCtaJump, 0, kGateJump));
         }
         if (o->replace_every > 0) {
             if (minnorm)
-                HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateReplace), s,
+                HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateReplace), c.s,
                                       nullptr));
-            HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateReplace), s, &gr));
+            HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateReplace), c.s, &gr));
             HIP_TRY(c.step(R, {gr}, kPostCtaReplace, products, kGateReplace));
         }
         return TA_OK;
@@ -582,9 +645,9 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     // the new recurrence residual
     auto enqueue_check = [&]() -> int {
         if (minnorm)
-            HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateCandidate), s,
+            HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateCandidate), c.s,
                                   nullptr));
-        HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateCandidate), s, &g));
+        HIP_TRY(launch_matvec(c.A, x, r, kEpiResid, eres, c.out(R, kGateCandidate), c.s, &g));
         HIP_TRY(c.step(R, {g}, kPostCtaCand, products, kGateCandidate));
         return TA_OK;
     };
@@ -598,21 +661,33 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     Chunker ch(o->chunk);
     State h;
     Progress prog;
+    ChunkGraphs graphs;
+    const bool use_graphs = o->launch_mode == 0 && !noalloc && !o->t_cycle;
     bool inline_checks = false;
     int64_t k_done = 0;  // iterations done when the chunk starts
-    for (;;) {
+    for (int64_t chunk_no = 0;; ++chunk_no) {
         const int64_t k = ch.take();
-        for (int64_t i = 0; i < k; ++i) {
-            // the order of an iteration is its index's; a chunk that runs into
-            // a candidate resumes the schedule from the state's count
-            if ((rc = enqueue_iteration(order_of(k_done + i))) != TA_OK) return rc;
-            if (inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
-        }
-        if (!inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
-        if (minnorm)
-            HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateFinal), s,
-                                  nullptr));
-        HIP_TRY(enqueue_exit_diagnostics(c, b, x, r, tmp_n));
+        auto body = [&]() -> int {
+            for (int64_t i = 0; i < k; ++i) {
+                // the order of an iteration is its index's; a chunk that runs
+                // into a candidate resumes the schedule from the state's count
+                int rb2 = enqueue_iteration(order_of(k_done + i));
+                if (rb2 != TA_OK) return rb2;
+                if (inline_checks && (rb2 = enqueue_check()) != TA_OK) return rb2;
+            }
+            int rb3 = TA_OK;
+            if (!inline_checks && (rb3 = enqueue_check()) != TA_OK) return rb3;
+            if (minnorm)
+                HIP_TRY(launch_matvec(c.AT, y, x, kEpiNorm, EpiArgs{}, c.out(0, kGateFinal), c.s,
+                                      nullptr));
+            HIP_TRY(enqueue_exit_diagnostics(c, b, x, r, tmp_n));
+            return TA_OK;
+        };
+        // the first chunk runs as plain launches (a solve that stops in it
+        // pays no capture), later ones from graphs
+        if ((rc = enqueue_chunk(use_graphs && chunk_no > 0 ? &graphs : nullptr,
+                                2 * k + (inline_checks ? 1 : 0), c, s, body)) != TA_OK)
+            return rc;
         if ((rc = read_state(c.st, h, s, noalloc)) != TA_OK) return rc;
         if (h.done && h.stop != kStopCandidate) break;
         k_done = h.k;
@@ -673,27 +748,27 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     // y = Op v with the epilogue of the outer pass (gate and slot of `out`)
     auto op_apply = [&](const double *v, double *y, int32_t epi, const EpiArgs &ea, const Out &out,
                         int32_t *blocks) -> hipError_t {
-        if (!ne) return launch_matvec(c.A, v, y, epi, ea, out, s, blocks);
+        if (!ne) return launch_matvec(c.A, v, y, epi, ea, out, c.s, blocks);
         Out inner = out;
         inner.slot = 5;
-        hipError_t e = launch_matvec(c.A, v, tA, kEpiNorm, EpiArgs{}, inner, s, nullptr);
+        hipError_t e = launch_matvec(c.A, v, tA, kEpiNorm, EpiArgs{}, inner, c.s, nullptr);
         if (e != hipSuccess) return e;
-        return launch_matvec(c.AT, tA, y, epi, ea, out, s, blocks);
+        return launch_matvec(c.AT, tA, y, epi, ea, out, c.s, blocks);
     };
     // y = Op^T v (Op^T = Op on the normal equation)
     auto op_apply_t = [&](const double *v, double *y, int32_t epi, const Out &out,
                           int32_t *blocks) -> hipError_t {
-        if (!ne) return launch_matvec(c.AT, v, y, epi, EpiArgs{}, out, s, blocks);
+        if (!ne) return launch_matvec(c.AT, v, y, epi, EpiArgs{}, out, c.s, blocks);
         return op_apply(v, y, epi, EpiArgs{}, out, blocks);
     };
     const double *be = b;  // the right-hand side the iteration works on
     if (ne) {
-        HIP_TRY(launch_matvec(c.AT, b, bt, kEpiNorm, EpiArgs{}, c.out(5, kGateAlways), s, nullptr));
+        HIP_TRY(launch_matvec(c.AT, b, bt, kEpiNorm, EpiArgs{}, c.out(5, kGateAlways), c.s, nullptr));
         be = bt;
     }
     // slots: 0 ||c||^2; 1, 2: r^T d, ||d||^2; 3, 4: ||r||^2, r^T b
     const int32_t warm = o->warm_start ? 1 : 0;
-    HIP_TRY(launch_ta_init(mo, n, be, r, bp, x, warm, c.out(3, kGateAlways), s, &g));
+    HIP_TRY(launch_ta_init(mo, n, be, r, bp, x, warm, c.out(3, kGateAlways), c.s, &g));
     HIP_TRY(c.step(3, {g}, kPostTaInit, warm, kGateAlways));
     // LP feasibility (x >= 0): c = A^T r is replaced by its positive part
     const int32_t epi_c = o->nonneg ? kEpiNormPos : kEpiNorm;
@@ -717,7 +792,7 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
         HIP_TRY(c.step(0, {g}, kPostTaC, 0, kGateNeedC));
         HIP_TRY(op_apply(cv, d, kEpiTaD, ed, c.out(1, kGatePivot), &g));
         HIP_TRY(c.step(1, {g, g}, kPostTaS, 0, kGatePivot));
-        HIP_TRY(launch_ta_update(mo, n, be, bp, d, r, x, cv, c.out(3, kGatePivot), s, &g));
+        HIP_TRY(launch_ta_update(mo, n, be, bp, d, r, x, cv, c.out(3, kGatePivot), c.s, &g));
         HIP_TRY(c.step(3, {g, g}, kPostTaEnd, 0, kGatePivot));
         return TA_OK;
     };
@@ -742,15 +817,25 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     Chunker ch(o->chunk);
     State h;
     Progress prog;
+    ChunkGraphs graphs;
+    const bool use_graphs = o->launch_mode == 0;
     bool inline_checks = false;
-    for (;;) {
+    for (int64_t chunk_no = 0;; ++chunk_no) {
         const int64_t k = ch.take();
-        for (int64_t i = 0; i < k; ++i) {
-            if ((rc = enqueue_iteration()) != TA_OK) return rc;
-            if (inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
-        }
-        if (!inline_checks && (rc = enqueue_check()) != TA_OK) return rc;
-        HIP_TRY(enqueue_exit_diagnostics(c, b, x, tA, cv, ne));
+        auto body = [&]() -> int {
+            for (int64_t i = 0; i < k; ++i) {
+                int rb2 = enqueue_iteration();
+                if (rb2 != TA_OK) return rb2;
+                if (inline_checks && (rb2 = enqueue_check()) != TA_OK) return rb2;
+            }
+            int rb3 = TA_OK;
+            if (!inline_checks && (rb3 = enqueue_check()) != TA_OK) return rb3;
+            HIP_TRY(enqueue_exit_diagnostics(c, b, x, tA, cv, ne));
+            return TA_OK;
+        };
+        if ((rc = enqueue_chunk(use_graphs && chunk_no > 0 ? &graphs : nullptr,
+                                2 * k + (inline_checks ? 1 : 0), c, s, body)) != TA_OK)
+            return rc;
         if ((rc = read_state(c.st, h, s)) != TA_OK) return rc;
         if (h.done && h.stop != kStopCandidate) break;
         inline_checks = inline_checks || h.rejects > 0;

@@ -405,3 +405,38 @@ def test_plan_rejects_malformed_csr():
     bad = Csr(3, 3, np.array([0, 2, 1, 3], np.int32), np.array([0, 1, 2], np.int32), np.ones(3))
     with pytest.raises(P.TaError, match="EINVAL"):
         P.plan(bad)
+
+
+@pytest.mark.parametrize("case", ["cta_x", "cta_y", "ta", "ta_ne", "cta_accel_replace", "cta_cycle"])
+def test_graph_replay_equals_plain_launches(case):
+    """Single-system chains replay their chunks from captured HIP graphs
+    (launch_mode 0, the default) or launch every kernel (launch_mode 1): the
+    same kernels with the same arguments, so x, the history and every count
+    must agree bit for bit.  The solves run many chunks, so each graph is
+    replayed several times, with the other mode's eager work in between."""
+    p = convection_diffusion(12)
+    g = np.random.default_rng(4)
+    A = p.A
+    kw = dict(tol=1e-10, max_iter=3000)
+    if case == "cta_x":
+        run = lambda **o: P.cta_solve(A, p.b, t=3, **kw, **o)
+    elif case == "cta_y":
+        run = lambda **o: P.cta_minnorm(A, p.b, t=2, **kw, **o)
+    elif case == "ta":
+        q = dense_gaussian(20, seed=3, m=12)
+        run = lambda **o: P.ta_solve(q.A, q.b, tol=1e-9, max_iter=20000, **o)
+    elif case == "ta_ne":
+        a = g.standard_normal((30, 12))
+        bb = g.standard_normal(30)
+        run = lambda **o: P.ta_solve(a, bb, tol=1e-7, max_iter=20000, normal_eq=True, **o)
+    elif case == "cta_accel_replace":
+        run = lambda **o: P.cta_solve(A, p.b, t=2, accel=0.5, replace_every=7, **kw, **o)
+    else:
+        run = lambda **o: P.cta_solve(A, p.b, t=4, t_cycle=True, **kw, **o)
+    for _ in range(2):
+        xg, hg, ig = run(graph=True)
+        xl, hl, il = run(graph=False)
+        assert (ig.stop, ig.iters, ig.matvecs) == (il.stop, il.iters, il.matvecs)
+        assert ig.iters > 64, ig  # several chunks, graphs replayed
+        assert torch.equal(xg, xl) and torch.equal(hg, hl)
+        assert ig.rel_res == il.rel_res and ig.rho == il.rho

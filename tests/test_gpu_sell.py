@@ -95,7 +95,7 @@ def test_format_choice():
     assert P.plan(kac_clement(1001).A).format(True) == "sell64"
     assert P.plan(_uneven()).format(False) == "csr_rows"
     d = P.plan(dense_gaussian(50, seed=1).A)
-    assert (d.format(False), d.format(True)) == ("dense_rows", "dense_cols")
+    assert (d.format(False), d.format(True)) == ("dense_rows", "dense_rows")
 
 
 @pytest.mark.parametrize("name", sorted(SELL))
