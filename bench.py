@@ -197,7 +197,7 @@ def batched_uneven_bench(args, P, torch, dev, pool=None):
 
     # BF16 products (FP32 accumulation) with FP64 refinement, one solve
     bf16 = None
-    if args.precision != "bf16":
+    if args.precision != "bf16" and not args.no_bf16:
         bp16 = P.BatchPlan(systems, "bf16")
         solve(bp16, "bf16")  # warm-up (row-lane tuning)
         torch.cuda.synchronize()
@@ -722,7 +722,21 @@ def main():
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the HBM-resident size sweep of the product kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 batched leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB on the device three times (the reference kernel "
+                         "that scales the HBM traffic counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        a = torch.ones(2 ** 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copied 1 GiB three times")
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
