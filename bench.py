@@ -723,6 +723,9 @@ def main():
                     help="skip the HBM-resident size sweep of the product kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 batched leg")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only the HBM-resident size sweep of the product kernels (for "
+                         "profiling them), printed as one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device three times (the reference kernel "
                          "that scales the HBM traffic counters) and exit")
@@ -758,6 +761,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.sweep_only:
+        print(json.dumps({"hbm_sweep": hbm_sweep_bench(args, P, torch, dev)}), flush=True)
+        return
     res = batched_uneven_bench(args, P, torch, dev, pool)
     if pool is not None:
         pool[0].close()

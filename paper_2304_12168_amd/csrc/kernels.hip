@@ -583,33 +583,44 @@ __global__ __launch_bounds__(kBlock) void k_rows_vector(MatView M, const double 
         if constexpr (EPI == kEpiResid) {
             if (lane == 0) acc.p = ea.b[row];
         }
+        // rounds of U entries per lane, predicated on the row end, a lane's
+        // terms summed in storage order (j, j + W, j + 2W, ...)
+        constexpr int U = 8;
         if (M.kind == kDenseRows) {
             const double *a = M.val + row * M.ld;
-            int64_t j = lane;
-            for (; j + 3 * W < M.cols; j += 4 * W) {
-                const double a0 = a[j], a1 = a[j + W], a2 = a[j + 2 * W], a3 = a[j + 3 * W];
-                const double x0 = x[j], x1 = x[j + W], x2 = x[j + 2 * W], x3 = x[j + 3 * W];
-                acc_fma(acc, sgn * a0, x0);
-                acc_fma(acc, sgn * a1, x1);
-                acc_fma(acc, sgn * a2, x2);
-                acc_fma(acc, sgn * a3, x3);
+            for (int64_t j0 = lane; j0 < M.cols; j0 += U * W) {
+                double av[U], xv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t j = j0 + u * W;
+                    av[u] = j < M.cols ? a[j] : 0.0;
+                    xv[u] = j < M.cols ? x[j] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (j0 + u * W < M.cols) acc_fma(acc, sgn * av[u], xv[u]);
             }
-            for (; j < M.cols; j += W) acc_fma(acc, sgn * a[j], x[j]);
         } else {
             const int32_t e = M.rp[row + 1];
-            int32_t k = M.rp[row] + lane;
-            for (; k + 3 * W < e; k += 4 * W) {
-                const int32_t c0 = M.ci[k], c1 = M.ci[k + W], c2 = M.ci[k + 2 * W],
-                              c3 = M.ci[k + 3 * W];
-                const double a0 = M.val[k], a1 = M.val[k + W], a2 = M.val[k + 2 * W],
-                             a3 = M.val[k + 3 * W];
-                const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-                acc_fma(acc, sgn * a0, x0);
-                acc_fma(acc, sgn * a1, x1);
-                acc_fma(acc, sgn * a2, x2);
-                acc_fma(acc, sgn * a3, x3);
+            for (int32_t k0 = M.rp[row] + lane; k0 < e; k0 += U * W) {
+                int32_t c[U];
+                double av[U], xv[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int32_t k = k0 + u * W;
+                    c[u] = -1;
+                    av[u] = 0.0;
+                    if (k < e) {
+                        c[u] = M.ci[k];
+                        av[u] = M.val[k];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+                    if (c[u] >= 0) acc_fma(acc, sgn * av[u], xv[u]);
             }
-            for (; k < e; k += W) acc_fma(acc, sgn * M.val[k], x[M.ci[k]]);
         }
     }
     acc = group_reduce<W>(acc);
@@ -643,24 +654,30 @@ __global__ __launch_bounds__(kBlock) void k_rows_sliced(MatView M, const double 
     }
     const int32_t *sg = M.seg + row * (kSlices + 1) + slice;
     const int32_t e = sg[1];
-    int32_t k = sg[0] + lane;
-    for (; k + 3 * W < e; k += 4 * W) {
-        const int32_t c0 = __builtin_nontemporal_load(M.ci + k);
-        const int32_t c1 = __builtin_nontemporal_load(M.ci + k + W);
-        const int32_t c2 = __builtin_nontemporal_load(M.ci + k + 2 * W);
-        const int32_t c3 = __builtin_nontemporal_load(M.ci + k + 3 * W);
-        const double a0 = __builtin_nontemporal_load(M.val + k);
-        const double a1 = __builtin_nontemporal_load(M.val + k + W);
-        const double a2 = __builtin_nontemporal_load(M.val + k + 2 * W);
-        const double a3 = __builtin_nontemporal_load(M.val + k + 3 * W);
-        const double x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-        acc_fma(acc, sgn * a0, x0);
-        acc_fma(acc, sgn * a1, x1);
-        acc_fma(acc, sgn * a2, x2);
-        acc_fma(acc, sgn * a3, x3);
+    // Rounds of U entries per lane, each entry predicated on the segment end:
+    // a segment of up to U W entries takes one round, i.e. one wait for the
+    // index and value loads and one for the gathers.  A lane's terms are still
+    // summed in storage order (k, k + W, k + 2W, ...).
+    constexpr int U = 8;
+    for (int32_t k0 = sg[0] + lane; k0 < e; k0 += U * W) {
+        int32_t c[U];
+        double a[U], xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t k = k0 + u * W;
+            c[u] = -1;
+            a[u] = 0.0;
+            if (k < e) {
+                c[u] = __builtin_nontemporal_load(M.ci + k);
+                a[u] = __builtin_nontemporal_load(M.val + k);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0) acc_fma(acc, sgn * a[u], xv[u]);
     }
-    for (; k < e; k += W)
-        acc_fma(acc, sgn * __builtin_nontemporal_load(M.val + k), x[__builtin_nontemporal_load(M.ci + k)]);
     acc = group_reduce<W>(acc);
     if (lane == 0) M.ypart[(int64_t)slice * M.rows + row] = make_double2(acc.p, acc.s);
 }
