@@ -686,13 +686,15 @@ def hbm_sweep_bench(args, P, torch, dev):
         by_ba = csr_pass_bytes(m, n, nnz, 4, 4, 4, 32)
         by_bt = csr_pass_bytes(n, m, nnz, 4, 4, 4, 32)
         row = {"matrix": kind, "size": size, "n": n, "m": m, "nnz": nnz,
-               "fp64_matrix_mb": nnz * 12 / 1e6, "generated_s": gen_s}
+               "fp64_matrix_mb": nnz * 12 / 1e6, "generated_s": gen_s,
+               "format_A": pl.format(False), "format_AT": pl.format(True)}
         for key, by, ms in (("fp64_A", by_a, ms_a), ("fp64_AT", by_t, ms_t),
                             ("fp32_k32_A", by_ba, ms_ba), ("fp32_k32_AT", by_bt, ms_bt)):
             gbs = by / ms / 1e6
             row[key] = {"us": ms * 1e3, "bytes": by, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
         out.append(row)
-        log(f"[bench] HBM sweep {kind} {size}: FP64 A {row['fp64_A']['GB_s']:.0f} GB/s, "
+        log(f"[bench] HBM sweep {kind} {size} ({row['format_A']}, {row['format_AT']}): "
+            f"FP64 A {row['fp64_A']['GB_s']:.0f} GB/s, "
             f"A^T {row['fp64_AT']['GB_s']:.0f} GB/s; FP32 K=32 A {row['fp32_k32_A']['GB_s']:.0f} "
             f"GB/s, A^T {row['fp32_k32_AT']['GB_s']:.0f} GB/s")
         del pl, A, x, u, Ah

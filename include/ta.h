@@ -239,8 +239,13 @@ int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
 /* ---- prepared operators (plans) ----
  *
  * A plan holds what the solvers derive from A alone: A^T as a canonical CSR
- * built on the device (for a dense A, a row-major copy of A^T), and for matrices with long rows (more than 16
- * nonzeros per row on average) and at least 131072 columns, a copy of A with
+ * built on the device (for a dense A, a row-major copy of A^T), and for A or
+ * A^T with long rows (more than 16 nonzeros per row on average) one of two
+ * regrouped copies: with at least 16384 columns and at least 3 entries per
+ * (row, 8192-column tile) on average, the entries stored tile after tile
+ * with 16-bit column offsets, so that each block stages one tile of x in LDS
+ * and gathers from there (TA_FMT_CSR_TILED; one partial sum per row and
+ * tile is merged afterwards); else, with at least 131072 columns, a copy with
  * sorted columns split into 8 column slices so that each XCD of the MI355X
  * gathers from its own eighth of x.  A or A^T with short rows (16 or fewer
  * nonzeros on average) whose 64-row slices pad the entries by at most a
@@ -264,10 +269,10 @@ int ta_plan_destroy(ta_plan *plan);
 
 /* Storage the plan's products use for A (trans = 0) or A^T (trans = 1):
  * TA_FMT_CSR_ROWS, TA_FMT_DENSE_ROWS, TA_FMT_DENSE_COLS, TA_FMT_CSR_SLICED
- * (column slices) or TA_FMT_SELL64, written to *format (host).  TA_EINVAL for
- * a NULL argument. */
+ * (column slices), TA_FMT_SELL64 or TA_FMT_CSR_TILED (LDS column tiles),
+ * written to *format (host).  TA_EINVAL for a NULL argument. */
 enum { TA_FMT_CSR_ROWS = 0, TA_FMT_DENSE_ROWS = 1, TA_FMT_DENSE_COLS = 2,
-       TA_FMT_CSR_SLICED = 3, TA_FMT_SELL64 = 4 };
+       TA_FMT_CSR_SLICED = 3, TA_FMT_SELL64 = 4, TA_FMT_CSR_TILED = 5 };
 int ta_plan_format(const ta_plan *plan, int32_t trans, int32_t *format);
 
 /* The solvers above on a prepared operator; other arguments as there. */
@@ -291,7 +296,8 @@ int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, d
  * State is set from a kernel argument and read back into host stack memory.
  * The plan itself is made beforehand with ta_plan_create (which allocates).
  *   Limit: the workspace is 8 (t + 1) (m + n) bytes (8 (m + n) more with
- *   accel, 128 m or 128 n more for a plan with column slices) plus the
+ *   accel, 128 m or 128 n more for a plan with column slices, 16 m
+ *   ceil(n / 8192) or 16 n ceil(m / 8192) more for one with column tiles) plus the
  *   per-block partial sums; a solve that needs more than the buffer returns
  *   TA_ESCRATCH before any device work.  For t = 3 and m = n that is
  *   n up to about 1e6.

@@ -35,7 +35,8 @@ EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror",
            "ta_batch_time_spmm", "ta_csr_outer", "ta_minnorm", "ta_minnorm_plan", "ta_plan_format",
            "cta_solve_plan_noalloc")
 # storage of a plan's products (ta_plan_format)
-FORMATS = {0: "csr_rows", 1: "dense_rows", 2: "dense_cols", 3: "csr_sliced", 4: "sell64"}
+FORMATS = {0: "csr_rows", 1: "dense_rows", 2: "dense_cols", 3: "csr_sliced", 4: "sell64",
+           5: "csr_tiled"}
 
 
 class TaMat(C.Structure):

@@ -148,9 +148,19 @@ enum MatKind : int32_t {
     kDenseCols = 2,  // dense row-major A viewed as M = A^T: one thread per column of A
     kCsrSliced = 3,  // CSR with columns sorted, split into kSlices column slices (one per XCD)
     kCsrSell = 4,    // CSR copied into 64-row slices (SELL-64), one thread per row
+    kCsrTiled = 5,   // CSR regrouped by column tiles of kTileW; each tile of x staged in LDS
 };
 
 constexpr int kSlices = 8;  // XCDs of the part; blocks b with b % 8 == s take column slice s
+constexpr int kTileW = 8192;     // columns per tile: 64 KB of FP64 x in LDS, 16-bit local index
+constexpr int kTileBlock = 512;  // threads of a tiled block: 2 blocks (16 waves) per CU
+// W lanes per row take U entries each per round (W U = 8 slots per row and
+// round, U = 1 from W = 8 on); PR row passes go together, within the 128
+// registers that keep two blocks on a CU; a block's batch covers
+// PR kTileBlock / W rows
+constexpr int tile_u(int W) { return W >= 8 ? 1 : 8 / W; }
+constexpr int tile_pr(int W) { return W == 1 ? 2 : 4; }
+constexpr int tile_batch_rows(int W) { return tile_pr(W) * (kTileBlock / W); }
 
 struct MatView {
     int32_t kind;
@@ -161,13 +171,23 @@ struct MatView {
     const double *val;
     int32_t lanes;       // kCsrRows: 1 = one thread per row, else lanes per row
     const int32_t *seg;  // kCsrSliced: rows x (kSlices + 1) slice starts inside each row
-    double2 *ypart;      // kCsrSliced: kSlices x rows compensated partial sums (workspace)
+    double2 *ypart;      // kCsrSliced: kSlices x rows compensated partial sums (workspace);
+                         // kCsrTiled: nt x rows
     // kCsrSell: slice s (rows 64 s .. 64 s + 63) holds slots [so[s], so[s + 1]),
     // position k of row 64 s + i at slot so[s] + 64 k + i; a row's entries keep
     // their CSR order, and the slots past its end hold column -1, value 0
     const int64_t *so;
     const int32_t *sc;
     const double *sv;
+    // kCsrTiled: the entries of tile q (columns q kTileW .. q kTileW + kTileW - 1)
+    // stored tile after tile, rows in order inside a tile; the run of row r in
+    // tile q is [rp[q rows + r], rp[q rows + r + 1]), its columns in lc as
+    // offsets from the tile start (ascending), its values in val.  A block
+    // takes the rows [c rchunk, c rchunk + rchunk) of one tile.
+    const uint16_t *lc;
+    int32_t nt;       // tiles
+    int32_t nchunk;   // row chunks per tile
+    int64_t rchunk;   // rows per chunk
 };
 
 // ---- launchers (kernels.hip); each returns the grid size it used in *blocks ----
@@ -205,6 +225,12 @@ hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
                             const int32_t *ci, int32_t *flag, hipStream_t s);
 hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,
                                  int64_t cols, int32_t *seg, hipStream_t s);
+// Tile-major copy of a CSR whose columns are sorted inside each row (the
+// kCsrTiled layout): trp (nt rows + 1), lc and tval (nnz each).  work:
+// nt rows + cdiv(nt rows, 1024) + 8 int32 entries.
+hipError_t launch_tile_build(int64_t rows, int64_t cols, const int32_t *rp, const int32_t *ci_sorted,
+                             const double *val_sorted, int32_t *trp, uint16_t *lc, double *tval,
+                             int32_t *work, hipStream_t s);
 hipError_t launch_norm2(int64_t n, const double *x, const Out &o, hipStream_t s,
                         int32_t *blocks);
 hipError_t launch_csr_outer(int64_t m, const int32_t *rp, const int32_t *ci, const double *u,

@@ -701,6 +701,150 @@ __global__ __launch_bounds__(kBlock) void k_slices_combine(MatView M, double *y,
     block_partials<EpiNV<EPI>::value>(v, o);
 }
 
+// ---------------------------------------------------------------------------
+// Column tiles staged in LDS (kCsrTiled).  A block copies one tile of x
+// (kTileW consecutive entries, coalesced) into LDS and then walks the runs
+// of its chunk of rows inside that tile, W lanes per row, gathering from
+// LDS: the gathers no longer cost one L2 request per nonzero.  The blocks of
+// one tile are consecutive logical blocks, hence on one XCD, so the tile is
+// fetched from memory once per XCD and re-read from its L2.  The entries
+// and their 16-bit local columns are read non-temporally.  Each
+// (tile, row) partial is an unrounded compensated pair; the combine kernel
+// merges a row's tiles and runs the epilogue.
+// ---------------------------------------------------------------------------
+// One batch of a tiled block (tile_pr(W) row passes): the run bounds of
+// every pass, then rounds of tile_u(W) entries per lane for all passes at
+// once until every run is done (a row of n entries takes ceil(n / (U W))
+// rounds), then the group reductions and the partial stores.  `stage` runs
+// between the first round's loads and its use of the LDS tile (the first
+// batch copies the tile there while its loads are in flight).  A lane's
+// terms are summed in storage order (k, k + W, ...); the W lanes of a row
+// stay together, so the group reduction sees all of them.
+template <int W, int EPI, class Stage>
+__device__ __forceinline__ void tiled_batch(const MatView &M, const int32_t *rp, double2 *yp,
+                                            const double *xs, int64_t rb, int64_t r1, int lane,
+                                            Stage &&stage) {
+    constexpr int G = kTileBlock / W, U = tile_u(W), PR = tile_pr(W);
+    constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
+    int32_t sk[PR], ek[PR];
+#pragma unroll
+    for (int p = 0; p < PR; ++p) {
+        const int64_t row = rb + p * G;
+        sk[p] = row < r1 ? rp[row] : 0;
+        ek[p] = row < r1 ? rp[row + 1] : 0;
+    }
+    Acc acc[PR];
+#pragma unroll
+    for (int p = 0; p < PR; ++p) acc[p] = Acc{0.0, 0.0};
+    bool first = true;
+    for (int32_t off = lane;; off += U * W) {
+        int cl[PR][U];
+        double a[PR][U];
+        bool more = false;
+#pragma unroll
+        for (int p = 0; p < PR; ++p) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int32_t k = sk[p] + off + u * W;
+                cl[p][u] = -1;
+                a[p][u] = 0.0;
+                if (k < ek[p]) {
+                    cl[p][u] = (int)__builtin_nontemporal_load(M.lc + k);
+                    a[p][u] = __builtin_nontemporal_load(M.val + k);
+                }
+            }
+            more |= sk[p] + (off - lane) + U * W < ek[p];
+        }
+        if (first) {
+            stage();
+            first = false;
+        }
+#pragma unroll
+        for (int p = 0; p < PR; ++p)
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (cl[p][u] >= 0) acc_fma(acc[p], sgn * a[p][u], xs[cl[p][u]]);
+        if (!more) break;
+    }
+#pragma unroll
+    for (int p = 0; p < PR; ++p) {
+        const int64_t row = rb + p * G;
+        if (row < r1) {
+            const Acc v = group_reduce<W>(acc[p]);
+            if (lane == 0) yp[row] = make_double2(v.p, v.s);
+        }
+    }
+}
+
+template <int W, int EPI>
+__global__ __launch_bounds__(kTileBlock) void k_rows_tiled(MatView M, const double *__restrict__ x,
+                                                            Out o) {
+    __shared__ double xs[kTileW];
+    if (!producer_runs(o)) return;
+    const int64_t L = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t q = L / M.nchunk;
+    const int64_t c0 = q * kTileW;
+    const int wq = (int)min((int64_t)kTileW, M.cols - c0);
+    constexpr int NS = kTileW / kTileBlock;
+    double t[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+        const int j = (int)threadIdx.x + i * kTileBlock;
+        t[i] = j < wq ? x[c0 + j] : 0.0;
+    }
+    const int lane = threadIdx.x % W;
+    const int64_t r0 = (L % M.nchunk) * M.rchunk;
+    const int64_t r1 = min(M.rows, r0 + M.rchunk);
+    const int32_t *rp = M.rp + q * M.rows;
+    double2 *yp = M.ypart + q * M.rows;
+    // the first batch: every thread takes part (rows past r1 predicated off)
+    // because the block-wide barrier that publishes the tile sits inside it
+    const int64_t rb0 = r0 + threadIdx.x / W;
+    tiled_batch<W, EPI>(M, rp, yp, xs, rb0, r1, lane, [&] {
+#pragma unroll
+        for (int i = 0; i < NS; ++i) xs[threadIdx.x + i * kTileBlock] = t[i];
+        __syncthreads();
+    });
+    for (int64_t rb = rb0 + tile_batch_rows(W); rb < r1; rb += tile_batch_rows(W))
+        tiled_batch<W, EPI>(M, rp, yp, xs, rb, r1, lane, [] {});
+}
+
+// kCombineLanes lanes per row: lane l merges the partials of tiles l,
+// l + kCombineLanes, ... in tile order, the lanes are merged by the group
+// reduction, then (for the residual) b is merged in front.
+constexpr int kCombineLanes = 8;
+
+template <int EPI>
+__global__ __launch_bounds__(kBlock) void k_tiles_combine(MatView M, double *y, EpiArgs ea,
+                                                           Out o) {
+    if (!producer_runs(o)) return;
+    constexpr int CW = kCombineLanes;
+    constexpr int U = 8;
+    const int lane = threadIdx.x % CW;
+    const int64_t row = (int64_t)blockIdx.x * (kBlock / CW) + threadIdx.x / CW;
+    Acc a = {0.0, 0.0};
+    if (row < M.rows) {
+        for (int64_t q0 = lane; q0 < M.nt; q0 += U * CW) {
+            double2 p[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t q = q0 + u * CW;
+                p[u] = q < M.nt ? M.ypart[q * M.rows + row] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (q0 + u * CW < M.nt) a = acc_merge(a, Acc{p[u].x, p[u].y});
+        }
+    }
+    a = group_reduce<CW>(a);
+    Acc v[EpiNV<EPI>::value] = {};
+    if (row < M.rows && lane == 0) {
+        if constexpr (EPI == kEpiResid) a = acc_merge(Acc{ea.b[row], 0.0}, a);
+        epilogue<EPI>(row, acc_val(a), y, ea, o.st, v);
+    }
+    block_partials<EpiNV<EPI>::value>(v, o);
+}
+
 // First entry of each column slice inside each row of a column-sorted CSR.
 __global__ void k_slice_segments(int64_t m, const int32_t *__restrict__ rp,
                                  const int32_t *__restrict__ ci, int64_t slice_w, int32_t *seg) {
@@ -1082,6 +1226,7 @@ int64_t matvec_blocks(const MatView &M) {
         case kDenseCols: return cdiv(rows, kBlock);
         case kDenseRows: return cdiv(rows, kBlock / 64);
         case kCsrSliced: return elementwise_blocks(rows);  // the combine kernel
+        case kCsrTiled: return cdiv(rows, kBlock / kCombineLanes);  // the combine kernel
         case kCsrSell: return cdiv(rows, kBlock);
         default: return M.lanes > 1 ? cdiv(rows, kBlock / M.lanes) : cdiv(rows, kBlock);
     }
@@ -1116,6 +1261,20 @@ static void launch_sliced(const MatView &M, const double *x, const EpiArgs &ea, 
 }
 
 template <int EPI>
+static void launch_tiled(const MatView &M, const double *x, const Out &o, hipStream_t s) {
+    const dim3 grid((unsigned)((int64_t)M.nt * M.nchunk));
+    switch (M.lanes) {
+        case 1: k_rows_tiled<1, EPI><<<grid, kTileBlock, 0, s>>>(M, x, o); break;
+        case 2: k_rows_tiled<2, EPI><<<grid, kTileBlock, 0, s>>>(M, x, o); break;
+        case 4: k_rows_tiled<4, EPI><<<grid, kTileBlock, 0, s>>>(M, x, o); break;
+        case 8: k_rows_tiled<8, EPI><<<grid, kTileBlock, 0, s>>>(M, x, o); break;
+        case 16: k_rows_tiled<16, EPI><<<grid, kTileBlock, 0, s>>>(M, x, o); break;
+        case 32: k_rows_tiled<32, EPI><<<grid, kTileBlock, 0, s>>>(M, x, o); break;
+        default: k_rows_tiled<64, EPI><<<grid, kTileBlock, 0, s>>>(M, x, o); break;
+    }
+}
+
+template <int EPI>
 static void launch_matvec_t(const MatView &M, const double *x, double *y, const EpiArgs &ea,
                             const Out &o, hipStream_t s, dim3 grid) {
     switch (M.kind) {
@@ -1129,6 +1288,10 @@ static void launch_matvec_t(const MatView &M, const double *x, double *y, const 
         case kCsrSliced:
             launch_sliced<EPI>(M, x, ea, o, s);
             k_slices_combine<EPI><<<grid, kBlock, 0, s>>>(M, y, ea, o);
+            break;
+        case kCsrTiled:
+            if (M.rows > 0 && M.nt > 0) launch_tiled<EPI>(M, x, o, s);
+            k_tiles_combine<EPI><<<grid, kBlock, 0, s>>>(M, y, ea, o);
             break;
         case kCsrSell: k_sell<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
         default:
@@ -1312,6 +1475,64 @@ hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
                                                                         n_long, flag);
     k_tr_sort_long<<<1024, kBlock, 0, s>>>(at_rp, src, long_rows, n_long);
     if (nnz > 0) k_tr_fill<<<gn, kBlock, 0, s>>>(m, nnz, rp, val, src, at_ci, at_val);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Tile-major copy of a column-sorted CSR (kCsrTiled): the run length of
+// every (tile, row), an exclusive scan of the lengths in tile-major order,
+// then each row's entries copied to their run with the column made local to
+// the tile.  One thread per row; runs are contiguous because the columns
+// are sorted, and each (tile, row) slot has one writer.
+// ---------------------------------------------------------------------------
+__global__ void k_tile_count(int64_t rows, const int32_t *__restrict__ rp,
+                             const int32_t *__restrict__ ci, int32_t *cnt) {
+    for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row < rows;
+         row += (int64_t)gridDim.x * kBlock) {
+        const int32_t e = rp[row + 1];
+        for (int32_t k = rp[row]; k < e;) {
+            const int32_t q = ci[k] / kTileW;
+            int32_t k1 = k + 1;
+            while (k1 < e && ci[k1] / kTileW == q) ++k1;
+            cnt[(int64_t)q * rows + row] = k1 - k;
+            k = k1;
+        }
+    }
+}
+
+__global__ void k_tile_fill(int64_t rows, const int32_t *__restrict__ rp,
+                            const int32_t *__restrict__ ci, const double *__restrict__ val,
+                            const int32_t *__restrict__ trp, uint16_t *lc, double *tval) {
+    for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row < rows;
+         row += (int64_t)gridDim.x * kBlock) {
+        const int32_t e = rp[row + 1];
+        for (int32_t k = rp[row]; k < e;) {
+            const int32_t q = ci[k] / kTileW;
+            int32_t pos = trp[(int64_t)q * rows + row];
+            for (; k < e && ci[k] / kTileW == q; ++k, ++pos) {
+                lc[pos] = (uint16_t)(ci[k] - q * kTileW);
+                tval[pos] = val[k];
+            }
+        }
+    }
+}
+
+hipError_t launch_tile_build(int64_t rows, int64_t cols, const int32_t *rp, const int32_t *ci_sorted,
+                             const double *val_sorted, int32_t *trp, uint16_t *lc, double *tval,
+                             int32_t *work, hipStream_t s) {
+    const int64_t N = cdiv(cols > 0 ? cols : 1, kTileW) * rows;
+    if (N <= 0) return hipSuccess;
+    const int64_t ntiles = cdiv(N, kScanTile);
+    int32_t *cnt = work;
+    int32_t *tiles = cnt + N;
+    hipError_t e;
+    if ((e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)N, s)) != hipSuccess) return e;
+    const dim3 gr((unsigned)elementwise_blocks(rows));
+    k_tile_count<<<gr, kBlock, 0, s>>>(rows, rp, ci_sorted, cnt);
+    k_scan_tiles<<<(unsigned)ntiles, kBlock, 0, s>>>(N, cnt, trp, tiles);
+    k_scan_sums<<<1, kBlock, 0, s>>>(ntiles, tiles, trp + N);
+    k_scan_add<<<(unsigned)elementwise_blocks(N), kBlock, 0, s>>>(N, trp, tiles);
+    k_tile_fill<<<gr, kBlock, 0, s>>>(rows, rp, ci_sorted, val_sorted, trp, lc, tval);
     return hipGetLastError();
 }
 

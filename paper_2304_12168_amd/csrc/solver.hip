@@ -99,10 +99,56 @@ static int pick_lanes(int64_t nnz, int64_t rows) {
     return 64;
 }
 
-// Matrices whose rows hold more nonzeros than this per row, on average, get
-// lanes-per-row kernels; with at least kSliceMinCols columns they are also
-// split into XCD column slices so the gathered x stays in L2.
+// Matrices whose rows hold more nonzeros than 16 per row, on average, get
+// lanes-per-row kernels.  With at least kTileMinCols columns and runs of at
+// least kTileMinRun entries per (column tile, row) on average they are
+// regrouped by column tiles whose x is staged in LDS; otherwise, with at
+// least kSliceMinCols columns, they are split into XCD column slices so the
+// gathered x stays in L2.  (The tiles trade one L2 request per nonzero for
+// a partial sum per (tile, row): they pay while the runs are long enough.)
 constexpr int64_t kSliceMinCols = 1 << 17;
+constexpr int64_t kTileMinCols = 2 * kTileW;
+constexpr int64_t kTileMinRun = 3;
+#ifndef TA_TILE_BLOCKS
+#define TA_TILE_BLOCKS 2048
+#endif
+
+static int64_t n_tiles(int64_t cols) { return (cols + kTileW - 1) / kTileW; }
+
+static bool use_tiles(int64_t nnz, int64_t rows, int64_t cols) {
+    if (rows <= 0 || cols < kTileMinCols) return false;
+    const int64_t runs = n_tiles(cols) * rows;
+    return runs * kTileMinRun <= nnz && runs < (int64_t(1) << 30);
+}
+
+// Lanes per row for the tiled kernel (the fewest, from 2, with 4 W at least
+// the average run; W = 2 puts a run of up to 8 entries in one round), and
+// the row chunks: about TA_TILE_BLOCKS blocks in all (measured
+// on the 10000 x 1e6 LP shape: 2048 blocks of one or two batches beat 1024
+// or 4096), each chunk a whole number of the block's batches.
+static MatView tiled_view(int64_t rows, int64_t cols, int64_t nnz, const int32_t *trp,
+                          const uint16_t *lc, const double *tval) {
+    const int64_t nt = n_tiles(cols);
+    const double run = (double)nnz / (double)(nt * rows);
+#ifdef TA_TILE_LANES
+    const int W = TA_TILE_LANES;
+#else
+    int W = 2;
+    while (W < 64 && 4.0 * W < run) W *= 2;
+#endif
+    const int64_t G = tile_batch_rows(W);
+    int64_t nchunk = std::max<int64_t>(1, (TA_TILE_BLOCKS + nt - 1) / nt);
+    nchunk = std::min(nchunk, (rows + G - 1) / G);
+    int64_t rchunk = (rows + nchunk - 1) / nchunk;
+    rchunk = (rchunk + G - 1) / G * G;
+    nchunk = (rows + rchunk - 1) / rchunk;
+    MatView v{kCsrTiled, rows, cols, 0, trp, nullptr, tval, W, nullptr, nullptr};
+    v.lc = lc;
+    v.nt = (int32_t)nt;
+    v.nchunk = (int32_t)nchunk;
+    v.rchunk = rchunk;
+    return v;
+}
 
 // ---------------------------------------------------------------------------
 // Plan: a prepared operator.  Holds A^T (canonical CSR built on the device)
@@ -226,14 +272,17 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
     }
     const int64_t nnz = M->nnz;
     const int la = pick_lanes(nnz, m), lt = pick_lanes(nnz, n);
-    const bool slice_a = need_t && la > 1 && n >= kSliceMinCols;
-    const bool slice_t = need_t && lt > 1 && m >= kSliceMinCols;
+    const bool tile_a = need_t && la > 1 && use_tiles(nnz, m, n);
+    const bool tile_t = need_t && lt > 1 && use_tiles(nnz, n, m);
+    const bool slice_a = need_t && la > 1 && !tile_a && n >= kSliceMinCols;
+    const bool slice_t = need_t && lt > 1 && !tile_t && m >= kSliceMinCols;
 
     // owned memory
     Workspace own(s);
     int32_t *at_rp = nullptr, *at_ci = nullptr, *ac_ci = nullptr, *a_seg = nullptr,
-            *t_seg = nullptr;
-    double *at_val = nullptr, *ac_val = nullptr;
+            *t_seg = nullptr, *a_trp = nullptr, *t_trp = nullptr;
+    double *at_val = nullptr, *ac_val = nullptr, *a_tv = nullptr, *t_tv = nullptr;
+    uint16_t *a_lc = nullptr, *t_lc = nullptr;
     if (need_t) {
         own.reserve(&at_rp, n + 1);
         own.reserve(&at_ci, nnz);
@@ -245,14 +294,32 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
         own.reserve(&a_seg, m * (kSlices + 1));
     }
     if (slice_t) own.reserve(&t_seg, n * (kSlices + 1));
-    // temporary memory
+    if (tile_a) {
+        own.reserve(&a_trp, n_tiles(n) * m + 1);
+        own.reserve(&a_lc, nnz);
+        own.reserve(&a_tv, nnz);
+    }
+    if (tile_t) {
+        own.reserve(&t_trp, n_tiles(m) * n + 1);
+        own.reserve(&t_lc, nnz);
+        own.reserve(&t_tv, nnz);
+    }
+    // temporary memory (a tiled A takes its column-sorted copy from here)
     Workspace tmp(s);
     int32_t *flag = nullptr, *work = nullptr, *ac_rp = nullptr;
     const int64_t mx = std::max(m, n);
     const int64_t ntiles = (std::max<int64_t>(mx, 1) + 1023) / 1024;
+    int64_t runs = 0;
+    if (tile_a) runs = std::max(runs, n_tiles(n) * m);
+    if (tile_t) runs = std::max(runs, n_tiles(m) * n);
     tmp.reserve(&flag, 8);
-    if (need_t) tmp.reserve(&work, 2 * mx + ntiles + 8 + nnz);
-    if (slice_a) tmp.reserve(&ac_rp, m + 1);
+    if (need_t)
+        tmp.reserve(&work, std::max(2 * mx + ntiles + 8 + nnz, runs + (runs + 1023) / 1024 + 8));
+    if (slice_a || tile_a) tmp.reserve(&ac_rp, m + 1);
+    if (tile_a) {
+        tmp.reserve(&ac_ci, nnz);
+        tmp.reserve(&ac_val, nnz);
+    }
     if ((rc = own.commit()) != TA_OK) return rc;
     if ((rc = tmp.commit()) != TA_OK) return rc;
     if ((rc = check_csr_device(M, flag, s)) != TA_OK) return rc;
@@ -262,18 +329,28 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
         HIP_TRY(launch_transpose(m, n, nnz, M->row_ptr, M->col_idx, M->val, at_rp, at_ci, at_val,
                                  work, flag, s));
         P->AT = MatView{kCsrRows, n, m, 0, at_rp, at_ci, at_val, lt, nullptr, nullptr};
-        if (slice_a) {
+        if (slice_a || tile_a) {
             // (A^T)^T: A with columns sorted inside each row
             HIP_TRY(launch_transpose(n, m, nnz, at_rp, at_ci, at_val, ac_rp, ac_ci, ac_val, work,
                                      flag, s));
+        }
+        if (slice_a) {
             HIP_TRY(launch_slice_segments(m, M->row_ptr, ac_ci, n, a_seg, s));
             P->A = MatView{kCsrSliced, m, n, 0, M->row_ptr, ac_ci, ac_val,
                            pick_slice_lanes(nnz, m), a_seg, nullptr};
+        }
+        if (tile_a) {
+            HIP_TRY(launch_tile_build(m, n, ac_rp, ac_ci, ac_val, a_trp, a_lc, a_tv, work, s));
+            P->A = tiled_view(m, n, nnz, a_trp, a_lc, a_tv);
         }
         if (slice_t) {
             HIP_TRY(launch_slice_segments(n, at_rp, at_ci, m, t_seg, s));
             P->AT = MatView{kCsrSliced, n, m, 0, at_rp, at_ci, at_val, pick_slice_lanes(nnz, n),
                             t_seg, nullptr};
+        }
+        if (tile_t) {
+            HIP_TRY(launch_tile_build(n, m, at_rp, at_ci, at_val, t_trp, t_lc, t_tv, work, s));
+            P->AT = tiled_view(n, m, nnz, t_trp, t_lc, t_tv);
         }
         int32_t h = 0;
         HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -308,6 +385,9 @@ struct Chain {
         if (A.kind == kCsrSliced) ws.reserve(&A.ypart, kSlices * std::max<int64_t>(A.rows, 1));
         if (P.has_t && AT.kind == kCsrSliced)
             ws.reserve(&AT.ypart, kSlices * std::max<int64_t>(AT.rows, 1));
+        if (A.kind == kCsrTiled) ws.reserve(&A.ypart, (int64_t)A.nt * std::max<int64_t>(A.rows, 1));
+        if (P.has_t && AT.kind == kCsrTiled)
+            ws.reserve(&AT.ypart, (int64_t)AT.nt * std::max<int64_t>(AT.rows, 1));
     }
     Out out(int32_t slot, int32_t gate) const {
         Out o;
@@ -1166,7 +1246,7 @@ int ta_plan_format(const ta_plan *plan, int32_t trans, int32_t *format) {
     if (plan == nullptr || format == nullptr) return TA_EINVAL;
     static_assert(ta::kCsrRows == TA_FMT_CSR_ROWS && ta::kDenseRows == TA_FMT_DENSE_ROWS &&
                       ta::kDenseCols == TA_FMT_DENSE_COLS && ta::kCsrSliced == TA_FMT_CSR_SLICED &&
-                      ta::kCsrSell == TA_FMT_SELL64,
+                      ta::kCsrSell == TA_FMT_SELL64 && ta::kCsrTiled == TA_FMT_CSR_TILED,
                   "storage kinds");
     *format = trans ? plan->p.AT.kind : plan->p.A.kind;
     return TA_OK;

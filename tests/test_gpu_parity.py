@@ -344,14 +344,9 @@ def test_dense_500_first_iterations():
 
 
 # ---------------------------------------------------------------------------
-# prepared operators and the XCD column-sliced kernels
+# prepared operators, the LDS column-tiled and the XCD column-sliced kernels
 # ---------------------------------------------------------------------------
-def _wide():  # 600 nonzeros per row, 200k columns: A is split into column slices
-    return lp_shaped(2000, 200_000, seed=5)
-
-
-def _tall():  # its transpose: A^T has the long rows and is the sliced operand
-    p = _wide()
+def _transpose(p):  # A^T has the long rows and is the regrouped operand
     At = p.A.to_scipy().T.tocsr()
     At.sort_indices()
     A = Csr(At.shape[0], At.shape[1], At.indptr.astype(np.int32), At.indices.astype(np.int32),
@@ -360,11 +355,58 @@ def _tall():  # its transpose: A^T has the long rows and is the sliced operand
     return type("Pb", (), {"A": A, "b": A.to_scipy() @ xs})()
 
 
-@pytest.mark.parametrize("make", [_wide, _tall], ids=["wide_sliced_A", "tall_sliced_AT"])
-def test_sliced_products_match_oracle(make):
+def _wide():  # 600 nonzeros per row, 200k columns: 25 tiles, ~24 entries per (row, tile)
+    return lp_shaped(2000, 200_000, seed=5)
+
+
+def _wide_sliced():  # 61 per row over 25 tiles is too thin for tiles: column slices
+    return lp_shaped(20_000, 200_000, seed=6)
+
+
+def _ragged_tiles():
+    """3 tiles (20000 columns, the last one ragged), ~200 entries per row at
+    random columns, every 7th row and the last row empty, a few rows whose
+    entries all fall in one tile."""
+    g = np.random.default_rng(21)
+    m, n = 301, 20_000
+    rows, cols = [], []
+    for i in range(m):
+        if i % 7 == 3 or i == m - 1:
+            continue
+        if i % 11 == 5:
+            c = g.choice(np.arange(8192, 16384), size=150, replace=False)
+        else:
+            c = g.choice(n, size=int(g.integers(150, 250)), replace=False)
+        rows += [i] * len(c)
+        cols += list(c)
+    A = csr_from_coo(m, n, np.array(rows), np.array(cols), g.standard_normal(len(rows)))
+    x = g.standard_normal(n)
+    return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
+
+
+REGROUPED = {
+    "wide_tiled_A": (_wide, ("csr_tiled", None)),
+    "tall_tiled_AT": (lambda: _transpose(_wide()), (None, "csr_tiled")),
+    "ragged_tiled_A": (_ragged_tiles, ("csr_tiled", None)),
+    "wide_sliced_A": (_wide_sliced, ("csr_sliced", None)),
+    "tall_sliced_AT": (lambda: _transpose(_wide_sliced()), (None, "csr_sliced")),
+}
+
+
+def _plan_checked(make, fmt):
     p = make()
+    pl = P.plan(p.A)
+    for trans, f in ((False, fmt[0]), (True, fmt[1])):
+        if f is not None:
+            assert pl.format(trans) == f
+    return p, pl
+
+
+@pytest.mark.parametrize("case", sorted(REGROUPED))
+def test_regrouped_products_match_oracle(case):
+    make, fmt = REGROUPED[case]
+    p, pl = _plan_checked(make, fmt)
     A = p.A
-    pl = P.plan(A)
     g = np.random.default_rng(4)
     x = g.standard_normal(A.n)
     u = g.standard_normal(A.m)
@@ -375,16 +417,19 @@ def test_sliced_products_match_oracle(make):
     pl.close()
 
 
-@pytest.mark.parametrize("make", [_wide, _tall], ids=["wide_sliced_A", "tall_sliced_AT"])
-def test_sliced_solves_match_oracle(make):
-    p = make()
-    pl = P.plan(p.A)
+@pytest.mark.parametrize("case", sorted(REGROUPED))
+def test_regrouped_solves_match_oracle(case):
+    make, fmt = REGROUPED[case]
+    p, pl = _plan_checked(make, fmt)
     g = P.cta_minnorm(pl, p.b, tol=1e-10, t=3, max_iter=200)
     o = oracle.cta_minnorm(p.A, p.b, tol=1e-10, t=3, max_iter=200)
     _compare(g, o)
     g = P.cta_solve(pl, p.b, tol=1e-10, t=2, max_iter=200)
     o = oracle.cta(p.A, p.b, tol=1e-10, t=2, max_iter=200)
     _compare(g, o)
+    g = P.ta_solve(pl, p.b, tol=1e-3, max_iter=300)
+    o = oracle.ta(p.A, p.b, tol=1e-3, max_iter=300)
+    _compare(g, o, x_rtol=1e-9)
     pl.close()
 
 
