@@ -168,6 +168,15 @@ def batched_uneven_bench(args, P, torch, dev, pool=None):
     stencil_its = sum(s for _, s in sums) / elapsed
     rand_iters = sorted(i.iters for s, inf in enumerate(runs[-1]) for i in inf
                         if bt.kinds[s] == "random" and i.stop == "residual")
+    # what per-column masks could skip: a system runs until its last column
+    # stops, so each earlier-stopping column idles (max - its count) iterations
+    idle = busy = 0
+    for s, inf in enumerate(runs[-1]):
+        if inf:
+            top = max(i.iters for i in inf)
+            idle += sum(top - i.iters for i in inf)
+            busy += top * len(inf)
+    idle_frac = idle / busy if busy else 0.0
     x_mixed = [x.cpu().numpy() for x in last_x[0]]  # the last timed step's solutions
     # bytes the step's matrix products move (algorithmic): per system, 2t passes
     # over its matrix per iteration while any column is active, and per column
@@ -306,6 +315,7 @@ def batched_uneven_bench(args, P, torch, dev, pool=None):
             "budget": budget, "seed": args.seed, "precision": args.precision,
             "columns_converged_per_step": conv // args.steps,
             "random_iterations_median": rand_iters[len(rand_iters) // 2] if rand_iters else None,
+            "stopped_column_idle_fraction": idle_frac,
             "stencil_iterations_per_s": stencil_its, "plan_ms": plan_ms,
             "fp64_batched_columns_per_s": conv64 / b64_s,
             "bf16_batched": bf16,
