@@ -712,6 +712,34 @@ def hbm_sweep_bench(args, P, torch, dev):
     return out
 
 
+def dense_products_bench(args, P, torch, dev):
+    """Secondary: the dense multi-right-hand-side products (matrix cores for
+    BF16 / FP32, the compensated CSR copy for FP64) on 4 dense Gaussian
+    systems of 4096^2, A pass at K = 64, 16 and 1, HIP events through the
+    library's hook; bytes = the matrix in its precision plus the input and
+    output blocks, flops = 2 n^2 K per system."""
+    import numpy as np
+
+    n, nsys = 4096, 4
+    g = np.random.default_rng([args.seed, 4096])
+    mats = [g.standard_normal((n, n)) for _ in range(nsys)]
+    out = []
+    for prec, vb, xb in (("bf16", 2, 4), ("fp32", 4, 4), ("fp64", 8, 8)):
+        plan = P.BatchPlan(mats, prec)
+        for K in (64, 16, 1):
+            ms = P.batch_time_spmm(plan, K, trans=False, precision=prec, reps=args.reps)
+            by = nsys * (n * n * vb + 2 * n * K * xb)
+            fl = nsys * 2 * n * n * K
+            out.append({"precision": prec, "K": K, "us": ms * 1e3, "TFLOP_s": fl / ms / 1e9,
+                        "GB_s": by / ms / 1e6, "hbm_bound_us": by / HBM_PEAK_GBS / 1e3,
+                        "frac": by / ms / 1e6 / HBM_PEAK_GBS})
+            log(f"[bench] dense {nsys} x {n}^2 {prec} K={K}: {ms * 1e3:.1f} us, "
+                f"{fl / ms / 1e9:.1f} TFLOP/s, {by / ms / 1e6:.0f} GB/s")
+        plan.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -736,8 +764,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 batched leg")
     ap.add_argument("--sweep-only", action="store_true",
-                    help="only the HBM-resident size sweep of the product kernels (for "
-                         "profiling them), printed as one JSON line")
+                    help="only the HBM-resident size sweep of the product kernels and the "
+                         "dense products (for profiling them), printed as one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device three times (the reference kernel "
                          "that scales the HBM traffic counters) and exit")
@@ -774,7 +802,9 @@ def main():
     torch.cuda.set_device(dev)
 
     if args.sweep_only:
-        print(json.dumps({"hbm_sweep": hbm_sweep_bench(args, P, torch, dev)}), flush=True)
+        print(json.dumps({"hbm_sweep": hbm_sweep_bench(args, P, torch, dev),
+                          "dense_products": dense_products_bench(args, P, torch, dev)}),
+              flush=True)
         return
     res = batched_uneven_bench(args, P, torch, dev, pool)
     if pool is not None:
@@ -789,6 +819,7 @@ def main():
         res["config"]["configs"] = configs_bench(args, P, torch, dev)
     if not args.no_sweep:
         res["config"]["hbm_sweep"] = hbm_sweep_bench(args, P, torch, dev)
+        res["config"]["dense_products"] = dense_products_bench(args, P, torch, dev)
     out = {
         "metric": "solves/s and HBM GB/s to rel-residual 1e-6: CTA mixed+batched vs FP64 plain",
         "value": res["value"],

@@ -617,7 +617,11 @@ struct DSys {
     int32_t cols;  // columns of the matrix = rows of the input block it multiplies
     int32_t x0;    // the system's first row in the input block
     int32_t y0;    // the system's first row in the output block
+    int32_t xt0;   // the system's first entry in each row of the transposed input (XT)
 };
+
+// Entries per row of the system in XT: its row stride rounded up to a stage.
+__host__ __device__ inline int32_t xt_len(int32_t ld) { return (ld + 63) / 64 * 64; }
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
@@ -669,6 +673,42 @@ struct MfmaOp<uint16_t> {
     }
 };
 
+// The input block of a dense product, transposed and converted once per
+// product for the matrix cores: XT[c * ldxt + xt0 + k] = X[x0 + k][c] (the
+// instruction's input type) for the KP = 16 ceil(K / 16) columns c and the
+// xt_len(ld) inputs k of each system, zero past the system's columns and
+// past K.  Every workgroup of the product then stages its slices of XT with
+// plain 16-byte copies instead of converting and transposing X itself.
+template <typename V, typename X, int K>
+__global__ __launch_bounds__(kBlock) void k_bxprep(const X *__restrict__ x,
+                                                    const DSys *__restrict__ dsys, int64_t ldxt,
+                                                    typename MfmaOp<V>::In *xt) {
+    // a block moves a tile of 64 inputs k by 16 columns c of one system
+    // through LDS: reads along the rows of X, writes along the rows of XT
+    using Op = MfmaOp<V>;
+    using In = typename Op::In;
+    constexpr int NCT = (K + 15) / 16;  // column tiles
+    constexpr int TK = 64;
+    __shared__ In sh[16][TK + 1];
+    const DSys ds = dsys[blockIdx.y];
+    const int32_t len = xt_len(ds.ld);
+    const int c0 = 16 * (int)(blockIdx.x % NCT);
+    for (int32_t k0 = (int32_t)(blockIdx.x / NCT) * TK; k0 < len;
+         k0 += (int32_t)(gridDim.x / NCT) * TK) {
+        for (int e = threadIdx.x; e < TK * 16; e += kBlock) {
+            const int k = e / 16, c = e % 16;
+            const bool in = k0 + k < ds.cols && c0 + c < K;
+            sh[c][k] = Op::conv(in ? x[((int64_t)ds.x0 + k0 + k) * K + c0 + c] : X(0));
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < TK * 16; e += kBlock) {
+            const int c = e / TK, k = e % TK;
+            xt[(int64_t)(c0 + c) * ldxt + ds.xt0 + k0 + k] = sh[c][k];
+        }
+        __syncthreads();
+    }
+}
+
 // Split over the matrix columns: with nseg > 1, workgroup b takes tile
 // b / nseg and the seg = b % nseg-th share of the columns (a multiple of 16),
 // and writes its raw sums to part_y[seg][row][c] (rows of the whole output
@@ -676,7 +716,8 @@ struct MfmaOp<uint16_t> {
 template <typename V, typename X, int K, int EPI>
 __global__ __launch_bounds__(kBlock) void k_bgemm(const V *__restrict__ mat,
                                                    const DSys *__restrict__ dsys,
-                                                   const X *__restrict__ x, X *y,
+                                                   const typename MfmaOp<V>::In *__restrict__ xt,
+                                                   int64_t ldxt, X *y,
                                                    const double *__restrict__ b,
                                                    const BRange *__restrict__ blocks, Groups gs,
                                                    double2 *partials, int64_t cap, int32_t slot,
@@ -696,54 +737,40 @@ __global__ __launch_bounds__(kBlock) void k_bgemm(const V *__restrict__ mat,
     const DSys ds = dsys[br.sys];
     const int32_t klen = ((ds.ld / 16 + nseg - 1) / nseg) * 16;
     const int32_t k_lo = min(seg * klen, ds.ld), k_hi = min(k_lo + klen, ds.ld);
+    const int32_t k_end = xt_len(ds.ld);  // the system's entries in a row of XT
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int li = lane % 16, g = lane / 16;
     const int64_t arow = (int64_t)br.r0 + wave * 16 + li;  // this lane's A-operand row
     const bool arow_ok = arow < br.r1;
     const V *mrow = mat + ds.off + (arow_ok ? (arow - ds.y0) : 0) * (int64_t)ds.ld;
     // A stage covers KB = 64 matrix columns: lane group g holds columns
-    // kb + 16 g + [0, 16) of its row and feeds them as 4 sub-steps of 4.
+    // kb + 16 g + [0, 16) of its row and feeds them as 4 sub-steps of 4; the
+    // XT slice of the stage is KP rows of KB entries, copied in 16-byte
+    // vectors.  The next stage's A entries and XT vectors are loaded into
+    // registers while the current stage's products run.
     constexpr int KB = 64;
-    constexpr int LSB = KB + (sizeof(In) == 8 ? 2 : 4);  // LDS column stride (padded)
-    __shared__ In bt[KP * LSB];  // X slice, bt[c * LSB + k]
+    constexpr int EV = 16 / (int)sizeof(In);               // entries per 16-byte vector
+    constexpr int VR = KB / EV;                            // vectors per XT row of a stage
+    constexpr int NXV = (KP * VR + kBlock - 1) / kBlock;   // vectors per thread
+    constexpr int LSB = KB + EV;  // LDS row stride (entries): 16-byte aligned, odd in vectors
+    __shared__ __attribute__((aligned(16))) In bt[KP * LSB];  // bt[c * LSB + k]
     typename Op::Acc4 acc[NT];
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[ct][v] = 0;
-    for (int kb = k_lo; kb < k_hi; kb += KB) {
-        // stage X[kb .. kb+KB)[0 .. KP) (zero outside the share, the system or K),
-        // 4 consecutive columns per thread when K allows
-        constexpr int CW = K >= 4 ? 4 : 1;
-        for (int e = threadIdx.x; e < KB * KP / CW; e += kBlock) {
-            const int k = e / (KP / CW), c = (e % (KP / CW)) * CW;
-            X v[CW];
+    const In *xsys = xt + ds.xt0;
+    auto load_x = [&](int32_t kb, uint4 (&r)[NXV]) {
 #pragma unroll
-            for (int w = 0; w < CW; ++w) v[w] = X(0);
-            if (kb + k < k_hi && kb + k < ds.cols && c < K) {
-                const X *src = x + ((int64_t)ds.x0 + kb + k) * K + c;
-                if constexpr (CW == 4 && sizeof(X) == 4) {
-                    const float4 q = *reinterpret_cast<const float4 *>(src);
-                    v[0] = q.x;
-                    v[1] = q.y;
-                    v[2] = q.z;
-                    v[3] = q.w;
-                } else if constexpr (CW == 4) {
-                    const double2 q0 = *reinterpret_cast<const double2 *>(src);
-                    const double2 q1 = *reinterpret_cast<const double2 *>(src + 2);
-                    v[0] = q0.x;
-                    v[1] = q0.y;
-                    v[2] = q1.x;
-                    v[3] = q1.y;
-                } else {
-                    v[0] = src[0];
-                }
-            }
-#pragma unroll
-            for (int w = 0; w < CW; ++w) bt[(c + w) * LSB + k] = Op::conv(v[w]);
+        for (int i = 0; i < NXV; ++i) {
+            const int e = threadIdx.x + i * kBlock;
+            const int c = e / VR, j = e % VR;
+            r[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < KP * VR && kb + j * EV < k_end)
+                r[i] = *reinterpret_cast<const uint4 *>(xsys + (int64_t)c * ldxt + kb + j * EV);
         }
-        // the lane's 16 matrix entries: one aligned block, inside or outside the share
-        In a[16];
+    };
+    auto load_a = [&](int32_t kb, In (&a)[16]) {
         if (arow_ok && kb + 16 * g < k_hi) {
             constexpr int NV = 16 * (int)sizeof(In) / 16;
             const uint4 *src = reinterpret_cast<const uint4 *>(mrow + kb + 16 * g);
@@ -755,7 +782,28 @@ __global__ __launch_bounds__(kBlock) void k_bgemm(const V *__restrict__ mat,
 #pragma unroll
             for (int e = 0; e < 16; ++e) a[e] = In(0);
         }
+    };
+    uint4 xr[NXV];
+    In an[16];
+    if (k_lo < k_hi) {
+        load_x(k_lo, xr);
+        load_a(k_lo, an);
+    }
+    for (int kb = k_lo; kb < k_hi; kb += KB) {
+#pragma unroll
+        for (int i = 0; i < NXV; ++i) {
+            const int e = threadIdx.x + i * kBlock;
+            if (e < KP * VR)
+                *reinterpret_cast<uint4 *>(bt + (e / VR) * LSB + (e % VR) * EV) = xr[i];
+        }
+        In a[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) a[e] = an[e];
         __syncthreads();
+        if (kb + KB < k_hi) {
+            load_x(kb + KB, xr);
+            load_a(kb + KB, an);
+        }
 #pragma unroll
         for (int ss = 0; ss < 4; ++ss) {
             In as[4];
@@ -822,16 +870,24 @@ __global__ __launch_bounds__(kBlock) void k_bgemm(const V *__restrict__ mat,
     }
 }
 
+constexpr int kMaxShares = 16;  // column shares of a dense product, at most
+
 // Sum of the column shares of k_bgemm (in share order) and the epilogue, per
-// 64-row tile: one lane per (row, column), K columns across the lanes.
+// 64-row tile: one lane per (row, column), K columns across the lanes, 16
+// waves, so that a tile's rows are all in flight at once.
+constexpr int kFinBlock = 1024;
+
 template <typename T, typename X, int K, int EPI>
-__global__ __launch_bounds__(kBlock) void k_bgemm_fin(const T *__restrict__ part_y,
-                                                       int32_t nseg, int64_t rows_all, X *y,
-                                                       const double *__restrict__ b,
-                                                       const BRange *__restrict__ blocks,
-                                                       Groups gs, double2 *partials, int64_t cap,
-                                                       int32_t slot, int32_t gate) {
-    constexpr int R = K >= 64 ? 1 : 64 / K;  // rows per wave
+__global__ __launch_bounds__(kFinBlock) void k_bgemm_fin(const T *__restrict__ part_y,
+                                                          int32_t nseg, int64_t rows_all, X *y,
+                                                          const double *__restrict__ b,
+                                                          const BRange *__restrict__ blocks,
+                                                          Groups gs, double2 *partials,
+                                                          int64_t cap, int32_t slot,
+                                                          int32_t gate) {
+    constexpr int NW = kFinBlock / 64;
+    constexpr int R = K >= 64 ? 1 : 64 / K;      // rows per wave and pass
+    constexpr int RU = 1;                         // passes of a lane in flight together
     if (!bgate(gate, gs)) return;
     const BRange br = blocks[blockIdx.x];
     if (br.r0 >= br.r1) return;
@@ -840,13 +896,32 @@ __global__ __launch_bounds__(kBlock) void k_bgemm_fin(const T *__restrict__ part
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int c = lane % K, rsub = lane / K;
     Acc part = {0.0, 0.0};
-    for (int64_t row = br.r0 + wave * R + rsub; row < br.r1; row += 4 * R) {
-        double v = 0.0;
-        for (int sg = 0; sg < nseg; ++sg) v += (double)part_y[((int64_t)sg * rows_all + row) * K + c];
-        if constexpr (EPI == kBResid) v = b[row * K + c] - v;
-        if constexpr (EPI != kBNormOnly) y[row * K + c] = (X)v;
-        const double q = (double)(X)v;
-        acc_fma(part, q, q);
+    // every share of RU rows is loaded before any is added (at most
+    // kMaxShares shares); the adds keep share order
+    for (int64_t r0 = br.r0 + wave * R + rsub; r0 < br.r1; r0 += RU * NW * R) {
+        T p[RU][kMaxShares];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t row = r0 + u * NW * R;
+#pragma unroll
+            for (int sg = 0; sg < kMaxShares; ++sg)
+                p[u][sg] = (sg < nseg && row < br.r1)
+                               ? part_y[((int64_t)sg * rows_all + row) * K + c]
+                               : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+            const int64_t row = r0 + u * NW * R;
+            if (row >= br.r1) break;
+            double v = 0.0;
+#pragma unroll
+            for (int sg = 0; sg < kMaxShares; ++sg)
+                if (sg < nseg) v += (double)p[u][sg];
+            if constexpr (EPI == kBResid) v = b[row * K + c] - v;
+            if constexpr (EPI != kBNormOnly) y[row * K + c] = (X)v;
+            const double q = (double)(X)v;
+            acc_fma(part, q, q);
+        }
     }
 #pragma unroll
     for (int off = K; off < 64; off <<= 1) {
@@ -855,12 +930,12 @@ __global__ __launch_bounds__(kBlock) void k_bgemm_fin(const T *__restrict__ part
         o.s = __shfl_xor(part.s, off);
         part = acc_merge(part, o);
     }
-    __shared__ Acc red[kBlock / 64][K];
+    __shared__ Acc red[NW][K];
     if (lane < K) red[wave][lane] = part;
     __syncthreads();
     if (threadIdx.x < K) {
         Acc a = red[0][threadIdx.x];
-        for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
+        for (int w = 1; w < NW; ++w) a = acc_merge(a, red[w][threadIdx.x]);
         partials[((int64_t)slot * K + threadIdx.x) * cap + br.part] = make_double2(a.p, a.s);
     }
 }
@@ -1476,6 +1551,10 @@ struct BatchPlan {
     double *d_val = nullptr, *dt_val = nullptr;
     void *d_low = nullptr, *dt_low = nullptr;
     DSys *d_sysA = nullptr, *d_sysT = nullptr;
+    // row length of the transposed, converted input block (XT) of the A and
+    // A^T products: the sum of the systems' xt_len
+    int64_t xt_a = 0, xt_t = 0;
+    int64_t xt_len_a = 0, xt_len_t = 0;  // the longest system row of XT, per orientation
     // row lanes picked by timing for the low-precision products, per
     // (K, value type, orientation); filled on first use
     mutable std::mutex tune_mu;
@@ -1535,15 +1614,22 @@ __global__ __launch_bounds__(kBlock) void k_dense_transpose(int64_t m, int64_t n
 static int bplan_build_dense(int32_t nsys, const ta_mat *A, int32_t precision, hipStream_t s,
                              BatchPlan *P) {
     P->dense = true;
+    if (nsys > 65535) return TA_ENOTSUP;  // the input conversion takes one grid row per system
     std::vector<DSys> ha(nsys), ht(nsys);
     int64_t na = 0, nt = 0;
     for (int32_t i = 0; i < nsys; ++i) {
         const int64_t lda = cdivh(std::max<int64_t>(A[i].n, 1), 16) * 16;
         const int64_t ldt = cdivh(std::max<int64_t>(A[i].m, 1), 16) * 16;
-        ha[i] = DSys{na, (int32_t)lda, (int32_t)A[i].n, (int32_t)P->co[i], (int32_t)P->ro[i]};
-        ht[i] = DSys{nt, (int32_t)ldt, (int32_t)A[i].m, (int32_t)P->ro[i], (int32_t)P->co[i]};
+        ha[i] = DSys{na, (int32_t)lda, (int32_t)A[i].n, (int32_t)P->co[i], (int32_t)P->ro[i],
+                     (int32_t)P->xt_a};
+        ht[i] = DSys{nt, (int32_t)ldt, (int32_t)A[i].m, (int32_t)P->ro[i], (int32_t)P->co[i],
+                     (int32_t)P->xt_t};
         na += A[i].m * lda;
         nt += A[i].n * ldt;
+        P->xt_a += xt_len((int32_t)lda);
+        P->xt_t += xt_len((int32_t)ldt);
+        P->xt_len_a = std::max<int64_t>(P->xt_len_a, xt_len((int32_t)lda));
+        P->xt_len_t = std::max<int64_t>(P->xt_len_t, xt_len((int32_t)ldt));
     }
     Workspace own(s);
     own.reserve(&P->d_val, std::max<int64_t>(na, 1));
@@ -1870,9 +1956,24 @@ static void spmm(const int32_t *rp, const int32_t *ci, const void *val, const vo
 // (trans = 0) or A^T (trans = 1) of the plan; V is the matrix element type
 // (double = the FP64 values, float / uint16_t = the plan's low-precision copy).
 // Dense products split over the matrix columns when there are few row tiles:
-// about 2048 workgroups in all, at most 16 shares.
+// about TA_DENSE_BLOCKS workgroups in all, at most 16 shares (on 4 systems of
+// 4096^2 at K = 64, 1024 workgroups beat 512 and 2048: more shares cost their
+// merge more than the extra workgroups gain).
+#ifndef TA_DENSE_BLOCKS
+#define TA_DENSE_BLOCKS 1024
+#endif
 static int32_t dense_nseg(int32_t nblk) {
-    return (int32_t)std::min<int64_t>(16, std::max<int64_t>(1, cdivh(2048, std::max(nblk, 1))));
+    return (int32_t)std::min<int64_t>(
+        kMaxShares, std::max<int64_t>(1, cdivh(TA_DENSE_BLOCKS, std::max(nblk, 1))));
+}
+
+// Doubles of a dense product's scratch that hold XT (the converted,
+// transposed input block; 8 bytes per entry covers every input type),
+// ahead of the column shares.
+static int64_t dense_xt_doubles(const BatchPlan &P, int K) {
+    if (!P.dense) return 0;
+    const int64_t kp = 16 * ((K + 15) / 16);
+    return (kp * std::max(P.xt_a, P.xt_t) + 31) / 32 * 32;
 }
 
 template <typename V, typename X, int K, int EPI>
@@ -1883,18 +1984,29 @@ static void prod(const BatchPlan &P, int trans, const void *x, void *y, const do
     if (nblk <= 0) return;
     const bool low = !std::is_same<V, double>::value;
     if (P.dense) {
+        // scratch (every dense call site passes one): XT, then the column shares
         using T = typename MfmaOp<V>::AccT;
+        using In = typename MfmaOp<V>::In;
         const void *m = low ? (trans ? P.dt_low : P.d_low)
                             : (trans ? (const void *)P.dt_val : (const void *)P.d_val);
         const int64_t rows_all = trans ? P.N : P.M;
-        const int32_t nseg = scratch != nullptr ? dense_nseg(nblk) : 1;
+        const DSys *dsys = trans ? P.d_sysT : P.d_sysA;
+        const int64_t ldxt = trans ? P.xt_t : P.xt_a;
+        In *xt = (In *)scratch;
+        T *shares = (T *)((double *)scratch + dense_xt_doubles(P, K));
+        const int32_t nseg = dense_nseg(nblk);
+        const int64_t len_max = trans ? P.xt_len_t : P.xt_len_a;
+        const int64_t nct = (K + 15) / 16;
+        const dim3 gp((unsigned)(nct * std::max<int64_t>(1, std::min<int64_t>(cdivh(len_max, 64), 256))),
+                      (unsigned)P.nsys);
+        k_bxprep<V, X, K><<<gp, kBlock, 0, s>>>((const X *)x, dsys, ldxt, xt);
         k_bgemm<V, X, K, EPI><<<(unsigned)(nblk * nseg), kBlock, 0, s>>>(
-            (const V *)m, trans ? P.d_sysT : P.d_sysA, (const X *)x, (X *)y, b, tab, gs, partials,
-            cap, slot, gate, nseg, (T *)scratch, rows_all);
+            (const V *)m, dsys, xt, ldxt, (X *)y, b, tab, gs, partials, cap, slot, gate, nseg,
+            shares, rows_all);
         if (nseg > 1)
-            k_bgemm_fin<T, X, K, EPI><<<nblk, kBlock, 0, s>>>((const T *)scratch, nseg, rows_all,
-                                                               (X *)y, b, tab, gs, partials, cap,
-                                                               slot, gate);
+            k_bgemm_fin<T, X, K, EPI><<<nblk, kFinBlock, 0, s>>>(shares, nseg, rows_all, (X *)y,
+                                                                  b, tab, gs, partials, cap, slot,
+                                                                  gate);
         return;
     }
     const void *val = low ? (trans ? P.t_low : P.a_low)
@@ -2056,8 +2168,9 @@ struct Engine {
         ws.reserve(&TN, N * K);
         double *DS = nullptr;  // column shares of the dense products
         if (P.dense)
-            ws.reserve(&DS, (int64_t)dense_nseg(std::max(std::min(na, nt), 1)) *
-                                std::max<int64_t>(std::max(M, N), 1) * K);
+            ws.reserve(&DS, dense_xt_doubles(P, K) +
+                                (int64_t)dense_nseg(std::max(std::min(na, nt), 1)) *
+                                    std::max<int64_t>(std::max(M, N), 1) * K);
         ws.reserve(&partials, (int64_t)nslots * K * cap);
         ws.reserve(&d_ta, std::max(na, 1));
         ws.reserve(&d_tt, std::max(nt, 1));
@@ -2594,7 +2707,9 @@ static int time_spmm_k(const BatchPlan &P, int32_t trans, int32_t reps, double *
     ws.reserve(&gs.flags, 4);
     ws.reserve(&gs.sys_active, P.nsys);
     double *DS = nullptr;
-    if (P.dense) ws.reserve(&DS, (int64_t)dense_nseg(std::max(nb, 1)) * std::max<int64_t>(rows, 1) * K);
+    if (P.dense)
+        ws.reserve(&DS, dense_xt_doubles(P, K) +
+                            (int64_t)dense_nseg(std::max(nb, 1)) * std::max<int64_t>(rows, 1) * K);
     int rc = ws.commit();
     if (rc != TA_OK) return rc;
     HIP_TRY(hipMemcpyAsync(d_tab, tab.data(), sizeof(BRange) * nb, hipMemcpyHostToDevice, s));
