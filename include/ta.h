@@ -109,9 +109,11 @@ typedef struct ta_opts {
                               and replayed (single-system solves: from the second chunk on,
                               not with t_cycle, not in cta_solve_plan_noalloc), 1 = kernels
                               launched one by one; results are identical */
-    int32_t h_mode;        /* cta_solve: 0 = H = A A^T (section 5), 1 = H = A for a square
-                              symmetric positive semidefinite A (not checked): t products per
-                              iteration instead of 2t, phi_i = r^T A^i r.  Other solvers: 0 */
+    int32_t h_mode;        /* cta_solve and cta_solve_batched's x-form: 0 = H = A A^T
+                              (section 5), 1 = H = A for a square symmetric positive
+                              semidefinite A (not checked; in a batch every system square, a
+                              dense batch in TA_FP64 only): t products per iteration instead
+                              of 2t, phi_i = r^T A^i r.  Other solvers: 0 */
     int32_t t_cycle;       /* cta_solve / cta_minnorm: 1 = the order of iteration k (k = 0, 1,
                               ...) cycles 1, 2, ..., t, t-1, ..., 2, 1, 2, ... (section 5.1's
                               order cycling, read as a triangle wave of period 2(t-1)); 0 = the
@@ -328,15 +330,17 @@ int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, cons
  * TA_FP64, on any dense plan) run there, with compensated sums like every
  * CSR plan.
  *
- * cta_solve_batched runs Algorithm 1 (CTA, H = A_s A_s^T) independently for
- * every (system s, right-hand side c), all advanced together:
+ * cta_solve_batched runs Algorithm 1 (CTA, H = A_s A_s^T, or H = A_s with
+ * opts->h_mode 1) independently for every (system s, right-hand side c), all
+ * advanced together:
  *   nrhs : host, nsys counts k_s in [0, 64];
  *   B    : host array of nsys device pointers, B[s] column-major m_s x k_s;
  *   X    : host array of nsys device pointers, X[s] column-major n_s x k_s (out);
  *   opts : as cta_solve; opts->precision is TA_FP64 or the plan's precision;
  *          opts->warm_start and opts->replace_every are not used; opts->chunk
  *          is the number of iterations between true-residual checks
- *          (0 = automatic);
+ *          (0 = automatic); h_mode as cta_solve; t_cycle, enhanced and accel
+ *          must be 0 (TA_EINVAL);
  *   minnorm : 1 = the y-form of cta_minnorm (x = A^T y), 0 = the x-form;
  *   info : host, sum k_s entries, system-major (s, then c): iterations, products,
  *          stop code, FP64 true relative residual, normal-equation residual.

@@ -223,9 +223,9 @@ def make_opts(tol=1e-6, t=3, max_iter=100000, tol_normal=0.0, replace_every=0, w
 
 
 class Plan:
-    """A prepared operator (ta_plan): A^T and, for long rows, the XCD column
-    slices of A; for short even rows, SELL-64 copies of A and A^T.  Built once
-    on the device.  Keeps the matrix alive."""
+    """A prepared operator (ta_plan): A^T and, for long rows, the LDS column
+    tiles or the XCD column slices of A (or A^T); for short even rows, SELL-64
+    copies of A and A^T.  Built once on the device.  Keeps the matrix alive."""
 
     def __init__(self, A):
         lib = load_library()

@@ -97,6 +97,7 @@ struct Groups {
     const int32_t *t_blk;  // per system: first block of the A^T-row table (nsys + 1)
     int32_t nsys, K, t;
     int32_t minnorm, mixed;
+    int32_t hmode;  // 1: H = A (square symmetric systems), the chain is A passes only
     int64_t max_iter;
     double tol, tol_normal;
 };
@@ -136,7 +137,11 @@ __device__ __forceinline__ float ldv(const uint16_t *v, int64_t k) {
     return __uint_as_float((uint32_t)v[k] << 16);
 }
 
-enum BEpi : int32_t { kBNorm = 0, kBResid = 1, kBNormOnly = 2 };
+// Product epilogues: store and column norms into slot; residual b - M x;
+// norms only (no store); store, the dot of each output column with the
+// input column at the same rows (square systems, H = A) into slot and the
+// norms into slot + 1.
+enum BEpi : int32_t { kBNorm = 0, kBResid = 1, kBNormOnly = 2, kBNormDot = 3 };
 
 // Value of lane S of the calling lane's group of KL consecutive lanes (KL a
 // power of two, groups aligned).  Groups inside one 16-lane DPP row use a
@@ -317,9 +322,10 @@ constexpr int64_t kRoundNnz = 6;
 
 // Waves per SIMD asked of the SpMM: the low-precision chain at K = 64 fits
 // 64 VGPRs without spilling (8 waves instead of 7); the widths in between
-// would spill, and the FP64 chain keeps what its registers allow.
-template <typename X, int K>
-constexpr int kBspmmWaves = (sizeof(X) != 8 && K == 64) ? 8 : 1;
+// would spill, and so would the dot epilogue (H = A); the FP64 chain keeps
+// what its registers allow.
+template <typename X, int K, int EPI>
+constexpr int kBspmmWaves = (sizeof(X) != 8 && K == 64 && EPI != kBNormDot) ? 8 : 1;
 
 // Widths whose low-precision SpMM runs the row loop software-pipelined (see
 // k_bspmm): measured faster at K = 8, 16, 32; at K = 64 the lookahead's
@@ -336,7 +342,7 @@ struct Lanes {
 };
 
 template <typename V, typename X, int K, int EPI, int U>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBspmmWaves<X, K>)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kBspmmWaves<X, K, EPI>)))
 void k_bspmm(const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ ci,
                                                    const V *__restrict__ val,
@@ -358,9 +364,9 @@ void k_bspmm(const int32_t *__restrict__ rp,
     const int cl = lane % KL, l = (lane / KL) % L, rsub = lane / (KL * L);
     const int RL = 64 / (KL * L);
     const int c0 = cl * CV, gbase = lane - cl;
-    Acc part[CV];
+    Acc part[CV], pdot[CV];  // column norms; dots with the input (kBNormDot)
 #pragma unroll
-    for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
+    for (int v = 0; v < CV; ++v) part[v] = pdot[v] = Acc{0.0, 0.0};
     // Rows are visited tile by tile (see BRange).  Nonzeros go in chunks of U
     // per lane, each chunk predicated on the row end: a short row issues all
     // its column-index and x loads in one round.
@@ -448,10 +454,13 @@ void k_bspmm(const int32_t *__restrict__ rp,
 #pragma unroll
                 for (int v = 0; v < CV; ++v) yv[v] = (double)acc[v];
                 if constexpr (EPI != kBNormOnly) vst<X, CV>(y + row * K + c0, yv);
+                double xi[CV];
+                if constexpr (EPI == kBNormDot) vld<X, CV>(x + row * K + c0, xi);
 #pragma unroll
                 for (int v = 0; v < CV; ++v) {
                     const double q = (double)(X)yv[v];
                     part[v].p = __fma_rn(q, q, part[v].p);
+                    if constexpr (EPI == kBNormDot) pdot[v].p = __fma_rn(q, xi[v], pdot[v].p);
                 }
             }
             s_cur = s_nxt;
@@ -554,15 +563,20 @@ void k_bspmm(const int32_t *__restrict__ rp,
         }
         if (l == 0) {
             if constexpr (EPI != kBNormOnly) vst<X, CV>(y + row * K + c0, yv);
+            double xi[CV];
+            if constexpr (EPI == kBNormDot) vld<X, CV>(x + row * K + c0, xi);
 #pragma unroll
             for (int v = 0; v < CV; ++v) {
                 const double q = (double)(X)yv[v];
                 // FP64 chains: compensated, as the single-vector kernels; the
                 // low-precision chain's FP32 outputs need only an FP64 sum
-                if constexpr (kF64)
+                if constexpr (kF64) {
                     acc_fma(part[v], q, q);
-                else
+                    if constexpr (EPI == kBNormDot) acc_fma(pdot[v], q, xi[v]);
+                } else {
                     part[v].p = __fma_rn(q, q, part[v].p);
+                    if constexpr (EPI == kBNormDot) pdot[v].p = __fma_rn(q, xi[v], pdot[v].p);
+                }
             }
         }
         s_cur = s_nxt;
@@ -570,26 +584,34 @@ void k_bspmm(const int32_t *__restrict__ rp,
         it = nit;
     }
     }
-    // reduce over the rows of the block for each column
-    for (int off = KL; off < 64; off <<= 1) {
-#pragma unroll
-        for (int v = 0; v < CV; ++v) {
-            Acc o;
-            o.p = __shfl_xor(part[v].p, off);
-            o.s = __shfl_xor(part[v].s, off);
-            part[v] = acc_merge(part[v], o);
-        }
-    }
+    // reduce over the rows of the block for each column: the norms into
+    // slot (slot + 1 with the dots, which go to slot)
     __shared__ Acc red[kBlock / 64][K];
-    if (lane < KL) {
+    auto write_slot = [&](Acc (&pv)[CV], int32_t sl) {
+        for (int off = KL; off < 64; off <<= 1) {
 #pragma unroll
-        for (int v = 0; v < CV; ++v) red[wave][c0 + v] = part[v];
-    }
-    __syncthreads();
-    if (threadIdx.x < K) {
-        Acc a = red[0][threadIdx.x];
-        for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
-        partials[((int64_t)slot * K + threadIdx.x) * cap + br.part] = make_double2(a.p, a.s);
+            for (int v = 0; v < CV; ++v) {
+                Acc o;
+                o.p = __shfl_xor(pv[v].p, off);
+                o.s = __shfl_xor(pv[v].s, off);
+                pv[v] = acc_merge(pv[v], o);
+            }
+        }
+        if (lane < KL) {
+#pragma unroll
+            for (int v = 0; v < CV; ++v) red[wave][c0 + v] = pv[v];
+        }
+        __syncthreads();
+        if (threadIdx.x < K) {
+            Acc a = red[0][threadIdx.x];
+            for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[w][threadIdx.x]);
+            partials[((int64_t)sl * K + threadIdx.x) * cap + br.part] = make_double2(a.p, a.s);
+        }
+    };
+    write_slot(part, EPI == kBNormDot ? slot + 1 : slot);
+    if constexpr (EPI == kBNormDot) {
+        __syncthreads();
+        write_slot(pdot, slot);
     }
 }
 
@@ -600,16 +622,19 @@ void k_bspmm(const int32_t *__restrict__ rp,
 // row-major with a row stride padded with zeros to a multiple of 16.  One
 // workgroup computes a tile of 64 rows of one system against all K columns:
 // wave w takes rows 16 w .. 16 w + 15, as ceil(K / 16) output tiles of 16 x 16
-// on the MFMA unit.  Per step of 16 matrix columns the workgroup stages the
-// 16 x K slice of X in LDS (converted to the instruction's input type and
-// stored column by column), each lane loads 4 consecutive matrix entries of
-// its row, and the products run as
+// on the MFMA unit.  The input block is first converted to the instruction's
+// input type and transposed, once per product (k_bxprep); per stage of 64
+// matrix columns the workgroup copies the K x 64 slice of that transpose into
+// LDS, each lane loads 16 consecutive matrix entries of its row (4 steps of
+// 4), and the products run as
 //   FP64: v_mfma_f64_16x16x4f64, 4 instructions per column tile,
 //   FP32: v_mfma_f32_16x16x4f32, 4 instructions per column tile,
 //   BF16: v_mfma_f32_16x16x16bf16_1k, 1 instruction per column tile (the FP32
 //         vector entries are rounded to BF16 on the way into LDS).
-// Lane l supplies row l % 16 and matrix columns 16 s + 4 (l / 16) + e; the
-// instructions sum over l / 16, so every column of the step is covered once.
+// In sub-step ss of the stage at column kb, lane l supplies row l % 16 and
+// matrix columns kb + 16 (l / 16) + 4 ss + e (e = 0..3), and the B operand
+// the same columns of the transposed input; the instructions sum over l / 16,
+// so every column of the stage is covered once.
 // The epilogues are those of the sparse kernel.
 struct DSys {
     int64_t off;   // offset of the system's matrix in the packed array
@@ -1005,7 +1030,8 @@ __global__ __launch_bounds__(kBlock) void k_bstep_init(Groups gs, const double2 
 }
 
 // Gram step: one block per group; wave w reduces slots w, w + 4, ...
-// (even slots: A^T passes over the A^T-row table, odd: A passes).
+// (even slots: A^T passes over the A^T-row table, odd: A passes; with
+// H = A every slot comes from an A pass).
 __global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 *partials,
                                                         int64_t cap) {
     if (gs.flags[0]) return;
@@ -1015,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 
     const int wave = threadIdx.x >> 6;
     __shared__ double phi[kPhiStride];
     for (int q = wave; q < 2 * t; q += kBlock / 64) {
-        const int32_t *tab = (q % 2 == 0) ? gs.t_blk : gs.a_blk;
+        const int32_t *tab = (q % 2 == 0 && !gs.hmode) ? gs.t_blk : gs.a_blk;
         const double v = wave_slot_sum(partials + ((int64_t)q * gs.K + c) * cap, tab[s], tab[s + 1]);
         if ((threadIdx.x & 63) == 0) phi[q + 1] = v;
     }
@@ -1023,14 +1049,16 @@ __global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 
     if (threadIdx.x != 0) return;
     double *gp = gs.phi + (int64_t)g * kPhiStride;
     for (int i = 1; i <= 2 * t; ++i) gp[i] = phi[i];
-    gs.matvecs[g] += 2 * t;
+    gs.matvecs[g] += gs.hmode ? t : 2 * t;
     for (int i = 1; i <= 2 * t; ++i)
         if (!isfinite(phi[i])) {
             gs.status[g] = kFinished;
             gs.stop[g] = TA_STOP_BREAKDOWN;
             return;
         }
-    if (sqrt(phi[1]) <= gs.tol_ne_nab[g] || phi[2] == 0.0) {
+    // the normal-equation test on ||A^T r||: phi_1, or phi_2 = ||A r||^2 when
+    // H = A (A symmetric)
+    if (sqrt(gs.hmode ? phi[2] : phi[1]) <= gs.tol_ne_nab[g] || phi[2] == 0.0) {
         gs.status[g] = kFinished;
         gs.stop[g] = TA_STOP_NORMAL;
         return;
@@ -1984,6 +2012,9 @@ static void prod(const BatchPlan &P, int trans, const void *x, void *y, const do
     if (nblk <= 0) return;
     const bool low = !std::is_same<V, double>::value;
     if (P.dense) {
+        // the dot epilogue (H = A) is not on the matrix cores: dense batches
+        // reject H = A in low precision, and FP64 runs on the CSR copy
+        if constexpr (EPI == kBNormDot) return;
         // scratch (every dense call site passes one): XT, then the column shares
         using T = typename MfmaOp<V>::AccT;
         using In = typename MfmaOp<V>::In;
@@ -2158,9 +2189,12 @@ struct Engine {
         ws.reserve(&Bc, M * K);
         ws.reserve(&R, M * K);
         for (int j = 1; j <= t; ++j) ws.reserve(&U[j], M * K);
-        // W_j is kept for the x update only in the FP64 x-form
+        // W_j is kept for the x update only in the FP64 x-form; with H = A
+        // (square systems) the chain has no A^T pass, and W_0 only serves the
+        // row-lane tuner of the low-precision chain
+        const bool ha = o->h_mode == 1;
         const bool one_w = minnorm || mixed;
-        for (int j = 0; j < (one_w ? 1 : t); ++j) ws.reserve(&W[j], N * K);
+        for (int j = 0; j < (ha ? (mixed ? 1 : 0) : (one_w ? 1 : t)); ++j) ws.reserve(&W[j], N * K);
         if (minnorm) ws.reserve(&Y, M * K);
         ws.reserve(&Xc, N * K);
         if (mixed) ws.reserve(&D, M * K);
@@ -2229,6 +2263,7 @@ struct Engine {
         gs.t = t;
         gs.minnorm = minnorm;
         gs.mixed = mixed;
+        gs.hmode = ha ? 1 : 0;
         gs.max_iter = o->max_iter;
         gs.tol = o->tol;
         gs.tol_normal = o->tol_normal;
@@ -2271,6 +2306,12 @@ struct Engine {
         auto iteration = [&]() {
             for (int j = 0; j < t; ++j) {
                 const void *uj = j == 0 ? (const void *)R : (const void *)U[j];
+                if (ha) {
+                    // u_{j+1} = A u_j; phi_{2j+1} = u_j . u_{j+1}, phi_{2j+2} = ||u_{j+1}||^2
+                    prod<V, X, K, kBNormDot>(P, 0, uj, U[j + 1], nullptr, d_ta, na, gs,
+                                             partials, cap, 2 * j, kBRun, La, cs, DS);
+                    continue;
+                }
                 X *wj = W[one_w ? 0 : j];
                 prod<V, X, K, kBNorm>(P, 1, uj, wj, nullptr, d_tt, nt, gs, partials,
                                       cap, 2 * j, kBRun, Lt, cs, DS);
@@ -2281,15 +2322,17 @@ struct Engine {
             BVecs uv{};
             uv.p[0] = R;
             for (int j = 1; j <= t; ++j) uv.p[j] = U[j];
+            // the x-form with H = A takes y-form's update into x itself
+            // (x += sum_i alpha_i u_{i-1}); x and the rows of A coincide
             if (na > 0) {
                 if (mixed)
                     k_bupdate_r<X, K, X><<<na, kBlock, 0, cs>>>(uv, R, D, d_ta, gs, partials, cap,
                                                                  1);
                 else
-                    k_bupdate_r<X, K, double><<<na, kBlock, 0, cs>>>(uv, R, Y, d_ta, gs, partials,
-                                                                      cap, minnorm ? 1 : 0);
+                    k_bupdate_r<X, K, double><<<na, kBlock, 0, cs>>>(
+                        uv, R, ha ? Xc : Y, d_ta, gs, partials, cap, (minnorm || ha) ? 1 : 0);
             }
-            if (!minnorm && !mixed && nt > 0) {
+            if (!minnorm && !mixed && !ha && nt > 0) {
                 BVecs wv{};
                 for (int j = 0; j < t; ++j) wv.p[j] = W[j];
                 if (mixed)
@@ -2303,8 +2346,9 @@ struct Engine {
         const int32_t products = minnorm ? 2 : 1;
         auto tail = [&]() {
             if (mixed) {
-                if (minnorm) {
-                    if (na > 0) k_bfold<X, K><<<na, kBlock, 0, cs>>>(D, Y, d_ta, gs, 1);
+                if (minnorm || ha) {
+                    // y += Z (or, with H = A, x += Z: x and the rows coincide)
+                    if (na > 0) k_bfold<X, K><<<na, kBlock, 0, cs>>>(D, minnorm ? Y : Xc, d_ta, gs, 1);
                 } else {
                     // x += A^T Z (the chunk's increment), Z = 0.  The product
                     // is the FP64 one: with the low-precision A^T the increment
@@ -2483,9 +2527,17 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         return TA_EINVAL;
     if (o->t < 1 || o->t > kTMax || o->max_iter < 0 || o->chunk < 0) return TA_EINVAL;
     if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
-    if (o->h_mode != 0 || o->t_cycle != 0 || o->nonneg != 0 || o->rho_max != 0.0 ||
-        o->enhanced != 0 || o->normal_eq != 0 || o->accel != 0.0)
-        return TA_EINVAL;  // batched: CTA with H = A A^T and a fixed t
+    if (o->t_cycle != 0 || o->nonneg != 0 || o->rho_max != 0.0 || o->enhanced != 0 ||
+        o->normal_eq != 0 || o->accel != 0.0)
+        return TA_EINVAL;  // batched: CTA with a fixed t
+    if (o->h_mode != 0 && o->h_mode != 1) return TA_EINVAL;
+    if (o->h_mode == 1) {
+        // H = A: the x-form on square systems (symmetric positive semidefinite,
+        // not checked); dense batches take it in FP64 only (on their CSR copy)
+        if (minnorm || (P.dense && o->precision != TA_FP64)) return TA_EINVAL;
+        for (int32_t i = 0; i < P.nsys; ++i)
+            if (!P.square[i]) return TA_EINVAL;
+    }
     if (minnorm && o->warm_start) return TA_EINVAL;
     if (o->precision != TA_FP64 && o->precision != P.precision) return TA_EINVAL;
     if (P.dense && o->precision == TA_FP64 && P.csr64)

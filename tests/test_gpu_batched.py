@@ -335,3 +335,76 @@ def test_graph_replay_matches_plain_launches(prec):
         assert np.array_equal(host(Xg[s]), host(Xp[s])), s
         assert ig[s] == ip[s], s
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# H = A (h_mode 1) in the batched engine: square symmetric positive
+# semidefinite systems, the chain of A passes only (section 5's H = A for
+# such matrices); each column against the oracle's H = A run
+# ---------------------------------------------------------------------------
+def _spd_systems():
+    g = np.random.default_rng(33)
+    # and a random symmetric diagonally dominant matrix (positive definite)
+    d = g.standard_normal((40, 40))
+    d = d + d.T
+    d += np.diag(2.0 * np.abs(d).sum(axis=1))
+    A = [poisson5(12), poisson5(7), csr_from_dense(d)]
+    ks = [5, 1, 3]
+    B = [a.to_scipy() @ g.standard_normal((a.n, k)) for a, k in zip(A, ks)]
+    return A, B, ks
+
+
+def test_batched_h_equals_a_fp64_matches_oracle():
+    A, B, ks = _spd_systems()
+    plan = P.BatchPlan(A, "fp64")
+    tol, t, budget = 1e-10, 3, 5000
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=budget, h_is_a=True,
+                                   tol_normal=1e-14)
+    for s, (a, b) in enumerate(zip(A, B)):
+        xg = host(X[s])
+        for c in range(ks[s]):
+            xo, ho, io = oracle.cta(a, b[:, c], tol=tol, t=t, max_iter=budget, h_is_a=True,
+                                    tol_normal=1e-14)
+            ig = infos[s][c]
+            assert io.stop == "residual", (s, c, io)
+            assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), (s, c, ig, io)
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-10 * np.linalg.norm(xo)
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batched_h_equals_a_mixed_reaches_tolerance(prec):
+    A, B, ks = _spd_systems()
+    plan = P.BatchPlan(A, prec)
+    tol, t = 1e-8, 3
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=20000, h_is_a=True,
+                                   precision=prec)
+    for s, (a, b) in enumerate(zip(A, B)):
+        xg = host(X[s])
+        for c in range(ks[s]):
+            ig = infos[s][c]
+            assert ig.stop == "residual" and ig.rel_res <= tol, (s, c, ig)
+            r = b[:, c] - a.to_scipy() @ xg[:, c]
+            assert np.linalg.norm(r) <= tol * (1 + 1e-6) * np.linalg.norm(b[:, c])
+            xo, _, io = oracle.cta(a, b[:, c], tol=tol, t=t, max_iter=20000, h_is_a=True)
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-6 * np.linalg.norm(xo), (s, c)
+    plan.close()
+
+
+def test_batched_h_equals_a_needs_square_x_form():
+    A, B, ks = _spd_systems()
+    plan = P.BatchPlan(A, "fp64")
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.cta_solve_batched(plan, B, tol=1e-8, t=3, h_is_a=True, minnorm=True)
+    plan.close()
+    rect = [lp_shaped(20, 60, seed=1).A, poisson5(5)]
+    g = np.random.default_rng(2)
+    plan = P.BatchPlan(rect, "fp64")
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.cta_solve_batched(plan, [g.standard_normal((20, 1)), g.standard_normal((25, 1))],
+                            tol=1e-8, t=2, h_is_a=True)
+    plan.close()
+    d = P.BatchPlan([np.eye(6) * 2.0], "fp32")
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.cta_solve_batched(d, [np.ones((6, 1))], tol=1e-8, t=2, h_is_a=True, precision="fp32")
+    d.close()
