@@ -408,3 +408,39 @@ def test_batched_h_equals_a_needs_square_x_form():
     with pytest.raises(P.TaError, match="EINVAL"):
         P.cta_solve_batched(d, [np.ones((6, 1))], tol=1e-8, t=2, h_is_a=True, precision="fp32")
     d.close()
+
+
+# ---------------------------------------------------------------------------
+# systems wider than 65536 columns beside small ones, and a 300 x 70000
+# system whose A and A^T differ in shape by two orders of magnitude
+# ---------------------------------------------------------------------------
+def test_batched_wide_systems_fp64():
+    g = np.random.default_rng(8)
+    A = [random_diag_dominant(70_000, 3, seed=1), poisson5(6)]
+    ks = [2, 1]
+    B = [a.to_scipy() @ g.standard_normal((a.n, k)) for a, k in zip(A, ks)]
+    plan = P.BatchPlan(A, "fp64")
+    tol, t = 1e-10, 3
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=3000)
+    for s, (a, b) in enumerate(zip(A, B)):
+        for c in range(ks[s]):
+            xo, _, io = oracle.cta(a, b[:, c], tol=tol, t=t, max_iter=3000)
+            ig = infos[s][c]
+            assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), (s, c)
+            assert np.linalg.norm(host(X[s])[:, c] - xo) <= 1e-10 * np.linalg.norm(xo)
+    plan.close()
+
+
+def test_batched_mixed_wide_system():
+    g = np.random.default_rng(9)
+    a = lp_shaped(300, 70_000, seed=4).A
+    b = a.to_scipy() @ g.standard_normal((a.n, 2))
+    plan = P.BatchPlan([a], "fp32")
+    tol = 1e-8
+    X, infos = P.cta_solve_batched(plan, [b], tol=tol, t=3, max_iter=4000, minnorm=True,
+                                   precision="fp32")
+    for c in range(2):
+        assert infos[0][c].stop == "residual" and infos[0][c].rel_res <= tol
+        xo, _, io = oracle.cta_minnorm(a, b[:, c], tol=tol, t=3, max_iter=4000)
+        assert np.linalg.norm(host(X[0])[:, c] - xo) <= 1e-6 * np.linalg.norm(xo)
+    plan.close()
