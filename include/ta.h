@@ -114,10 +114,12 @@ typedef struct ta_opts {
                               semidefinite A (not checked; in a batch every system square, a
                               dense batch in TA_FP64 only): t products per iteration instead
                               of 2t, phi_i = r^T A^i r.  Other solvers: 0 */
-    int32_t t_cycle;       /* cta_solve / cta_minnorm: 1 = the order of iteration k (k = 0, 1,
-                              ...) cycles 1, 2, ..., t, t-1, ..., 2, 1, 2, ... (section 5.1's
-                              order cycling, read as a triangle wave of period 2(t-1)); 0 = the
-                              fixed order t.  Batched solves: 0 */
+    int32_t t_cycle;       /* cta_solve / cta_minnorm / cta_solve_batched: 1 = the order of
+                              iteration k (k = 0, 1, ...) cycles 1, 2, ..., t, t-1, ..., 2, 1,
+                              2, ... (section 5.1's order cycling, read as a triangle wave of
+                              period 2(t-1)); 0 = the fixed order t.  In a batch each column
+                              takes the order of its own k, while the chain runs t steps for
+                              all of them */
     int32_t nonneg;        /* ta_solve: 1 = LP feasibility {A x = b, x >= 0} (section 6): the
                               pivot uses c+ = max(A^T (b - b'), 0) in place of c (Proposition
                               eq. vrend2), so x stays >= 0; stop NORMAL when ||c+|| <=
@@ -339,8 +341,8 @@ int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, cons
  *   opts : as cta_solve; opts->precision is TA_FP64 or the plan's precision;
  *          opts->warm_start and opts->replace_every are not used; opts->chunk
  *          is the number of iterations between true-residual checks
- *          (0 = automatic); h_mode as cta_solve; t_cycle, enhanced and accel
- *          must be 0 (TA_EINVAL);
+ *          (0 = automatic); h_mode and t_cycle as cta_solve; enhanced and
+ *          accel must be 0 (TA_EINVAL);
  *   minnorm : 1 = the y-form of cta_minnorm (x = A^T y), 0 = the x-form;
  *   info : host, sum k_s entries, system-major (s, then c): iterations, products,
  *          stop code, FP64 true relative residual, normal-equation residual.

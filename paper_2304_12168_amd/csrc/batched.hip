@@ -98,6 +98,7 @@ struct Groups {
     int32_t nsys, K, t;
     int32_t minnorm, mixed;
     int32_t hmode;  // 1: H = A (square symmetric systems), the chain is A passes only
+    int32_t t_cycle;  // 1: the order of a group's iteration k is cycle_order(t, k)
     int64_t max_iter;
     double tol, tol_normal;
 };
@@ -1029,6 +1030,14 @@ __global__ __launch_bounds__(kBlock) void k_bstep_init(Groups gs, const double2 
     group_loop_top(gs, g);
 }
 
+// Order of iteration k under order cycling: the triangle wave 1, 2, ..., t,
+// t - 1, ..., 2, 1, 2, ... (period 2 (t - 1)).
+__device__ __forceinline__ int cycle_order(int t, int64_t k) {
+    if (t <= 1) return 1;
+    const int64_t p = k % (2 * (int64_t)t - 2);
+    return (int)(p < t ? p + 1 : 2 * (int64_t)t - 1 - p);
+}
+
 // Gram step: one block per group; wave w reduces slots w, w + 4, ...
 // (even slots: A^T passes over the A^T-row table, odd: A passes; with
 // H = A every slot comes from an A pass).
@@ -1047,10 +1056,14 @@ __global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    // with order cycling the chain still runs t steps for every group; a
+    // group of order tk < t uses phi_1 .. phi_2tk and takes alpha_i = 0 past
+    // tk, so its update is that of order tk
+    const int tk = gs.t_cycle ? cycle_order(t, gs.k[g]) : t;
     double *gp = gs.phi + (int64_t)g * kPhiStride;
     for (int i = 1; i <= 2 * t; ++i) gp[i] = phi[i];
-    gs.matvecs[g] += gs.hmode ? t : 2 * t;
-    for (int i = 1; i <= 2 * t; ++i)
+    gs.matvecs[g] += gs.hmode ? tk : 2 * tk;
+    for (int i = 1; i <= 2 * tk; ++i)
         if (!isfinite(phi[i])) {
             gs.status[g] = kFinished;
             gs.stop[g] = TA_STOP_BREAKDOWN;
@@ -1064,14 +1077,14 @@ __global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 
         return;
     }
     double a[kTMax];
-    gram_alpha(phi, t, a);
-    for (int i = 0; i < t; ++i)
+    gram_alpha(phi, tk, a);
+    for (int i = 0; i < tk; ++i)
         if (!isfinite(a[i])) {
             gs.status[g] = kFinished;
             gs.stop[g] = TA_STOP_BREAKDOWN;
             return;
         }
-    for (int i = 0; i < kTMax; ++i) gs.alpha[(int64_t)g * kTMax + i] = i < t ? a[i] : 0.0;
+    for (int i = 0; i < kTMax; ++i) gs.alpha[(int64_t)g * kTMax + i] = i < tk ? a[i] : 0.0;
 }
 
 struct BVecs {
@@ -1147,7 +1160,8 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
                     if (j < t) {
 #pragma unroll
                         for (int v = 0; v < CV; ++v)
-                            yi[v] = __fma_rn(sal[j][c0 + v], (double)uv[j].v[v], yi[v]);
+                            if (sal[j][c0 + v] != 0.0)  // past a cycled order (unused u_j)
+                                yi[v] = __fma_rn(sal[j][c0 + v], (double)uv[j].v[v], yi[v]);
                     }
 #pragma unroll
                 for (int v = 0; v < CV; ++v)
@@ -1162,7 +1176,8 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
                 if (j < t) {
 #pragma unroll
                     for (int v = 0; v < CV; ++v)
-                        rn[v] = __fma_rn(-sal[j][c0 + v], (double)uv[j + 1].v[v], rn[v]);
+                        if (sal[j][c0 + v] != 0.0)
+                            rn[v] = __fma_rn(-sal[j][c0 + v], (double)uv[j + 1].v[v], rn[v]);
                 }
 #pragma unroll
             for (int v = 0; v < CV; ++v) {
@@ -1239,7 +1254,8 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, XA *xv,
             if (j < t) {
 #pragma unroll
                 for (int v = 0; v < CV; ++v)
-                    xi[v] = __fma_rn(sal[j][c0 + v], (double)wv[j].v[v], xi[v]);
+                    if (sal[j][c0 + v] != 0.0)
+                        xi[v] = __fma_rn(sal[j][c0 + v], (double)wv[j].v[v], xi[v]);
             }
 #pragma unroll
         for (int v = 0; v < CV; ++v)
@@ -2264,6 +2280,7 @@ struct Engine {
         gs.minnorm = minnorm;
         gs.mixed = mixed;
         gs.hmode = ha ? 1 : 0;
+        gs.t_cycle = o->t_cycle;
         gs.max_iter = o->max_iter;
         gs.tol = o->tol;
         gs.tol_normal = o->tol_normal;
@@ -2527,9 +2544,10 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         return TA_EINVAL;
     if (o->t < 1 || o->t > kTMax || o->max_iter < 0 || o->chunk < 0) return TA_EINVAL;
     if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
-    if (o->t_cycle != 0 || o->nonneg != 0 || o->rho_max != 0.0 || o->enhanced != 0 ||
-        o->normal_eq != 0 || o->accel != 0.0)
-        return TA_EINVAL;  // batched: CTA with a fixed t
+    if (o->nonneg != 0 || o->rho_max != 0.0 || o->enhanced != 0 || o->normal_eq != 0 ||
+        o->accel != 0.0)
+        return TA_EINVAL;  // batched: no enhanced stop, no convex-combination step
+    if (o->t_cycle != 0 && o->t_cycle != 1) return TA_EINVAL;
     if (o->h_mode != 0 && o->h_mode != 1) return TA_EINVAL;
     if (o->h_mode == 1) {
         // H = A: the x-form on square systems (symmetric positive semidefinite,

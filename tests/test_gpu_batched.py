@@ -444,3 +444,42 @@ def test_batched_mixed_wide_system():
         xo, _, io = oracle.cta_minnorm(a, b[:, c], tol=tol, t=3, max_iter=4000)
         assert np.linalg.norm(host(X[0])[:, c] - xo) <= 1e-6 * np.linalg.norm(xo)
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# order cycling in batches: each column takes the order of its own iteration
+# count (section 5.1's cycling, triangle wave), with H = A A^T and H = A
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("h_is_a", [False, True], ids=["AAt", "A"])
+def test_batched_order_cycling_fp64_matches_oracle(h_is_a):
+    A, B, ks = _spd_systems() if h_is_a else _systems()
+    plan = P.BatchPlan(A, "fp64")
+    tol, t, budget = 1e-9, 4, 20000
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=budget, t_cycle=True,
+                                   h_is_a=h_is_a)
+    for s, (a, b) in enumerate(zip(A, B)):
+        xg = host(X[s])
+        for c in range(ks[s]):
+            xo, _, io = oracle.cta(a, b[:, c], tol=tol, t=t, max_iter=budget, t_cycle=True,
+                                   h_is_a=h_is_a)
+            ig = infos[s][c]
+            assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), (s, c, ig, io)
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-10 * max(np.linalg.norm(xo), 1e-300)
+    plan.close()
+
+
+def test_batched_order_cycling_mixed_reaches_tolerance():
+    A, B, ks = _systems()
+    plan = P.BatchPlan(A, "fp32")
+    tol = 1e-8
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=4, max_iter=20000, t_cycle=True,
+                                   minnorm=True, precision="fp32")
+    for s, (a, b) in enumerate(zip(A, B)):
+        for c in range(ks[s]):
+            ig = infos[s][c]
+            xo, _, io = oracle.cta_minnorm(a, b[:, c], tol=tol, t=4, max_iter=20000, t_cycle=True)
+            if io.stop != "residual":  # the inconsistent column of the tall system
+                continue
+            assert ig.stop == "residual" and ig.rel_res <= tol, (s, c, ig)
+            assert np.linalg.norm(host(X[s])[:, c] - xo) <= 1e-6 * np.linalg.norm(xo), (s, c)
+    plan.close()

@@ -104,10 +104,11 @@ def test_cycling_and_h_a_together():
 
 
 def test_batched_rejects_variants():
-    """Order cycling, the enhanced stop and the convex-combination step are
-    single-system options (H = A is tested in test_gpu_batched.py)."""
+    """The enhanced stop and the convex-combination step are single-system
+    options (H = A and order cycling in batches are tested in
+    test_gpu_batched.py)."""
     plan = P.BatchPlan([poisson5(4)], "fp64")
-    for kw in (dict(t_cycle=True), dict(enhanced=True, tol_normal=1e-9), dict(accel=0.5)):
+    for kw in (dict(enhanced=True, tol_normal=1e-9), dict(accel=0.5)):
         with pytest.raises(P.TaError, match="EINVAL"):
             P.cta_solve_batched(plan, [np.ones((16, 1))], **kw)
     plan.close()
