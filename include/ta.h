@@ -156,8 +156,8 @@ typedef struct ta_opts {
                               line, so that the next step solves such a system; never twice in
                               a row.  The combination takes no product and is not counted as an
                               iteration; hist[k] holds the combined residual.  0 = off; a value
-                              outside [0, 1) is TA_EINVAL.  Other solvers and batched solves:
-                              0 */
+                              outside [0, 1) is TA_EINVAL.  cta_solve_batched: the same, each
+                              column deciding on its own residuals.  Other solvers: 0 */
 } ta_opts;
 
 /* Result summary (host struct). */
@@ -341,8 +341,8 @@ int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, cons
  *   opts : as cta_solve; opts->precision is TA_FP64 or the plan's precision;
  *          opts->warm_start and opts->replace_every are not used; opts->chunk
  *          is the number of iterations between true-residual checks
- *          (0 = automatic); h_mode and t_cycle as cta_solve; enhanced and
- *          accel must be 0 (TA_EINVAL);
+ *          (0 = automatic); h_mode, t_cycle and accel as cta_solve; enhanced
+ *          must be 0 (TA_EINVAL);
  *   minnorm : 1 = the y-form of cta_minnorm (x = A^T y), 0 = the x-form;
  *   info : host, sum k_s entries, system-major (s, then c): iterations, products,
  *          stop code, FP64 true relative residual, normal-equation residual.

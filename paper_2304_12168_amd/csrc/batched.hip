@@ -99,6 +99,11 @@ struct Groups {
     int32_t minnorm, mixed;
     int32_t hmode;  // 1: H = A (square symmetric systems), the chain is A passes only
     int32_t t_cycle;  // 1: the order of a group's iteration k is cycle_order(t, k)
+    // convex-combination step (accel = theta > 0): per group, whether the
+    // last iteration combined, and this iteration's weight a (0 = none)
+    double accel;
+    int32_t *jumped;
+    double *ajump;
     int64_t max_iter;
     double tol, tol_normal;
 };
@@ -1020,6 +1025,10 @@ __global__ __launch_bounds__(kBlock) void k_bstep_init(Groups gs, const double2 
     gs.nb[g] = nb;
     gs.tol_nb[g] = gs.tol * nb;
     gs.rr[g] = bb;
+    if (gs.accel > 0.0) {
+        gs.jumped[g] = 0;
+        gs.ajump[g] = 0.0;
+    }
     gs.status[g] = kActive;
     gs.stop[g] = 0;
     if (nb == 0.0) {
@@ -1112,7 +1121,8 @@ template <typename X, int K, typename YA>
 __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
                                                        const BRange *__restrict__ blocks,
                                                        Groups gs, double2 *partials,
-                                                       int64_t cap, int32_t acc_y) {
+                                                       int64_t cap, int32_t acc_y, X *r_keep,
+                                                       YA *y_keep) {
     if (gs.flags[0]) return;
     constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
     const BRange br = blocks[blockIdx.x];
@@ -1147,6 +1157,9 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
                 if (j <= t) uv[j] = *reinterpret_cast<const VecT<X, CV> *>((const X *)U.p[j] + e);
             VecT<YA, CV> yw;
             if (acc_y) yw = *reinterpret_cast<const VecT<YA, CV> *>(yv + e);
+            // r_k and the iterate before the update, for the convex-combination step
+            if (r_keep != nullptr) *reinterpret_cast<VecT<X, CV> *>(r_keep + e) = uv[0];
+            if (acc_y && y_keep != nullptr) *reinterpret_cast<VecT<YA, CV> *>(y_keep + e) = yw;
             double ri[CV];
 #pragma unroll
             for (int v = 0; v < CV; ++v) ri[v] = (double)uv[0].v[v];
@@ -1218,7 +1231,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_r(BVecs U, X *r, YA *yv,
 template <typename X, int K, typename XA>
 __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, XA *xv,
                                                        const BRange *__restrict__ blocks,
-                                                       Groups gs) {
+                                                       Groups gs, XA *x_keep) {
     if (gs.flags[0]) return;
     constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
     const BRange br = blocks[blockIdx.x];
@@ -1247,6 +1260,7 @@ __global__ __launch_bounds__(kBlock) void k_bupdate_x(BVecs W, XA *xv,
             if (j < t) wv[j] = *reinterpret_cast<const VecT<X, CV> *>((const X *)W.p[j] + e);
         double xi[CV], x0[CV];
         vld<XA, CV>(xv + e, x0);
+        if (x_keep != nullptr) vst<XA, CV>(x_keep + e, x0);  // x_k, for the combination
 #pragma unroll
         for (int v = 0; v < CV; ++v) xi[v] = x0[v];
 #pragma unroll
@@ -1345,8 +1359,116 @@ __global__ __launch_bounds__(kBlock) void k_bstep_end(Groups gs, const double2 *
     const int s = g / gs.K, c = g % gs.K;
     const double rr = wave_slot_sum(partials + (int64_t)c * cap, gs.a_blk[s], gs.a_blk[s + 1]);
     if ((threadIdx.x & 63) != 0) return;
+    const double rr0 = gs.rr[g];
     gs.rr[g] = rr;
     gs.k[g] += 1;
+    if (gs.accel > 0.0) {
+        // the convex-combination step of the theorem on the dynamics of
+        // first-order CTA (section 3.4): rho = ||r_{k+1}|| / ||r_k|| >= theta,
+        // not twice in a row, weight a = rho / (rho + 1); the loop top then
+        // waits for the combined residual (k_bstep_jump)
+        const double rho = rr0 > 0.0 ? sqrt(rr / rr0) : 0.0;
+        const bool jump = !gs.jumped[g] && rho >= gs.accel;
+        gs.jumped[g] = jump ? 1 : 0;
+        gs.ajump[g] = jump ? rho / (rho + 1.0) : 0.0;
+        if (jump) return;
+    }
+    group_loop_top(gs, g);
+}
+
+// The combination for the groups that take it: r = a r_k + (1 - a) r_{k+1}
+// (with r != nullptr; partial ||r||^2 in slot 0) and the same of the iterate
+// the table's rows hold (y, x, or the chunk's increment; with xy !=
+// nullptr), from the copies the update kernels made of r_k and the iterate
+// before the update.
+template <typename X, int K, typename XA>
+__global__ __launch_bounds__(kBlock) void k_bjump(X *r, const X *__restrict__ rp, XA *xy,
+                                                   const XA *__restrict__ xyp,
+                                                   const BRange *__restrict__ blocks, Groups gs,
+                                                   double2 *partials, int64_t cap) {
+    if (gs.flags[0]) return;
+    constexpr int CV = Lanes<X, K>::CV, KL = Lanes<X, K>::KL, R = 64 / KL;
+    const BRange br = blocks[blockIdx.x];
+    if (br.r0 >= br.r1) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cl = lane % KL, rsub = lane / KL, c0 = cl * CV;
+    double a[CV];
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < CV; ++v) {
+        const int g = br.sys * K + c0 + v;
+        a[v] = gs.status[g] == kActive ? gs.ajump[g] : 0.0;
+        any |= a[v] > 0.0;
+    }
+    Acc part[CV];
+#pragma unroll
+    for (int v = 0; v < CV; ++v) part[v] = Acc{0.0, 0.0};
+    if (any) {
+        for (BIter it = brow_first(br, R, wave, rsub); it.row >= 0;
+             it = brow_next(br, R, wave, rsub, it)) {
+            const int64_t e = (int64_t)it.row * K + c0;
+            if (r != nullptr) {
+                double rv[CV], pv[CV];
+                vld<X, CV>(r + e, rv);
+                vld<X, CV>(rp + e, pv);
+#pragma unroll
+                for (int v = 0; v < CV; ++v)
+                    if (a[v] > 0.0) rv[v] = __fma_rn(a[v], pv[v], (1.0 - a[v]) * rv[v]);
+                vst<X, CV>(r + e, rv);
+#pragma unroll
+                for (int v = 0; v < CV; ++v)
+                    if (a[v] > 0.0) {
+                        const double q = (double)(X)rv[v];
+                        acc_fma(part[v], q, q);
+                    }
+            }
+            if (xy != nullptr) {
+                double xv[CV], pv[CV];
+                vld<XA, CV>(xy + e, xv);
+                vld<XA, CV>(xyp + e, pv);
+#pragma unroll
+                for (int v = 0; v < CV; ++v)
+                    if (a[v] > 0.0) xv[v] = __fma_rn(a[v], pv[v], (1.0 - a[v]) * xv[v]);
+                vst<XA, CV>(xy + e, xv);
+            }
+        }
+    }
+    if (r == nullptr) return;
+#pragma unroll
+    for (int off = KL; off < 64; off <<= 1) {
+#pragma unroll
+        for (int v = 0; v < CV; ++v) {
+            Acc o;
+            o.p = __shfl_xor(part[v].p, off);
+            o.s = __shfl_xor(part[v].s, off);
+            part[v] = acc_merge(part[v], o);
+        }
+    }
+    __shared__ Acc red[kBlock / 64][K];
+    if (rsub == 0) {
+#pragma unroll
+        for (int v = 0; v < CV; ++v) red[wave][c0 + v] = part[v];
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        Acc s2 = red[0][threadIdx.x];
+        for (int w = 1; w < kBlock / 64; ++w) s2 = acc_merge(s2, red[w][threadIdx.x]);
+        partials[(int64_t)threadIdx.x * cap + br.part] = make_double2(s2.p, s2.s);
+    }
+}
+
+// After the combination: ||r||^2 of the groups that took it, then their loop top.
+__global__ __launch_bounds__(kBlock) void k_bstep_jump(Groups gs, const double2 *partials,
+                                                        int64_t cap) {
+    if (gs.flags[0]) return;
+    const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (g >= gs.nsys * gs.K) return;
+    if (gs.status[g] != kActive || !(gs.ajump[g] > 0.0)) return;
+    const int s = g / gs.K, c = g % gs.K;
+    const double rr = wave_slot_sum(partials + (int64_t)c * cap, gs.a_blk[s], gs.a_blk[s + 1]);
+    if ((threadIdx.x & 63) != 0) return;
+    gs.rr[g] = rr;
+    gs.ajump[g] = 0.0;
     group_loop_top(gs, g);
 }
 
@@ -2216,6 +2338,21 @@ struct Engine {
         if (mixed) ws.reserve(&D, M * K);
         ws.reserve(&RT, M * K);
         ws.reserve(&TN, N * K);
+        // the convex-combination step: r_k and the iterate before each update
+        // (y, x with H = A, or the low-precision increment: M rows; the FP64
+        // x-form's x: N rows, FP64)
+        const bool accel = o->accel > 0.0;
+        X *Rk = nullptr, *XYk_lo = nullptr;  // the low-precision increment's copy
+        double *XYk_64 = nullptr;            // y's or x's (FP64)
+        if (accel) {
+            ws.reserve(&Rk, M * K);
+            if (mixed)
+                ws.reserve(&XYk_lo, M * K);
+            else
+                ws.reserve(&XYk_64, (minnorm || ha ? M : N) * K);
+            ws.reserve(&gs.jumped, G);
+            ws.reserve(&gs.ajump, G);
+        }
         double *DS = nullptr;  // column shares of the dense products
         if (P.dense)
             ws.reserve(&DS, dense_xt_doubles(P, K) +
@@ -2281,6 +2418,7 @@ struct Engine {
         gs.mixed = mixed;
         gs.hmode = ha ? 1 : 0;
         gs.t_cycle = o->t_cycle;
+        gs.accel = o->accel;
         gs.max_iter = o->max_iter;
         gs.tol = o->tol;
         gs.tol_normal = o->tol_normal;
@@ -2344,20 +2482,36 @@ struct Engine {
             if (na > 0) {
                 if (mixed)
                     k_bupdate_r<X, K, X><<<na, kBlock, 0, cs>>>(uv, R, D, d_ta, gs, partials, cap,
-                                                                 1);
+                                                                 1, Rk, XYk_lo);
                 else
                     k_bupdate_r<X, K, double><<<na, kBlock, 0, cs>>>(
-                        uv, R, ha ? Xc : Y, d_ta, gs, partials, cap, (minnorm || ha) ? 1 : 0);
+                        uv, R, ha ? Xc : Y, d_ta, gs, partials, cap, (minnorm || ha) ? 1 : 0, Rk,
+                        XYk_64);
             }
             if (!minnorm && !mixed && !ha && nt > 0) {
                 BVecs wv{};
                 for (int j = 0; j < t; ++j) wv.p[j] = W[j];
-                if (mixed)
-                    k_bupdate_x<X, K, X><<<nt, kBlock, 0, cs>>>(wv, D, d_tt, gs);
-                else
-                    k_bupdate_x<X, K, double><<<nt, kBlock, 0, cs>>>(wv, Xc, d_tt, gs);
+                k_bupdate_x<X, K, double><<<nt, kBlock, 0, cs>>>(wv, Xc, d_tt, gs, XYk_64);
             }
             k_bstep_end<<<gw, kBlock, 0, cs>>>(gs, partials, cap);
+            if (accel) {
+                // the combination of r and of the iterate: r and y, x (H = A) or
+                // the chunk's increment on the A rows; the FP64 x-form's x on
+                // the A^T rows
+                if (na > 0) {
+                    if (mixed)
+                        k_bjump<X, K, X><<<na, kBlock, 0, cs>>>(R, Rk, D, XYk_lo, d_ta, gs,
+                                                                 partials, cap);
+                    else
+                        k_bjump<X, K, double><<<na, kBlock, 0, cs>>>(
+                            R, Rk, (minnorm || ha) ? (minnorm ? Y : Xc) : nullptr, XYk_64, d_ta, gs,
+                            partials, cap);
+                }
+                if (!minnorm && !mixed && !ha && nt > 0)
+                    k_bjump<X, K, double><<<nt, kBlock, 0, cs>>>(nullptr, nullptr, Xc, XYk_64,
+                                                                  d_tt, gs, partials, cap);
+                k_bstep_jump<<<gw, kBlock, 0, cs>>>(gs, partials, cap);
+            }
             k_bsummary<<<1, kBlock, 0, cs>>>(gs, 1);
         };
         const int32_t products = minnorm ? 2 : 1;
@@ -2544,9 +2698,9 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         return TA_EINVAL;
     if (o->t < 1 || o->t > kTMax || o->max_iter < 0 || o->chunk < 0) return TA_EINVAL;
     if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
-    if (o->nonneg != 0 || o->rho_max != 0.0 || o->enhanced != 0 || o->normal_eq != 0 ||
-        o->accel != 0.0)
-        return TA_EINVAL;  // batched: no enhanced stop, no convex-combination step
+    if (o->nonneg != 0 || o->rho_max != 0.0 || o->enhanced != 0 || o->normal_eq != 0)
+        return TA_EINVAL;  // batched: no enhanced stop
+    if (!(o->accel >= 0.0 && o->accel < 1.0)) return TA_EINVAL;
     if (o->t_cycle != 0 && o->t_cycle != 1) return TA_EINVAL;
     if (o->h_mode != 0 && o->h_mode != 1) return TA_EINVAL;
     if (o->h_mode == 1) {

@@ -483,3 +483,44 @@ def test_batched_order_cycling_mixed_reaches_tolerance():
             assert ig.stop == "residual" and ig.rel_res <= tol, (s, c, ig)
             assert np.linalg.norm(host(X[s])[:, c] - xo) <= 1e-6 * np.linalg.norm(xo), (s, c)
     plan.close()
+
+
+# ---------------------------------------------------------------------------
+# the convex-combination step in batches (section 3.4's dynamics theorem):
+# each column decides on its own residuals
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["x_form", "y_form", "h_a"])
+@pytest.mark.parametrize("t", [1, 3])
+def test_batched_convex_combination_fp64_matches_oracle(form, t):
+    h_is_a, minnorm = form == "h_a", form == "y_form"
+    A, B, ks = _spd_systems() if h_is_a else _systems()
+    plan = P.BatchPlan(A, "fp64")
+    tol, budget = 1e-9, 20000
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=t, max_iter=budget, accel=0.5,
+                                   h_is_a=h_is_a, minnorm=minnorm)
+    for s, (a, b) in enumerate(zip(A, B)):
+        xg = host(X[s])
+        for c in range(ks[s]):
+            xo, _, io = oracle.cta(a, b[:, c], tol=tol, t=t, max_iter=budget, accel=0.5,
+                                   h_is_a=h_is_a, minnorm=minnorm)
+            ig = infos[s][c]
+            assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), (s, c, ig, io)
+            assert np.linalg.norm(xg[:, c] - xo) <= 1e-10 * max(np.linalg.norm(xo), 1e-300)
+    plan.close()
+
+
+def test_batched_convex_combination_mixed_reaches_tolerance():
+    A, B, ks = _systems()
+    plan = P.BatchPlan(A, "fp32")
+    tol = 1e-8
+    X, infos = P.cta_solve_batched(plan, B, tol=tol, t=1, max_iter=20000, accel=0.5,
+                                   precision="fp32")
+    for s, (a, b) in enumerate(zip(A, B)):
+        for c in range(ks[s]):
+            xo, _, io = oracle.cta(a, b[:, c], tol=tol, t=1, max_iter=20000, accel=0.5)
+            if io.stop != "residual":
+                continue
+            ig = infos[s][c]
+            assert ig.stop == "residual" and ig.rel_res <= tol, (s, c, ig)
+            assert np.linalg.norm(host(X[s])[:, c] - xo) <= 1e-6 * np.linalg.norm(xo), (s, c)
+    plan.close()

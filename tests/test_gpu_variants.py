@@ -104,11 +104,11 @@ def test_cycling_and_h_a_together():
 
 
 def test_batched_rejects_variants():
-    """The enhanced stop and the convex-combination step are single-system
-    options (H = A and order cycling in batches are tested in
-    test_gpu_batched.py)."""
+    """The enhanced stop is a single-system option (H = A, order cycling and
+    the convex-combination step in batches are tested in
+    test_gpu_batched.py); theta must lie in [0, 1)."""
     plan = P.BatchPlan([poisson5(4)], "fp64")
-    for kw in (dict(enhanced=True, tol_normal=1e-9), dict(accel=0.5)):
+    for kw in (dict(enhanced=True, tol_normal=1e-9), dict(accel=1.0), dict(accel=-0.5)):
         with pytest.raises(P.TaError, match="EINVAL"):
             P.cta_solve_batched(plan, [np.ones((16, 1))], **kw)
     plan.close()
