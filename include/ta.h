@@ -128,7 +128,8 @@ typedef struct ta_opts {
     double rho_max;        /* ta_solve: > 0 = stop with WITNESS once the radius would grow
                               beyond rho_max (the termination bound section 6 asks for);
                               0 = no bound.  Other solvers: 0 */
-    int32_t enhanced;      /* cta_solve / cta_minnorm: 1 = the enhanced stop of section 3.2 (for
+    int32_t enhanced;      /* cta_solve / cta_minnorm / cta_solve_batched (per column): 1 =
+                              the enhanced stop of section 3.2 (for
                               t >= 2): in every iteration of order t >= 2 the j-fold first-order
                               iterates f_j = F_1(f_{j-1}), f_0 = r, j = 1..t-1, are also tested,
                               and the first with ||A^T f_j|| <= tol_normal ||A^T b|| (||A f_j||
@@ -341,8 +342,8 @@ int cta_solve_plan_noalloc(const ta_plan *plan, const double *b, double *x, cons
  *   opts : as cta_solve; opts->precision is TA_FP64 or the plan's precision;
  *          opts->warm_start and opts->replace_every are not used; opts->chunk
  *          is the number of iterations between true-residual checks
- *          (0 = automatic); h_mode, t_cycle and accel as cta_solve; enhanced
- *          must be 0 (TA_EINVAL);
+ *          (0 = automatic); h_mode, t_cycle, enhanced and accel as cta_solve,
+ *          per column;
  *   minnorm : 1 = the y-form of cta_minnorm (x = A^T y), 0 = the x-form;
  *   info : host, sum k_s entries, system-major (s, then c): iterations, products,
  *          stop code, FP64 true relative residual, normal-equation residual.

@@ -104,6 +104,10 @@ struct Groups {
     double accel;
     int32_t *jumped;
     double *ajump;
+    // the enhanced stop (section 3.2): per group, whether this iteration's
+    // update is x^ (the solve then stops NORMAL after it)
+    int32_t enhanced;
+    int32_t *enh_hit;
     int64_t max_iter;
     double tol, tol_normal;
 };
@@ -1029,6 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_bstep_init(Groups gs, const double2 
         gs.jumped[g] = 0;
         gs.ajump[g] = 0.0;
     }
+    if (gs.enhanced) gs.enh_hit[g] = 0;
     gs.status[g] = kActive;
     gs.stop[g] = 0;
     if (nb == 0.0) {
@@ -1086,6 +1091,12 @@ __global__ __launch_bounds__(kBlock) void k_bstep_gram(Groups gs, const double2 
         return;
     }
     double a[kTMax];
+    if (gs.enhanced && tk >= 2 && gs.tol_ne_nab[g] > 0.0 &&
+        enhanced_hit(phi, tk, gs.hmode, gs.tol_ne_nab[g], a)) {
+        for (int i = 0; i < kTMax; ++i) gs.alpha[(int64_t)g * kTMax + i] = i < tk ? a[i] : 0.0;
+        gs.enh_hit[g] = 1;
+        return;
+    }
     gram_alpha(phi, tk, a);
     for (int i = 0; i < tk; ++i)
         if (!isfinite(a[i])) {
@@ -1362,6 +1373,11 @@ __global__ __launch_bounds__(kBlock) void k_bstep_end(Groups gs, const double2 *
     const double rr0 = gs.rr[g];
     gs.rr[g] = rr;
     gs.k[g] += 1;
+    if (gs.enhanced && gs.enh_hit[g]) {  // the update just applied x^
+        gs.status[g] = kFinished;
+        gs.stop[g] = TA_STOP_NORMAL;
+        return;
+    }
     if (gs.accel > 0.0) {
         // the convex-combination step of the theorem on the dynamics of
         // first-order CTA (section 3.4): rho = ||r_{k+1}|| / ||r_k|| >= theta,
@@ -2353,6 +2369,7 @@ struct Engine {
             ws.reserve(&gs.jumped, G);
             ws.reserve(&gs.ajump, G);
         }
+        if (o->enhanced) ws.reserve(&gs.enh_hit, G);
         double *DS = nullptr;  // column shares of the dense products
         if (P.dense)
             ws.reserve(&DS, dense_xt_doubles(P, K) +
@@ -2419,6 +2436,7 @@ struct Engine {
         gs.hmode = ha ? 1 : 0;
         gs.t_cycle = o->t_cycle;
         gs.accel = o->accel;
+        gs.enhanced = o->enhanced;
         gs.max_iter = o->max_iter;
         gs.tol = o->tol;
         gs.tol_normal = o->tol_normal;
@@ -2698,8 +2716,8 @@ static int solve_batched(const BatchPlan &P, const int32_t *nrhs, const double *
         return TA_EINVAL;
     if (o->t < 1 || o->t > kTMax || o->max_iter < 0 || o->chunk < 0) return TA_EINVAL;
     if (o->launch_mode != 0 && o->launch_mode != 1) return TA_EINVAL;
-    if (o->nonneg != 0 || o->rho_max != 0.0 || o->enhanced != 0 || o->normal_eq != 0)
-        return TA_EINVAL;  // batched: no enhanced stop
+    if (o->nonneg != 0 || o->rho_max != 0.0 || o->normal_eq != 0) return TA_EINVAL;
+    if (o->enhanced != 0 && o->enhanced != 1) return TA_EINVAL;
     if (!(o->accel >= 0.0 && o->accel < 1.0)) return TA_EINVAL;
     if (o->t_cycle != 0 && o->t_cycle != 1) return TA_EINVAL;
     if (o->h_mode != 0 && o->h_mode != 1) return TA_EINVAL;

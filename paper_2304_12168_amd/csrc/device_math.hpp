@@ -57,6 +57,39 @@ __device__ __forceinline__ Acc group_reduce(Acc v) {
     return v;
 }
 
+// Enhanced stop (section 3.2, t >= 2): the first-order iterates
+// f_j = F_1(f_{j-1}), f_0 = r, lie in r + span{H r, ..., H^j r}:
+// f_j = sum_k c_k H^k r, so f^T H^p f = sum_{k,l} c_k c_l phi_{k+l+p} needs
+// phi up to 2j + 2 <= 2t.  a_j = (f^T H f) / (f^T H^2 f); the test is on
+// ||A^T f_j||^2 = f^T H f (H = A A^T) or ||A f_j||^2 = f^T H^2 f (H = A);
+// x^ = x + sum_i a_{i+1} (A^T) f_i has the coefficients beta_k on the vectors
+// the update already uses (A^T H^k r, or H^k r), so the update kernels apply
+// x^ as they apply alpha, and r - sum beta_k H^{k+1} r is x^'s residual.
+// Returns true at the first j that passes, with beta_0 .. beta_{t-1} set.
+__device__ inline bool enhanced_hit(const double *phi, int t, int hmode, double tol_ne_nab,
+                                    double *beta) {
+    double c[kTMax + 1] = {1.0};
+    for (int i = 0; i < t; ++i) beta[i] = 0.0;
+    const int ptest = hmode ? 2 : 1;
+    for (int j = 1; j < t; ++j) {
+        double e1 = 0.0, e2 = 0.0;
+        for (int k = 0; k < j; ++k)
+            for (int l = 0; l < j; ++l) {
+                e1 += c[k] * c[l] * phi[k + l + 1];
+                e2 += c[k] * c[l] * phi[k + l + 2];
+            }
+        if (!(e2 > 0.0) || !isfinite(e1) || !isfinite(e2)) return false;
+        const double aj = e1 / e2;
+        for (int k = 0; k < j; ++k) beta[k] = fma(aj, c[k], beta[k]);
+        for (int k = j; k >= 1; --k) c[k] = fma(-aj, c[k - 1], c[k]);
+        double q = 0.0;
+        for (int k = 0; k <= j; ++k)
+            for (int l = 0; l <= j; ++l) q += c[k] * c[l] * phi[k + l + ptest];
+        if (sqrt(fmax(q, 0.0)) <= tol_ne_nab) return true;
+    }
+    return false;
+}
+
 // Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous
 // range of logical blocks so neighbouring rows share one L2.
 __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {

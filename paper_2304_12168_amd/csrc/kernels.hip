@@ -99,37 +99,12 @@ __device__ void post_action(const Step &sp, const double *v, bool computed) {
             double phi[2 * kTMax + 2];
             for (int i = 0; i <= 2 * t; ++i) phi[i] = st->phi[i];
             double a[kTMax];
-            // Enhanced stop (section 3.2, t >= 2): the first-order iterates
-            // f_j = F_1(f_{j-1}), f_0 = r, lie in r + span{H r, ..., H^j r}:
-            // f_j = sum_k c_k H^k r, so f^T H^p f = sum_{k,l} c_k c_l phi_{k+l+p}
-            // needs phi up to 2j + 2 <= 2t.  a_j = (f^T H f) / (f^T H^2 f);
-            // the test is on ||A^T f_j||^2 = f^T H f (H = A A^T) or ||A f_j||^2
-            // = f^T H^2 f (H = A); x^ = x + sum_i a_{i+1} (A^T) f_i has the
-            // coefficients beta_k on the vectors the update already uses
-            // (A^T H^k r, or H^k r), so the update kernels apply x^ as they
-            // apply alpha, and r - sum beta_k H^{k+1} r is x^'s residual.
             if (st->enhanced && t >= 2 && st->tol_ne_nab > 0.0) {
-                double c[kTMax + 1] = {1.0}, beta[kTMax] = {};
-                const int ptest = st->hmode ? 2 : 1;
-                for (int j = 1; j < t; ++j) {
-                    double e1 = 0.0, e2 = 0.0;
-                    for (int k = 0; k < j; ++k)
-                        for (int l = 0; l < j; ++l) {
-                            e1 += c[k] * c[l] * phi[k + l + 1];
-                            e2 += c[k] * c[l] * phi[k + l + 2];
-                        }
-                    if (!(e2 > 0.0) || !isfinite(e1) || !isfinite(e2)) break;
-                    const double aj = e1 / e2;
-                    for (int k = 0; k < j; ++k) beta[k] = fma(aj, c[k], beta[k]);
-                    for (int k = j; k >= 1; --k) c[k] = fma(-aj, c[k - 1], c[k]);
-                    double q = 0.0;
-                    for (int k = 0; k <= j; ++k)
-                        for (int l = 0; l <= j; ++l) q += c[k] * c[l] * phi[k + l + ptest];
-                    if (sqrt(fmax(q, 0.0)) <= st->tol_ne_nab) {
-                        for (int i = 0; i < t; ++i) st->alpha[i] = beta[i];
-                        st->enh_hit = 1;
-                        return;
-                    }
+                double beta[kTMax];
+                if (enhanced_hit(phi, t, st->hmode, st->tol_ne_nab, beta)) {
+                    for (int i = 0; i < t; ++i) st->alpha[i] = beta[i];
+                    st->enh_hit = 1;
+                    return;
                 }
             }
             gram_alpha(phi, t, a);

@@ -108,12 +108,19 @@ def test_accel_rejected_outside_cta():
         P.cta_solve(A, b, accel=1.5)
 
 
-def test_accel_rejected_by_batched_engine():
+def test_accel_in_the_batched_engine_with_order_cycling():
+    """The batched engine takes the step per column (its own tests are in
+    test_gpu_batched.py); here together with order cycling, against the
+    oracle."""
     p = kac_clement(101)
     plan = P.BatchPlan([p.A], "fp64")
-    B = [np.asarray(p.b)]
-    with pytest.raises(P.TaError, match="EINVAL"):
-        P.cta_solve_batched(plan, B, tol=1e-8, t=2, accel=0.5)
+    kw = dict(tol=1e-8, t=3, max_iter=20_000, accel=0.5, t_cycle=True)
+    X, infos = P.cta_solve_batched(plan, [np.asarray(p.b)], **kw)
+    plan.close()
+    xo, _, io = oracle.cta(p.A, p.b, **kw)
+    ig = infos[0][0]
+    assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs)
+    assert np.linalg.norm(X[0][:, 0].cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
 @pytest.mark.parametrize("t", [3, 5])

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import paper_2304_12168_amd as P
-from workloads import csr_from_dense, kac_clement
+from workloads import csr_from_dense, kac_clement, poisson5
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -109,3 +109,46 @@ def test_inconsistent_kac(t):
     assert ig.rel_normal <= 1e-6 * (1 + 1e-6) and io.rel_normal <= 1e-6 * (1 + 1e-6)
     _, _, ip = P.cta_solve(A, b, tol=1e-10, t=t, max_iter=200000, tol_normal=1e-6)
     assert ip.stop == "normal" and ig.iters <= ip.iters
+
+
+@pytest.mark.parametrize("t", [2, 3, 4])
+@pytest.mark.parametrize("form", ["x_form", "y_form", "h_a"])
+def test_batched_enhanced_matches_oracle(form, t):
+    """The enhanced stop in cta_solve_batched: a window case beside a second
+    system with two right-hand sides (Kac / Clement, consistent and
+    inconsistent; with H = A a Poisson matrix, which is symmetric positive
+    definite), each column against its own oracle run -- exactly for the
+    window case; for the other columns, whose tests carry no margin, the stop
+    codes agree and the counts within one iteration, as in
+    test_inconsistent_kac."""
+    A, b, tol_ne = _window_case(form == "h_a", t)
+    g = np.random.default_rng(5)
+    if form == "h_a":
+        other = poisson5(8)
+        B2 = other.to_scipy() @ g.standard_normal((other.n, 2))
+    else:
+        kac = kac_clement(101)
+        other = kac.A
+        B2 = np.stack([kac.b, g.standard_normal(101)], axis=1)
+    systems = [csr_from_dense(A), other]
+    B = [b.reshape(-1, 1), B2]
+    minnorm = form == "y_form"
+    kw = dict(tol=1e-12, t=t, max_iter=3000, tol_normal=tol_ne, enhanced=True,
+              h_is_a=form == "h_a")
+    plan = P.BatchPlan(systems, "fp64")
+    X, infos = P.cta_solve_batched(plan, B, minnorm=minnorm, **kw)
+    plan.close()
+    run = oracle.cta_minnorm if minnorm else oracle.cta
+    assert infos[0][0].stop == "normal" and infos[0][0].iters == 1
+    for s, (a, bb) in enumerate(zip(systems, B)):
+        for c in range(bb.shape[1]):
+            xo, _, io = run(a, bb[:, c], **kw)
+            ig = infos[s][c]
+            xg = X[s][:, c].cpu().numpy()
+            if s == 0 or ig.iters == io.iters:
+                assert (ig.stop, ig.iters, ig.matvecs) == (io.stop, io.iters, io.matvecs), \
+                    (s, c, ig, io)
+                assert np.linalg.norm(xg - xo) <= 1e-9 * max(np.linalg.norm(xo), 1e-300)
+            else:
+                assert ig.stop == io.stop == "normal" and abs(ig.iters - io.iters) <= 1, (ig, io)
+                assert ig.rel_normal <= tol_ne * (1 + 1e-6)

@@ -103,12 +103,11 @@ def test_cycling_and_h_a_together():
     assert np.linalg.norm(xg.cpu().numpy() - xo) <= 1e-10 * np.linalg.norm(xo)
 
 
-def test_batched_rejects_variants():
-    """The enhanced stop is a single-system option (H = A, order cycling and
-    the convex-combination step in batches are tested in
-    test_gpu_batched.py); theta must lie in [0, 1)."""
+def test_batched_rejects_bad_variant_options():
+    """Batches take every CTA variant (tested in test_gpu_batched.py and
+    test_gpu_enhanced.py); theta must lie in [0, 1) and the flags be 0 or 1."""
     plan = P.BatchPlan([poisson5(4)], "fp64")
-    for kw in (dict(enhanced=True, tol_normal=1e-9), dict(accel=1.0), dict(accel=-0.5)):
+    for kw in (dict(accel=1.0), dict(accel=-0.5)):
         with pytest.raises(P.TaError, match="EINVAL"):
             P.cta_solve_batched(plan, [np.ones((16, 1))], **kw)
     plan.close()
