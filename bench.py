@@ -740,6 +740,75 @@ def dense_products_bench(args, P, torch, dev):
     return out
 
 
+def traffic_record(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv):
+    """Write the HBM traffic record of the dominant kernel (TRAFFIC_FILE)
+    from four rocprofv3 counter collections (csv): FETCH_SIZE and WRITE_SIZE
+    of this script's default run filtered to k_bspmm, and of --copy-calibration.
+    The timing hook's last four runs of >= 20 back-to-back launches of the
+    FP32 K = 64 kernel, in the order the script times them (part 0 A, A^T,
+    part 1 A, A^T), each averaged over its last 20 (timed) launches, are
+    scaled by the copy's counts per GiB; the record
+    carries the SHA-256 of the kernel source, which measured_traffic checks."""
+    import collections
+    import csv
+    import hashlib
+    import statistics
+
+    def dispatches(path):
+        d = collections.OrderedDict()
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                k = int(r["Dispatch_Id"])
+                e = d.setdefault(k, {"name": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                                     "val": 0.0})
+                e["val"] += float(r["Counter_Value"])
+        return list(d.items())
+
+    def runs(path, name):
+        items = [(k, v) for k, v in dispatches(path) if v["name"].startswith(name)]
+        out, i = [], 0
+        while i < len(items):
+            j = i
+            while (j + 1 < len(items) and items[j + 1][1]["grid"] == items[i][1]["grid"]
+                   and items[j + 1][0] == items[j][0] + 1):
+                j += 1
+            if j - i + 1 >= 20:  # the last 20: the timed launches after tuning and warm-up
+                out.append((items[i][1]["grid"],
+                            statistics.mean(x[1]["val"] for x in items[j - 19:j + 1])))
+            i = j + 1
+        return out[-4:]  # the hook's runs come after the solve's own tuning
+
+    def copy_kib(path):
+        vals = [v["val"] for _, v in dispatches(path) if "copyBuffer" in v["name"]]
+        return statistics.median(vals)
+
+    gib = 2 ** 30 / 1024
+    fcopy, wcopy = copy_kib(copy_fetch_csv), copy_kib(copy_write_csv)
+    name = "void ta::bt::k_bspmm<float, float, 64, 0, 6"
+    fr, wr = runs(fetch_csv, name), runs(write_csv, name)
+    if len(fr) != 4 or len(wr) != 4:
+        raise SystemExit(f"expected 4 timed launch runs, found {len(fr)} and {len(wr)}")
+    keys = [("A", 0), ("AT", 0), ("A", 1), ("AT", 1)]
+    entries = []
+    for (ps, part), (grid, fk), (_, wk) in zip(keys, fr, wr):
+        entries.append({"precision": "fp32", "K": 64, "pass": ps, "part": part, "grid": grid,
+                        "fetch_kib": round(fk, 1), "write_kib": round(wk, 1),
+                        "bytes_per_launch": int(round((fk * gib / fcopy + wk * gib / wcopy) * 1024))})
+    with open(KERNEL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    rec = {"kernel": "k_bspmm<float, float, 64, 0, 6>",
+           "workload": "batched uneven systems (seed 0), K = 64 width group, one launch per "
+                       "row-length part, the timing hook's 20 timed launches",
+           "kernel_source": "paper_2304_12168_amd/csrc/batched.hip",
+           "kernel_source_sha256": sha,
+           "copy_calibration": {"fetch_kib_per_GiB": fcopy, "write_kib_per_GiB": wcopy,
+                                "fetch_scale": gib / fcopy, "write_scale": gib / wcopy},
+           "entries": entries}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    log(f"[bench] traffic record written: {TRAFFIC_FILE}")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -766,10 +835,17 @@ def main():
     ap.add_argument("--sweep-only", action="store_true",
                     help="only the HBM-resident size sweep of the product kernels and the "
                          "dense products (for profiling them), printed as one JSON line")
+    ap.add_argument("--traffic-record", nargs=4, metavar="CSV",
+                    help="write the dominant kernel's traffic record from the FETCH_SIZE and "
+                         "WRITE_SIZE counter csv files of a default run and of "
+                         "--copy-calibration (in that order), and exit; needs no GPU")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB on the device three times (the reference kernel "
                          "that scales the HBM traffic counters) and exit")
     args = ap.parse_args()
+    if args.traffic_record:
+        traffic_record(*args.traffic_record)
+        return
     if args.copy_calibration:
         import torch
 
