@@ -384,8 +384,21 @@ def _ragged_tiles():
     return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
 
 
+def _two_tiles():
+    """Exactly 2 tiles (16384 columns, the smallest tiled width), 300 random
+    entries per row."""
+    g = np.random.default_rng(22)
+    m, n = 257, 16_384
+    rows = np.repeat(np.arange(m), 300)
+    cols = np.concatenate([g.choice(n, size=300, replace=False) for _ in range(m)])
+    A = csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
+    x = g.standard_normal(n)
+    return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
+
+
 REGROUPED = {
     "wide_tiled_A": (_wide, ("csr_tiled", None)),
+    "two_tiles_A": (_two_tiles, ("csr_tiled", None)),
     "tall_tiled_AT": (lambda: _transpose(_wide()), (None, "csr_tiled")),
     "ragged_tiled_A": (_ragged_tiles, ("csr_tiled", None)),
     "wide_sliced_A": (_wide_sliced, ("csr_sliced", None)),

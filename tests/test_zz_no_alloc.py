@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import paper_2304_12168_amd as P
-from workloads import convection_diffusion, csr_from_coo, dense_gaussian
+from workloads import convection_diffusion, csr_from_coo, dense_gaussian, lp_shaped
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -77,3 +77,18 @@ def test_noalloc_refuses_a_solve_larger_than_its_buffer():
         assert info.stop == "residual" and torch.allclose(x, torch.full_like(x, 0.5))
     finally:
         pl.close()
+
+
+def test_noalloc_on_regrouped_plans():
+    """Plans whose A is stored in LDS column tiles (per-(tile, row) partials)
+    or XCD column slices (per-(slice, row) partials): the partials are carved
+    from the buffer too."""
+    for m, n, fmt in ((2000, 200_000, "csr_tiled"), (20_000, 200_000, "csr_sliced")):
+        p = lp_shaped(m, n, seed=5)
+        pl = P.Plan(p.A)
+        try:
+            assert pl.format(False) == fmt
+            kw = dict(tol=1e-8, t=3, max_iter=200)
+            _same(P.cta_solve_noalloc(pl, p.b, **kw), P.cta_solve(pl, p.b, **kw))
+        finally:
+            pl.close()
