@@ -257,8 +257,17 @@ int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
  * quarter is also copied into SELL-64 form (each slice stored position by
  * position, padded to its widest row), so its products need no row bounds
  * and make contiguous index loads; the sums keep the CSR order, so results
- * are unchanged.  The one-shot solvers build the same; the one-shot
- * products (ta_spmv, ta_residual, ta_time_matvec) do not.  Solving many
+ * are unchanged.  A or A^T left to the row kernels whose longest row holds
+ * at least 512 nonzeros and at least 32 times the average gets a merge-path
+ * partition instead (TA_FMT_CSR_MERGE; Merrill and Garland's merge-based
+ * SpMV, SC 2016): the row ends and the nonzeros form one sequence that is
+ * cut into equal shares of 2048 items per block, 8 per thread, so that a
+ * long row is split over many threads and blocks; the pieces of a row are
+ * compensated sums merged in a fixed order, so results do not depend on
+ * timing.  The partition is one int32 per 2048 items, and a call's
+ * workspace holds 48 bytes per block for the pieces that cross blocks.
+ * The one-shot solvers build the same; the one-shot products (ta_spmv,
+ * ta_residual, ta_time_matvec) build the merge-path partition only.  Solving many
  * right-hand sides with one matrix builds them once.  The plan refers to A's device arrays (row_ptr,
  * col_idx, val, or the dense val): they must stay allocated and unchanged
  * while the plan lives.  A plan is read-only once created and may serve
@@ -274,10 +283,12 @@ int ta_plan_destroy(ta_plan *plan);
 
 /* Storage the plan's products use for A (trans = 0) or A^T (trans = 1):
  * TA_FMT_CSR_ROWS, TA_FMT_DENSE_ROWS, TA_FMT_DENSE_COLS, TA_FMT_CSR_SLICED
- * (column slices), TA_FMT_SELL64 or TA_FMT_CSR_TILED (LDS column tiles),
- * written to *format (host).  TA_EINVAL for a NULL argument. */
+ * (column slices), TA_FMT_SELL64, TA_FMT_CSR_TILED (LDS column tiles) or
+ * TA_FMT_CSR_MERGE (merge-path partition), written to *format (host).
+ * TA_EINVAL for a NULL argument. */
 enum { TA_FMT_CSR_ROWS = 0, TA_FMT_DENSE_ROWS = 1, TA_FMT_DENSE_COLS = 2,
-       TA_FMT_CSR_SLICED = 3, TA_FMT_SELL64 = 4, TA_FMT_CSR_TILED = 5 };
+       TA_FMT_CSR_SLICED = 3, TA_FMT_SELL64 = 4, TA_FMT_CSR_TILED = 5,
+       TA_FMT_CSR_MERGE = 6 };
 int ta_plan_format(const ta_plan *plan, int32_t trans, int32_t *format);
 
 /* The solvers above on a prepared operator; other arguments as there. */
@@ -302,8 +313,9 @@ int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, d
  * The plan itself is made beforehand with ta_plan_create (which allocates).
  *   Limit: the workspace is 8 (t + 1) (m + n) bytes (8 (m + n) more with
  *   accel, 128 m or 128 n more for a plan with column slices, 16 m
- *   ceil(n / 8192) or 16 n ceil(m / 8192) more for one with column tiles) plus the
- *   per-block partial sums; a solve that needs more than the buffer returns
+ *   ceil(n / 8192) or 16 n ceil(m / 8192) more for one with column tiles, 48
+ *   bytes per 2048 items of (rows + nonzeros) for a merge-path partition)
+ *   plus the per-block partial sums; a solve that needs more than the buffer returns
  *   TA_ESCRATCH before any device work.  For t = 3 and m = n that is
  *   n up to about 1e6.
  *   Sharing: every call on one GPU uses that GPU's buffer, so calls that

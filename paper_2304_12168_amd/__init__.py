@@ -36,7 +36,7 @@ EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror",
            "cta_solve_plan_noalloc")
 # storage of a plan's products (ta_plan_format)
 FORMATS = {0: "csr_rows", 1: "dense_rows", 2: "dense_cols", 3: "csr_sliced", 4: "sell64",
-           5: "csr_tiled"}
+           5: "csr_tiled", 6: "csr_merge"}
 
 
 class TaMat(C.Structure):

@@ -149,6 +149,7 @@ enum MatKind : int32_t {
     kCsrSliced = 3,  // CSR with columns sorted, split into kSlices column slices (one per XCD)
     kCsrSell = 4,    // CSR copied into 64-row slices (SELL-64), one thread per row
     kCsrTiled = 5,   // CSR regrouped by column tiles of kTileW; each tile of x staged in LDS
+    kCsrMerge = 6,   // CSR split along the merge path of row ends and nonzeros (skewed rows)
 };
 
 constexpr int kSlices = 8;  // XCDs of the part; blocks b with b % 8 == s take column slice s
@@ -161,6 +162,9 @@ constexpr int kTileBlock = 512;  // threads of a tiled block: 2 blocks (16 waves
 constexpr int tile_u(int W) { return W >= 8 ? 1 : 8 / W; }
 constexpr int tile_pr(int W) { return W == 1 ? 2 : 4; }
 constexpr int tile_batch_rows(int W) { return tile_pr(W) * (kTileBlock / W); }
+// kCsrMerge: path items (row ends + nonzeros) per thread and per block
+constexpr int kMergeIpt = 8;
+constexpr int kMergeItems = kBlock * kMergeIpt;
 
 struct MatView {
     int32_t kind;
@@ -172,7 +176,7 @@ struct MatView {
     int32_t lanes;       // kCsrRows: 1 = one thread per row, else lanes per row
     const int32_t *seg;  // kCsrSliced: rows x (kSlices + 1) slice starts inside each row
     double2 *ypart;      // kCsrSliced: kSlices x rows compensated partial sums (workspace);
-                         // kCsrTiled: nt x rows
+                         // kCsrTiled: nt x rows; kCsrMerge: 3 mb (per-block head and carry)
     // kCsrSell: slice s (rows 64 s .. 64 s + 63) holds slots [so[s], so[s + 1]),
     // position k of row 64 s + i at slot so[s] + 64 k + i; a row's entries keep
     // their CSR order, and the slots past its end hold column -1, value 0
@@ -188,6 +192,11 @@ struct MatView {
     int32_t nt;       // tiles
     int32_t nchunk;   // row chunks per tile
     int64_t rchunk;   // rows per chunk
+    // kCsrMerge: block b of the product takes path items [b kMergeItems,
+    // (b + 1) kMergeItems) of the rows + nnz; mp[b] (mb + 1 entries) is the
+    // number of rows completed before its first item
+    const int32_t *mp;
+    int64_t mb;
 };
 
 // ---- launchers (kernels.hip); each returns the grid size it used in *blocks ----
@@ -231,6 +240,11 @@ hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci
 hipError_t launch_tile_build(int64_t rows, int64_t cols, const int32_t *rp, const int32_t *ci_sorted,
                              const double *val_sorted, int32_t *trp, uint16_t *lc, double *tval,
                              int32_t *work, hipStream_t s);
+// kCsrMerge partition: mp[b] for b = 0 .. mb
+hipError_t launch_merge_part(int64_t rows, const int32_t *rp, int64_t mb, int32_t *mp,
+                             hipStream_t s);
+// out[0] = max(out[0], longest row of the CSR rp); out must hold a value <= 0 first
+hipError_t launch_row_max(int64_t rows, const int32_t *rp, int32_t *out, hipStream_t s);
 hipError_t launch_norm2(int64_t n, const double *x, const Out &o, hipStream_t s,
                         int32_t *blocks);
 hipError_t launch_csr_outer(int64_t m, const int32_t *rp, const int32_t *ci, const double *u,

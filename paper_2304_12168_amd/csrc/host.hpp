@@ -135,4 +135,16 @@ inline int check_csr_device(const ta_mat *A, int32_t *dflag, hipStream_t s) {
     return h ? TA_EINVAL : TA_OK;
 }
 
+// check_csr_device, also returning the longest row (dflag: 2 entries)
+inline int check_csr_longest(const ta_mat *A, int32_t *dflag, int64_t *longest, hipStream_t s) {
+    HIP_TRY(hipMemsetAsync(dflag, 0, 2 * sizeof(int32_t), s));
+    HIP_TRY(launch_check_csr(A->m, A->n, A->nnz, A->row_ptr, A->col_idx, dflag, s));
+    HIP_TRY(launch_row_max(A->m, A->row_ptr, dflag + 1, s));
+    int32_t h[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(h, dflag, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *longest = h[1];
+    return h[0] ? TA_EINVAL : TA_OK;
+}
+
 }  // namespace ta

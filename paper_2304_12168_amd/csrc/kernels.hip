@@ -288,7 +288,7 @@ __device__ __forceinline__ bool producer_runs(const Out &o) {
 
 // Block-reduce NV values and write one partial each (thread 0, plain stores).
 template <int NV>
-__device__ void block_partials(Acc (&v)[NV], const Out &o) {
+__device__ void block_partials(Acc (&v)[NV], const Out &o, int64_t bidx = -1) {
     __shared__ Acc red[2][kBlock / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -302,7 +302,8 @@ __device__ void block_partials(Acc (&v)[NV], const Out &o) {
         for (int q = 0; q < NV; ++q) {
             Acc a = red[q][0];
             for (int w = 1; w < kBlock / 64; ++w) a = acc_merge(a, red[q][w]);
-            o.partials[(int64_t)(o.slot + q) * o.cap + blockIdx.x] = make_double2(a.p, a.s);
+            o.partials[(int64_t)(o.slot + q) * o.cap + (bidx < 0 ? (int64_t)blockIdx.x : bidx)] =
+                make_double2(a.p, a.s);
         }
     }
 }
@@ -820,6 +821,264 @@ __global__ __launch_bounds__(kBlock) void k_tiles_combine(MatView M, double *y, 
     block_partials<EpiNV<EPI>::value>(v, o);
 }
 
+// ---------------------------------------------------------------------------
+// Merge-path CSR product for skewed row lengths (kCsrMerge; the merge-based
+// SpMV of Merrill and Garland, SC 2016, restated).  The path merges the row
+// ends with the nonzeros: item d of the path is either nonzero k or the end
+// of row i, where i + k = d and a row's end follows its last nonzero.  Block
+// b takes the kMergeItems items from b kMergeItems on (its first row is
+// mp[b], from the plan), and each of its threads kMergeIpt of them, so a long
+// row is shared by many threads and a thread crosses many short rows.
+//
+// A block stages its nonzeros' exact products (TwoProduct) and its row
+// pointers in LDS.  A thread sums each row it meets in storage order
+// (compensated) and runs the epilogue on the rows that begin and end in it.
+// A row that began in an earlier thread and ends here is its head; the row
+// it is in when its items run out is its carry.  A segmented scan over the
+// block's threads merges each head with the carries before it, in thread
+// order; a head whose row began in an earlier block, and the block's last
+// carry, go to the block's slots, and k_merge_fixup merges those across
+// blocks in block order.  Every row sum is a fixed-order merge of
+// compensated pieces, so the result does not depend on timing.
+// ---------------------------------------------------------------------------
+constexpr int kMergePad = kMergeItems + kMergeItems / kMergeIpt;  // one pad slot per 8 products
+
+// rows completed among the first d items of the path
+__device__ __forceinline__ int64_t merge_split(const int32_t *__restrict__ rp, int64_t rows,
+                                               int64_t nnz, int64_t d) {
+    int64_t lo = d > nnz ? d - nnz : 0, hi = d < rows ? d : rows;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid + 1] <= d - mid - 1)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_merge_part(int64_t rows, const int32_t *__restrict__ rp, int64_t mb,
+                             int32_t *__restrict__ mp) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > mb) return;
+    const int64_t nnz = rp[rows], total = rows + nnz;
+    const int64_t d = min(b * (int64_t)kMergeItems, total);
+    mp[b] = (int32_t)merge_split(rp, rows, nnz, d);
+}
+
+// A scan element: the merged carries of a run of threads; f = this element
+// starts a run, o = the run starts at thread 0 inside a row begun before the
+// block.
+struct SegAcc {
+    Acc v;
+    int32_t f, o;
+};
+
+__device__ __forceinline__ SegAcc seg_combine(const SegAcc &a, const SegAcc &b) {
+    SegAcc c;
+    c.v = b.f ? b.v : acc_merge(a.v, b.v);
+    c.f = a.f | b.f;
+    c.o = b.f ? b.o : a.o;
+    return c;
+}
+
+// The block's slots in M.ypart (mb each): head values, carry values, then
+// head rows and carry rows as int32.
+struct MergeSlots {
+    double2 *hv, *cv;
+    int32_t *hr, *cr;
+};
+
+__device__ __forceinline__ MergeSlots merge_slots(const MatView &M) {
+    MergeSlots q;
+    q.hv = M.ypart;
+    q.cv = M.ypart + M.mb;
+    q.hr = reinterpret_cast<int32_t *>(M.ypart + 2 * M.mb);
+    q.cr = q.hr + M.mb;
+    return q;
+}
+
+template <int EPI>
+__global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *__restrict__ x,
+                                                        double *y, EpiArgs ea, Out o) {
+    if (!producer_runs(o)) return;
+    constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
+    __shared__ double2 s_hp[kMergePad];
+    __shared__ int32_t s_rp[kMergeItems + 2];
+    __shared__ SegAcc s_wave[kBlock / 64];
+    __shared__ int32_t s_hr, s_cr;
+    __shared__ double2 s_hv, s_cv;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t rows = M.rows;
+    const int64_t b = blockIdx.x;
+    const int64_t i0 = M.mp[b], i1 = M.mp[b + 1];
+    const int64_t nnz = M.rp[rows], total = rows + nnz;
+    const int64_t D0 = b * kMergeItems, D1 = min(D0 + (int64_t)kMergeItems, total);
+    const int64_t k0 = D0 - i0, k1 = D1 - i1;
+    const int nk = (int)(k1 - k0);
+    // row pointers rp[i0 .. min(i1, rows - 1) + 1]
+    const int nr = i0 < rows ? (int)(min(i1, rows - 1) + 2 - i0) : 0;
+    for (int j = tid; j < nr; j += kBlock) s_rp[j] = M.rp[i0 + j];
+#pragma unroll
+    for (int u = 0; u < kMergeIpt; ++u) {
+        const int j = u * kBlock + tid;
+        if (j < nk) {
+            const double a = sgn * M.val[k0 + j];
+            const double xv = x[M.ci[k0 + j]];
+            const double h = a * xv;
+            s_hp[j + j / kMergeIpt] = make_double2(h, __fma_rn(a, xv, -h));
+        }
+    }
+    if (tid == 0) {
+        s_hr = -1;
+        s_cr = -1;
+    }
+    __syncthreads();
+
+    // this thread's start on the path: il rows completed inside the block
+    const int64_t dl = min((int64_t)tid * kMergeIpt, D1 - D0);
+    const int64_t dle = min(dl + kMergeIpt, D1 - D0);
+    int64_t lo = dl > nk ? dl - nk : 0, hi = min(dl, i1 - i0);
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)s_rp[mid + 1] <= k0 + dl - mid - 1)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    int64_t i = i0 + lo, k = k0 + dl - lo;
+    Acc v[EpiNV<EPI>::value] = {};
+    bool head = i < rows && k > s_rp[i - i0];
+    bool cont = head;  // inside one row begun earlier, so far
+    Acc acc = {0.0, 0.0};
+    if constexpr (EPI == kEpiResid) {
+        if (i < rows && !head) acc.p = ea.b[i];
+    }
+    int32_t hr = -1;
+    Acc hv = {0.0, 0.0};
+    int64_t ks = k;
+    int64_t e = i < rows ? s_rp[i - i0 + 1] : 0;
+    for (int64_t d = dl; d < dle; ++d) {
+        if (i < rows && k >= e) {  // the end of row i
+            if (head) {
+                hr = (int32_t)i;
+                hv = acc;
+                head = false;
+            } else {
+                epilogue<EPI>(i, acc_val(acc), y, ea, o.st, v);
+            }
+            cont = false;
+            ++i;
+            acc = Acc{0.0, 0.0};
+            ks = k;
+            if (i < rows) {
+                e = s_rp[i - i0 + 1];
+                if constexpr (EPI == kEpiResid) acc.p = ea.b[i];
+            }
+        } else {
+            const int64_t j = k - k0;
+            const double2 p = s_hp[j + j / kMergeIpt];
+            acc_add_split(acc, p.x, p.y);
+            ++k;
+        }
+    }
+    const bool carry = i < rows && k > ks;
+
+    // segmented inclusive scan of the carries over the block's threads
+    SegAcc c;
+    c.v = carry ? acc : Acc{0.0, 0.0};
+    c.f = (tid == 0 || !cont) ? 1 : 0;
+    c.o = (tid == 0 && cont) ? 1 : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        SegAcc u;
+        u.v.p = __shfl_up(c.v.p, off);
+        u.v.s = __shfl_up(c.v.s, off);
+        u.f = __shfl_up(c.f, off);
+        u.o = __shfl_up(c.o, off);
+        if (lane >= off) c = seg_combine(u, c);
+    }
+    if (lane == 63) s_wave[wave] = c;
+    __syncthreads();
+    SegAcc pre;  // the inclusive scan up to the thread before this wave
+    pre.v = Acc{0.0, 0.0};
+    pre.f = 1;
+    pre.o = 0;
+    for (int w = 0; w < wave; ++w) pre = w == 0 ? s_wave[0] : seg_combine(pre, s_wave[w]);
+    if (wave > 0) c = seg_combine(pre, c);
+    // the inclusive scan at the thread before this one
+    SegAcc prev;
+    prev.v.p = __shfl_up(c.v.p, 1);
+    prev.v.s = __shfl_up(c.v.s, 1);
+    prev.f = __shfl_up(c.f, 1);
+    prev.o = __shfl_up(c.o, 1);
+    if (lane == 0) prev = pre;
+
+    if (hr >= 0) {
+        if (tid == 0) {  // the row began in an earlier block
+            s_hr = hr;
+            s_hv = make_double2(hv.p, hv.s);
+        } else {
+            const Acc t = acc_merge(prev.v, hv);
+            if (prev.o) {
+                s_hr = hr;
+                s_hv = make_double2(t.p, t.s);
+            } else {
+                epilogue<EPI>(hr, acc_val(t), y, ea, o.st, v);
+            }
+        }
+    }
+    if (tid == kBlock - 1 && carry) {
+        s_cr = (int32_t)i;
+        s_cv = make_double2(c.v.p, c.v.s);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const MergeSlots q = merge_slots(M);
+        q.hr[b] = s_hr;
+        q.hv[b] = s_hv;
+        q.cr[b] = s_cr;
+        q.cv[b] = s_cv;
+    }
+    block_partials<EpiNV<EPI>::value>(v, o);
+}
+
+// One wave per block of k_merge_spmv: a head row begun in earlier blocks is
+// completed from the carries of the run of blocks before it (each lane merges
+// every 64th carry in order, the lanes then merge in a fixed tree) and the
+// head.  Partials go after the product kernel's.
+template <int EPI>
+__global__ __launch_bounds__(kBlock) void k_merge_fixup(MatView M, double *y, EpiArgs ea, Out o) {
+    if (!producer_runs(o)) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const MergeSlots q = merge_slots(M);
+    Acc v[EpiNV<EPI>::value] = {};
+    const int32_t r = j < M.mb ? q.hr[j] : -1;
+    if (r >= 0) {
+        // the run j0 .. j - 1 of blocks whose carry is row r (j - 1 always is)
+        int64_t j0 = -1;
+        for (int64_t c = 0; j0 < 0; c += 64) {
+            const int64_t u = j - 1 - c - lane;
+            const bool in = u >= 0 && q.cr[u] == r;
+            const uint64_t out = __ballot(!in);
+            if (out != 0) j0 = j - c - (int64_t)__ffsll((unsigned long long)out) + 1;
+        }
+        Acc a = {0.0, 0.0};
+        for (int64_t u = j0 + lane; u < j; u += 64) {
+            const double2 cv = q.cv[u];
+            a = acc_merge(a, Acc{cv.x, cv.y});
+        }
+        a = group_reduce<64>(a);
+        if (lane == 0) {
+            const double2 h = q.hv[j];
+            a = acc_merge(a, Acc{h.x, h.y});
+            epilogue<EPI>(r, acc_val(a), y, ea, o.st, v);
+        }
+    }
+    block_partials<EpiNV<EPI>::value>(v, o, M.mb + blockIdx.x);
+}
+
 // First entry of each column slice inside each row of a column-sorted CSR.
 __global__ void k_slice_segments(int64_t m, const int32_t *__restrict__ rp,
                                  const int32_t *__restrict__ ci, int64_t slice_w, int32_t *seg) {
@@ -1202,6 +1461,7 @@ int64_t matvec_blocks(const MatView &M) {
         case kDenseRows: return cdiv(rows, kBlock / 64);
         case kCsrSliced: return elementwise_blocks(rows);  // the combine kernel
         case kCsrTiled: return cdiv(rows, kBlock / kCombineLanes);  // the combine kernel
+        case kCsrMerge: return M.mb + cdiv(M.mb, kBlock / 64);    // product, then fix-up
         case kCsrSell: return cdiv(rows, kBlock);
         default: return M.lanes > 1 ? cdiv(rows, kBlock / M.lanes) : cdiv(rows, kBlock);
     }
@@ -1269,6 +1529,10 @@ static void launch_matvec_t(const MatView &M, const double *x, double *y, const 
             k_tiles_combine<EPI><<<grid, kBlock, 0, s>>>(M, y, ea, o);
             break;
         case kCsrSell: k_sell<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        case kCsrMerge:
+            k_merge_spmv<EPI><<<dim3((unsigned)M.mb), kBlock, 0, s>>>(M, x, y, ea, o);
+            k_merge_fixup<EPI><<<dim3((unsigned)cdiv(M.mb, kBlock / 64)), kBlock, 0, s>>>(M, y, ea, o);
+            break;
         default:
             if (M.lanes > 1)
                 launch_vec_lanes<EPI>(M, grid, x, y, ea, o, s);
@@ -1276,6 +1540,34 @@ static void launch_matvec_t(const MatView &M, const double *x, double *y, const 
                 k_csr_stream<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o);
             break;
     }
+}
+
+hipError_t launch_merge_part(int64_t rows, const int32_t *rp, int64_t mb, int32_t *mp,
+                             hipStream_t s) {
+    k_merge_part<<<dim3((unsigned)cdiv(mb + 1, kBlock)), kBlock, 0, s>>>(rows, rp, mb, mp);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_max(int64_t rows, const int32_t *__restrict__ rp,
+                                                   int32_t *out) {
+    __shared__ int32_t red[kBlock / 64];
+    int32_t w = 0;
+    for (int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * kBlock)
+        w = max(w, rp[r + 1] - rp[r]);
+    for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kBlock / 64; ++q) w = max(w, red[q]);
+        atomicMax(out, w);
+    }
+}
+
+hipError_t launch_row_max(int64_t rows, const int32_t *rp, int32_t *out, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    k_row_max<<<dim3((unsigned)elementwise_blocks(rows)), kBlock, 0, s>>>(rows, rp, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_sell_widths(int64_t rows, const int32_t *rp, int32_t *w, hipStream_t s) {

@@ -115,6 +115,30 @@ constexpr int64_t kTileMinRun = 3;
 
 static int64_t n_tiles(int64_t cols) { return (cols + kTileW - 1) / kTileW; }
 
+// A CSR view left to the row kernels (one thread or a fixed number of
+// lanes per row, chosen from the average) whose longest row holds at least
+// kMergeMinRow nonzeros is split along the merge path instead when that row
+// holds at least kMergeSkew times the average (skewed rows), or when the row
+// kernels would run fewer than kMergeMinBlocks blocks and the path more (a
+// few long rows leave most of the chip idle).
+#ifndef TA_MERGE_SKEW
+#define TA_MERGE_SKEW 32
+#endif
+constexpr int64_t kMergeSkew = TA_MERGE_SKEW;
+constexpr int64_t kMergeMinRow = 512;
+constexpr int64_t kMergeMinBlocks = 512;
+
+static int64_t merge_blocks(int64_t rows, int64_t nnz) {
+    return std::max<int64_t>(1, (rows + nnz + kMergeItems - 1) / kMergeItems);
+}
+
+static bool use_merge(int64_t rows, int64_t nnz, int64_t longest, int lanes) {
+    if (rows <= 0 || longest < kMergeMinRow) return false;
+    if (longest * rows >= kMergeSkew * nnz) return true;
+    const int64_t row_blocks = (rows * std::max(lanes, 1) + kBlock - 1) / kBlock;
+    return row_blocks < kMergeMinBlocks && merge_blocks(rows, nnz) > row_blocks;
+}
+
 static bool use_tiles(int64_t nnz, int64_t rows, int64_t cols) {
     if (rows <= 0 || cols < kTileMinCols) return false;
     const int64_t runs = n_tiles(cols) * rows;
@@ -174,15 +198,64 @@ struct Plan {
     MatView A{}, AT{};
     bool has_t = false;
     void *mem = nullptr;
-    void *mem_sell = nullptr;  // SELL-64 copies of the views that take them
+    void *mem_sell = nullptr;   // SELL-64 copies of the views that take them
+    void *mem_merge = nullptr;  // merge-path partitions of the views that take them
     hipStream_t s_mem = nullptr;
 };
 
 static void plan_free(Plan *P) {
     if (P->mem != nullptr) (void)hipFreeAsync(P->mem, P->s_mem);
     if (P->mem_sell != nullptr) (void)hipFreeAsync(P->mem_sell, P->s_mem);
+    if (P->mem_merge != nullptr) (void)hipFreeAsync(P->mem_merge, P->s_mem);
     P->mem = nullptr;
     P->mem_sell = nullptr;
+    P->mem_merge = nullptr;
+}
+
+// Merge-path partitions for the CSR views that the row kernels would take
+// and use_merge selects (A's longest row is known from the validation; A^T's
+// is measured on the device and read back).
+static int plan_merge(Plan *P, int64_t nnz, int64_t longest_a, hipStream_t s) {
+    MatView *vs[2] = {&P->A, P->has_t ? &P->AT : nullptr};
+    bool cand[2] = {false, false};
+    for (int i = 0; i < 2; ++i)
+        cand[i] = vs[i] != nullptr && vs[i]->kind == kCsrRows && vs[i]->rows > 0;
+    if ((!cand[0] && !cand[1]) || nnz < kMergeMinRow) return TA_OK;
+    int rc = TA_OK;
+    int64_t longest[2] = {longest_a, 0};
+    if (cand[1]) {
+        Workspace wt(s);
+        int32_t *dmax = nullptr;
+        wt.reserve(&dmax, 1);
+        if ((rc = wt.commit()) != TA_OK) return rc;
+        HIP_TRY(hipMemsetAsync(dmax, 0, sizeof(int32_t), s));
+        HIP_TRY(launch_row_max(vs[1]->rows, vs[1]->rp, dmax, s));
+        int32_t h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, dmax, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        longest[1] = h;
+    }
+    bool use[2] = {false, false};
+    int64_t mb[2] = {0, 0};
+    for (int i = 0; i < 2; ++i) {
+        use[i] = cand[i] && use_merge(vs[i]->rows, nnz, longest[i], vs[i]->lanes);
+        if (use[i]) mb[i] = merge_blocks(vs[i]->rows, nnz);
+    }
+    if (!use[0] && !use[1]) return TA_OK;
+    Workspace mw(s);
+    int32_t *mp[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i)
+        if (use[i]) mw.reserve(&mp[i], mb[i] + 1);
+    if ((rc = mw.commit()) != TA_OK) return rc;
+    for (int i = 0; i < 2; ++i)
+        if (use[i]) {
+            HIP_TRY(launch_merge_part(vs[i]->rows, vs[i]->rp, mb[i], mp[i], s));
+            vs[i]->kind = kCsrMerge;
+            vs[i]->mp = mp[i];
+            vs[i]->mb = mb[i];
+        }
+    P->mem_merge = mw.release();
+    return TA_OK;
 }
 
 // SELL-64 copies for the one-thread-per-row CSR views whose 64-row slices
@@ -271,10 +344,23 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
         return TA_OK;
     }
     const int64_t nnz = M->nnz;
+    // validation, and A's longest row (one read back)
+    int64_t longest_a = 0;
+    {
+        Workspace probe(s);
+        int32_t *pflag = nullptr;
+        probe.reserve(&pflag, 2);
+        if ((rc = probe.commit()) != TA_OK) return rc;
+        if ((rc = check_csr_longest(M, pflag, &longest_a, s)) != TA_OK) return rc;
+    }
     const int la = pick_lanes(nnz, m), lt = pick_lanes(nnz, n);
-    const bool tile_a = need_t && la > 1 && use_tiles(nnz, m, n);
+    // A is regrouped from (A^T)^T, whose rows the transpose sorts: not for rows
+    // longer than kMaxColNnz, nor for rows the merge path takes
+    const bool regroup_a = need_t && la > 1 && longest_a <= kMaxColNnz &&
+                           !use_merge(m, nnz, longest_a, la);
+    const bool tile_a = regroup_a && use_tiles(nnz, m, n);
     const bool tile_t = need_t && lt > 1 && use_tiles(nnz, n, m);
-    const bool slice_a = need_t && la > 1 && !tile_a && n >= kSliceMinCols;
+    const bool slice_a = regroup_a && !tile_a && n >= kSliceMinCols;
     const bool slice_t = need_t && lt > 1 && !tile_t && m >= kSliceMinCols;
 
     // owned memory
@@ -322,7 +408,6 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
     }
     if ((rc = own.commit()) != TA_OK) return rc;
     if ((rc = tmp.commit()) != TA_OK) return rc;
-    if ((rc = check_csr_device(M, flag, s)) != TA_OK) return rc;
 
     P->A = MatView{kCsrRows, m, n, 0, M->row_ptr, M->col_idx, M->val, la, nullptr, nullptr};
     if (need_t) {
@@ -359,6 +444,7 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
     }
     P->mem = own.release();
     P->s_mem = s;
+    if ((rc = plan_merge(P, nnz, longest_a, s)) != TA_OK) return rc;
     if (sell) return plan_sell(P, nnz, s);
     return TA_OK;
 }
@@ -388,6 +474,8 @@ struct Chain {
         if (A.kind == kCsrTiled) ws.reserve(&A.ypart, (int64_t)A.nt * std::max<int64_t>(A.rows, 1));
         if (P.has_t && AT.kind == kCsrTiled)
             ws.reserve(&AT.ypart, (int64_t)AT.nt * std::max<int64_t>(AT.rows, 1));
+        if (A.kind == kCsrMerge) ws.reserve(&A.ypart, 3 * A.mb);
+        if (P.has_t && AT.kind == kCsrMerge) ws.reserve(&AT.ypart, 3 * AT.mb);
     }
     Out out(int32_t slot, int32_t gate) const {
         Out o;
@@ -1246,7 +1334,8 @@ int ta_plan_format(const ta_plan *plan, int32_t trans, int32_t *format) {
     if (plan == nullptr || format == nullptr) return TA_EINVAL;
     static_assert(ta::kCsrRows == TA_FMT_CSR_ROWS && ta::kDenseRows == TA_FMT_DENSE_ROWS &&
                       ta::kDenseCols == TA_FMT_DENSE_COLS && ta::kCsrSliced == TA_FMT_CSR_SLICED &&
-                      ta::kCsrSell == TA_FMT_SELL64 && ta::kCsrTiled == TA_FMT_CSR_TILED,
+                      ta::kCsrSell == TA_FMT_SELL64 && ta::kCsrTiled == TA_FMT_CSR_TILED &&
+                      ta::kCsrMerge == TA_FMT_CSR_MERGE,
                   "storage kinds");
     *format = trans ? plan->p.AT.kind : plan->p.A.kind;
     return TA_OK;

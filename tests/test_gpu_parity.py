@@ -15,7 +15,7 @@ import pytest
 import oracle
 import paper_2304_12168_amd as P
 from workloads import (Csr, convection_diffusion, csr_from_coo, csr_from_dense, dense_gaussian,
-                       kac_clement, lp_shaped, random_diag_dominant)
+                       kac_clement, lp_shaped, random_diag_dominant, skewed_rows)
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +76,10 @@ MATS = {
     "randsparse_3000": lambda: random_diag_dominant(3000, 7, seed=2),
     "dense_257x131": lambda: dense_gaussian(131, seed=2, m=257).A,
     "dense_64x300": lambda: dense_gaussian(300, seed=3, m=64).A,
+    # merge-path partitions (skewed rows; a few long rows; block-edge lengths)
+    "skewed_20000": lambda: skewed_rows(20_000, 20_000, seed=1, empty_frac=0.1, dense_rows=1).A,
+    "few_long_rows_4x20000": lambda: _few_long_rows().A,
+    "merge_edges_400x6000": lambda: _merge_edges().A,
 }
 
 
@@ -396,7 +400,56 @@ def _two_tiles():
     return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
 
 
+def _few_long_rows():
+    """4 rows of about 10000 random entries over 20000 columns: the row
+    kernels would run one block, the merge path 20."""
+    g = np.random.default_rng(23)
+    m, n = 4, 20_000
+    cols = [g.choice(n, size=int(g.integers(9000, 11000)), replace=False) for _ in range(m)]
+    rows = np.concatenate([np.full(c.size, i) for i, c in enumerate(cols)])
+    A = csr_from_coo(m, n, rows, np.concatenate(cols), g.standard_normal(rows.size))
+    x = g.standard_normal(n)
+    return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
+
+
+def _merge_edges():
+    """Row lengths placed against the merge path's 2048-item blocks and
+    8-item threads: a 3000-entry row first, empty rows (also last), rows of
+    7, 8, 9, 2047, 2048, 2049 and 4096 entries among short ones."""
+    g = np.random.default_rng(24)
+    m, n = 400, 6000
+    lens = g.integers(0, 10, size=m)
+    lens[0] = 3000
+    lens[m - 1] = 0
+    for i, w in zip((3, 50, 51, 52, 120, 121, 122, 300, 301), (0, 7, 8, 9, 2047, 2048, 2049, 4096, 0)):
+        lens[i] = w
+    rows = np.repeat(np.arange(m), lens)
+    cols = np.concatenate([g.choice(n, size=int(w), replace=False) for w in lens])
+    A = csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
+    x = g.standard_normal(n)
+    return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
+
+
+def _lp_dense_row():
+    """The LP shape (2000 x 200000, about 600 entries per row) with a dense
+    linking row appended: too skewed for column tiles, so the merge path."""
+    B = lp_shaped(2000, 200_000, seed=5).A.to_scipy().tocoo()
+    g = np.random.default_rng(25)
+    n = B.shape[1]
+    rows = np.concatenate([B.row, np.full(n, B.shape[0])])
+    cols = np.concatenate([B.col, np.arange(n)])
+    A = csr_from_coo(B.shape[0] + 1, n, rows, cols, np.concatenate([B.data, g.standard_normal(n)]))
+    x = g.standard_normal(n)
+    return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
+
+
 REGROUPED = {
+    "lp_dense_row_merge_A": (_lp_dense_row, ("csr_merge", None)),
+    "skewed_merge_A": (lambda: skewed_rows(20_000, 20_000, seed=1, empty_frac=0.1, dense_rows=1),
+                       ("csr_merge", None)),
+    "skewed_merge_AT": (lambda: _transpose(skewed_rows(6000, 8000, seed=2)), (None, "csr_merge")),
+    "few_long_rows_merge_A": (_few_long_rows, ("csr_merge", None)),
+    "edges_merge_A": (_merge_edges, ("csr_merge", None)),
     "wide_tiled_A": (_wide, ("csr_tiled", None)),
     "two_tiles_A": (_two_tiles, ("csr_tiled", None)),
     "tall_tiled_AT": (lambda: _transpose(_wide()), (None, "csr_tiled")),

@@ -15,6 +15,7 @@ from .gen import (  # noqa: F401
     lp_shaped,
     poisson5,
     random_diag_dominant,
+    skewed_rows,
     batched_uneven,
     perturbed_stencil,
     ladder,

@@ -17,7 +17,10 @@ Shapes follow the workloads the solvers are measured on:
   plus an identity slack block (the m = 1e4, n up to 1e6 class of section 5.3);
 * batches of uneven Poisson stencils and diagonally dominant random sparse
   systems with several right-hand sides each;
-* a randomly perturbed Poisson stencil.
+* a randomly perturbed Poisson stencil;
+* sparse matrices with heavy-tailed (Pareto) row lengths, optionally with
+  empty rows and fully dense rows (the skewed operands the merge-path product
+  is for).
 
 No solver arithmetic lives here.
 """
@@ -39,6 +42,7 @@ _STREAM = {
     "batched": 5,
     "stencil_perturbed": 6,
     "randsparse": 7,
+    "skewed": 8,
 }
 
 
@@ -249,6 +253,35 @@ def lp_shaped(m: int = 10000, n: int = 1_000_000, per_col: int = 6, seed: int = 
     xs = g.standard_normal(n)
     return Problem(f"lp_shaped_{m}x{n}_s{seed}", A, A.matvec(xs), xs,
                    {"m": m, "n": n, "per_col": per_col, "seed": seed})
+
+
+def skewed_rows(m: int, n: int, avg: float = 8.0, alpha: float = 1.5, seed: int = 0,
+                empty_frac: float = 0.0, dense_rows: int = 0) -> Problem:
+    """Row lengths Pareto(alpha) with mean ``avg`` (rounded, capped at n),
+    a fraction ``empty_frac`` of the rows emptied, and ``dense_rows`` rows
+    holding every column; columns uniform at random (repeats inside a row
+    are summed), N(0,1) values.  x* ~ N(0,1), b = A x*."""
+    g = _rng("skewed", seed)
+    xm = avg * (alpha - 1.0) / alpha
+    u = 1.0 - g.random(m)  # (0, 1]
+    lens = np.minimum(np.rint(xm * u ** (-1.0 / alpha)), n).astype(np.int64)
+    if empty_frac > 0.0:
+        lens[g.random(m) < empty_frac] = 0
+    if dense_rows > 0:
+        lens[g.choice(m, size=min(dense_rows, m), replace=False)] = n
+    rows = np.repeat(np.arange(m, dtype=np.int64), lens)
+    cols = g.integers(0, n, size=rows.size)
+    full = np.nonzero(lens == n)[0]
+    if full.size:  # dense rows hold every column once
+        starts = np.concatenate([[0], np.cumsum(lens)])[full]
+        for s0 in starts:
+            cols[s0:s0 + n] = np.arange(n)
+    vals = g.standard_normal(rows.size)
+    A = csr_from_coo(m, n, rows, cols, vals)
+    xs = g.standard_normal(n)
+    return Problem(f"skewed_{m}x{n}_s{seed}", A, A.matvec(xs), xs,
+                   {"m": m, "n": n, "avg": avg, "alpha": alpha, "seed": seed,
+                    "empty_frac": empty_frac, "dense_rows": dense_rows})
 
 
 # --------------------------------------------------------------------------
