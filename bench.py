@@ -663,18 +663,24 @@ def hbm_sweep_bench(args, P, torch, dev):
     operator's kernels) and the batched FP32 SpMM at K = 32, each timed with
     HIP events by the library's hooks; algorithmic bytes as in csr_pass_bytes.
     Past ~2e7 nonzeros the FP64 matrix (12 B per nonzero) no longer fits the
-    256 MB Infinity Cache."""
+    256 MB Infinity Cache.  Then skewed rows (FP64 only): 1e6 x 1e6 with
+    Pareto(1.5) row lengths of mean 8 (longest about 25000), without and with
+    4 dense rows, whose A pass takes the merge-path partition."""
     import numpy as np
 
-    from workloads import lp_shaped, poisson5
+    from workloads import lp_shaped, poisson5, skewed_rows
 
     out = []
     cases = [("lp_shaped", n) for n in (1_000_000, 4_000_000, 10_000_000)]
     cases += [("poisson5", N) for N in (1024, 2048, 2896)]
+    cases += [("skewed", 1_000_000), ("skewed_dense4", 1_000_000)]
     for kind, size in cases:
         t0 = time.perf_counter()
         if kind == "lp_shaped":
             Ah = lp_shaped(size // 100, size, per_col=6, seed=args.seed).A
+        elif kind.startswith("skewed"):
+            Ah = skewed_rows(size, size, seed=args.seed,
+                             dense_rows=4 if kind == "skewed_dense4" else 0).A
         else:
             Ah = poisson5(size)
         gen_s = time.perf_counter() - t0
@@ -689,24 +695,27 @@ def hbm_sweep_bench(args, P, torch, dev):
         ms_t = P.time_matvec(pl, u, trans=True, reps=args.reps)
         by_a = csr_pass_bytes(m, n, nnz, 8, 4, 8)
         by_t = csr_pass_bytes(n, m, nnz, 8, 4, 8)
-        bp = P.BatchPlan([A], "fp32")
-        ms_ba = P.batch_time_spmm(bp, 32, trans=False, precision="fp32", reps=args.reps)
-        ms_bt = P.batch_time_spmm(bp, 32, trans=True, precision="fp32", reps=args.reps)
-        bp.close()
-        by_ba = csr_pass_bytes(m, n, nnz, 4, 4, 4, 32)
-        by_bt = csr_pass_bytes(n, m, nnz, 4, 4, 4, 32)
+        passes = [("fp64_A", by_a, ms_a), ("fp64_AT", by_t, ms_t)]
+        if not kind.startswith("skewed"):
+            bp = P.BatchPlan([A], "fp32")
+            ms_ba = P.batch_time_spmm(bp, 32, trans=False, precision="fp32", reps=args.reps)
+            ms_bt = P.batch_time_spmm(bp, 32, trans=True, precision="fp32", reps=args.reps)
+            bp.close()
+            passes += [("fp32_k32_A", csr_pass_bytes(m, n, nnz, 4, 4, 4, 32), ms_ba),
+                       ("fp32_k32_AT", csr_pass_bytes(n, m, nnz, 4, 4, 4, 32), ms_bt)]
         row = {"matrix": kind, "size": size, "n": n, "m": m, "nnz": nnz,
                "fp64_matrix_mb": nnz * 12 / 1e6, "generated_s": gen_s,
                "format_A": pl.format(False), "format_AT": pl.format(True)}
-        for key, by, ms in (("fp64_A", by_a, ms_a), ("fp64_AT", by_t, ms_t),
-                            ("fp32_k32_A", by_ba, ms_ba), ("fp32_k32_AT", by_bt, ms_bt)):
+        for key, by, ms in passes:
             gbs = by / ms / 1e6
             row[key] = {"us": ms * 1e3, "bytes": by, "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
         out.append(row)
-        log(f"[bench] HBM sweep {kind} {size} ({row['format_A']}, {row['format_AT']}): "
-            f"FP64 A {row['fp64_A']['GB_s']:.0f} GB/s, "
-            f"A^T {row['fp64_AT']['GB_s']:.0f} GB/s; FP32 K=32 A {row['fp32_k32_A']['GB_s']:.0f} "
-            f"GB/s, A^T {row['fp32_k32_AT']['GB_s']:.0f} GB/s")
+        msg = (f"[bench] HBM sweep {kind} {size} ({row['format_A']}, {row['format_AT']}): "
+               f"FP64 A {row['fp64_A']['GB_s']:.0f} GB/s, A^T {row['fp64_AT']['GB_s']:.0f} GB/s")
+        if "fp32_k32_A" in row:
+            msg += (f"; FP32 K=32 A {row['fp32_k32_A']['GB_s']:.0f} GB/s, "
+                    f"A^T {row['fp32_k32_AT']['GB_s']:.0f} GB/s")
+        log(msg)
         del pl, A, x, u, Ah
         torch.cuda.empty_cache()
     return out

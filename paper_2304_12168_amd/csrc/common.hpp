@@ -163,7 +163,10 @@ constexpr int tile_u(int W) { return W >= 8 ? 1 : 8 / W; }
 constexpr int tile_pr(int W) { return W == 1 ? 2 : 4; }
 constexpr int tile_batch_rows(int W) { return tile_pr(W) * (kTileBlock / W); }
 // kCsrMerge: path items (row ends + nonzeros) per thread and per block
-constexpr int kMergeIpt = 8;
+#ifndef TA_MERGE_IPT
+#define TA_MERGE_IPT 8
+#endif
+constexpr int kMergeIpt = TA_MERGE_IPT;
 constexpr int kMergeItems = kBlock * kMergeIpt;
 
 struct MatView {

@@ -832,16 +832,19 @@ __global__ __launch_bounds__(kBlock) void k_tiles_combine(MatView M, double *y, 
 //
 // A block stages its nonzeros' exact products (TwoProduct) and its row
 // pointers in LDS.  A thread sums each row it meets in storage order
-// (compensated) and runs the epilogue on the rows that begin and end in it.
-// A row that began in an earlier thread and ends here is its head; the row
-// it is in when its items run out is its carry.  A segmented scan over the
-// block's threads merges each head with the carries before it, in thread
-// order; a head whose row began in an earlier block, and the block's last
-// carry, go to the block's slots, and k_merge_fixup merges those across
-// blocks in block order.  Every row sum is a fixed-order merge of
-// compensated pieces, so the result does not depend on timing.
+// (compensated).  A row that began in an earlier thread and ends here is the
+// thread's head; the row it is in when its items run out is its carry.  A
+// segmented scan over the block's threads merges each head with the carries
+// before it, in thread order; a head whose row began in an earlier block, and
+// the block's last carry, go to the block's slots, and k_merge_fixup merges
+// those across blocks in block order.  The sums of the rows completed in the
+// block are collected in LDS and their epilogues run in row order, so the
+// writes of y (and the epilogue's other vectors) are coalesced.  Every row sum
+// is a fixed-order merge of compensated pieces, so the result does not
+// depend on timing; the residual's b is merged in front of the products.
 // ---------------------------------------------------------------------------
-constexpr int kMergePad = kMergeItems + kMergeItems / kMergeIpt;  // one pad slot per 8 products
+// one pad slot per kMergeIpt products, so the lanes' runs start in different banks
+constexpr int kMergePad = kMergeItems + kMergeItems / kMergeIpt;
 
 // rows completed among the first d items of the path
 __device__ __forceinline__ int64_t merge_split(const int32_t *__restrict__ rp, int64_t rows,
@@ -898,6 +901,14 @@ __device__ __forceinline__ MergeSlots merge_slots(const MatView &M) {
     return q;
 }
 
+// A row's value from its compensated sum of the products (negated for the
+// residual, whose b is merged in front)
+template <int EPI>
+__device__ __forceinline__ double merge_row_value(int64_t row, Acc a, const EpiArgs &ea) {
+    if constexpr (EPI == kEpiResid) a = acc_merge(Acc{ea.b[row], 0.0}, a);
+    return acc_val(a);
+}
+
 template <int EPI>
 __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *__restrict__ x,
                                                         double *y, EpiArgs ea, Out o) {
@@ -905,7 +916,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
     constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
     __shared__ double2 s_hp[kMergePad];
     __shared__ int32_t s_rp[kMergeItems + 2];
-    __shared__ SegAcc s_wave[kBlock / 64];
+    __shared__ double s_wvp[kBlock / 64], s_wvs[kBlock / 64];  // each wave's total, by field
+    __shared__ int32_t s_wf[kBlock / 64], s_wo[kBlock / 64];
     __shared__ int32_t s_hr, s_cr;
     __shared__ double2 s_hv, s_cv;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -918,15 +930,35 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
     const int nk = (int)(k1 - k0);
     // row pointers rp[i0 .. min(i1, rows - 1) + 1]
     const int nr = i0 < rows ? (int)(min(i1, rows - 1) + 2 - i0) : 0;
-    for (int j = tid; j < nr; j += kBlock) s_rp[j] = M.rp[i0 + j];
+    if (nr > 0) {
+        int32_t rv[kMergeIpt + 1];
 #pragma unroll
-    for (int u = 0; u < kMergeIpt; ++u) {
-        const int j = u * kBlock + tid;
-        if (j < nk) {
-            const double a = sgn * M.val[k0 + j];
-            const double xv = x[M.ci[k0 + j]];
-            const double h = a * xv;
-            s_hp[j + j / kMergeIpt] = make_double2(h, __fma_rn(a, xv, -h));
+        for (int u = 0; u <= kMergeIpt; ++u) rv[u] = M.rp[i0 + min(u * kBlock + tid, nr - 1)];
+#pragma unroll
+        for (int u = 0; u <= kMergeIpt; ++u)
+            if (u * kBlock + tid < nr) s_rp[u * kBlock + tid] = rv[u];
+    }
+    if (nk > 0) {
+        // all loads first (indexes clamped into the block's nonzeros), then
+        // the gathers, then the exact products
+        int32_t cj[kMergeIpt];
+        double av[kMergeIpt], xv[kMergeIpt];
+#pragma unroll
+        for (int u = 0; u < kMergeIpt; ++u) {
+            const int j = min(u * kBlock + tid, nk - 1);
+            cj[u] = M.ci[k0 + j];
+            av[u] = M.val[k0 + j];
+        }
+#pragma unroll
+        for (int u = 0; u < kMergeIpt; ++u) xv[u] = x[cj[u]];
+#pragma unroll
+        for (int u = 0; u < kMergeIpt; ++u) {
+            const int j = u * kBlock + tid;
+            if (j < nk) {
+                const double a = sgn * av[u];
+                const double h = a * xv[u];
+                s_hp[j + j / kMergeIpt] = make_double2(h, __fma_rn(a, xv[u], -h));
+            }
         }
     }
     if (tid == 0) {
@@ -947,42 +979,44 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
             hi = mid;
     }
     int64_t i = i0 + lo, k = k0 + dl - lo;
-    Acc v[EpiNV<EPI>::value] = {};
-    bool head = i < rows && k > s_rp[i - i0];
-    bool cont = head;  // inside one row begun earlier, so far
+    const bool head0 = i < rows && k > s_rp[i - i0];
+    bool head = head0;
     Acc acc = {0.0, 0.0};
-    if constexpr (EPI == kEpiResid) {
-        if (i < rows && !head) acc.p = ea.b[i];
-    }
     int32_t hr = -1;
     Acc hv = {0.0, 0.0};
+    // rows that begin and end in this thread: offset from i0 and sum
+    int32_t yr[kMergeIpt];
+    Acc yv[kMergeIpt];
     int64_t ks = k;
     int64_t e = i < rows ? s_rp[i - i0 + 1] : 0;
-    for (int64_t d = dl; d < dle; ++d) {
-        if (i < rows && k >= e) {  // the end of row i
-            if (head) {
-                hr = (int32_t)i;
-                hv = acc;
-                head = false;
+#pragma unroll
+    for (int u = 0; u < kMergeIpt; ++u) {
+        yr[u] = -1;
+        yv[u] = Acc{0.0, 0.0};
+        if (dl + u < dle) {
+            if (i < rows && k >= e) {  // the end of row i
+                if (head) {
+                    hr = (int32_t)i;
+                    hv = acc;
+                    head = false;
+                } else {
+                    yr[u] = (int32_t)(i - i0);
+                    yv[u] = acc;
+                }
+                ++i;
+                acc = Acc{0.0, 0.0};
+                ks = k;
+                if (i < rows) e = s_rp[i - i0 + 1];
             } else {
-                epilogue<EPI>(i, acc_val(acc), y, ea, o.st, v);
+                const int64_t j = k - k0;
+                const double2 p = s_hp[j + j / kMergeIpt];
+                acc_add_split(acc, p.x, p.y);
+                ++k;
             }
-            cont = false;
-            ++i;
-            acc = Acc{0.0, 0.0};
-            ks = k;
-            if (i < rows) {
-                e = s_rp[i - i0 + 1];
-                if constexpr (EPI == kEpiResid) acc.p = ea.b[i];
-            }
-        } else {
-            const int64_t j = k - k0;
-            const double2 p = s_hp[j + j / kMergeIpt];
-            acc_add_split(acc, p.x, p.y);
-            ++k;
         }
     }
     const bool carry = i < rows && k > ks;
+    const bool cont = head0 && hr < 0;  // inside one row begun before this thread
 
     // segmented inclusive scan of the carries over the block's threads
     SegAcc c;
@@ -998,13 +1032,25 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
         u.o = __shfl_up(c.o, off);
         if (lane >= off) c = seg_combine(u, c);
     }
-    if (lane == 63) s_wave[wave] = c;
-    __syncthreads();
-    SegAcc pre;  // the inclusive scan up to the thread before this wave
-    pre.v = Acc{0.0, 0.0};
-    pre.f = 1;
-    pre.o = 0;
-    for (int w = 0; w < wave; ++w) pre = w == 0 ? s_wave[0] : seg_combine(pre, s_wave[w]);
+    if (lane == 63) {
+        s_wvp[wave] = c.v.p;
+        s_wvs[wave] = c.v.s;
+        s_wf[wave] = c.f;
+        s_wo[wave] = c.o;
+    }
+    __syncthreads();  // every walk is done: s_hp now holds the completed rows
+    // the inclusive scan up to the thread before this wave (wave 0: unused)
+    SegAcc pre;
+    pre.v = Acc{s_wvp[0], s_wvs[0]};
+    pre.f = s_wf[0];
+    pre.o = s_wo[0];
+    for (int w = 1; w < wave; ++w) {
+        SegAcc q;
+        q.v = Acc{s_wvp[w], s_wvs[w]};
+        q.f = s_wf[w];
+        q.o = s_wo[w];
+        pre = seg_combine(pre, q);
+    }
     if (wave > 0) c = seg_combine(pre, c);
     // the inclusive scan at the thread before this one
     SegAcc prev;
@@ -1014,6 +1060,11 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
     prev.o = __shfl_up(c.o, 1);
     if (lane == 0) prev = pre;
 
+    // the sums of the rows completed in this block, by row (offset from i0)
+    double2 *s_y = s_hp;
+#pragma unroll
+    for (int u = 0; u < kMergeIpt; ++u)
+        if (yr[u] >= 0) s_y[yr[u]] = make_double2(yv[u].p, yv[u].s);
     if (hr >= 0) {
         if (tid == 0) {  // the row began in an earlier block
             s_hr = hr;
@@ -1024,7 +1075,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
                 s_hr = hr;
                 s_hv = make_double2(t.p, t.s);
             } else {
-                epilogue<EPI>(hr, acc_val(t), y, ea, o.st, v);
+                s_y[hr - i0] = make_double2(t.p, t.s);
             }
         }
     }
@@ -1040,13 +1091,23 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
         q.cr[b] = s_cr;
         q.cv[b] = s_cv;
     }
+    // epilogues of the rows completed here, in row order (coalesced); row i0
+    // is left to k_merge_fixup when it began in an earlier block
+    Acc v[EpiNV<EPI>::value] = {};
+    const int64_t r0 = i0 + (i0 < rows && k0 > s_rp[0] ? 1 : 0);
+    for (int64_t r = r0 + tid; r < i1; r += kBlock) {
+        const double2 a = s_y[r - i0];
+        epilogue<EPI>(r, merge_row_value<EPI>(r, Acc{a.x, a.y}, ea), y, ea, o.st, v);
+    }
     block_partials<EpiNV<EPI>::value>(v, o);
 }
 
-// One wave per block of k_merge_spmv: a head row begun in earlier blocks is
-// completed from the carries of the run of blocks before it (each lane merges
-// every 64th carry in order, the lanes then merge in a fixed tree) and the
-// head.  Partials go after the product kernel's.
+// One wave per block j of k_merge_spmv: a head row r begun in earlier blocks
+// is completed from the carries of the run of blocks before j whose carry is
+// row r (block j - 1 always is one), then the head.  Lane l takes blocks
+// j - 1 - l, j - 65 - l, ... in that order, the lanes then merge in a fixed
+// tree.  The first 64 carries are loaded with the head row, before it is
+// known.  Partials go after the product kernel's.
 template <int EPI>
 __global__ __launch_bounds__(kBlock) void k_merge_fixup(MatView M, double *y, EpiArgs ea, Out o) {
     if (!producer_runs(o)) return;
@@ -1054,26 +1115,28 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(MatView M, double *y, Ep
     const int64_t j = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const MergeSlots q = merge_slots(M);
     Acc v[EpiNV<EPI>::value] = {};
-    const int32_t r = j < M.mb ? q.hr[j] : -1;
+    const bool valid = j < M.mb;
+    const int32_t r = valid ? q.hr[j] : -1;
+    int64_t u = j - 1 - lane;
+    int32_t cr = valid && u >= 0 ? q.cr[u] : -1;
+    double2 cv = valid && u >= 0 ? q.cv[u] : make_double2(0.0, 0.0);
+    const double2 h = valid ? q.hv[j] : make_double2(0.0, 0.0);
     if (r >= 0) {
-        // the run j0 .. j - 1 of blocks whose carry is row r (j - 1 always is)
-        int64_t j0 = -1;
-        for (int64_t c = 0; j0 < 0; c += 64) {
-            const int64_t u = j - 1 - c - lane;
-            const bool in = u >= 0 && q.cr[u] == r;
-            const uint64_t out = __ballot(!in);
-            if (out != 0) j0 = j - c - (int64_t)__ffsll((unsigned long long)out) + 1;
-        }
         Acc a = {0.0, 0.0};
-        for (int64_t u = j0 + lane; u < j; u += 64) {
-            const double2 cv = q.cv[u];
-            a = acc_merge(a, Acc{cv.x, cv.y});
+        for (;;) {
+            const uint64_t out = __ballot(cr != r);
+            // the lanes before the first one outside the run belong to it
+            const int first_out = out != 0 ? __ffsll((unsigned long long)out) - 1 : 64;
+            if (lane < first_out) a = acc_merge(a, Acc{cv.x, cv.y});
+            if (out != 0) break;
+            u -= 64;
+            cr = u >= 0 ? q.cr[u] : -1;
+            cv = u >= 0 ? q.cv[u] : make_double2(0.0, 0.0);
         }
         a = group_reduce<64>(a);
         if (lane == 0) {
-            const double2 h = q.hv[j];
             a = acc_merge(a, Acc{h.x, h.y});
-            epilogue<EPI>(r, acc_val(a), y, ea, o.st, v);
+            epilogue<EPI>(r, merge_row_value<EPI>(r, a, ea), y, ea, o.st, v);
         }
     }
     block_partials<EpiNV<EPI>::value>(v, o, M.mb + blockIdx.x);
