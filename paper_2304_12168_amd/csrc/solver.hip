@@ -115,12 +115,13 @@ constexpr int64_t kTileMinRun = 3;
 
 static int64_t n_tiles(int64_t cols) { return (cols + kTileW - 1) / kTileW; }
 
-// A CSR view left to the row kernels (one thread or a fixed number of
-// lanes per row, chosen from the average) whose longest row holds at least
-// kMergeMinRow nonzeros is split along the merge path instead when that row
-// holds at least kMergeSkew times the average (skewed rows), or when the row
-// kernels would run fewer than kMergeMinBlocks blocks and the path more (a
-// few long rows leave most of the chip idle).
+// A CSR view whose longest row holds at least kMergeMinRow nonzeros is split
+// along the merge path when that row holds at least kMergeSkew times the
+// average (skewed rows: before column tiles or slices, whose lanes per row
+// are chosen from the average too), or, where neither tiles nor slices take
+// it, when the row kernels (one thread or a fixed number of lanes per row)
+// would run fewer than kMergeMinBlocks blocks and the path more (a few long
+// rows leave most of the chip idle).
 #ifndef TA_MERGE_SKEW
 #define TA_MERGE_SKEW 32
 #endif
@@ -132,9 +133,13 @@ static int64_t merge_blocks(int64_t rows, int64_t nnz) {
     return std::max<int64_t>(1, (rows + nnz + kMergeItems - 1) / kMergeItems);
 }
 
+static bool skewed(int64_t rows, int64_t nnz, int64_t longest) {
+    return rows > 0 && longest >= kMergeMinRow && longest * rows >= kMergeSkew * nnz;
+}
+
 static bool use_merge(int64_t rows, int64_t nnz, int64_t longest, int lanes) {
     if (rows <= 0 || longest < kMergeMinRow) return false;
-    if (longest * rows >= kMergeSkew * nnz) return true;
+    if (skewed(rows, nnz, longest)) return true;
     const int64_t row_blocks = (rows * std::max(lanes, 1) + kBlock - 1) / kBlock;
     return row_blocks < kMergeMinBlocks && merge_blocks(rows, nnz) > row_blocks;
 }
@@ -355,9 +360,9 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
     }
     const int la = pick_lanes(nnz, m), lt = pick_lanes(nnz, n);
     // A is regrouped from (A^T)^T, whose rows the transpose sorts: not for rows
-    // longer than kMaxColNnz, nor for rows the merge path takes
+    // longer than kMaxColNnz, nor for skewed rows (the merge path takes them)
     const bool regroup_a = need_t && la > 1 && longest_a <= kMaxColNnz &&
-                           !use_merge(m, nnz, longest_a, la);
+                           !skewed(m, nnz, longest_a);
     const bool tile_a = regroup_a && use_tiles(nnz, m, n);
     const bool tile_t = need_t && lt > 1 && use_tiles(nnz, n, m);
     const bool slice_a = regroup_a && !tile_a && n >= kSliceMinCols;
