@@ -76,7 +76,7 @@ extern "C" {
  *           col_idx[nnz] (int32 in [0, n)), val[nnz] (float64).  Column order
  *           inside a row is free; duplicates are allowed and act as a sum.
  *           A^T is built on the device inside each solver call.  Supported:
- *           nnz < 2^31 and at most 8192 entries in any column.
+ *           nnz < 2^31 (a column may hold any number of them).
  *   TA_DENSE_ROWMAJOR: val[m*ld] row-major, ld >= n; row_ptr/col_idx unused.
  */
 typedef struct ta_mat {
@@ -273,8 +273,7 @@ int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
  * while the plan lives.  A plan is read-only once created and may serve
  * calls on several streams at the same time.  Its device memory is taken
  * stream-ordered on `stream` and returned by ta_plan_destroy on that same
- * stream.  Errors as the one-shot calls (TA_EINVAL for a malformed CSR,
- * TA_ENOTSUP for a column with more than 8192 entries).
+ * stream.  Errors as the one-shot calls (TA_EINVAL for a malformed CSR).
  */
 typedef struct ta_plan ta_plan;
 
@@ -434,8 +433,9 @@ int ta_residual(const ta_mat *A, const double *b, const double *x, double *r, do
  * ta_transpose - CSR of A^T from the CSR of A, built on the device:
  * at_row_ptr[n+1], at_col_idx[nnz], at_val[nnz] (device, caller-allocated).
  * Columns come out sorted inside each row, so the result is canonical and
- * deterministic.  Returns TA_ENOTSUP if a column of A holds more than 8192
- * entries.  Synchronises `stream` before returning.
+ * deterministic (a row of A^T is put in the order of A's storage; rows of
+ * more than 8192 entries are sorted by one block in global memory, more
+ * slowly).  Synchronises `stream` before returning.
  */
 int ta_transpose(const ta_mat *A, int32_t *at_row_ptr, int32_t *at_col_idx, double *at_val,
                  void *stream);

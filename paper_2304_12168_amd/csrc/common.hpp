@@ -15,7 +15,7 @@ constexpr int kBlock = 256;    // threads per block of every kernel
 #define TA_CHUNK 1024
 #endif
 constexpr int kChunk = TA_CHUNK;  // nnz staged through LDS per round (stream kernel)
-constexpr int kMaxColNnz = 8192;  // longest A^T row the transpose can sort
+constexpr int kMaxColNnz = 8192;  // longest A^T row the transpose sorts in LDS at once
 
 // Internal stop code: the recurrence residual passed the tolerance and the
 // host must confirm it on the true residual.
@@ -252,6 +252,8 @@ hipError_t launch_norm2(int64_t n, const double *x, const Out &o, hipStream_t s,
                         int32_t *blocks);
 hipError_t launch_csr_outer(int64_t m, const int32_t *rp, const int32_t *ci, const double *u,
                             const double *v, double alpha, double *out, hipStream_t s);
+// Canonical CSR of A^T.  flag (one int32) is cleared and stays zero: every
+// CSR that passes validation is handled (the callers' check of it remains).
 hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                             const int32_t *ci, const double *val, int32_t *at_rp,
                             int32_t *at_ci, double *at_val, int32_t *work, int32_t *flag,

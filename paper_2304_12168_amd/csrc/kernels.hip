@@ -1421,12 +1421,11 @@ __global__ void k_tr_scatter(int64_t m, int64_t nnz, const int32_t *__restrict__
 // Sort each row of the transpose by source position; short rows by one
 // thread, longer rows are listed for a block each.
 __global__ void k_tr_sort_short(int64_t n, const int32_t *__restrict__ at_rp, int32_t *src,
-                                int32_t *long_rows, int32_t *n_long, int32_t *flag) {
+                                int32_t *long_rows, int32_t *n_long) {
     for (int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x; j < n;
          j += (int64_t)gridDim.x * kBlock) {
         const int32_t s = at_rp[j], e = at_rp[j + 1], len = e - s;
         if (len > 32) {
-            if (len > kMaxColNnz) atomicOr(flag, 1);
             long_rows[atomicAdd(n_long, 1)] = (int32_t)j;
             continue;
         }
@@ -1442,38 +1441,93 @@ __global__ void k_tr_sort_short(int64_t n, const int32_t *__restrict__ at_rp, in
     }
 }
 
+// Ascending bitonic sorting network on keys that are all distinct, in the
+// form whose merges all run upwards: the first step of the merge of size K
+// pairs i with its mirror i ^ (K - 1), the later steps i with i + J.  Past the
+// c real keys the network sees +infinity, which never moves, so the padding to
+// a power of two is never stored.
+__device__ __forceinline__ void bitonic_pair(int64_t q, int64_t K, int64_t J, int64_t &i,
+                                             int64_t &l) {
+    if (J == K / 2) {  // the mirror step
+        const int64_t h = K / 2, base = (q / h) * K, a = q % h;
+        i = base + a;
+        l = base + K - 1 - a;
+    } else {
+        i = (q / J) * 2 * J + q % J;
+        l = i + J;
+    }
+}
+
+// Steps (K, J) for J from jfirst down to 1 of the network on g[0 .. c)
+// (c <= kMaxColNnz), in LDS; with jfirst = 0, the whole sort of g.
+__device__ void lds_bitonic(int32_t *g, int c, int jfirst, int32_t *key) {
+    for (int t = threadIdx.x; t < c; t += kBlock) key[t] = g[t];
+    __syncthreads();
+    int P = 1;
+    while (P < c) P <<= 1;
+    for (int K = jfirst > 0 ? 4 * jfirst : 2; K <= (jfirst > 0 ? 4 * jfirst : P); K <<= 1) {
+        for (int J = jfirst > 0 ? jfirst : K / 2; J > 0; J >>= 1) {
+            for (int q = threadIdx.x; q < P / 2; q += kBlock) {
+                int64_t i, l;
+                bitonic_pair(q, K, J, i, l);
+                if (l < c) {
+                    const int32_t x = key[i], y = key[l];
+                    if (x > y) {
+                        key[i] = y;
+                        key[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = threadIdx.x; t < c; t += kBlock) g[t] = key[t];
+    __syncthreads();
+}
+
+// Sorts the source indices of each A^T row with more than 32 entries (one
+// block per row).  Up to kMaxColNnz entries the row is sorted in LDS.  A
+// longer row runs the same network over the whole row: its chunks of
+// kMaxColNnz are sorted in LDS, then each merge of size K > kMaxColNnz makes
+// its steps with partners kMaxColNnz or more apart in global memory (one
+// block owns the row, so a barrier orders them) and its shorter steps chunk
+// by chunk in LDS.
 __global__ __launch_bounds__(kBlock) void k_tr_sort_long(const int32_t *__restrict__ at_rp,
                                                           int32_t *src,
                                                           const int32_t *__restrict__ long_rows,
                                                           const int32_t *__restrict__ n_long) {
     __shared__ int32_t key[kMaxColNnz];
+    constexpr int C = kMaxColNnz;
     const int32_t cnt = *n_long;
     for (int32_t li = blockIdx.x; li < cnt; li += gridDim.x) {
         const int32_t j = long_rows[li];
         const int32_t s = at_rp[j], len = at_rp[j + 1] - s;
-        if (len > kMaxColNnz) continue;  // reported through the flag
-        int P = 1;
+        int32_t *g = src + s;
+        if (len <= C) {
+            lds_bitonic(g, len, 0, key);
+            continue;
+        }
+        for (int64_t lo = 0; lo < len; lo += C) lds_bitonic(g + lo, (int)min((int64_t)C, len - lo), 0, key);
+        int64_t P = 1;
         while (P < len) P <<= 1;
-        for (int i = threadIdx.x; i < P; i += kBlock) key[i] = i < len ? src[s + i] : INT32_MAX;
-        __syncthreads();
-        for (int size = 2; size <= P; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int i = threadIdx.x; i < P; i += kBlock) {
-                    const int partner = i ^ stride;
-                    if (partner > i) {
-                        const bool up = ((i & size) == 0);
-                        const int32_t a = key[i], b = key[partner];
-                        if ((a > b) == up) {
-                            key[i] = b;
-                            key[partner] = a;
+        for (int64_t K = 2 * C; K <= P; K <<= 1) {
+            for (int64_t J = K / 2; J >= C; J >>= 1) {
+                for (int64_t q = threadIdx.x; q < P / 2; q += kBlock) {
+                    int64_t i, l;
+                    bitonic_pair(q, K, J, i, l);
+                    if (l < len) {
+                        const int32_t x = g[i], y = g[l];
+                        if (x > y) {
+                            g[i] = y;
+                            g[l] = x;
                         }
                     }
                 }
                 __syncthreads();
             }
+            for (int64_t lo = 0; lo < len; lo += C)
+                lds_bitonic(g + lo, (int)min((int64_t)C, len - lo), C / 2, key);
         }
-        for (int i = threadIdx.x; i < len; i += kBlock) src[s + i] = key[i];
-        __syncthreads();
     }
 }
 
@@ -1802,7 +1856,7 @@ hipError_t launch_transpose(int64_t m, int64_t n, int64_t nnz, const int32_t *rp
     if ((e = hipMemsetAsync(cnt, 0, sizeof(int32_t) * (size_t)n, s)) != hipSuccess) return e;
     if (nnz > 0) k_tr_scatter<<<gn, kBlock, 0, s>>>(m, nnz, rp, ci, at_rp, cnt, src);
     k_tr_sort_short<<<(unsigned)elementwise_blocks(n), kBlock, 0, s>>>(n, at_rp, src, long_rows,
-                                                                        n_long, flag);
+                                                                        n_long);
     k_tr_sort_long<<<1024, kBlock, 0, s>>>(at_rp, src, long_rows, n_long);
     if (nnz > 0) k_tr_fill<<<gn, kBlock, 0, s>>>(m, nnz, rp, val, src, at_ci, at_val);
     return hipGetLastError();

@@ -144,6 +144,8 @@ static bool use_merge(int64_t rows, int64_t nnz, int64_t longest, int lanes) {
     return row_blocks < kMergeMinBlocks && merge_blocks(rows, nnz) > row_blocks;
 }
 
+static int pick_slice_lanes(int64_t nnz, int64_t rows);
+
 static bool use_tiles(int64_t nnz, int64_t rows, int64_t cols) {
     if (rows <= 0 || cols < kTileMinCols) return false;
     const int64_t runs = n_tiles(cols) * rows;
@@ -177,6 +179,18 @@ static MatView tiled_view(int64_t rows, int64_t cols, int64_t nnz, const int32_t
     v.nchunk = (int32_t)nchunk;
     v.rchunk = rchunk;
     return v;
+}
+
+// A regrouped layout with fewer than kRegroupMinBlocks blocks leaves most of
+// the chip idle; the merge path then takes the operand when it has more
+// (measured: 600 rows of 9000 entries over 20000 columns, 57 tiled blocks,
+// 67.7 us tiled against 33.8 us on the merge path; 64 rows of 2e5 entries
+// over 1e6 columns, 246 tiled blocks, 42.8 us against 92.6 us).
+constexpr int64_t kRegroupMinBlocks = 128;
+
+static int64_t tiled_blocks(int64_t rows, int64_t cols, int64_t nnz) {
+    const MatView v = tiled_view(rows, cols, nnz, nullptr, nullptr, nullptr);
+    return (int64_t)v.nt * v.nchunk;
 }
 
 // ---------------------------------------------------------------------------
@@ -359,14 +373,26 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
         if ((rc = check_csr_longest(M, pflag, &longest_a, s)) != TA_OK) return rc;
     }
     const int la = pick_lanes(nnz, m), lt = pick_lanes(nnz, n);
-    // A is regrouped from (A^T)^T, whose rows the transpose sorts: not for rows
-    // longer than kMaxColNnz, nor for skewed rows (the merge path takes them)
-    const bool regroup_a = need_t && la > 1 && longest_a <= kMaxColNnz &&
-                           !skewed(m, nnz, longest_a);
-    const bool tile_a = regroup_a && use_tiles(nnz, m, n);
-    const bool tile_t = need_t && lt > 1 && use_tiles(nnz, n, m);
-    const bool slice_a = regroup_a && !tile_a && n >= kSliceMinCols;
-    const bool slice_t = need_t && lt > 1 && !tile_t && m >= kSliceMinCols;
+    // A is regrouped from (A^T)^T, except for skewed rows (the merge path
+    // takes them)
+    const bool regroup_a = need_t && la > 1 && !skewed(m, nnz, longest_a);
+    // blocks of the regrouped layout, and whether the merge path should take
+    // the operand instead (for A^T: its average row already holds
+    // kMergeMinRow, so its longest does)
+    auto starved = [&](int64_t rows, int64_t cols, bool tiled) {
+        const int64_t per = kBlock / pick_slice_lanes(nnz, rows);  // rows per sliced block
+        const int64_t blocks =
+            tiled ? tiled_blocks(rows, cols, nnz) : kSlices * ((rows + per - 1) / per);
+        return blocks < kRegroupMinBlocks && merge_blocks(rows, nnz) > blocks;
+    };
+    bool tile_a = regroup_a && use_tiles(nnz, m, n);
+    bool slice_a = regroup_a && !tile_a && n >= kSliceMinCols;
+    if ((tile_a || slice_a) && longest_a >= kMergeMinRow && starved(m, n, tile_a))
+        tile_a = slice_a = false;
+    bool tile_t = need_t && lt > 1 && use_tiles(nnz, n, m);
+    bool slice_t = need_t && lt > 1 && !tile_t && m >= kSliceMinCols;
+    if ((tile_t || slice_t) && nnz >= kMergeMinRow * n && starved(n, m, tile_t))
+        tile_t = slice_t = false;
 
     // owned memory
     Workspace own(s);
@@ -1410,7 +1436,7 @@ const char *ta_strerror(int code) {
         case TA_EINVAL: return "invalid argument";
         case TA_ENOMEM: return "device allocation failed";
         case TA_EHIP: return ta::hip_msg().empty() ? "HIP error" : ta::hip_msg().c_str();
-        case TA_ENOTSUP: return "input not supported (a column of A holds more than 8192 entries)";
+        case TA_ENOTSUP: return "input not supported (outside the sizes the call handles)";
         case TA_ESCRATCH:
             return "the solve needs more device memory than the fixed buffer of "
                    "cta_solve_plan_noalloc holds (64 MiB)";

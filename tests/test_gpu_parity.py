@@ -68,8 +68,21 @@ def _ragged_csr(m, n, seed, long_rows=()):
     return A
 
 
+def _long_columns():
+    """50000 x 40 with columns of 50000 (dense), 8192, 8193, 16384, 16385 and
+    40000 entries and the rest about 10: A^T rows past the 8192 entries the
+    transpose sorts in LDS at once."""
+    g = np.random.default_rng(26)
+    m, n = 50_000, 40
+    lens = [m, 8192, 8193, 16384, 16385, 40_000] + [int(w) for w in g.integers(1, 20, size=n - 6)]
+    cols = np.concatenate([np.full(w, j) for j, w in enumerate(lens)])
+    rows = np.concatenate([g.choice(m, size=w, replace=False) for w in lens])
+    return csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
+
+
 MATS = {
     "kac_1001": lambda: kac_clement(1001).A,
+    "long_columns_50000x40": _long_columns,
     "convdiff_33": lambda: convection_diffusion(33).A,
     "ragged_700x517": lambda: _ragged_csr(700, 517, 1, long_rows=(5, 300)),
     "lp_500x20000": lambda: lp_shaped(500, 20000, seed=3).A,
@@ -116,7 +129,8 @@ def test_one_thread_per_row_products_are_bit_exact(name):
     assert np.array_equal(w, oracle.apply_t(A, x[: A.m]))
 
 
-@pytest.mark.parametrize("name", ["kac_1001", "ragged_700x517", "lp_500x20000", "convdiff_33"])
+@pytest.mark.parametrize("name", ["kac_1001", "ragged_700x517", "lp_500x20000", "convdiff_33",
+                                  "long_columns_50000x40"])
 def test_transpose_is_exact(name):
     A = MATS[name]()
     rp, ci, v = P.transpose(P.to_device(A))
@@ -496,6 +510,27 @@ def test_regrouped_solves_match_oracle(case):
     g = P.ta_solve(pl, p.b, tol=1e-3, max_iter=300)
     o = oracle.ta(p.A, p.b, tol=1e-3, max_iter=300)
     _compare(g, o, x_rtol=1e-9)
+    pl.close()
+
+
+def test_long_rows_keep_their_column_tiles():
+    """256 rows of 20000 random entries over 10^6 columns: column tiles (984
+    blocks), built from (A^T)^T, whose rows are longer than one LDS sort;
+    products and a short CTA solve against the oracle."""
+    g = np.random.default_rng(27)
+    m, n, w = 256, 1_000_000, 20_000
+    rows = np.repeat(np.arange(m), w)
+    cols = np.concatenate([g.choice(n, size=w, replace=False) for _ in range(m)])
+    A = csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
+    pl = P.plan(A)
+    assert pl.format(False) == "csr_tiled"
+    x = g.standard_normal(n)
+    u = g.standard_normal(m)
+    assert ulps(host(P.spmv(pl, x)), oracle.apply(A, x)).max() <= 1
+    assert ulps(host(P.spmv(pl, u, trans=True)), oracle.apply_t(A, u)).max() <= 1
+    b = A.to_scipy() @ g.standard_normal(n)
+    _compare(P.cta_minnorm(pl, b, tol=1e-10, t=3, max_iter=20),
+             oracle.cta_minnorm(A, b, tol=1e-10, t=3, max_iter=20))
     pl.close()
 
 
