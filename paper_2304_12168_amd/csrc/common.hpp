@@ -200,6 +200,10 @@ struct MatView {
     // number of rows completed before its first item
     const int32_t *mp;
     int64_t mb;
+    // kCsrSell: load the slots with non-temporal loads (set when the plan's
+    // copies of A and A^T together outgrow the Infinity Cache, so that the
+    // stream does not evict the gathered x; smaller ones are better kept)
+    int32_t nt_stream;
 };
 
 // ---- launchers (kernels.hip); each returns the grid size it used in *blocks ----

@@ -419,8 +419,8 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(MatView M, const double *
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u * kBlock;
-                c[u] = i < cnt ? M.ci[base + i] : 0;
-                a[u] = i < cnt ? M.val[base + i] : 0.0;
+                c[u] = i < cnt ? __builtin_nontemporal_load(M.ci + base + i) : 0;
+                a[u] = i < cnt ? __builtin_nontemporal_load(M.val + base + i) : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) xv[u] = x[c[u]];
@@ -455,9 +455,11 @@ __global__ __launch_bounds__(kBlock) void k_csr_stream(MatView M, const double *
 // index and value load of the wave is one contiguous access and no row bound
 // is loaded.  Terms are added in storage order with the compensated steps of
 // k_csr_stream, so both give the same bits.  Up to 6 positions are loaded
-// before the first gather (the width is uniform over the wave).
+// before the first gather (the width is uniform over the wave).  NT: the
+// slots are read with non-temporal loads (a separate instantiation: a run-time
+// choice between the two loads is merged into one plain load by the compiler).
 // ---------------------------------------------------------------------------
-template <int EPI>
+template <int EPI, bool NT>
 __global__ __launch_bounds__(kBlock) void k_sell(MatView M, const double *__restrict__ x,
                                                   double *y, EpiArgs ea, Out o) {
     if (!producer_runs(o)) return;
@@ -484,8 +486,13 @@ __global__ __launch_bounds__(kBlock) void k_sell(MatView M, const double *__rest
                 cc[u] = -1;
                 aa[u] = 0.0;
                 if (k + u < w) {
-                    cc[u] = c[(int64_t)(k + u) * 64];
-                    aa[u] = a[(int64_t)(k + u) * 64];
+                    if constexpr (NT) {
+                        cc[u] = __builtin_nontemporal_load(c + (int64_t)(k + u) * 64);
+                        aa[u] = __builtin_nontemporal_load(a + (int64_t)(k + u) * 64);
+                    } else {
+                        cc[u] = c[(int64_t)(k + u) * 64];
+                        aa[u] = a[(int64_t)(k + u) * 64];
+                    }
                 }
             }
 #pragma unroll
@@ -946,8 +953,8 @@ __global__ __launch_bounds__(kBlock) void k_merge_spmv(MatView M, const double *
 #pragma unroll
         for (int u = 0; u < kMergeIpt; ++u) {
             const int j = min(u * kBlock + tid, nk - 1);
-            cj[u] = M.ci[k0 + j];
-            av[u] = M.val[k0 + j];
+            cj[u] = __builtin_nontemporal_load(M.ci + k0 + j);
+            av[u] = __builtin_nontemporal_load(M.val + k0 + j);
         }
 #pragma unroll
         for (int u = 0; u < kMergeIpt; ++u) xv[u] = x[cj[u]];
@@ -1645,7 +1652,12 @@ static void launch_matvec_t(const MatView &M, const double *x, double *y, const 
             if (M.rows > 0 && M.nt > 0) launch_tiled<EPI>(M, x, o, s);
             k_tiles_combine<EPI><<<grid, kBlock, 0, s>>>(M, y, ea, o);
             break;
-        case kCsrSell: k_sell<EPI><<<grid, kBlock, 0, s>>>(M, x, y, ea, o); break;
+        case kCsrSell:
+            if (M.nt_stream)
+                k_sell<EPI, true><<<grid, kBlock, 0, s>>>(M, x, y, ea, o);
+            else
+                k_sell<EPI, false><<<grid, kBlock, 0, s>>>(M, x, y, ea, o);
+            break;
         case kCsrMerge:
             k_merge_spmv<EPI><<<dim3((unsigned)M.mb), kBlock, 0, s>>>(M, x, y, ea, o);
             k_merge_fixup<EPI><<<dim3((unsigned)cdiv(M.mb, kBlock / 64)), kBlock, 0, s>>>(M, y, ea, o);

@@ -277,10 +277,17 @@ static int plan_merge(Plan *P, int64_t nnz, int64_t longest_a, hipStream_t s) {
     return TA_OK;
 }
 
+// The MI355X's Infinity Cache (MALL) in front of HBM
+constexpr int64_t kInfinityCacheBytes = int64_t(256) << 20;
+
 // SELL-64 copies for the one-thread-per-row CSR views whose 64-row slices
 // pad the entries by at most a quarter (rows of even length: stencils,
 // banded and degree-bounded sparse matrices).  Widths come back to the host
-// for the slice offsets; the slots are filled on the device.
+// for the slice offsets; the slots are filled on the device.  Plans whose A
+// and A^T together outgrow the Infinity Cache stream the slots with
+// non-temporal loads (measured on the 2896^2 Poisson matrix: 135 -> 123 us;
+// on the 1e4 x 1e6 LP shape's A^T, 144 MB with A, they made 27 -> 35 us).
+
 static int plan_sell(Plan *P, int64_t nnz, hipStream_t s) {
     MatView *vs[2] = {&P->A, P->has_t ? &P->AT : nullptr};
     int64_t nsl[2] = {0, 0};
@@ -326,6 +333,7 @@ static int plan_sell(Plan *P, int64_t nnz, hipStream_t s) {
             HIP_TRY(launch_sell_fill(vs[i]->rows, vs[i]->rp, vs[i]->ci, vs[i]->val, d_so[i],
                                      d_sc[i], d_sv[i], s));
             vs[i]->kind = kCsrSell;
+            vs[i]->nt_stream = 2 * 12 * nnz > kInfinityCacheBytes;
             vs[i]->so = d_so[i];
             vs[i]->sc = d_sc[i];
             vs[i]->sv = d_sv[i];
