@@ -251,8 +251,9 @@ int ta_minnorm(const ta_mat *A, const double *b, const double *x_eps, double *x,
  * with 16-bit column offsets, so that each block stages one tile of x in LDS
  * and gathers from there (TA_FMT_CSR_TILED; one partial sum per row and
  * tile is merged afterwards); else, with at least 131072 columns, a copy with
- * sorted columns split into 8 column slices so that each XCD of the MI355X
- * gathers from its own eighth of x.  A or A^T with short rows (16 or fewer
+ * sorted columns split into s = 8 g column slices (g doubling, up to 8, while a
+ * slice of x exceeds 8 MB), run 8 at a time so that each XCD of the MI355X
+ * gathers from its own slice of x (TA_FMT_CSR_SLICED).  A or A^T with short rows (16 or fewer
  * nonzeros on average) whose 64-row slices pad the entries by at most a
  * quarter is also copied into SELL-64 form (each slice stored position by
  * position, padded to its widest row), so its products need no row bounds
@@ -311,7 +312,7 @@ int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, d
  * State is set from a kernel argument and read back into host stack memory.
  * The plan itself is made beforehand with ta_plan_create (which allocates).
  *   Limit: the workspace is 8 (t + 1) (m + n) bytes (8 (m + n) more with
- *   accel, 128 m or 128 n more for a plan with column slices, 16 m
+ *   accel, 16 s m or 16 s n more for a plan with s column slices, 16 m
  *   ceil(n / 8192) or 16 n ceil(m / 8192) more for one with column tiles, 48
  *   bytes per 2048 items of (rows + nonzeros) for a merge-path partition)
  *   plus the per-block partial sums; a solve that needs more than the buffer returns

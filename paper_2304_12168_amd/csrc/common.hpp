@@ -146,13 +146,13 @@ enum MatKind : int32_t {
     kCsrRows = 0,    // CSR: one thread per row (LDS-staged) or `lanes` lanes per row
     kDenseRows = 1,  // dense row-major, rows of M, 64 lanes per row
     kDenseCols = 2,  // dense row-major A viewed as M = A^T: one thread per column of A
-    kCsrSliced = 3,  // CSR with columns sorted, split into kSlices column slices (one per XCD)
+    kCsrSliced = 3,  // CSR with columns sorted, split into nsl column slices (8 in flight, one per XCD)
     kCsrSell = 4,    // CSR copied into 64-row slices (SELL-64), one thread per row
     kCsrTiled = 5,   // CSR regrouped by column tiles of kTileW; each tile of x staged in LDS
     kCsrMerge = 6,   // CSR split along the merge path of row ends and nonzeros (skewed rows)
 };
 
-constexpr int kSlices = 8;  // XCDs of the part; blocks b with b % 8 == s take column slice s
+constexpr int kSlices = 8;  // XCDs of the part: slices go 8 at a time, slice 8 g + s on XCD s
 constexpr int kTileW = 8192;     // columns per tile: 64 KB of FP64 x in LDS, 16-bit local index
 constexpr int kTileBlock = 512;  // threads of a tiled block: 2 blocks (16 waves) per CU
 // W lanes per row take U entries each per round (W U = 8 slots per row and
@@ -177,8 +177,8 @@ struct MatView {
     const int32_t *ci;
     const double *val;
     int32_t lanes;       // kCsrRows: 1 = one thread per row, else lanes per row
-    const int32_t *seg;  // kCsrSliced: rows x (kSlices + 1) slice starts inside each row
-    double2 *ypart;      // kCsrSliced: kSlices x rows compensated partial sums (workspace);
+    const int32_t *seg;  // kCsrSliced: rows x (nsl + 1) slice starts inside each row
+    double2 *ypart;      // kCsrSliced: nsl x rows compensated partial sums (workspace);
                          // kCsrTiled: nt x rows; kCsrMerge: 3 mb (per-block head and carry)
     // kCsrSell: slice s (rows 64 s .. 64 s + 63) holds slots [so[s], so[s + 1]),
     // position k of row 64 s + i at slot so[s] + 64 k + i; a row's entries keep
@@ -204,6 +204,7 @@ struct MatView {
     // copies of A and A^T together outgrow the Infinity Cache, so that the
     // stream does not evict the gathered x; smaller ones are better kept)
     int32_t nt_stream;
+    int32_t nsl;  // kCsrSliced: column slices, a multiple of kSlices
 };
 
 // ---- launchers (kernels.hip); each returns the grid size it used in *blocks ----
@@ -240,7 +241,7 @@ hipError_t launch_state_set(State *d, const State &h, hipStream_t s);
 hipError_t launch_check_csr(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                             const int32_t *ci, int32_t *flag, hipStream_t s);
 hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,
-                                 int64_t cols, int32_t *seg, hipStream_t s);
+                                 int64_t cols, int32_t nsl, int32_t *seg, hipStream_t s);
 // Tile-major copy of a CSR whose columns are sorted inside each row (the
 // kCsrTiled layout): trp (nt rows + 1), lc and tval (nnz each).  work:
 // nt rows + cdiv(nt rows, 1024) + 8 int32 entries.

@@ -613,12 +613,14 @@ __global__ __launch_bounds__(kBlock) void k_rows_vector(MatView M, const double 
 }
 
 // ---------------------------------------------------------------------------
-// CSR split into kSlices column slices.  Block b works on slice b % 8 (its
-// XCD under round-robin dispatch) for a group of rows, so each XCD gathers
-// only from its own 1/8 of x, which stays in that XCD's L2.  The matrix
-// stream is read non-temporally so it does not evict the slice of x.  Each
-// (row, slice) partial is kept as an unrounded compensated pair; the combine
-// kernel merges the slices of a row in slice order and runs the epilogue.
+// CSR split into nsl = 8 g column slices, each of a few MB of x.
+// Blocks go in g groups of 8 slices: block b takes XCD lane b % 8 (its XCD
+// under round-robin dispatch), group (b / 8) / RB and row block (b / 8) % RB,
+// so while a group runs each XCD gathers only from its own slice of x, which
+// stays in that XCD's L2 (or close to it) and the Infinity Cache.  The matrix stream is read non-temporally so it does
+// not evict the slice of x.  Each (row, slice) partial is kept as an
+// unrounded compensated pair; the combine kernel merges the slices of a row
+// in slice order and runs the epilogue.
 // ---------------------------------------------------------------------------
 template <int W, int EPI>
 __global__ __launch_bounds__(kBlock) void k_rows_sliced(MatView M, const double *__restrict__ x,
@@ -627,15 +629,17 @@ __global__ __launch_bounds__(kBlock) void k_rows_sliced(MatView M, const double 
     constexpr int G = kBlock / W;
     constexpr double sgn = (EPI == kEpiResid) ? -1.0 : 1.0;
     const int tid = threadIdx.x;
-    const int slice = (int)(blockIdx.x % kSlices);
-    const int64_t row = (int64_t)(blockIdx.x / kSlices) * G + tid / W;
+    const int64_t RB = (M.rows + G - 1) / G;
+    const int64_t t = blockIdx.x / kSlices;
+    const int slice = (int)((t / RB) * kSlices + blockIdx.x % kSlices);
+    const int64_t row = (t % RB) * G + tid / W;
     const int lane = tid % W;
     if (row >= M.rows) return;  // no block-wide synchronisation below
     Acc acc = {0.0, 0.0};
     if constexpr (EPI == kEpiResid) {
         if (slice == 0 && lane == 0) acc.p = ea.b[row];
     }
-    const int32_t *sg = M.seg + row * (kSlices + 1) + slice;
+    const int32_t *sg = M.seg + row * (M.nsl + 1) + slice;
     const int32_t e = sg[1];
     // Rounds of U entries per lane, each entry predicated on the segment end:
     // a segment of up to U W entries takes one round, i.e. one wait for the
@@ -674,8 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_slices_combine(MatView M, double *y,
          row += (int64_t)gridDim.x * kBlock) {
         double2 p = M.ypart[row];
         Acc a = {p.x, p.y};
-#pragma unroll
-        for (int sl = 1; sl < kSlices; ++sl) {
+        for (int sl = 1; sl < M.nsl; ++sl) {
             p = M.ypart[(int64_t)sl * M.rows + row];
             a = acc_merge(a, Acc{p.x, p.y});
         }
@@ -1151,13 +1154,14 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(MatView M, double *y, Ep
 
 // First entry of each column slice inside each row of a column-sorted CSR.
 __global__ void k_slice_segments(int64_t m, const int32_t *__restrict__ rp,
-                                 const int32_t *__restrict__ ci, int64_t slice_w, int32_t *seg) {
+                                 const int32_t *__restrict__ ci, int64_t slice_w, int32_t nsl,
+                                 int32_t *seg) {
     for (int64_t row = (int64_t)blockIdx.x * kBlock + threadIdx.x; row < m;
          row += (int64_t)gridDim.x * kBlock) {
         const int32_t s = rp[row], e = rp[row + 1];
-        int32_t *out = seg + row * (kSlices + 1);
+        int32_t *out = seg + row * (nsl + 1);
         out[0] = s;
-        for (int sl = 1; sl < kSlices; ++sl) {
+        for (int sl = 1; sl < nsl; ++sl) {
             const int64_t bound = sl * slice_w;
             int32_t lo = s, hi = e;  // first k with ci[k] >= bound
             while (lo < hi) {
@@ -1169,7 +1173,7 @@ __global__ void k_slice_segments(int64_t m, const int32_t *__restrict__ rp,
             }
             out[sl] = lo;
         }
-        out[kSlices] = e;
+        out[nsl] = e;
     }
 }
 
@@ -1608,7 +1612,7 @@ template <int EPI>
 static void launch_sliced(const MatView &M, const double *x, const EpiArgs &ea, const Out &o,
                           hipStream_t s) {
     const int W = M.lanes;
-    const dim3 grid((unsigned)(kSlices * cdiv(M.rows > 0 ? M.rows : 1, kBlock / W)));
+    const dim3 grid((unsigned)(M.nsl * cdiv(M.rows > 0 ? M.rows : 1, kBlock / W)));
     switch (W) {
         case 2: k_rows_sliced<2, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
         case 4: k_rows_sliced<4, EPI><<<grid, kBlock, 0, s>>>(M, x, ea, o); break;
@@ -1787,9 +1791,10 @@ hipError_t launch_ta_update(int64_t m, int64_t n, const double *b, double *bp, c
 }
 
 hipError_t launch_slice_segments(int64_t m, const int32_t *rp, const int32_t *ci_sorted,
-                                 int64_t cols, int32_t *seg, hipStream_t s) {
-    const int64_t w = cdiv(cols > 0 ? cols : 1, kSlices);
-    k_slice_segments<<<(unsigned)elementwise_blocks(m), kBlock, 0, s>>>(m, rp, ci_sorted, w, seg);
+                                 int64_t cols, int32_t nsl, int32_t *seg, hipStream_t s) {
+    const int64_t w = cdiv(cols > 0 ? cols : 1, nsl);
+    k_slice_segments<<<(unsigned)elementwise_blocks(m), kBlock, 0, s>>>(m, rp, ci_sorted, w, nsl,
+                                                                        seg);
     return hipGetLastError();
 }
 

@@ -144,7 +144,21 @@ static bool use_merge(int64_t rows, int64_t nnz, int64_t longest, int lanes) {
     return row_blocks < kMergeMinBlocks && merge_blocks(rows, nnz) > row_blocks;
 }
 
-static int pick_slice_lanes(int64_t nnz, int64_t rows);
+static int pick_slice_lanes(int64_t nnz, int64_t rows, int32_t nsl);
+
+// Column slices per operand: 8 g (g a power of two) so that one slice of x
+// takes at most TA_SLICE_BYTES.  Measured on the LP shape's A pass (600
+// random columns per row): n = 1e7, 8 slices of 10 MB 747 us, 16 of 5 MB
+// 626 us, 32 759 us, 64 884 us (more slices add a partial sum and a segment
+// bound per row and slice); n = 4e6, 8 slices of 4 MB 206 us, 16 235 us.
+#ifndef TA_SLICE_BYTES
+#define TA_SLICE_BYTES (8 << 20)
+#endif
+static int32_t n_slices(int64_t cols) {
+    int32_t g = 1;
+    while (g < 64 && 8 * cols > (int64_t)kSlices * g * TA_SLICE_BYTES) g *= 2;
+    return kSlices * g;
+}
 
 static bool use_tiles(int64_t nnz, int64_t rows, int64_t cols) {
     if (rows <= 0 || cols < kTileMinCols) return false;
@@ -200,11 +214,11 @@ static int64_t tiled_blocks(int64_t rows, int64_t cols, int64_t nnz) {
 // streams at once; per-call scratch lives in each call's workspace.
 // ---------------------------------------------------------------------------
 // Lanes per row for the sliced kernel, from the nonzeros per (row, slice).
-static int pick_slice_lanes(int64_t nnz, int64_t rows) {
+static int pick_slice_lanes(int64_t nnz, int64_t rows, int32_t nsl) {
 #ifdef TA_SLICE_LANES
     return TA_SLICE_LANES;
 #endif
-    const double avg = rows > 0 ? (double)nnz / (double)rows / kSlices : 0.0;
+    const double avg = rows > 0 ? (double)nnz / (double)rows / nsl : 0.0;
     if (avg <= 32.0) return 4;
     if (avg <= 64.0) return 8;
     if (avg <= 128.0) return 16;
@@ -388,9 +402,10 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
     // the operand instead (for A^T: its average row already holds
     // kMergeMinRow, so its longest does)
     auto starved = [&](int64_t rows, int64_t cols, bool tiled) {
-        const int64_t per = kBlock / pick_slice_lanes(nnz, rows);  // rows per sliced block
+        const int32_t nsl = n_slices(cols);
+        const int64_t per = kBlock / pick_slice_lanes(nnz, rows, nsl);  // rows per sliced block
         const int64_t blocks =
-            tiled ? tiled_blocks(rows, cols, nnz) : kSlices * ((rows + per - 1) / per);
+            tiled ? tiled_blocks(rows, cols, nnz) : nsl * ((rows + per - 1) / per);
         return blocks < kRegroupMinBlocks && merge_blocks(rows, nnz) > blocks;
     };
     bool tile_a = regroup_a && use_tiles(nnz, m, n);
@@ -416,9 +431,9 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
     if (slice_a) {
         own.reserve(&ac_ci, nnz);
         own.reserve(&ac_val, nnz);
-        own.reserve(&a_seg, m * (kSlices + 1));
+        own.reserve(&a_seg, m * (n_slices(n) + 1));
     }
-    if (slice_t) own.reserve(&t_seg, n * (kSlices + 1));
+    if (slice_t) own.reserve(&t_seg, n * (n_slices(m) + 1));
     if (tile_a) {
         own.reserve(&a_trp, n_tiles(n) * m + 1);
         own.reserve(&a_lc, nnz);
@@ -459,18 +474,22 @@ static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool
                                      flag, s));
         }
         if (slice_a) {
-            HIP_TRY(launch_slice_segments(m, M->row_ptr, ac_ci, n, a_seg, s));
+            const int32_t nsl = n_slices(n);
+            HIP_TRY(launch_slice_segments(m, M->row_ptr, ac_ci, n, nsl, a_seg, s));
             P->A = MatView{kCsrSliced, m, n, 0, M->row_ptr, ac_ci, ac_val,
-                           pick_slice_lanes(nnz, m), a_seg, nullptr};
+                           pick_slice_lanes(nnz, m, nsl), a_seg, nullptr};
+            P->A.nsl = nsl;
         }
         if (tile_a) {
             HIP_TRY(launch_tile_build(m, n, ac_rp, ac_ci, ac_val, a_trp, a_lc, a_tv, work, s));
             P->A = tiled_view(m, n, nnz, a_trp, a_lc, a_tv);
         }
         if (slice_t) {
-            HIP_TRY(launch_slice_segments(n, at_rp, at_ci, m, t_seg, s));
-            P->AT = MatView{kCsrSliced, n, m, 0, at_rp, at_ci, at_val, pick_slice_lanes(nnz, n),
-                            t_seg, nullptr};
+            const int32_t nsl = n_slices(m);
+            HIP_TRY(launch_slice_segments(n, at_rp, at_ci, m, nsl, t_seg, s));
+            P->AT = MatView{kCsrSliced, n, m, 0, at_rp, at_ci, at_val,
+                            pick_slice_lanes(nnz, n, nsl), t_seg, nullptr};
+            P->AT.nsl = nsl;
         }
         if (tile_t) {
             HIP_TRY(launch_tile_build(n, m, at_rp, at_ci, at_val, t_trp, t_lc, t_tv, work, s));
@@ -507,9 +526,9 @@ struct Chain {
         cap = std::max<int64_t>(cap, 1);
         ws.reserve(&st, 1);
         ws.reserve(&partials, (int64_t)nslots * cap);
-        if (A.kind == kCsrSliced) ws.reserve(&A.ypart, kSlices * std::max<int64_t>(A.rows, 1));
+        if (A.kind == kCsrSliced) ws.reserve(&A.ypart, (int64_t)A.nsl * std::max<int64_t>(A.rows, 1));
         if (P.has_t && AT.kind == kCsrSliced)
-            ws.reserve(&AT.ypart, kSlices * std::max<int64_t>(AT.rows, 1));
+            ws.reserve(&AT.ypart, (int64_t)AT.nsl * std::max<int64_t>(AT.rows, 1));
         if (A.kind == kCsrTiled) ws.reserve(&A.ypart, (int64_t)A.nt * std::max<int64_t>(A.rows, 1));
         if (P.has_t && AT.kind == kCsrTiled)
             ws.reserve(&AT.ypart, (int64_t)AT.nt * std::max<int64_t>(AT.rows, 1));

@@ -457,7 +457,22 @@ def _lp_dense_row():
     return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
 
 
+def _wide_random(m, n, per_row, seed):
+    """m rows of per_row random columns (repeats summed) over n columns: too
+    few entries per (row, 8192-column tile) for tiles, so column slices:
+    8 g of them, g the least power of two with n <= g 2^23 (x's slice within
+    8 MB): 16 at n = 1.1e7, 32 at n = 2e7."""
+    g = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(m), per_row)
+    cols = g.integers(0, n, size=rows.size)
+    A = csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
+    x = g.standard_normal(n)
+    return type("Pb", (), {"A": A, "b": A.to_scipy() @ x})()
+
+
 REGROUPED = {
+    "sliced16_A": (lambda: _wide_random(1000, 11_000_000, 600, 28), ("csr_sliced", None)),
+    "sliced32_A": (lambda: _wide_random(500, 20_000_000, 600, 29), ("csr_sliced", None)),
     "lp_dense_row_merge_A": (_lp_dense_row, ("csr_merge", None)),
     "skewed_merge_A": (lambda: skewed_rows(20_000, 20_000, seed=1, empty_frac=0.1, dense_rows=1),
                        ("csr_merge", None)),

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import paper_2304_12168_amd as P
-from workloads import convection_diffusion, csr_from_coo, dense_gaussian, lp_shaped
+from workloads import convection_diffusion, csr_from_coo, dense_gaussian, lp_shaped, skewed_rows
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -80,11 +80,14 @@ def test_noalloc_refuses_a_solve_larger_than_its_buffer():
 
 
 def test_noalloc_on_regrouped_plans():
-    """Plans whose A is stored in LDS column tiles (per-(tile, row) partials)
-    or XCD column slices (per-(slice, row) partials): the partials are carved
-    from the buffer too."""
-    for m, n, fmt in ((2000, 200_000, "csr_tiled"), (20_000, 200_000, "csr_sliced")):
-        p = lp_shaped(m, n, seed=5)
+    """Plans whose A is stored in LDS column tiles (per-(tile, row) partials),
+    XCD column slices (per-(slice, row) partials) or a merge-path partition
+    (per-block head and carry slots): those are carved from the buffer too."""
+    cases = [(lambda: lp_shaped(2000, 200_000, seed=5), "csr_tiled"),
+             (lambda: lp_shaped(20_000, 200_000, seed=5), "csr_sliced"),
+             (lambda: skewed_rows(20_000, 20_000, seed=1, empty_frac=0.1, dense_rows=1), "csr_merge")]
+    for make, fmt in cases:
+        p = make()
         pl = P.Plan(p.A)
         try:
             assert pl.format(False) == fmt
