@@ -549,6 +549,39 @@ def test_long_rows_keep_their_column_tiles():
     pl.close()
 
 
+def _skewed_spd(n=3000, seed=5):
+    """B + B^T plus a dominant diagonal, B with skewed rows and one dense row:
+    symmetric positive definite, with a dense row and column."""
+    from scipy import sparse
+
+    B = skewed_rows(n, n, seed=seed, dense_rows=1).A.to_scipy()
+    S = (B + B.T).tocsr()
+    S = (S + sparse.diags(abs(S).sum(axis=1).A1 + 1.0)).tocsr()
+    S.sort_indices()
+    return Csr(n, n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.copy())
+
+
+def test_merge_path_epilogues_in_solves():
+    """The merge-path product under the epilogues of H = A (CTA, the dot with
+    the input) and of TA's LP-feasibility form (the positive part), against
+    the oracle."""
+    S = _skewed_spd()
+    pl = P.plan(S)
+    assert pl.format(False) == pl.format(True) == "csr_merge"
+    b = S.to_scipy() @ np.random.default_rng(3).standard_normal(S.n)
+    kw = dict(tol=1e-8, t=3, max_iter=5000, h_is_a=True)
+    _compare(P.cta_solve(pl, b, **kw), oracle.cta(S, b, **kw))
+    pl.close()
+    A = skewed_rows(2000, 20_000, seed=6, dense_rows=1).A
+    xs = np.abs(np.random.default_rng(4).standard_normal(A.n))
+    b = A.to_scipy() @ xs
+    pl = P.plan(A)
+    assert pl.format(False) == "csr_merge"
+    kw = dict(tol=1e-4, max_iter=20_000, nonneg=True)
+    _compare(P.ta_solve(pl, b, **kw), oracle.ta(A, b, **kw), x_rtol=1e-9)
+    pl.close()
+
+
 def test_plan_and_one_shot_are_identical():
     p = kac_clement(3001)
     pl = P.plan(p.A)
