@@ -1523,16 +1523,27 @@ __global__ __launch_bounds__(kBlock) void k_tr_sort_long(const int32_t *__restri
         while (P < len) P <<= 1;
         for (int64_t K = 2 * C; K <= P; K <<= 1) {
             for (int64_t J = K / 2; J >= C; J >>= 1) {
-                for (int64_t q = threadIdx.x; q < P / 2; q += kBlock) {
-                    int64_t i, l;
-                    bitonic_pair(q, K, J, i, l);
-                    if (l < len) {
-                        const int32_t x = g[i], y = g[l];
-                        if (x > y) {
-                            g[i] = y;
-                            g[l] = x;
+                // 4 pairs per thread and round, loaded before any is compared
+                constexpr int R = 4;
+                for (int64_t q0 = threadIdx.x; q0 < P / 2; q0 += R * kBlock) {
+                    int64_t i[R], l[R];
+                    int32_t x[R], y[R];
+#pragma unroll
+                    for (int u = 0; u < R; ++u) {
+                        const int64_t q = q0 + u * kBlock;
+                        l[u] = len;  // no pair
+                        if (q < P / 2) bitonic_pair(q, K, J, i[u], l[u]);
+                        if (l[u] < len) {
+                            x[u] = g[i[u]];
+                            y[u] = g[l[u]];
                         }
                     }
+#pragma unroll
+                    for (int u = 0; u < R; ++u)
+                        if (l[u] < len && x[u] > y[u]) {
+                            g[i[u]] = y[u];
+                            g[l[u]] = x[u];
+                        }
                 }
                 __syncthreads();
             }

@@ -80,9 +80,21 @@ def _long_columns():
     return csr_from_coo(m, n, rows, cols, g.standard_normal(rows.size))
 
 
+def _dense_columns():
+    """2e6 x 3: a dense column, one of 1e6 random rows and one of 10: A^T rows
+    that the transpose sorts through merges of up to 2^21 entries."""
+    g = np.random.default_rng(30)
+    m = 2_000_000
+    parts = [np.arange(m), g.choice(m, size=1_000_000, replace=False), g.choice(m, size=10, replace=False)]
+    rows = np.concatenate(parts)
+    cols = np.concatenate([np.full(p.size, j) for j, p in enumerate(parts)])
+    return csr_from_coo(m, 3, rows, cols, g.standard_normal(rows.size))
+
+
 MATS = {
     "kac_1001": lambda: kac_clement(1001).A,
     "long_columns_50000x40": _long_columns,
+    "dense_columns_2e6x3": _dense_columns,
     "convdiff_33": lambda: convection_diffusion(33).A,
     "ragged_700x517": lambda: _ragged_csr(700, 517, 1, long_rows=(5, 300)),
     "lp_500x20000": lambda: lp_shaped(500, 20000, seed=3).A,
@@ -130,7 +142,7 @@ def test_one_thread_per_row_products_are_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", ["kac_1001", "ragged_700x517", "lp_500x20000", "convdiff_33",
-                                  "long_columns_50000x40"])
+                                  "long_columns_50000x40", "dense_columns_2e6x3"])
 def test_transpose_is_exact(name):
     A = MATS[name]()
     rp, ci, v = P.transpose(P.to_device(A))
