@@ -19,6 +19,8 @@ FLAGS = [
     # no packed FP32 instructions in any HIP code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+    # roctx ranges around the host-side phases
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -1,8 +1,9 @@
 // Host-side helpers shared by the drivers of libta: HIP error handling,
-// stream-ordered workspace, descriptor checks.
+// stream-ordered workspace, descriptor checks, trace ranges.
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stdint.h>
 #include <stdio.h>
 
@@ -26,6 +27,17 @@ inline int hip_fail(hipError_t e, const char *what) {
     hip_msg() = buf;
     return e == hipErrorOutOfMemory ? TA_ENOMEM : TA_EHIP;
 }
+
+// A roctx range over a host-side phase (plan preparation, one chunk of
+// iterations and its state read-back): rocprofv3 --marker-trace shows them
+// beside the kernels.  Without a profiler attached the calls do nothing.
+class Range {
+   public:
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 #define HIP_TRY(call)                                   \
     do {                                                \

@@ -360,6 +360,7 @@ static int plan_sell(Plan *P, int64_t nnz, hipStream_t s) {
 // sell: also build SELL-64 copies (plans and solves; not the one-shot
 // products, which would spend more on the copy than they save)
 static int plan_build(const ta_mat *M, bool need_t, hipStream_t s, Plan *P, bool sell = false) {
+    Range trace("ta:prepare");
     int rc = validate_mat(M);
     if (rc != TA_OK) return rc;
     P->desc = *M;
@@ -893,6 +894,7 @@ static int cta_run(const Plan &P, const double *b, double *x, const ta_opts *o, 
     int64_t k_done = 0;  // iterations done when the chunk starts
     for (int64_t chunk_no = 0;; ++chunk_no) {
         const int64_t k = ch.take();
+        Range trace("cta:chunk");
         auto body = [&]() -> int {
             for (int64_t i = 0; i < k; ++i) {
                 // the order of an iteration is its index's; a chunk that runs
@@ -1048,6 +1050,7 @@ static int ta_run(const Plan &P, const double *b, double *x, const ta_opts *o, d
     bool inline_checks = false;
     for (int64_t chunk_no = 0;; ++chunk_no) {
         const int64_t k = ch.take();
+        Range trace("ta:chunk");
         auto body = [&]() -> int {
             for (int64_t i = 0; i < k; ++i) {
                 int rb2 = enqueue_iteration();

@@ -54,7 +54,8 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
            "-Xarch_host", "-fno-omit-frame-pointer",
            "-I", os.path.join(ROOT, "include"), "-I", csrc,
            os.path.join(csrc, "kernels.hip"), os.path.join(csrc, "solver.hip"),
-           os.path.join(csrc, "batched.hip"), os.path.join(HERE, "library_driver.hip"), "-o", exe]
+           os.path.join(csrc, "batched.hip"), os.path.join(HERE, "library_driver.hip"),
+           "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-o", exe]
     subprocess.run(cmd, check=True, timeout=900, capture_output=True)
     out = _run(exe, tmp_path)
     assert "0 failures" in out
