@@ -315,6 +315,14 @@ __global__ __launch_bounds__(kBlock) void k_step(Step sp) {
     const bool computed = !(sp.gate == kGateNeedC && st->have_c);
     __shared__ double vals[kMaxSlots];
     __shared__ Acc red[kBlock / 64];
+    // The scalar logic runs on a copy of the state in LDS: one coalesced load
+    // of it here, one store after, instead of the one thread's chain of
+    // dependent global reads and writes.
+    __shared__ State sst;
+    constexpr int kStateWords = (int)(sizeof(State) / sizeof(int32_t));
+    static_assert(sizeof(State) % sizeof(int32_t) == 0, "State is copied as 32-bit words");
+    for (int i = threadIdx.x; i < kStateWords; i += kBlock)
+        reinterpret_cast<int32_t *>(&sst)[i] = reinterpret_cast<const int32_t *>(st)[i];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (computed) {
         for (int q = 0; q < sp.nslots; ++q) {
@@ -345,7 +353,15 @@ __global__ __launch_bounds__(kBlock) void k_step(Step sp) {
             __syncthreads();
         }
     }
-    if (threadIdx.x == 0) post_action(sp, vals, computed);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Step sl = sp;
+        sl.st = &sst;
+        post_action(sl, vals, computed);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kStateWords; i += kBlock)
+        reinterpret_cast<int32_t *>(sp.st)[i] = reinterpret_cast<const int32_t *>(&sst)[i];
 }
 
 template <int EPI>
