@@ -81,6 +81,9 @@ def _load():
         lib.or_ta_minnorm.restype = C.c_int64
         lib.or_ta_minnorm.argtypes = [C.POINTER(_Mat), P, P, P, C.POINTER(_Opts),
                                       C.POINTER(_Info)]
+        lib.or_ta_halving.restype = C.c_int
+        lib.or_ta_halving.argtypes = [C.POINTER(_Mat), P, P, C.POINTER(_Opts), C.c_int32,
+                                      C.POINTER(_Info), C.POINTER(C.c_int32)]
         _lib = lib
     return _lib
 
@@ -230,6 +233,26 @@ def ta(A, b, tol=1e-6, max_iter=100000, tol_normal=0.0, rho0=0.0, fixed_rho=Fals
     _load().or_ta(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), _ptr(hist), cap, C.byref(inf))
     info = _info(inf)
     return x, hist[:min(info.iters + 1, cap)], info
+
+
+def ta_halving(A, b, tol=1e-6, tol_normal=0.0, max_halvings=20, max_iter=100000, rho0=0.0,
+               fixed_rho=False, x0: Optional[np.ndarray] = None):
+    """Algorithm 3 restarted with eps' halved each time it ends on the normal
+    equation (the remark after the theorem on its properties, section 4.3),
+    at most ``max_halvings`` times; eps' starts at ``tol_normal``, or at tol
+    when 0.  Returns (x, info, halvings): iterations and products summed over
+    the runs, the rest of info from the last run."""
+    M = _MatRef(A)
+    b = _f64(b)
+    x = np.zeros(M.n) if x0 is None else _f64(x0).copy()
+    o = _opts(tol, tol_normal, 1, max_iter, 0, x0 is not None, rho0, fixed_rho)
+    inf = _Info()
+    h = C.c_int32(0)
+    rc = _load().or_ta_halving(C.byref(M.s), _ptr(b), _ptr(x), C.byref(o), int(max_halvings),
+                               C.byref(inf), C.byref(h))
+    if rc != 0:
+        raise RuntimeError(f"or_ta_halving: {rc}")
+    return x, _info(inf), int(h.value)
 
 
 def csr_outer(A, u, v, alpha=1.0) -> np.ndarray:

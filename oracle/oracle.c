@@ -698,6 +698,37 @@ int or_ta(const or_mat *A, const double *b0, double *x, const or_opts *o, double
     return 0;
 }
 
+/* The restart of the remark that follows the theorem on Algorithm 3's
+ * properties (section 4.3): take eps' = eps at first (tol_normal = 0 means
+ * so); whenever a run ends with an eps'-approximate solution of the normal
+ * equation, halve eps' and run Algorithm 3 again from the current
+ * approximate solution (b' = A x first), at most max_halvings times.
+ * Iterations and products are summed over the runs; stop, residuals and
+ * radii are the last run's. */
+int or_ta_halving(const or_mat *A, const double *b, double *x, const or_opts *o,
+                  int32_t max_halvings, or_info *info, int32_t *halvings) {
+    or_opts p = *o;
+    if (!(p.tol_normal > 0.0)) p.tol_normal = p.tol;
+    int64_t iters = 0, matvecs = 0;
+    int32_t h = 0;
+    for (;;) {
+        or_info r;
+        const int rc = or_ta(A, b, x, &p, NULL, 0, &r);
+        if (rc != 0) return rc;
+        iters += r.iters;
+        matvecs += r.matvecs;
+        *info = r;
+        if (r.stop != OR_NORMAL || h >= max_halvings) break;
+        p.tol_normal *= 0.5;
+        p.warm_start = 1;
+        ++h;
+    }
+    info->iters = iters;
+    info->matvecs = matvecs;
+    *halvings = h;
+    return 0;
+}
+
 /* ---------------------------------------------------------------------- */
 /* Gradient of the solution map (not in the paper)                         */
 /* ---------------------------------------------------------------------- */
