@@ -302,6 +302,25 @@ int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, d
                     const ta_opts *opts, ta_info *info, int64_t *tests, void *stream);
 
 /*
+ * ta_solve_halving - Algorithm 3 restarted as the remark after the theorem
+ * on its properties (section 4.3) suggests: eps' (opts->tol_normal, or
+ * opts->tol when that is 0) is halved each time a run ends with an
+ * eps'-approximate solution of the normal equation (stop NORMAL), and TA
+ * runs again from the x it returned (b' = A x, one product more), at most
+ * max_halvings times; a consistent system whose normal-equation test fires
+ * first thus still reaches ||b - A x|| <= tol ||b||.  The first run starts
+ * from 0, or from the x passed in with opts->warm_start.
+ *   x         : device, n doubles, output (input too with warm_start);
+ *   info      : iters and matvecs summed over the runs; stop, rel_res,
+ *               rel_normal, rho and rho_lo of the last run;
+ *   halvings  : host, may be NULL: restarts made.
+ * Each run has opts->max_iter iterations.  TA_EINVAL for max_halvings < 0 or
+ * opts->normal_eq; other errors as ta_solve_plan.
+ */
+int ta_solve_halving(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                     int32_t max_halvings, ta_info *info, int32_t *halvings, void *stream);
+
+/*
  * cta_solve_plan_noalloc - cta_solve_plan for callers that cannot allocate
  * device memory (code that must not call hipMalloc, tight serving loops,
  * harnesses that forbid allocation).  Same arguments, same kernels, same

@@ -33,7 +33,7 @@ EXPORTS = ("cta_solve", "cta_minnorm", "ta_solve", "ta_validate", "ta_strerror",
            "cta_solve_plan", "cta_minnorm_plan", "ta_solve_plan", "ta_time_matvec_plan",
            "ta_spmv_plan", "ta_batch_plan_create", "ta_batch_plan_destroy", "cta_solve_batched",
            "ta_batch_time_spmm", "ta_csr_outer", "ta_minnorm", "ta_minnorm_plan", "ta_plan_format",
-           "cta_solve_plan_noalloc")
+           "cta_solve_plan_noalloc", "ta_solve_halving")
 # storage of a plan's products (ta_plan_format)
 FORMATS = {0: "csr_rows", 1: "dense_rows", 2: "dense_cols", 3: "csr_sliced", 4: "sell64",
            5: "csr_tiled", 6: "csr_merge"}
@@ -118,6 +118,8 @@ def load_library(path: str = LIB_PATH):
             f.restype = C.c_int
             f.argtypes = [P if name.endswith("plan") else MP, P, P, P, OP, IP,
                           C.POINTER(C.c_int64), P]
+        lib.ta_solve_halving.restype = C.c_int
+        lib.ta_solve_halving.argtypes = [P, P, P, OP, I32, IP, C.POINTER(C.c_int32), P]
         lib.ta_csr_outer.restype = C.c_int
         lib.ta_csr_outer.argtypes = [MP, P, P, C.c_double, P, P]
         lib.ta_time_matvec.restype = C.c_int
@@ -438,6 +440,27 @@ def ta_minnorm(A, b, x_eps, tol=1e-6, max_iter=100000, **kw):
                             C.byref(tests), _stream())
         _check(rc, "ta_minnorm")
     return x, _info(info), int(tests.value)
+
+
+def ta_solve_halving(plan, b, tol=1e-6, tol_normal=0.0, max_halvings=20, max_iter=100000,
+                     **kw):
+    """TA restarted with eps' halved after each stop on the normal equation
+    (ta_solve_halving), on a Plan.  Returns (x, info, halvings)."""
+    import torch
+
+    lib = load_library()
+    if not isinstance(plan, Plan):
+        raise TypeError("ta_solve_halving takes a Plan")
+    bd = _vec(b)
+    x = torch.zeros(plan.n, dtype=torch.float64, device=bd.device)
+    opts = make_opts(tol=tol, tol_normal=tol_normal, max_iter=max_iter, **kw)
+    info = TaInfo()
+    h = C.c_int32(0)
+    rc = lib.ta_solve_halving(plan.handle, C.c_void_p(bd.data_ptr()), C.c_void_p(x.data_ptr()),
+                              C.byref(opts), int(max_halvings), C.byref(info), C.byref(h),
+                              _stream())
+    _check(rc, "ta_solve_halving")
+    return x, _info(info), int(h.value)
 
 
 def csr_outer(A, u, v, alpha: float = 1.0):

@@ -1454,6 +1454,37 @@ int ta_minnorm_plan(const ta_plan *plan, const double *b, const double *x_eps, d
     return ta::minnorm_run(plan->p, b, x_eps, x, opts, info, tests, (hipStream_t)stream);
 }
 
+// The restart of the remark after the theorem on Algorithm 3's properties
+// (section 4.3): eps' halved after each run that ends on the normal
+// equation, the next run warm-started from that run's x.
+int ta_solve_halving(const ta_plan *plan, const double *b, double *x, const ta_opts *opts,
+                     int32_t max_halvings, ta_info *info, int32_t *halvings, void *stream) {
+    if (plan == nullptr || opts == nullptr || info == nullptr || max_halvings < 0)
+        return TA_EINVAL;
+    if (opts->normal_eq) return TA_EINVAL;
+    ta_opts o = *opts;
+    if (!(o.tol_normal > 0.0)) o.tol_normal = o.tol;
+    int64_t iters = 0, matvecs = 0;
+    int32_t h = 0;
+    for (;;) {
+        ta_info r;
+        memset(&r, 0, sizeof r);
+        const int rc = ta::ta_run(plan->p, b, x, &o, nullptr, 0, &r, (hipStream_t)stream);
+        if (rc != TA_OK) return rc;
+        iters += r.iters;
+        matvecs += r.matvecs;
+        *info = r;
+        if (r.stop != TA_STOP_NORMAL || h >= max_halvings) break;
+        o.tol_normal *= 0.5;
+        o.warm_start = 1;
+        ++h;
+    }
+    info->iters = iters;
+    info->matvecs = matvecs;
+    if (halvings != nullptr) *halvings = h;
+    return TA_OK;
+}
+
 int ta_validate(const ta_mat *A, const ta_opts *opts, int32_t solver) {
     int rc = ta::validate_mat(A);
     if (rc != TA_OK) return rc;

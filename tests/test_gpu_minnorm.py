@@ -111,3 +111,24 @@ def test_lp_shaped_plan_and_one_shot():
     assert np.array_equal(host(x1), host(x2)) and (i1, t1) == (i2, t2)
     xo, io, to = oracle.ta_minnorm(prob.A, prob.b, xe, tol=1e-4, max_iter=2_000_000)
     _same(i1, io, host(x1), xo, t1, to)
+
+
+@pytest.mark.parametrize("N,tol", [(101, 1e-6), (301, 1e-6), (301, 1e-4)])
+def test_halving_restarts_match_oracle(N, tol):
+    """TA restarted with eps' halved after each stop on the normal equation
+    (the remark after the theorem on Algorithm 3, section 4.3): equal stops,
+    restart counts, summed iteration and product counts; x within 1e-9."""
+    from workloads import kac_clement
+
+    p = kac_clement(N)
+    pl = P.plan(p.A)
+    x, ig, hg = P.ta_solve_halving(pl, p.b, tol=tol, max_iter=200_000)
+    xo, io, ho = oracle.ta_halving(p.A, p.b, tol=tol, max_iter=200_000)
+    assert (ig.stop, ig.iters, ig.matvecs, hg) == (io.stop, io.iters, io.matvecs, ho), (ig, io)
+    assert ig.stop == "residual" and hg >= 1
+    assert np.linalg.norm(host(x) - xo) <= 1e-9 * np.linalg.norm(xo)
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.ta_solve_halving(pl, p.b, tol=tol, max_halvings=-1)
+    with pytest.raises(P.TaError, match="EINVAL"):
+        P.ta_solve_halving(pl, p.b, tol=tol, normal_eq=True)
+    pl.close()
