@@ -95,3 +95,18 @@ def test_normal_eq_is_a_ta_option_only():
         P.cta_solve(A, b, normal_eq=True)
     with pytest.raises(P.TaError, match="EINVAL"):
         P.cta_minnorm(A, b, normal_eq=True)
+
+
+@pytest.mark.parametrize("kind", ["dense", "csr"])
+def test_normal_eq_from_a_warm_start(kind):
+    """The remark after the theorem on Algorithm 3 lets TA move to the normal
+    equation from the current iterate when A x = b does not look solvable:
+    TA on (A, b) until its normal-equation test at 1e-3, then TA with normal_eq warm-started
+    from its x (b' = A^T A x first), against the oracle doing the same."""
+    A, b = _rank_deficient(7)
+    M = csr_from_dense(A) if kind == "csr" else A
+    x1, _, i1 = P.ta_solve(M, b, tol=1e-6, tol_normal=1e-3, max_iter=200_000)
+    xo1, _, io1 = oracle.ta(M, b, tol=1e-6, tol_normal=1e-3, max_iter=200_000)
+    assert (i1.stop, i1.iters) == (io1.stop, io1.iters) and io1.stop == "normal"
+    _compare(P.ta_solve(M, b, tol=1e-6, max_iter=200_000, normal_eq=True, x0=x1),
+             oracle.ta(M, b, tol=1e-6, max_iter=200_000, normal_eq=True, x0=xo1))
