@@ -95,6 +95,11 @@ MATS = {
     "kac_1001": lambda: kac_clement(1001).A,
     "long_columns_50000x40": _long_columns,
     "dense_columns_2e6x3": _dense_columns,
+    # one dense row (the merge path on A) and one dense column (a 1e5-entry A^T row)
+    "one_row_1x100000": lambda: csr_from_dense(
+        np.random.default_rng(31).standard_normal((1, 100_000))),
+    "one_column_100000x1": lambda: csr_from_dense(
+        np.random.default_rng(32).standard_normal((100_000, 1))),
     "convdiff_33": lambda: convection_diffusion(33).A,
     "ragged_700x517": lambda: _ragged_csr(700, 517, 1, long_rows=(5, 300)),
     "lp_500x20000": lambda: lp_shaped(500, 20000, seed=3).A,
@@ -142,7 +147,8 @@ def test_one_thread_per_row_products_are_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", ["kac_1001", "ragged_700x517", "lp_500x20000", "convdiff_33",
-                                  "long_columns_50000x40", "dense_columns_2e6x3"])
+                                  "long_columns_50000x40", "dense_columns_2e6x3",
+                                  "one_column_100000x1"])
 def test_transpose_is_exact(name):
     A = MATS[name]()
     rp, ci, v = P.transpose(P.to_device(A))
