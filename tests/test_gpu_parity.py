@@ -619,7 +619,8 @@ def test_plan_rejects_malformed_csr():
         P.plan(bad)
 
 
-@pytest.mark.parametrize("case", ["cta_x", "cta_y", "ta", "ta_ne", "cta_accel_replace", "cta_cycle"])
+@pytest.mark.parametrize("case", ["cta_x", "cta_y", "ta", "ta_ne", "cta_accel_replace", "cta_cycle",
+                                  "cta_merge", "cta_tiled", "cta_sliced"])
 def test_graph_replay_equals_plain_launches(case):
     """Single-system chains replay their chunks from captured HIP graphs
     (launch_mode 0, the default) or launch every kernel (launch_mode 1): the
@@ -643,6 +644,15 @@ def test_graph_replay_equals_plain_launches(case):
         run = lambda **o: P.ta_solve(a, bb, tol=1e-7, max_iter=20000, normal_eq=True, **o)
     elif case == "cta_accel_replace":
         run = lambda **o: P.cta_solve(A, p.b, t=2, accel=0.5, replace_every=7, **kw, **o)
+    elif case in ("cta_merge", "cta_tiled", "cta_sliced"):
+        # plans whose products take the merge path (with its fix-up kernel),
+        # column tiles or column slices (each with its combine kernel)
+        q = {"cta_merge": lambda: skewed_rows(5000, 5000, seed=8, dense_rows=1),
+             "cta_tiled": _wide, "cta_sliced": _wide_sliced}[case]()
+        pl = P.plan(q.A)
+        assert pl.format(False) == {"cta_merge": "csr_merge", "cta_tiled": "csr_tiled",
+                                    "cta_sliced": "csr_sliced"}[case]
+        run = lambda **o: P.cta_minnorm(pl, q.b, t=3, tol=1e-20, max_iter=200, **o)
     else:
         run = lambda **o: P.cta_solve(A, p.b, t=4, t_cycle=True, **kw, **o)
     for _ in range(2):
