@@ -15,7 +15,7 @@ import pytest
 import oracle
 import paper_2304_12168_amd as P
 from workloads import (Csr, convection_diffusion, csr_from_coo, csr_from_dense, dense_gaussian,
-                       kac_clement, lp_shaped, random_diag_dominant, skewed_rows)
+                       kac_clement, lp_shaped, poisson5, random_diag_dominant, skewed_rows)
 
 pytestmark = pytest.mark.gpu
 
@@ -662,3 +662,28 @@ def test_graph_replay_equals_plain_launches(case):
         assert ig.iters > 64, ig  # several chunks, graphs replayed
         assert torch.equal(xg, xl) and torch.equal(hg, hl)
         assert ig.rel_res == il.rel_res and ig.rho == il.rho
+
+
+FULL = {
+    # the bandwidth sweep's sizes, in the layouts the benchmark times
+    "skewed_1e6_merge": (lambda: skewed_rows(1_000_000, 1_000_000, seed=0).A, "csr_merge"),
+    "poisson_2896_sell_nt": (lambda: poisson5(2896), "sell64"),
+    "lp_1e7_sliced16": (lambda: lp_shaped(100_000, 10_000_000, seed=0).A, "csr_sliced"),
+}
+
+
+@pytest.mark.parametrize("case", sorted(FULL))
+def test_full_size_products_match_oracle(case):
+    """Every output entry of the A and A^T products at the benchmark's sizes
+    (the merge path on 8e6 skewed nonzeros, SELL-64 with non-temporal loads on
+    4.2e7, 16 column slices on 6e7) within 1 ulp of the oracle."""
+    make, fmt = FULL[case]
+    A = make()
+    pl = P.plan(A)
+    assert pl.format(False) == fmt
+    g = np.random.default_rng(5)
+    x = g.standard_normal(A.n)
+    u = g.standard_normal(A.m)
+    assert ulps(host(P.spmv(pl, x)), oracle.apply(A, x)).max() <= 1
+    assert ulps(host(P.spmv(pl, u, trans=True)), oracle.apply_t(A, u)).max() <= 1
+    pl.close()
